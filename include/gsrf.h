@@ -1,0 +1,218 @@
+/*
+ * gsrf.h -- C ABI of the MI355X (gfx950) GSRF hot-path library, libgsrf.so.
+ *
+ * GSRF (arXiv 2502.01826) renders complex-valued 3D Gaussians onto a
+ * receiver's azimuth x elevation ray grid: orthographic splatting onto the 2D
+ * receiving RF plane (Sec. 3.3), per-tile depth sorting with 64-bit
+ * (tile | distance) keys (App. E, Alg. 1), and complex front-to-back ray
+ * accumulation (Sec. 3.4 eq. rendering; App. A), plus its adjoint (App. C
+ * backward kernel; App. D gradients).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless the comment says HOST.  Arrays are
+ *     row-major, FP32 unless stated, and owned by the caller; the library
+ *     never allocates or frees memory.
+ *   - Every call is asynchronous on the HIP stream passed as `stream`
+ *     (a hipStream_t; NULL = the null stream) and does no host
+ *     synchronisation, except gsrf_splat_count, which synchronises the stream.
+ *     Calls on one problem must be issued in the order
+ *     project -> bin_sort -> render_fwd [-> render_bwd] on one stream.
+ *   - Arguments are validated on the host before anything is launched:
+ *     GSRF_EINVAL means nothing was enqueued.  GSRF_EDEVICE reports a HIP
+ *     launch error.  NaN or Inf parameters are not checked; they propagate.
+ *   - A problem with no Gaussians, or pairs whose scene is empty, is valid and
+ *     renders exact zeros.
+ */
+#ifndef GSRF_H_
+#define GSRF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gsrf_status {
+  GSRF_OK = 0,
+  GSRF_EINVAL = 1,     /* bad argument; nothing enqueued */
+  GSRF_ECAPACITY = 2,  /* more splats than splat_capacity (see gsrf_splat_count) */
+  GSRF_EDEVICE = 3,    /* a HIP call or kernel launch failed */
+  GSRF_ENOTSUP = 4     /* valid request this build does not implement */
+} gsrf_status;
+
+/*
+ * Receiver ray grid and render constants.
+ *   Rays sit at cell centres of the 2D receiving RF plane (Sec. 3.3 eqs.
+ *   spherical coordinates and discretization): azimuth
+ *   alpha_u = 2 pi (u + 1/2) / n_az, elevation
+ *   beta_v = el_lo + (el_hi - el_lo)(v + 1/2) / n_el, direction
+ *   fp32(cos b cos a, cos b sin a, sin b) evaluated in FP64.
+ *   fle_L      Fourier-Legendre degree L of the radiance (Sec. 3.2 eq. FLE),
+ *              K = (L+1)^2 complex coefficients per Gaussian; 0 <= L <= 6.
+ *   r_rx       radius of the ray-emitting spherical surface (Sec. 3.3; the
+ *              paper uses 1.0): a Gaussian counts only if its chord midpoint
+ *              lies at ray parameter >= r_rx.
+ *   t_min      a ray stops before the first hit whose transmittance < t_min.
+ *   alpha_max  opacity clamp, in (0, 1).
+ *   tile_w/h   rays per tile (App. E uses 16 x 16); tile_w * tile_h must be
+ *              64, 128 or 256.
+ */
+typedef struct gsrf_grid {
+  int32_t n_az, n_el;
+  float el_lo, el_hi;
+  int32_t fle_L;
+  float r_rx;
+  float t_min;
+  float alpha_max;
+  int32_t tile_w, tile_h;
+} gsrf_grid;
+
+/*
+ * One transmitter/receiver query (Sec. 3.1 problem formulation: TX at t,
+ * RX at r).  40 bytes.  freq_hz is the carrier; wavelength = 3e8 / freq_hz.
+ * scene indexes the CSR scene table.
+ */
+typedef struct gsrf_pair {
+  float rx[3];
+  float tx[3];
+  double freq_hz;
+  int32_t scene;
+  int32_t reserved;
+} gsrf_pair;
+
+/*
+ * A batch: S scenes of Gaussians concatenated in one parameter set, and P
+ * pairs, each rendering one scene.  Gaussian parameters (Sec. 3.2 primitive
+ * zeta_k = (mu, R, S, psi, rho)):
+ *   means           [G,3]    mu
+ *   log_scales      [G,3]    s = exp(log_scales); Sigma = R diag(s)^2 R^T
+ *   quats           [G,4]    rotation (w,x,y,z), normalised in-kernel
+ *   opacity_logits  [G]      o = sigmoid(logit); transmittance 1 - o G
+ *   coeffs          [G,K,2]  complex FLE coefficients c_i, i = l^2 + l + m
+ * scene_offsets (HOST) and scene_offsets_dev (DEVICE) hold the same S+1
+ * non-decreasing values with scene_offsets[0] = 0, scene_offsets[S] = G.
+ * pair_scene (HOST, [P]) repeats pairs[k].scene for host-side sizing.
+ * workspace (DEVICE, workspace_bytes >= gsrf_workspace_size) holds every
+ * intermediate; it must stay untouched between the calls of one render.
+ */
+typedef struct gsrf_problem {
+  const float *means, *log_scales, *quats, *opacity_logits, *coeffs;
+  int64_t n_gauss;
+  int32_t n_scenes;
+  const int64_t *scene_offsets;      /* HOST [S+1] */
+  const int64_t *scene_offsets_dev;  /* DEVICE [S+1] */
+  const gsrf_pair *pairs;            /* DEVICE [P] */
+  const int32_t *pair_scene;         /* HOST [P] */
+  int32_t n_pairs;
+  gsrf_grid grid;
+  int64_t splat_capacity;            /* max (tile, Gaussian) splats, < 2^32 */
+  void *workspace;
+  size_t workspace_bytes;
+} gsrf_problem;
+
+/* Byte offsets of the workspace arrays that tests and tools may read. */
+typedef struct gsrf_layout {
+  size_t rec_key;      /* uint32 [R]      per (pair, Gaussian) depth key bits(fp32(|mu-r|^2)) */
+  size_t rec_rect;     /* uint16 [R][4]   tile rectangle (tu0, ntu, tv0, ntv) */
+  size_t rec_base;     /* int64  [P+1]    first record of each pair; R = rec_base[P] */
+  size_t counters;     /* int64  [4]      [0] splat count, [1] = count if over capacity else 0 */
+  size_t sorted_khi;   /* uint32 [cap]    sorted splat key, high word = pair * T + tile */
+  size_t sorted_klo;   /* uint32 [cap]    sorted splat key, low word = depth key */
+  size_t sorted_val;   /* uint32 [cap]    Gaussian index of each sorted splat */
+  size_t tile_start;   /* uint32 [P*T]    first sorted splat of each tile */
+  size_t tile_end;     /* uint32 [P*T]    one past the last */
+  int64_t n_records;   /* R */
+  int32_t n_tiles;     /* T per pair */
+  int32_t n_tiles_az;  /* tile columns (azimuth) */
+} gsrf_layout;
+
+/* Human-readable status name; never NULL. */
+const char *gsrf_status_str(gsrf_status s);
+
+/* Message of the last failing call in this thread (empty if none). */
+const char *gsrf_last_error(void);
+
+/*
+ * Size of the workspace for `p` (only its sizes, grid and host arrays are
+ * read; device pointers may be NULL).  HOST out.
+ */
+gsrf_status gsrf_workspace_size(const gsrf_problem *p, size_t *bytes);
+
+/* Workspace offsets for `p` (same reading as gsrf_workspace_size). HOST out. */
+gsrf_status gsrf_layout_of(const gsrf_problem *p, gsrf_layout *out);
+
+/*
+ * Steps a1 + a2: per-Gaussian activation (Sec. 2 Sigma = R S S^T R^T; App. A.3
+ * normalised pdf) and orthographic splatting of every (pair, Gaussian)
+ * (Sec. 3.3 splatting process; Alg. 1 sphericalGaussian/sphericalSplatting):
+ * depth key, and the tile rectangle covered by the Gaussian's bounding cap of
+ * radius 3 max(s) widened by 1e-5 rad -- conservative, so binning only culls.
+ * Gaussians wholly inside the RESS or outside the elevation span are culled.
+ * Ends with the splat count, readable by gsrf_splat_count.
+ */
+gsrf_status gsrf_project(const gsrf_problem *p, void *stream);
+
+/*
+ * Synchronises `stream` and returns (HOST) the number of splats the last
+ * gsrf_project produced.  Returns GSRF_ECAPACITY if it exceeds
+ * splat_capacity (the caller then re-sizes and re-runs from gsrf_project).
+ */
+gsrf_status gsrf_splat_count(const gsrf_problem *p, int64_t *n_splats, void *stream);
+
+/*
+ * Steps a3 + a4 (Alg. 1 sphericalSplatting, the radix sort of App. E,
+ * computeGridRange): emit one (key64, Gaussian) splat per covered tile with
+ * key64 = (pair * T + tile) << 32 | depth key, stable LSD radix sort on key64,
+ * then the [start, end) range of each tile.  Within a tile, Gaussians end up
+ * in (depth key, index) order.  If the splat count exceeds splat_capacity the
+ * device-side overflow counter is set and only the first splat_capacity
+ * splats are sorted; results are then invalid (see gsrf_splat_count).
+ */
+gsrf_status gsrf_bin_sort(const gsrf_problem *p, void *stream);
+
+/*
+ * Steps a5 + a6 (Sec. 3.4 eq. rendering; App. A; Alg. 1 Blend): for every
+ * ray, in tile depth order, a Gaussian is hit iff B^2 - A(C - 9) >= 0 and the
+ * chord midpoint t = -B/A >= r_rx (App. D.3.3); it adds T * N G(x_mid) * psi *
+ * e^{-j 2 pi (|mu - tx| + t)/lambda} and multiplies T by
+ * 1 - min(o G(x_mid), alpha_max); the ray stops before a hit with T < t_min.
+ *   signal      [P, n_el, n_az, 2]  complex received signal per ray (re, im)
+ *   signal_sum  [P, 2]              S_hat = sum over rays (Sec. 3.4 single antenna)
+ *   rssi_dbm    [P] or NULL         10 log10 |S_hat|^2 (-inf when S_hat = 0)
+ * Deterministic: repeated calls give bit-identical outputs.
+ */
+gsrf_status gsrf_render_fwd(const gsrf_problem *p, float *signal, float *signal_sum, float *rssi_dbm,
+                            void *stream);
+
+/*
+ * Steps a7 + a8 (App. C backward kernel; App. D gradients, including the
+ * covariance chain the paper omits): recomputes each ray's transmittance
+ * front to back (no per-ray state is stored by render_fwd beyond `signal`)
+ * and forms the gradient of L with respect to every parameter, where the
+ * caller supplies dL/dS per ray and per pair:
+ *   signal       [P, n_el, n_az, 2]  the render_fwd output for this problem
+ *   grad_signal  [P, n_el, n_az, 2]  dL/dRe S + j dL/dIm S
+ *   grad_sum     [P, 2] or NULL      dL/dS_hat (added to every ray of the pair)
+ * Outputs are OVERWRITTEN (not accumulated), summed over all pairs:
+ *   d_means [G,3], d_log_scales [G,3], d_quats [G,4], d_logits [G], d_coeffs [G,K,2].
+ * Discrete decisions (hit test, termination, clamp) are treated as constant.
+ * Uses float atomics, so results are reproducible only to rounding.
+ */
+gsrf_status gsrf_render_bwd(const gsrf_problem *p, const float *signal, const float *grad_signal,
+                            const float *grad_sum, float *d_means, float *d_log_scales, float *d_quats,
+                            float *d_logits, float *d_coeffs, void *stream);
+
+/*
+ * Instrumentation for the roofline: replays the render_fwd traversal of a
+ * problem prepared by gsrf_project + gsrf_bin_sort without writing any
+ * output, and stores (DEVICE, int64 [4], overwritten) the number of
+ * (ray, Gaussian) hit tests, processed hits, staged list entries and rays.
+ */
+gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSRF_H_ */

@@ -225,9 +225,9 @@ def depth_order(means, rx) -> np.ndarray:
 class Bands:
     """Widths of the FP32-marginal bands for discrete decisions (R28)."""
 
-    q: float = 1e-3        # |Q - 9| (absolute, Mahalanobis^2 units)
+    q: float = 3e-4        # |Q - 9| (absolute, Mahalanobis^2 units)
     t: float = 1e-5        # |t - r_rx| relative to max(1, t)
-    T: float = 1e-3        # |T - t_min| relative to t_min
+    T: float = 3e-4        # |T - t_min| relative to t_min
 
 
 def _per_ray_terms(P: Params, act, rx, tx, lam, grid, dirs, Y, cols):
@@ -382,16 +382,21 @@ def trace(scene_or_params, pair, grid, rays_uv=None, *, grad=False, bands: Bands
 
 
 def _marginal(terms, hit, active, T, grid, bands: Bands):
-    """Rays with a discrete decision inside the FP32-marginal band (R28)."""
+    """Rays with a discrete decision inside the FP32-marginal band (R28).
+
+    Only decisions the ray actually reaches count: a Gaussian whose incoming
+    transmittance is already clearly below t_min is never examined.
+    """
     with torch.no_grad():
         r_rx, t_min = _f32(grid.r_rx), _f32(grid.t_min)
         Q, t = terms["Q"], terms["t"]
-        q_edge = ((Q - LEVEL).abs() <= bands.q) & (t >= r_rx - bands.t * torch.clamp(t.abs(), min=1.0))
-        t_edge = ((t - r_rx).abs() <= bands.t * torch.clamp(t.abs(), min=1.0)) & (Q <= LEVEL + bands.q)
-        # termination: a hit whose T sits inside the band around t_min
+        reached = T >= t_min * (1.0 - bands.T)
+        tb = bands.t * torch.clamp(t.abs(), min=1.0)
+        q_edge = ((Q - LEVEL).abs() <= bands.q) & (t >= r_rx - tb)
+        t_edge = ((t - r_rx).abs() <= tb) & (Q <= LEVEL + bands.q)
         near_hit = hit | q_edge | t_edge
         T_edge = near_hit & ((T - t_min).abs() <= bands.T * t_min)
-        return (q_edge | t_edge | T_edge).any(1)
+        return ((q_edge | t_edge) & reached | T_edge).any(1)
 
 
 def ray_sequence(scene, pair, grid, u: int, v: int, *, direction=None, basis=None):

@@ -1,0 +1,246 @@
+// Host side of the C ABI: argument validation, workspace layout and launch
+// sequencing.  Nothing here allocates device memory or synchronises, except
+// gsrf_splat_count, whose contract is to synchronise.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "gsrf_internal.h"
+
+namespace gsrf {
+
+static thread_local char g_err[512];
+
+static gsrf_status fail(gsrf_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static gsrf_status fail(gsrf_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+static gsrf_status dev(hipError_t e, const char *where) {
+  if (e == hipSuccess) return GSRF_OK;
+  return fail(GSRF_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int bits_for(int64_t x) {  // bits needed to represent 0..x
+  int b = 0;
+  while (x > 0) {
+    ++b;
+    x >>= 1;
+  }
+  return b;
+}
+
+// Validates the host-readable parts of a problem and computes its layout.
+static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
+  if (!p || !lay) return fail(GSRF_EINVAL, "null problem or output");
+  const gsrf_grid &g = p->grid;
+  if (g.n_az <= 0 || g.n_el <= 0 || g.n_az > 65535 || g.n_el > 65535)
+    return fail(GSRF_EINVAL, "grid size %d x %d out of range [1, 65535]", g.n_az, g.n_el);
+  if (g.fle_L < 0 || g.fle_L > 6) return fail(GSRF_EINVAL, "fle_L = %d outside [0, 6]", g.fle_L);
+  const int nt = g.tile_w * g.tile_h;
+  if (g.tile_w <= 0 || g.tile_h <= 0 || (nt != 64 && nt != 128 && nt != 256))
+    return fail(GSRF_EINVAL, "tile %d x %d: tile_w * tile_h must be 64, 128 or 256", g.tile_w, g.tile_h);
+  if (!(g.el_lo < g.el_hi) || g.el_lo < -1.5707964f || g.el_hi > 1.5707964f)
+    return fail(GSRF_EINVAL, "elevation span [%g, %g] invalid", (double)g.el_lo, (double)g.el_hi);
+  if (!(g.r_rx >= 0.f) || !(g.t_min >= 0.f) || !(g.alpha_max > 0.f && g.alpha_max < 1.f))
+    return fail(GSRF_EINVAL, "need r_rx >= 0, t_min >= 0, 0 < alpha_max < 1");
+  if (p->n_gauss < 0 || p->n_gauss >= ((int64_t)1 << 31)) return fail(GSRF_EINVAL, "n_gauss = %lld", (long long)p->n_gauss);
+  if (p->n_pairs < 0 || p->n_pairs > 65535) return fail(GSRF_EINVAL, "n_pairs = %d outside [0, 65535]", p->n_pairs);
+  if (p->n_scenes < 1) return fail(GSRF_EINVAL, "n_scenes must be >= 1");
+  if (!p->scene_offsets) return fail(GSRF_EINVAL, "scene_offsets (host) is NULL");
+  if (p->scene_offsets[0] != 0 || p->scene_offsets[p->n_scenes] != p->n_gauss)
+    return fail(GSRF_EINVAL, "scene_offsets must start at 0 and end at n_gauss");
+  int64_t max_scene = 0;
+  for (int s = 0; s < p->n_scenes; ++s) {
+    const int64_t n = p->scene_offsets[s + 1] - p->scene_offsets[s];
+    if (n < 0) return fail(GSRF_EINVAL, "scene_offsets not non-decreasing at %d", s);
+    if (n > max_scene) max_scene = n;
+  }
+  if (p->n_pairs > 0 && !p->pair_scene) return fail(GSRF_EINVAL, "pair_scene (host) is NULL");
+  int64_t R = 0, max_used = 0;
+  for (int k = 0; k < p->n_pairs; ++k) {
+    const int s = p->pair_scene[k];
+    if (s < 0 || s >= p->n_scenes) return fail(GSRF_EINVAL, "pair %d: scene %d out of range", k, s);
+    const int64_t n = p->scene_offsets[s + 1] - p->scene_offsets[s];
+    R += n;
+    if (n > max_used) max_used = n;
+  }
+  if (p->splat_capacity < 0 || p->splat_capacity >= ((int64_t)1 << 32) - 1)
+    return fail(GSRF_EINVAL, "splat_capacity = %lld outside [0, 2^32 - 1)", (long long)p->splat_capacity);
+  const int nta = (g.n_az + g.tile_w - 1) / g.tile_w;
+  const int nte = (g.n_el + g.tile_h - 1) / g.tile_h;
+  const int64_t T = (int64_t)nta * nte;
+  if ((int64_t)p->n_pairs * T >= ((int64_t)1 << 31)) return fail(GSRF_EINVAL, "n_pairs * tiles too large");
+  if (need_device) {
+    if (p->n_gauss > 0 && (!p->means || !p->log_scales || !p->quats || !p->opacity_logits || !p->coeffs))
+      return fail(GSRF_EINVAL, "a Gaussian parameter pointer is NULL");
+    if (!p->scene_offsets_dev) return fail(GSRF_EINVAL, "scene_offsets_dev is NULL");
+    if (p->n_pairs > 0 && !p->pairs) return fail(GSRF_EINVAL, "pairs is NULL");
+    if (!p->workspace) return fail(GSRF_EINVAL, "workspace is NULL");
+    if ((uintptr_t)p->workspace & 255) return fail(GSRF_EINVAL, "workspace must be 256-byte aligned");
+  }
+  Layout L{};
+  L.n_records = R;
+  L.max_scene = max_used;
+  L.cap = p->splat_capacity;
+  L.T = (int32_t)T;
+  L.nta = nta;
+  L.nte = nte;
+  L.K = fle_K(g.fle_L);
+  L.acc_stride = 11 + 2 * L.K;
+  L.n_rec_blocks = (int32_t)((R + kScanTile - 1) / kScanTile);
+  L.n_sort_blocks = (int32_t)((L.cap + kSortTile - 1) / kSortTile);
+  L.n_hist_blocks = (int32_t)(((int64_t)256 * L.n_sort_blocks + kScanTile - 1) / kScanTile);
+  const int64_t PT = (int64_t)p->n_pairs * T;
+  L.sort_passes = 4 + (bits_for(PT > 0 ? PT - 1 : 0) + 7) / 8;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const int64_t G = p->n_gauss;
+  L.prep = take((size_t)G * kPrep * 4);
+  L.rec_base = take((size_t)(p->n_pairs + 1) * 8);
+  L.rec_key = take((size_t)R * 4);
+  L.rec_rect = take((size_t)R * 8);
+  L.rec_cnt = take((size_t)R * 4);
+  L.rec_off = take((size_t)R * 8);
+  L.scan_tmp = take((size_t)(L.n_rec_blocks + 1) * 8);
+  L.counters = take(4 * 8);
+  for (int b = 0; b < 2; ++b) {
+    L.khi[b] = take((size_t)L.cap * 4);
+    L.klo[b] = take((size_t)L.cap * 4);
+    L.val[b] = take((size_t)L.cap * 4);
+  }
+  L.hist = take((size_t)256 * L.n_sort_blocks * 4);
+  L.hist_scan = take((size_t)256 * L.n_sort_blocks * 4);
+  L.hist_tmp = take((size_t)(L.n_hist_blocks + 1) * 4);
+  L.tile_start = take((size_t)PT * 4);
+  L.tile_end = take((size_t)PT * 4);
+  L.tile_sum = take((size_t)PT * 8);
+  L.grad_acc = take((size_t)G * L.acc_stride * 4);
+  L.total = o;
+  if (need_device && p->workspace_bytes < L.total)
+    return fail(GSRF_EINVAL, "workspace_bytes %zu < required %zu", p->workspace_bytes, L.total);
+  *lay = L;
+  return GSRF_OK;
+}
+
+}  // namespace gsrf
+
+using namespace gsrf;
+
+extern "C" {
+
+const char *gsrf_status_str(gsrf_status s) {
+  switch (s) {
+    case GSRF_OK: return "GSRF_OK";
+    case GSRF_EINVAL: return "GSRF_EINVAL";
+    case GSRF_ECAPACITY: return "GSRF_ECAPACITY";
+    case GSRF_EDEVICE: return "GSRF_EDEVICE";
+    case GSRF_ENOTSUP: return "GSRF_ENOTSUP";
+  }
+  return "GSRF_UNKNOWN";
+}
+
+const char *gsrf_last_error(void) { return g_err; }
+
+gsrf_status gsrf_workspace_size(const gsrf_problem *p, size_t *bytes) {
+  if (!bytes) return fail(GSRF_EINVAL, "bytes is NULL");
+  Layout L;
+  gsrf_status st = plan(p, &L, false);
+  if (st != GSRF_OK) return st;
+  *bytes = L.total;
+  return GSRF_OK;
+}
+
+gsrf_status gsrf_layout_of(const gsrf_problem *p, gsrf_layout *out) {
+  if (!out) return fail(GSRF_EINVAL, "out is NULL");
+  Layout L;
+  gsrf_status st = plan(p, &L, false);
+  if (st != GSRF_OK) return st;
+  const int cur = L.sort_passes & 1;
+  out->rec_key = L.rec_key;
+  out->rec_rect = L.rec_rect;
+  out->rec_base = L.rec_base;
+  out->counters = L.counters;
+  out->sorted_khi = L.khi[cur];
+  out->sorted_klo = L.klo[cur];
+  out->sorted_val = L.val[cur];
+  out->tile_start = L.tile_start;
+  out->tile_end = L.tile_end;
+  out->n_records = L.n_records;
+  out->n_tiles = L.T;
+  out->n_tiles_az = L.nta;
+  return GSRF_OK;
+}
+
+gsrf_status gsrf_project(const gsrf_problem *p, void *stream) {
+  Layout L;
+  gsrf_status st = plan(p, &L, true);
+  if (st != GSRF_OK) return st;
+  return dev(launch_project(p, L, (char *)p->workspace, (hipStream_t)stream), "gsrf_project");
+}
+
+gsrf_status gsrf_splat_count(const gsrf_problem *p, int64_t *n_splats, void *stream) {
+  if (!n_splats) return fail(GSRF_EINVAL, "n_splats is NULL");
+  Layout L;
+  gsrf_status st = plan(p, &L, true);
+  if (st != GSRF_OK) return st;
+  int64_t c[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(c, (char *)p->workspace + L.counters, sizeof(c), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return dev(e, "gsrf_splat_count");
+  *n_splats = c[0];
+  if (c[0] > L.cap) return fail(GSRF_ECAPACITY, "%lld splats exceed capacity %lld", (long long)c[0], (long long)L.cap);
+  return GSRF_OK;
+}
+
+gsrf_status gsrf_bin_sort(const gsrf_problem *p, void *stream) {
+  Layout L;
+  gsrf_status st = plan(p, &L, true);
+  if (st != GSRF_OK) return st;
+  return dev(launch_bin_sort(p, L, (char *)p->workspace, (hipStream_t)stream), "gsrf_bin_sort");
+}
+
+gsrf_status gsrf_render_fwd(const gsrf_problem *p, float *signal, float *signal_sum, float *rssi_dbm, void *stream) {
+  Layout L;
+  gsrf_status st = plan(p, &L, true);
+  if (st != GSRF_OK) return st;
+  if (p->n_pairs > 0 && (!signal || !signal_sum)) return fail(GSRF_EINVAL, "signal or signal_sum is NULL");
+  return dev(launch_render_fwd(p, L, (char *)p->workspace, signal, signal_sum, rssi_dbm, (hipStream_t)stream),
+             "gsrf_render_fwd");
+}
+
+gsrf_status gsrf_render_bwd(const gsrf_problem *p, const float *signal, const float *grad_signal,
+                            const float *grad_sum, float *d_means, float *d_log_scales, float *d_quats,
+                            float *d_logits, float *d_coeffs, void *stream) {
+  Layout L;
+  gsrf_status st = plan(p, &L, true);
+  if (st != GSRF_OK) return st;
+  if (p->n_pairs > 0 && (!signal || !grad_signal)) return fail(GSRF_EINVAL, "signal or grad_signal is NULL");
+  if (p->n_gauss > 0 && (!d_means || !d_log_scales || !d_quats || !d_logits || !d_coeffs))
+    return fail(GSRF_EINVAL, "a gradient output pointer is NULL");
+  return dev(launch_render_bwd(p, L, (char *)p->workspace, signal, grad_signal, grad_sum, d_means, d_log_scales,
+                               d_quats, d_logits, d_coeffs, (hipStream_t)stream),
+             "gsrf_render_bwd");
+}
+
+gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stream) {
+  Layout L;
+  gsrf_status st = plan(p, &L, true);
+  if (st != GSRF_OK) return st;
+  if (!counts) return fail(GSRF_EINVAL, "counts is NULL");
+  return dev(launch_render_stats(p, L, (char *)p->workspace, counts, (hipStream_t)stream), "gsrf_render_stats");
+}
+
+}  // extern "C"

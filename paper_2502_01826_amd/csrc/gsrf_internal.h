@@ -1,0 +1,84 @@
+// Internal declarations shared by the libgsrf translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gsrf.h"
+
+namespace gsrf {
+
+// Speed of light fixed by the two-path example of Sec. 2 (3 m <-> 10 ns).
+constexpr double kC0 = 3.0e8;
+// Widening of the bounding cap used for binning (rad); covers the FP32
+// rounding of ray directions with a wide margin.
+constexpr double kCapSlack = 1e-5;
+// 3-sigma ellipsoid level (App. D.3.1).
+constexpr float kLevel = 9.0f;
+// Per-Gaussian prepared record: mu(3), N, M00 M11 M22 M01 M02 M12, o, pad(5).
+constexpr int kPrep = 16;
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;   // elements per scan block
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;   // keys per radix-sort block
+
+// Byte offsets of every workspace array plus derived sizes.
+struct Layout {
+  size_t prep, rec_base, rec_key, rec_rect, rec_cnt, rec_off, scan_tmp, counters;
+  size_t khi[2], klo[2], val[2];
+  size_t hist, hist_scan, hist_tmp;
+  size_t tile_start, tile_end, tile_sum, grad_acc;
+  size_t total;
+  int64_t n_records;
+  int64_t max_scene;
+  int64_t cap;
+  int32_t n_rec_blocks;   // scan blocks over records
+  int32_t n_sort_blocks;  // radix-sort blocks over capacity
+  int32_t n_hist_blocks;  // scan blocks over the radix histogram
+  int32_t T, nta, nte;
+  int32_t K, acc_stride;
+  int32_t sort_passes;
+};
+
+inline int fle_K(int L) { return (L + 1) * (L + 1); }
+
+// Launch helpers implemented in the .hip files; each returns hipSuccess or the
+// launch error.
+hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hipStream_t s);
+hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, hipStream_t s);
+hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws, float *signal,
+                             float *signal_sum, float *rssi_dbm, hipStream_t s);
+hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *ws, int64_t *counts, hipStream_t s);
+hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws, const float *signal,
+                             const float *grad_signal, const float *grad_sum, float *d_means,
+                             float *d_log_scales, float *d_quats, float *d_logits, float *d_coeffs,
+                             hipStream_t s);
+
+// Exclusive scan of n inputs (uint32) into int64 or uint32 outputs; writes the
+// grand total to *total (device) when total != nullptr.  n is host-known.
+hipError_t scan_u32_to_i64(const uint32_t *in, int64_t n, int64_t *out, int64_t *tmp, int32_t nblocks,
+                           int64_t *total, int64_t cap_for_flag, int64_t *flag, hipStream_t s);
+hipError_t scan_u32_to_u32(const uint32_t *in, int64_t n, uint32_t *out, uint32_t *tmp, int32_t nblocks,
+                           hipStream_t s);
+
+template <typename T>
+__global__ void k_fill(T *p, T v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+template <typename T>
+inline hipError_t fill(T *p, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace gsrf

@@ -1,0 +1,142 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, its structures match the ctypes mirrors, and host-side
+validation rejects bad problems before anything is launched (no GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsrf.h")
+
+from paper_2502_01826_amd import _lib  # noqa: E402
+from paper_2502_01826_amd._lib import GsrfGrid, GsrfLayout, GsrfPair, GsrfProblem  # noqa: E402
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsrf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 9
+    L = _lib.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_lib.EXPORTS) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+def test_struct_layout_matches_header():
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "gsrf.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("sizeof_grid %zu\nsizeof_pair %zu\nsizeof_problem %zu\nsizeof_layout %zu\n",
+         sizeof(gsrf_grid), sizeof(gsrf_pair), sizeof(gsrf_problem), sizeof(gsrf_layout));
+  P(gsrf_pair, freq_hz); P(gsrf_pair, scene);
+  P(gsrf_problem, n_gauss); P(gsrf_problem, grid); P(gsrf_problem, splat_capacity); P(gsrf_problem, workspace_bytes);
+  P(gsrf_layout, n_records); P(gsrf_layout, n_tiles_az);
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(prog)
+        exe = os.path.join(d, "t")
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        vals = dict(l.split() for l in subprocess.run([exe], capture_output=True, text=True).stdout.splitlines())
+    assert int(vals["sizeof_grid"]) == ctypes.sizeof(GsrfGrid)
+    assert int(vals["sizeof_pair"]) == ctypes.sizeof(GsrfPair) == 40
+    assert int(vals["sizeof_problem"]) == ctypes.sizeof(GsrfProblem)
+    assert int(vals["sizeof_layout"]) == ctypes.sizeof(GsrfLayout)
+    assert int(vals["gsrf_pair.freq_hz"]) == GsrfPair.freq_hz.offset
+    assert int(vals["gsrf_pair.scene"]) == GsrfPair.scene.offset
+    for f in ("n_gauss", "grid", "splat_capacity", "workspace_bytes"):
+        assert int(vals[f"gsrf_problem.{f}"]) == getattr(GsrfProblem, f).offset
+    for f in ("n_records", "n_tiles_az"):
+        assert int(vals[f"gsrf_layout.{f}"]) == getattr(GsrfLayout, f).offset
+
+
+def _host_problem(n_gauss=10, n_pairs=2, grid=None, cap=1000):
+    offs = np.array([0, n_gauss], np.int64)
+    ps = np.zeros(n_pairs, np.int32)
+    p = GsrfProblem()
+    p.n_gauss = n_gauss
+    p.n_scenes = 1
+    p.scene_offsets = offs.ctypes.data
+    p.pair_scene = ps.ctypes.data
+    p.n_pairs = n_pairs
+    p.grid = grid or GsrfGrid(360, 90, 0.0, 1.5707963, 2, 1.0, 1e-4, 0.99, 16, 16)
+    p.splat_capacity = cap
+    return p, (offs, ps)
+
+
+def test_workspace_size_and_layout():
+    L = _lib.lib()
+    p, keep = _host_problem()
+    n = ctypes.c_size_t()
+    assert L.gsrf_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    lay = GsrfLayout()
+    assert L.gsrf_layout_of(ctypes.byref(p), ctypes.byref(lay)) == 0
+    assert lay.n_records == 20 and lay.n_tiles == 23 * 6 and lay.n_tiles_az == 23
+    offs = [lay.rec_key, lay.rec_rect, lay.rec_base, lay.counters, lay.sorted_khi, lay.sorted_klo, lay.sorted_val,
+            lay.tile_start, lay.tile_end]
+    assert all(o % 256 == 0 and o < n.value for o in offs)
+    # bigger capacity, bigger workspace
+    p2, keep2 = _host_problem(cap=100000)
+    n2 = ctypes.c_size_t()
+    assert L.gsrf_workspace_size(ctypes.byref(p2), ctypes.byref(n2)) == 0
+    assert n2.value > n.value + 100000 * 24
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda p: setattr(p.grid, "tile_w", 5), "tile"),
+    (lambda p: setattr(p.grid, "fle_L", 7), "fle_L"),
+    (lambda p: setattr(p.grid, "n_az", 0), "grid size"),
+    (lambda p: setattr(p.grid, "alpha_max", 1.0), "alpha_max"),
+    (lambda p: setattr(p.grid, "el_hi", -0.5), "elevation"),
+    (lambda p: setattr(p, "splat_capacity", -1), "splat_capacity"),
+    (lambda p: setattr(p, "n_scenes", 0), "n_scenes"),
+])
+def test_validation_rejects_bad_problems(mutate, needle):
+    L = _lib.lib()
+    p, keep = _host_problem()
+    mutate(p)
+    n = ctypes.c_size_t()
+    st = L.gsrf_workspace_size(ctypes.byref(p), ctypes.byref(n))
+    assert st == _lib.GSRF_EINVAL
+    assert needle in L.gsrf_last_error().decode()
+
+
+def test_entry_points_reject_missing_device_pointers_without_launching():
+    L = _lib.lib()
+    p, keep = _host_problem()
+    # no device pointers / workspace: every entry point must refuse on the host
+    assert L.gsrf_project(ctypes.byref(p), None) == _lib.GSRF_EINVAL
+    assert L.gsrf_bin_sort(ctypes.byref(p), None) == _lib.GSRF_EINVAL
+    assert L.gsrf_render_fwd(ctypes.byref(p), None, None, None, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_render_bwd(ctypes.byref(p), *([None] * 9)) == _lib.GSRF_EINVAL
+    n = ctypes.c_int64()
+    assert L.gsrf_splat_count(ctypes.byref(p), ctypes.byref(n), None) == _lib.GSRF_EINVAL
+    assert L.gsrf_status_str(2) == b"GSRF_ECAPACITY"
+
+
+def test_pair_packing_matches_struct():
+    from paper_2502_01826_amd import pack_pairs
+    import synth
+    b = synth.tiny()
+    a = pack_pairs(b.pairs)
+    raw = a.view(np.uint8).tobytes()
+    s = GsrfPair.from_buffer_copy(raw[:40])
+    assert list(s.rx) == list(b.pairs[0].rx.astype(np.float32)) and s.freq_hz == 2.4e9 and s.scene == 0

@@ -1,0 +1,141 @@
+"""GPU parity of the adjoint (a7-a8) against the oracle's FP64 gradients, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from synth import Batch, Grid, Pair
+from gpu_common import GTOL, gpu_forward, gpu_problem, params_of, say
+from paper_2502_01826_amd import GSRFRender, Problem
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["means", "log_scales", "quats", "logits", "coeffs"]
+
+
+def _gpu_grads(prob, S_sig, G, gsum=None):
+    sig = torch.view_as_real(torch.from_numpy(S_sig.astype(np.complex64))).to("cuda").contiguous()
+    gt = torch.from_numpy(G.astype(np.float32)).to("cuda").contiguous()
+    gs = None if gsum is None else torch.from_numpy(np.asarray(gsum, np.float32)).to("cuda")
+    out = prob.render_bwd(sig, gt, gs)
+    torch.cuda.synchronize()
+    return {n: o.cpu().numpy().astype(np.float64) for n, o in zip(NAMES, out)}
+
+
+def _compare(gg, gr, tol=GTOL):
+    for n in NAMES:
+        num = np.linalg.norm(gg[n] - gr[n])
+        den = np.linalg.norm(gr[n])
+        say(f"  grad {n}: rel {num / max(den, 1e-30):.2e}  |ref| {den:.3e}")
+        assert num <= tol * den, n
+
+
+def test_tiny_gradients_match_oracle():
+    b = synth.tiny()
+    sc, p, g = b.scenes[0], b.pairs[0], b.grid
+    prob = gpu_problem(b)
+    sig, ssum, _ = prob.forward()
+    torch.cuda.synchronize()
+    ref = oracle.render(sc, p, g)
+    R = g.n_az * g.n_el
+    G = synth.cotangent((R,), seed=1).astype(np.float64)
+    G[ref["marginal"]] = 0.0            # rays at FP32-marginal decisions carry no cotangent
+    gsum = np.array([0.25, -0.4])
+    Gr = G.copy()
+    Gr[~ref["marginal"]] += gsum[None, :]
+    # GPU: per-ray cotangent G plus the S_hat cotangent gsum on every ray; the
+    # marginal rays get -gsum so that their total cotangent is zero as well
+    Gg = G.copy()
+    Gg[ref["marginal"]] = -gsum[None, :]
+    gr = oracle.vjp(sc, p, g, Gr)
+    gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), Gg.reshape(1, g.n_el, g.n_az, 2),
+                    gsum.reshape(1, 2))
+    say("tiny gradients", int(ref["marginal"].sum()), "marginal rays")
+    _compare(gg, gr)
+
+
+def test_gradients_against_central_differences():
+    """GPU gradients on a 400-Gaussian scene against FP64 central differences of the oracle."""
+    b = synth.tiny(n=400)
+    g = Grid(n_az=24, n_el=6, fle_L=2, tile_w=8, tile_h=8)
+    b = Batch(b.scenes, b.pairs, g)
+    sc = b.scenes[0]
+    sc = synth.Scene(sc.means, sc.log_scales, sc.quats, sc.logits, np.ascontiguousarray(sc.coeffs[:, :g.K]))
+    b = Batch([sc], b.pairs, g)
+    p = b.pairs[0]
+    prob = gpu_problem(b)
+    sig, _, _ = prob.forward()
+    base = oracle.render(sc, p, g)
+    G = synth.cotangent((g.n_az * g.n_el,), seed=2).astype(np.float64)
+    G[base["marginal"]] = 0.0
+    gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), G.reshape(1, g.n_el, g.n_az, 2))
+    rng = np.random.default_rng(3)
+    contrib = np.unique(np.concatenate([oracle.ray_sequence(sc, p, g, u, v)["order"][
+        oracle.ray_sequence(sc, p, g, u, v)["active"]] for v in range(0, g.n_el, 2) for u in range(0, g.n_az, 3)]))
+    checked = 0
+    sc64 = synth.Scene(*(getattr(sc, f).astype(np.float64) for f in NAMES[:4]), sc.coeffs.astype(np.float64))
+    for trial in range(40):
+        gi = int(rng.choice(contrib))
+        name = NAMES[trial % 5]
+        arr = getattr(sc64, name)
+        idx = (gi,) + tuple(int(rng.integers(0, s)) for s in arr.shape[1:])
+        h = 1e-6 * max(1.0, abs(float(arr[idx])))
+        vals, sigs = [], []
+        for sgn in (1, -1):
+            a2 = arr.copy()
+            a2[idx] += sgn * h
+            r = oracle.render(synth.Scene(**{**sc64.__dict__, name: a2}), p, g)
+            vals.append(float((G[:, 0] * r["S"].real + G[:, 1] * r["S"].imag).sum()))
+            sigs.append(r["active_sig"])
+        if not (np.array_equal(sigs[0], sigs[1]) and np.array_equal(sigs[0], base["active_sig"])):
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h)
+        scale = max(abs(fd), 1e-2 * np.abs(gg[name]).max())
+        assert abs(gg[name][idx] - fd) <= GTOL * scale + 1e-6, (name, idx, gg[name][idx], fd)
+        checked += 1
+    assert checked >= 25
+
+
+def test_autograd_function_l2_step():
+    """torch.autograd through GSRFRender: L2 loss on the spectrum vs a perturbed
+    target (rays at FP32-marginal decisions are masked out of the loss)."""
+    b = synth.tiny(n=600)
+    sc, p, g = b.scenes[0], b.pairs[0], b.grid
+    target = oracle.render(synth.Scene(sc.means + 0.01, sc.log_scales, sc.quats, sc.logits, sc.coeffs), p, g)
+    tgt = torch.tensor(np.stack([target["S"].real, target["S"].imag], -1).reshape(1, g.n_el, g.n_az, 2),
+                       dtype=torch.float32, device="cuda")
+    ref = oracle.render(sc, p, g)
+    ok = ~ref["marginal"]
+    mask = torch.tensor(ok.reshape(1, g.n_el, g.n_az, 1), dtype=torch.float32, device="cuda")
+    prob = gpu_problem(b)
+    ps = [torch.tensor(getattr(sc, n), device="cuda", requires_grad=True) for n in NAMES]
+    sig, ssum = GSRFRender.apply(prob, *ps)
+    loss = (mask * (sig - tgt) ** 2).sum()
+    loss.backward()
+    S = torch.view_as_complex(sig.detach()).cpu().numpy()[0].ravel().astype(np.complex128)
+    Gr = 2 * np.stack([S.real - target["S"].real, S.imag - target["S"].imag], -1) * ok[:, None]
+    gr = oracle.vjp(sc, p, g, Gr)
+    _compare({n: t.grad.cpu().numpy().astype(np.float64) for n, t in zip(NAMES, ps)}, gr, tol=2e-3)
+
+
+def test_paper_scale_gradients_on_sampled_rays():
+    """200k Gaussians, 360x90: cotangent on 48 sampled rays only, compared with
+    the oracle's gradient of the same rays."""
+    b = synth.paper_scale()
+    sc, p, g = b.scenes[0], b.pairs[0], b.grid
+    prob = gpu_problem(b)
+    sig, _, _ = prob.forward()
+    rng = np.random.default_rng(9)
+    uv = np.stack([rng.integers(0, g.n_az, 48), rng.integers(0, g.n_el, 48)], 1)
+    uv = np.unique(uv, axis=0)
+    ref = oracle.trace(sc, p, g, uv)
+    keep = ~ref["marginal"]
+    uv = uv[keep]
+    Gs = synth.cotangent((len(uv),), seed=4).astype(np.float64)
+    G = np.zeros((1, g.n_el, g.n_az, 2))
+    G[0, uv[:, 1], uv[:, 0]] = Gs
+    say("paper-scale gradients on", len(uv), "rays")
+    gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), G)
+    gr = oracle.vjp(sc, p, g, Gs, rays_uv=uv)
+    _compare(gg, gr)

@@ -1,0 +1,166 @@
+"""GPU parity of the forward path (a1-a6) against the FP64 oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from synth import Batch, Grid, Pair, Scene
+from gpu_common import (TOL, compare_rays, gpu_forward, gpu_lists, gpu_problem, oracle_tile_members, params_of,
+                        say)
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene_f32(s):
+    return Scene(*(np.ascontiguousarray(getattr(s, f), dtype=np.float32)
+                   for f in ("means", "log_scales", "quats", "logits", "coeffs")))
+
+
+def test_tiny_forward_matches_oracle_and_lists_are_bit_exact():
+    b = synth.tiny()
+    sc, p, g = b.scenes[0], b.pairs[0], b.grid
+    say("tiny: 2000 gaussians, 36x9 rays, tiles", g.tile_w, g.tile_h)
+    prob = gpu_problem(b)
+    S, Ssum, rssi = gpu_forward(prob)
+    ref = oracle.render(sc, p, g)
+    st = compare_rays(S[0].ravel(), ref, sc, p, g)
+    say("tiny forward", st)
+    A = ref["A_uv"]
+    assert abs(Ssum[0] - ref["S_sum"]) <= TOL * A.sum() + np.abs(S[0].ravel() - ref["S"])[ref["marginal"]].sum()
+    assert rssi[0] == pytest.approx(oracle.rssi_dbm(ref["S_sum"]), abs=1e-3)
+    # depth keys of every record and the tile lists, bit for bit
+    L = gpu_lists(prob)
+    assert L["overflow"] == 0
+    np.testing.assert_array_equal(L["rec_key"], oracle.depth_key32(sc.means, p.rx).astype(np.uint32))
+    tu0, ntu, tv0, ntv, marg = oracle.cap_rects(sc.means, sc.log_scales, p.rx, g)
+    np.testing.assert_array_equal(L["rec_rect"][~marg], np.stack([tu0, ntu, tv0, ntv], 1)[~marg])
+    lists, keys, _ = oracle.tile_lists(sc.means, sc.log_scales, p.rx, g)
+    assert L["n"] == sum(len(x) for x in lists)
+    for t in range(L["T"]):
+        a, e = L["ts"][t], L["te"][t]
+        assert np.all(L["khi"][a:e] == t)
+        np.testing.assert_array_equal(L["val"][a:e], lists[t].astype(np.uint32))
+        np.testing.assert_array_equal(L["klo"][a:e], keys[t].astype(np.uint32))
+
+
+def test_forward_is_deterministic():
+    b = synth.tiny()
+    prob = gpu_problem(b)
+    S1, s1, _ = gpu_forward(prob)
+    S2, s2, _ = gpu_forward(prob)
+    assert np.array_equal(S1.view(np.float64), S2.view(np.float64)) and np.array_equal(s1, s2)
+
+
+@pytest.mark.parametrize("tw,th", [(8, 8), (16, 8), (32, 8), (16, 16)])
+def test_ragged_tiles_and_seam(tw, th):
+    # 37 x 11 rays do not divide by any tile shape: ragged last column and row
+    g = Grid(n_az=37, n_el=11, fle_L=2, tile_w=tw, tile_h=th)
+    b = synth.tiny(grid=g, n=1500)
+    sc, p = b.scenes[0], b.pairs[0]
+    say("ragged", tw, th)
+    S, Ssum, _ = gpu_forward(gpu_problem(b))
+    ref = oracle.render(sc, p, g)
+    compare_rays(S[0].ravel(), ref, sc, p, g)
+
+
+@pytest.mark.parametrize("L", [0, 1, 3, 4, 6])
+def test_fle_degrees(L):
+    g = Grid(n_az=24, n_el=8, fle_L=L, tile_w=8, tile_h=8)
+    rng = np.random.default_rng([100, L])
+    sc = synth.draw_scene(rng, 800, (4.0, 4.0, 3.0), g.K)
+    p = Pair(np.array([2.0, 2.1, 1.0], np.float32), np.array([0.5, 3.0, 2.0], np.float32), 5.8e9)
+    say("fle degree", L)
+    S, _, _ = gpu_forward(gpu_problem(Batch([sc], [p], g)))
+    compare_rays(S[0].ravel(), oracle.render(sc, p, g), sc, p, g)
+
+
+def test_empty_scene_and_empty_lists():
+    g = Grid(n_az=36, n_el=9, fle_L=2)
+    empty = Scene(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32), np.zeros((0, 4), np.float32),
+                  np.zeros((0,), np.float32), np.zeros((0, g.K, 2), np.float32))
+    p = Pair(np.array([1, 1, 1], np.float32), np.array([2, 2, 2], np.float32), 2.4e9)
+    S, Ssum, rssi = gpu_forward(gpu_problem(Batch([empty], [p, p], g)))
+    assert np.all(S == 0) and np.all(Ssum == 0) and np.all(np.isneginf(rssi))
+    # every Gaussian below the RX: all culled, exact zeros
+    b = synth.tiny(n=300)
+    sc = b.scenes[0]
+    low = Scene(sc.means * np.array([1, 1, 0.0], np.float32) + np.array([0, 0, 0.1], np.float32), sc.log_scales - 1.0,
+                sc.quats, sc.logits, sc.coeffs)
+    S, Ssum, _ = gpu_forward(gpu_problem(Batch([low], b.pairs, b.grid)))
+    assert np.all(S == 0)
+
+
+def test_worked_example_on_gpu():
+    """Two nearly transparent Gaussians on one ray at path lengths 3 m and
+    3.0625 m (TX at the RX, 2.4 GHz) cancel: |S| <= 1e-4 A_uv in FP32."""
+    g = Grid(n_az=36, n_el=9, fle_L=0, tile_w=8, tile_h=8)
+    u, v = 7, 4
+    d = oracle.ray_dirs(g)[v, u]
+    rx = np.array([1.0, 1.5, 0.5])
+    mu = np.array([rx + 1.5 * d, rx + 1.53125 * d], np.float32)
+    c = np.zeros((2, 1, 2), np.float32)
+    c[:, 0, 0] = 0.7
+    sc = Scene(mu, np.full((2, 3), math.log(0.004), np.float32), np.tile(np.float32([1, 0, 0, 0]), (2, 1)),
+               np.full(2, -30.0, np.float32), c)
+    p = Pair(rx.astype(np.float32), rx.astype(np.float32), 2.4e9)
+    S, _, _ = gpu_forward(gpu_problem(Batch([sc], [p], g)))
+    ref = oracle.trace(sc, p, g, [(u, v)])
+    assert ref["n_active"][0] == 2
+    A = ref["A_uv"][0]
+    assert abs(S[0, v, u]) <= 1e-4 * A
+    one = Scene(*(getattr(sc, f)[:1] for f in ("means", "log_scales", "quats", "logits", "coeffs")))
+    S1, _, _ = gpu_forward(gpu_problem(Batch([one], [p], g)))
+    assert abs(S1[0, v, u]) == pytest.approx(A / 2, rel=1e-4)
+
+
+def test_multi_scene_multi_pair_batch():
+    g = Grid(n_az=48, n_el=12, fle_L=2, tile_w=8, tile_h=8)
+    rng = np.random.default_rng(77)
+    room = (6.0, 5.0, 3.0)
+    scenes = [synth.draw_scene(rng, n, room, g.K) for n in (700, 0, 1500)]
+    pairs = []
+    for s, f in [(0, 2.4e9), (2, 5.0e9), (1, 5.8e9), (2, 2.4e9), (0, 5.8e9)]:
+        pr = synth.draw_pair(rng, room, f, scene=s)
+        pairs.append(pr)
+    b = Batch(scenes, pairs, g)
+    say("batch: scenes 700/0/1500, 5 pairs")
+    S, Ssum, rssi = gpu_forward(gpu_problem(b))
+    for k, pr in enumerate(pairs):
+        sc = scenes[pr.scene]
+        ref = oracle.render(sc, pr, g)
+        compare_rays(S[k].ravel(), ref, sc, pr, g)
+        assert abs(Ssum[k] - S[k].sum()) <= 1e-5 * np.abs(S[k]).sum() + 1e-30
+
+
+def test_paper_scale_sampled_rays_and_tiles():
+    """200k Gaussians, 360x90 rays, 5 GHz, at the launch configuration the
+    benchmark times: sampled rays against the oracle, sampled tile lists bit
+    exact, and S_hat equal to the sum of the spectrum."""
+    b = synth.paper_scale()
+    sc, p, g = b.scenes[0], b.pairs[0], b.grid
+    say("paper scale: 200k gaussians, 360x90")
+    prob = gpu_problem(b)
+    S, Ssum, rssi = gpu_forward(prob)
+    rng = np.random.default_rng(5)
+    uv = np.stack([rng.integers(0, g.n_az, 160), rng.integers(0, g.n_el, 160)], 1)
+    ref = oracle.trace(sc, p, g, uv)
+    st = compare_rays(S[0][uv[:, 1], uv[:, 0]], ref, sc, p, g)
+    say("paper scale forward", st)
+    assert abs(Ssum[0] - S[0].sum()) <= 1e-5 * np.abs(S[0]).sum()
+    L = gpu_lists(prob)
+    assert L["overflow"] == 0
+    np.testing.assert_array_equal(L["rec_key"], oracle.depth_key32(sc.means, p.rx).astype(np.uint32))
+    tiles = rng.choice(L["T"], 12, replace=False)
+    ref_l, marg = oracle_tile_members(sc, p, g, tiles)
+    bad = set(np.nonzero(marg)[0].tolist())
+    for t in tiles:
+        a, e = L["ts"][t], L["te"][t]
+        gv, kv = L["val"][a:e].astype(np.int64), L["klo"][a:e].astype(np.int64)
+        rg, rk = ref_l[int(t)]
+        keep_g = np.array([x not in bad for x in gv], bool)
+        keep_r = np.array([x not in bad for x in rg], bool)
+        np.testing.assert_array_equal(gv[keep_g], rg[keep_r])
+        np.testing.assert_array_equal(kv[keep_g], rk[keep_r])
