@@ -1,0 +1,220 @@
+#!/usr/bin/env python
+"""Throughput of the GSRF hot path on one MI355X.
+
+A step is one pass of the whole path over one TX/RX pair of a 200k-Gaussian
+synthetic room at 360x90 rays and 5 GHz: activation + splatting
+(gsrf_project), binning + radix sort (gsrf_bin_sort), complex rendering +
+RSSI (gsrf_render_fwd) and the adjoint + chain rule (gsrf_render_bwd) with a
+seeded upstream gradient.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0).  Extra fields report the forward-only rate,
+a batched launch over many pairs of the same scene, the roofline of the
+dominant kernel and the FP64 oracle timed on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "received spectra/s (360×90 rays, 200k Gaussians) fwd & fwd+bwd; batched vs plain"
+PEAK_FP32_VALU = 157.3e12   # FLOP/s: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_HBM = 8.0e12           # B/s
+
+
+def flops_per(K: int) -> dict:
+    """Algorithmic FP32 FLOPs (FMA = 2) per hit test and per processed hit.
+
+    test: eps (6) + M v (15) + A (5) + b (5) + M eps (15) + c (5) + 1/A, b/A (2)
+          + Q (3) + t (2) + two compares (2) = 60
+    hit, forward: exp(-Q/2) (2) + alpha, p (3) + phase (2) + sincos (30)
+          + psi (8K) + psi e^{-j phase} (6) + c~ (2) + S, T update (7) = 52 + 8K
+    hit, adjoint extra: prefix and remainder (6) + dL/dp, dL/dphase, dL/dalpha (13)
+          + dL/dG, dL/dQ, dL/dt (7) + p_perp, M p_perp (18) + dL/dM (30)
+          + dL/dmu (9) + dL/dN, dL/do (2) + dL/dpsi (8) + dL/dc (6K) + T (2)
+          + one add per accumulator for the reduction over rays (12 + 2K)
+          = 107 + 8K
+    """
+    return dict(test=60.0, hit_fwd=52.0 + 8 * K, hit_bwd=52.0 + 8 * K + 107.0 + 8 * K)
+
+
+def cpu_baseline(scene, pair, grid, min_seconds: float = 8.0) -> dict:
+    """The FP64 oracle (forward + autograd gradient) on a sample of rays of the
+    same pair, scaled to a full spectrum."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+
+    rng = np.random.default_rng(123)
+    n_rays = grid.n_az * grid.n_el
+    sample = 256
+    while True:
+        uv = np.stack([rng.integers(0, grid.n_az, sample), rng.integers(0, grid.n_el, sample)], 1)
+        G = synth.cotangent((sample,), seed=7)
+        t0 = time.perf_counter()
+        oracle.vjp(scene, pair, grid, G, rays_uv=uv)
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or sample >= n_rays:
+            break
+        sample = min(n_rays, sample * 2)
+    per_spectrum = dt * n_rays / sample
+    return {"value": 1.0 / per_spectrum, "unit": "spectra/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"FP64 forward + autograd gradient of {sample} of {n_rays} rays of one pair "
+                      f"({dt:.1f} s), scaled by {n_rays / sample:.1f}"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batched-pairs", type=int, default=32)
+    ap.add_argument("--gaussians", type=int, default=200_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default="16x16", help="tile_w x tile_h (64, 128 or 256 rays)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} (WORLD_SIZE={world}) is not supported; "
+              "the pair batch would shard across GPUs with no exchange in the forward pass", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2502_01826_amd import Problem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    tw, th = (int(x) for x in args.tile.split("x"))
+    grid = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th)
+    batch = synth.paper_scale(n=args.gaussians, grid=grid)
+    scene, pair = batch.scenes[0], batch.pairs[0]
+    params = dict(means=scene.means, log_scales=scene.log_scales, quats=scene.quats, logits=scene.logits,
+                  coeffs=scene.coeffs)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def make(pairs):
+        prob = Problem(params, pairs, grid)
+        prob.forward()                    # sizes the splat buffers once (host sync here only)
+        prob.auto_capacity = False
+        P = len(pairs)
+        bufs = dict(
+            sig=torch.empty((P, grid.n_el, grid.n_az, 2), dtype=torch.float32, device=dev),
+            ssum=torch.empty((P, 2), dtype=torch.float32, device=dev),
+            rssi=torch.empty((P,), dtype=torch.float32, device=dev),
+            G=torch.from_numpy(synth.cotangent((P, grid.n_el, grid.n_az), seed=11)).to(dev),
+            gsum=torch.from_numpy(synth.cotangent((P,), seed=12)).to(dev),
+        )
+        G_ = prob.n_gauss
+        e = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+        bufs["grads"] = (e(G_, 3), e(G_, 3), e(G_, 4), e(G_), e(G_, grid.K, 2))
+        return prob, bufs
+
+    from paper_2502_01826_amd import _lib
+
+    def new_event():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)                  # creates the underlying hipEvent_t
+        return e
+
+    def run(prob, bufs, steps, bwd, ev=None):
+        for i in range(steps):
+            if ev is not None:
+                # the library records these around its render kernels only
+                _lib.lib().gsrf_set_kernel_events(ev["f0"][i].cuda_event, ev["f1"][i].cuda_event,
+                                                  ev["b0"][i].cuda_event, ev["b1"][i].cuda_event)
+            prob.project()
+            prob.bin_sort()
+            prob.render_fwd(bufs["sig"], bufs["ssum"], bufs["rssi"])
+            if bwd:
+                prob.render_bwd(bufs["sig"], bufs["G"], bufs["gsum"], out=bufs["grads"])
+        _lib.lib().gsrf_set_kernel_events(None, None, None, None)
+
+    def timed(prob, bufs, steps, warmup, bwd, ev=None):
+        run(prob, bufs, warmup, bwd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(prob, bufs, steps, bwd, ev)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    # ---- plain: one pair per launch sequence (the headline step) -------------
+    prob, bufs = make([pair])
+    ev = {k: [new_event() for _ in range(args.steps)] for k in ("f0", "f1", "b0", "b1")}
+    torch.cuda.synchronize()
+    t_step = timed(prob, bufs, args.steps, args.warmup, True, ev)
+    t_fwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["f0"], ev["f1"])) / args.steps * 1e-3
+    t_bwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["b0"], ev["b1"])) / args.steps * 1e-3
+    t_fwd_only = timed(prob, bufs, args.steps, 1, False)
+    stats = prob.render_stats()
+    n_splats, _ = prob.splat_count()
+    K = grid.K
+    f = flops_per(K)
+    fl_fwd = stats["tests"] * f["test"] + stats["hits"] * f["hit_fwd"]
+    fl_bwd = stats["tests"] * f["test"] + stats["hits"] * f["hit_bwd"]
+    if t_bwd_k >= t_fwd_k:
+        dom, fl, tk = "render_bwd", fl_bwd, t_bwd_k
+    else:
+        dom, fl, tk = "render_fwd", fl_fwd, t_fwd_k
+    achieved = fl / tk
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VALU, "traffic": None, "kernel": dom,
+            "kernel_ms": tk * 1e3, "flop_per_launch": fl, "timing": "HIP events recorded by the library "
+            "immediately around the render kernel on its stream, averaged over the timed steps",
+            "counts": {**stats, "splats": n_splats}}
+
+    # ---- batched: many pairs of the same scene in one launch sequence --------
+    batched = None
+    if args.batched_pairs > 1:
+        rng = np.random.default_rng([4, 1])
+        pairs = [synth.draw_pair(rng, (10.0, 8.0, 3.0), 5.0e9) for _ in range(args.batched_pairs)]
+        bprob, bbufs = make(pairs)
+        bsteps = max(2, args.steps // 4)
+        tb_fb = timed(bprob, bbufs, bsteps, 1, True)
+        tb_f = timed(bprob, bbufs, bsteps, 1, False)
+        batched = {"pairs": args.batched_pairs, "fwd_bwd_spectra_per_s": args.batched_pairs / tb_fb,
+                   "fwd_spectra_per_s": args.batched_pairs / tb_f, "ms_per_launch_fwd_bwd": tb_fb * 1e3}
+        del bprob, bbufs
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, pair, grid)
+
+    out = {
+        "metric": METRIC,
+        "value": 1.0 / t_step,
+        "unit": "spectra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale differentiated step: 200k Gaussians in a 10x8x3 m room, one TX/RX "
+                               "pair, 360x90 rays, 5 GHz, FLE L=2; project+bin_sort+render_fwd+render_bwd",
+                   "gaussians": args.gaussians, "rays": "360x90", "pairs": 1, "tile": args.tile},
+        "fwd_only": {"spectra_per_s": 1.0 / t_fwd_only, "ms": t_fwd_only * 1e3},
+        "kernels_ms": {"render_fwd": t_fwd_k * 1e3, "render_bwd": t_bwd_k * 1e3},
+        "batched": batched,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -211,6 +211,15 @@ gsrf_status gsrf_render_bwd(const gsrf_problem *p, const float *signal, const fl
  */
 gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stream);
 
+/*
+ * Instrumentation for kernel timing: every later gsrf_render_fwd records
+ * fwd_start / fwd_stop (hipEvent_t, caller-created; NULL = none) on its stream
+ * immediately before and after its render kernel, and every gsrf_render_bwd
+ * does the same with bwd_start / bwd_stop around its adjoint kernel.  The
+ * setting is process-wide; pass NULLs to switch it off.  Never fails.
+ */
+gsrf_status gsrf_set_kernel_events(void *fwd_start, void *fwd_stop, void *bwd_start, void *bwd_stop);
+
 #ifdef __cplusplus
 }
 #endif

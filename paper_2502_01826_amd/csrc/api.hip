@@ -243,4 +243,9 @@ gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stre
   return dev(launch_render_stats(p, L, (char *)p->workspace, counts, (hipStream_t)stream), "gsrf_render_stats");
 }
 
+gsrf_status gsrf_set_kernel_events(void *fwd_start, void *fwd_stop, void *bwd_start, void *bwd_stop) {
+  set_kernel_events(fwd_start, fwd_stop, bwd_start, bwd_stop);
+  return GSRF_OK;
+}
+
 }  // extern "C"

@@ -52,6 +52,7 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
 hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, hipStream_t s);
 hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws, float *signal,
                              float *signal_sum, float *rssi_dbm, hipStream_t s);
+void set_kernel_events(void *fwd_start, void *fwd_stop, void *bwd_start, void *bwd_stop);
 hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *ws, int64_t *counts, hipStream_t s);
 hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws, const float *signal,
                              const float *grad_signal, const float *grad_sum, float *d_means,

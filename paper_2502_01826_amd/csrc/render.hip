@@ -536,6 +536,22 @@ __global__ void k_chain(const float *__restrict__ log_scales, const float *__res
 }
 
 // ---------------------------------------------------------------------------
+// Instrumentation events recorded around the main render kernels.
+// ---------------------------------------------------------------------------
+static hipEvent_t g_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+void set_kernel_events(void *fwd_start, void *fwd_stop, void *bwd_start, void *bwd_stop) {
+  g_ev[0] = (hipEvent_t)fwd_start;
+  g_ev[1] = (hipEvent_t)fwd_stop;
+  g_ev[2] = (hipEvent_t)bwd_start;
+  g_ev[3] = (hipEvent_t)bwd_stop;
+}
+
+static void mark(int i, hipStream_t s) {
+  if (g_ev[i]) (void)hipEventRecord(g_ev[i], s);
+}
+
+// ---------------------------------------------------------------------------
 // launch helpers: dispatch on (L, threads per tile)
 // ---------------------------------------------------------------------------
 static RenderArgs make_args(const gsrf_problem *p, const Layout &lay, char *ws) {
@@ -609,9 +625,11 @@ hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws,
   const int nt = p->grid.tile_w * p->grid.tile_h;
   const int64_t nblocks = (int64_t)p->n_pairs * lay.T;
   float2 *tsum = (float2 *)(ws + lay.tile_sum);
+  mark(0, s);
   hipError_t e = [&]() -> hipError_t {
     GSRF_DISPATCH(fwd_launch, a, nblocks, (float2 *)signal, tsum, (unsigned long long *)nullptr, s)
   }();
+  mark(1, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rssi, dim3(p->n_pairs), dim3(256), 0, s, tsum, lay.T, signal_sum, rssi_dbm);
   return hipGetLastError();
@@ -638,10 +656,12 @@ hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws,
     const RenderArgs a = make_args(p, lay, ws);
     const int nt = p->grid.tile_w * p->grid.tile_h;
     const int64_t nblocks = (int64_t)p->n_pairs * lay.T;
+    mark(2, s);
     e = [&]() -> hipError_t {
       GSRF_DISPATCH(bwd_launch, a, nblocks, (const float2 *)signal, (const float2 *)grad_signal,
                     (const float2 *)grad_sum, lay.acc_stride, acc, s)
     }();
+    mark(3, s);
     if (e != hipSuccess) return e;
   }
   if (p->n_gauss > 0) {
