@@ -79,7 +79,8 @@ def main() -> int:
     ap.add_argument("--batched-pairs", type=int, default=32)
     ap.add_argument("--gaussians", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", default="16x16", help="tile_w x tile_h (64, 128 or 256 rays)")
+    ap.add_argument("--tile", default="8x8", help="tile_w x tile_h (64, 128 or 256 rays)")
+    ap.add_argument("--lanes", type=int, default=4, help="lanes per ray (1, 2 or 4)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -95,7 +96,7 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     tw, th = (int(x) for x in args.tile.split("x"))
-    grid = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th)
+    grid = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=args.lanes)
     batch = synth.paper_scale(n=args.gaussians, grid=grid)
     scene, pair = batch.scenes[0], batch.pairs[0]
     params = dict(means=scene.means, log_scales=scene.log_scales, quats=scene.quats, logits=scene.logits,
@@ -205,7 +206,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "paper-scale differentiated step: 200k Gaussians in a 10x8x3 m room, one TX/RX "
                                "pair, 360x90 rays, 5 GHz, FLE L=2; project+bin_sort+render_fwd+render_bwd",
-                   "gaussians": args.gaussians, "rays": "360x90", "pairs": 1, "tile": args.tile},
+                   "gaussians": args.gaussians, "rays": "360x90", "pairs": 1, "tile": args.tile,
+                   "lanes_per_ray": args.lanes},
         "fwd_only": {"spectra_per_s": 1.0 / t_fwd_only, "ms": t_fwd_only * 1e3},
         "kernels_ms": {"render_fwd": t_fwd_k * 1e3, "render_bwd": t_bwd_k * 1e3},
         "batched": batched,

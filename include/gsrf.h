@@ -57,6 +57,9 @@ typedef enum gsrf_status {
  *   alpha_max  opacity clamp, in (0, 1).
  *   tile_w/h   rays per tile (App. E uses 16 x 16); tile_w * tile_h must be
  *              64, 128 or 256.
+ *   lanes_per_ray  1, 2 or 4 (0 means 1): lanes that share one ray, each
+ *              testing a different entry of the depth-ordered list; results
+ *              agree to rounding for every value.
  */
 typedef struct gsrf_grid {
   int32_t n_az, n_el;
@@ -66,6 +69,7 @@ typedef struct gsrf_grid {
   float t_min;
   float alpha_max;
   int32_t tile_w, tile_h;
+  int32_t lanes_per_ray;
 } gsrf_grid;
 
 /*

@@ -26,6 +26,12 @@ static gsrf_status dev(hipError_t e, const char *where) {
   return fail(GSRF_EDEVICE, "%s: %s", where, hipGetErrorString(e));
 }
 
+static hipEvent_t g_kernel_events[4] = {nullptr, nullptr, nullptr, nullptr};
+
+void mark_kernel_event(int i, hipStream_t s) {
+  if (g_kernel_events[i]) (void)hipEventRecord(g_kernel_events[i], s);
+}
+
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int bits_for(int64_t x) {  // bits needed to represent 0..x
@@ -47,6 +53,8 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   const int nt = g.tile_w * g.tile_h;
   if (g.tile_w <= 0 || g.tile_h <= 0 || (nt != 64 && nt != 128 && nt != 256))
     return fail(GSRF_EINVAL, "tile %d x %d: tile_w * tile_h must be 64, 128 or 256", g.tile_w, g.tile_h);
+  if (g.lanes_per_ray != 0 && g.lanes_per_ray != 1 && g.lanes_per_ray != 2 && g.lanes_per_ray != 4)
+    return fail(GSRF_EINVAL, "lanes_per_ray = %d: must be 0, 1, 2 or 4", g.lanes_per_ray);
   if (!(g.el_lo < g.el_hi) || g.el_lo < -1.5707964f || g.el_hi > 1.5707964f)
     return fail(GSRF_EINVAL, "elevation span [%g, %g] invalid", (double)g.el_lo, (double)g.el_hi);
   if (!(g.r_rx >= 0.f) || !(g.t_min >= 0.f) || !(g.alpha_max > 0.f && g.alpha_max < 1.f))
@@ -244,7 +252,10 @@ gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stre
 }
 
 gsrf_status gsrf_set_kernel_events(void *fwd_start, void *fwd_stop, void *bwd_start, void *bwd_stop) {
-  set_kernel_events(fwd_start, fwd_stop, bwd_start, bwd_stop);
+  g_kernel_events[0] = (hipEvent_t)fwd_start;
+  g_kernel_events[1] = (hipEvent_t)fwd_stop;
+  g_kernel_events[2] = (hipEvent_t)bwd_start;
+  g_kernel_events[3] = (hipEvent_t)bwd_stop;
   return GSRF_OK;
 }
 

@@ -45,6 +45,15 @@ struct Layout {
 };
 
 inline int fle_K(int L) { return (L + 1) * (L + 1); }
+inline int lanes_per_ray(const gsrf_grid &g) { return g.lanes_per_ray <= 0 ? 1 : g.lanes_per_ray; }
+
+// Instrumentation events (set by gsrf_set_kernel_events): 0/1 around the
+// forward render kernel, 2/3 around the adjoint kernel.
+void mark_kernel_event(int i, hipStream_t s);
+
+
+struct RenderArgs;
+RenderArgs make_render_args(const gsrf_problem *p, const Layout &lay, char *ws);
 
 // Launch helpers implemented in the .hip files; each returns hipSuccess or the
 // launch error.
@@ -52,7 +61,6 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
 hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, hipStream_t s);
 hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws, float *signal,
                              float *signal_sum, float *rssi_dbm, hipStream_t s);
-void set_kernel_events(void *fwd_start, void *fwd_stop, void *bwd_start, void *bwd_stop);
 hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *ws, int64_t *counts, hipStream_t s);
 hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws, const float *signal,
                              const float *grad_signal, const float *grad_sum, float *d_means,

@@ -1,0 +1,309 @@
+// Steps a7-a8: the adjoint of the renderer (App. C backward kernel; App. D)
+// and the per-Gaussian chain rule through Sigma^-1 = R diag(s^-2) R^T (the
+// covariance gradient App. D.3 omits).
+//
+// Same traversal as the forward (render_common.h), recomputing each ray's
+// transmittance front to back; the remainder R_j = sum_{i>j} T_i c~_i comes
+// from the forward output S minus the running prefix, so no per-ray state is
+// stored between the passes.  Per processed hit a lane forms its contribution
+// to the Gaussian's accumulators; the rays of a wave are summed by a
+// reduce-scatter (recursive halving over lanes), the waves meet in LDS, and
+// one burst of global atomics per (tile, Gaussian) flushes them.
+#include "render_common.h"
+
+namespace gsrf {
+
+// Accumulator slots (SoA in global memory, acc[f * G + g]):
+//   0-5 dL/dM (M00 M11 M22 M01 M02 M12), 6-8 dL/dmu, 9 dL/dN, 10 dL/do,
+//   11.. dL/dc (2K); the LDS copy adds slot 11 + 2K = sum of dL/dt, whose TX leg
+//   (mu - tx)/|mu - tx| is folded into dL/dmu at the flush.
+template <int L, int NT, int G>
+__global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *__restrict__ signal,
+                                                   const float2 *__restrict__ grad_signal,
+                                                   const float2 *__restrict__ grad_sum, int64_t n_gauss,
+                                                   float *__restrict__ acc) {
+  constexpr int K = (L + 1) * (L + 1);
+  constexpr int B = lds_batch(L, NT, true);
+  constexpr int NACC = n_acc(L);               // 12 + 2K
+  constexpr int NV = pow2_at_least(NACC);
+  constexpr int RAYS = NT / G;
+  constexpr int SLOT_T = 11 + 2 * K;           // LDS slot of sum dL/dt
+  extern __shared__ float4 smem[];
+  float4 *sgeo = smem;                          // [B][kGeo]
+  float *scf = (float *)(smem + kGeo * B);      // [B][2K]
+  float *sacc = scf + 2 * K * B;                // [B][NACC]
+  int *sflag = (int *)(sacc + NACC * B);        // [B]
+  const int gt = blockIdx.x;
+  const int k = gt / a.T;
+  const int tile = gt - k * a.T;
+  const int tv = tile / a.nta, tu = tile - tv * a.nta;
+  const int r = (int)threadIdx.x / G, q = (int)threadIdx.x % G;
+  const int th_ = RAYS / a.tw;
+  const int u = tu * a.tw + r % a.tw;
+  const int v = tv * th_ + r / a.tw;
+  const bool valid = (u < a.n_az) && (v < a.n_el);
+  const int lane = threadIdx.x & 63;
+  const gsrf_pair pr = a.pairs[k];
+  const double lam = kC0 / pr.freq_hz;
+  const float twopi_lam = (float)(2.0 * 3.14159265358979323846 / lam);
+  float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
+  ray_setup<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
+  float Sfr = 0.f, Sfi = 0.f, Gr = 0.f, Gi = 0.f;
+  if (valid) {
+    const size_t ri = ((size_t)k * a.n_el + v) * a.n_az + u;
+    const float2 sf = signal[ri], gg = grad_signal[ri];
+    Sfr = sf.x; Sfi = sf.y; Gr = gg.x; Gi = gg.y;
+    if (grad_sum) {
+      const float2 gs = grad_sum[k];
+      Gr += gs.x;
+      Gi += gs.y;
+    }
+  }
+  for (int i = threadIdx.x; i < NACC * B; i += NT) sacc[i] = 0.f;
+  for (int i = threadIdx.x; i < B; i += NT) sflag[i] = 0;
+  const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
+  float T = 1.f, Pr = 0.f, Pi = 0.f;
+  bool done = !valid || (1.0f < a.t_min);
+  for (uint32_t base = s0; base < s1; base += B) {
+    const int nb = (int)min((uint32_t)B, s1 - base);
+    __syncthreads();
+    if ((int)threadIdx.x < nb)
+      stage_entry<K>(a, a.val[base + threadIdx.x], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], lam,
+                     sgeo + kGeo * threadIdx.x, scf + 2 * K * threadIdx.x);
+    __syncthreads();
+    if (__ballot(!done) != 0) {              // wave-uniform
+      for (int m = 0; m < nb; m += G) {
+        const int j = m + q;
+        const float4 *geo = sgeo + kGeo * j;
+        Terms h;
+        bool hit = false;
+        float f = 1.f, ctr = 0.f, cti = 0.f;
+        if (!done && j < nb) {
+          hit = test_hit(vx, vy, vz, geo, a.r_rx, h);
+          if (hit) {
+            hit_terms<K>(geo, scf + 2 * K * j, Yr, Yi, a.amax, h);
+            f = 1.0f - h.alpha;
+            ctr = h.p * h.pzr;
+            cti = h.p * h.pzi;
+          }
+        }
+        float excl, total;
+        group_prod<G>(f, q, excl, total);
+        const float Tj = T * excl;
+        const bool proc = hit && (Tj >= a.t_min);
+        const float wr = proc ? Tj * ctr : 0.f, wi = proc ? Tj * cti : 0.f;
+        float wr_in, wi_in, wr_tot, wi_tot;
+        group_sum<G>(wr, q, wr_in, wr_tot);
+        group_sum<G>(wi, q, wi_in, wi_tot);
+        T = T * total;
+        done = done || (T < a.t_min);
+        if (__ballot(proc) != 0) {
+          float c[NV];
+#pragma unroll
+          for (int i = 0; i < NV; ++i) c[i] = 0.f;
+          if (proc) {
+            const float Rr = Sfr - (Pr + wr_in), Ri = Sfi - (Pi + wi_in);
+            const float dLdp = Tj * fmaf(Gr, h.pzr, Gi * h.pzi);
+            const float dLdphi = Tj * fmaf(Gr, cti, -(Gi * ctr));
+            const float dLda = h.clamped ? 0.f : -fmaf(Gr, Rr, Gi * Ri) / (1.0f - h.alpha);
+            const float4 g0 = geo[0], g3 = geo[3];
+            const float D = g0.w;
+            const float dLdG = fmaf(dLdp, g3.z, dLda * g3.w);
+            const float gQ = -0.5f * h.G * dLdG;
+            const float gt_ = dLdphi * twopi_lam;
+            const float gtA = gt_ * h.rA;
+            // x_mid - mu = D (eps - (b/A) v), M (x_mid - mu) = D (M eps - (b/A) M v)
+            const float px = D * fmaf(-h.bA, vx, h.ex), py = D * fmaf(-h.bA, vy, h.ey),
+                        pz = D * fmaf(-h.bA, vz, h.ez);
+            const float qx = D * fmaf(-h.bA, h.w0, h.m0), qy = D * fmaf(-h.bA, h.w1, h.m1),
+                        qz = D * fmaf(-h.bA, h.w2, h.m2);
+            c[0] = fmaf(gQ * px, px, -(gtA * vx * px));
+            c[1] = fmaf(gQ * py, py, -(gtA * vy * py));
+            c[2] = fmaf(gQ * pz, pz, -(gtA * vz * pz));
+            c[3] = fmaf(gQ * px, py, -0.5f * gtA * fmaf(vx, py, px * vy));
+            c[4] = fmaf(gQ * px, pz, -0.5f * gtA * fmaf(vx, pz, px * vz));
+            c[5] = fmaf(gQ * py, pz, -0.5f * gtA * fmaf(vy, pz, py * vz));
+            c[6] = fmaf(-2.0f * gQ, qx, gtA * h.w0);
+            c[7] = fmaf(-2.0f * gQ, qy, gtA * h.w1);
+            c[8] = fmaf(-2.0f * gQ, qz, gtA * h.w2);
+            c[9] = dLdp * h.G;     // dL/dN
+            c[10] = dLda * h.G;    // dL/do
+            const float Tp = Tj * h.p;
+            const float dpr = Tp * fmaf(Gr, h.cs, -(Gi * h.sn));
+            const float dpi = Tp * fmaf(Gi, h.cs, Gr * h.sn);
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+              c[11 + 2 * i] = fmaf(dpr, Yr[i], dpi * Yi[i]);
+              c[12 + 2 * i] = fmaf(dpi, Yr[i], -(dpr * Yi[i]));
+            }
+            c[SLOT_T] = gt_;       // dL/dt; TX leg applied at the flush
+            sflag[j] = 1;
+          }
+          int first;
+          bool writer;
+          reduce_scatter<NV, G>(c, lane, &first, &writer);
+          constexpr int NF = (NV * G >= 64) ? NV * G / 64 : 1;
+          if (writer && j < nb) {
+            float *dst = sacc + NACC * j;
+#pragma unroll
+            for (int i = 0; i < NF; ++i)
+              if (first + i < NACC) atomicAdd(dst + first + i, c[i]);
+          }
+        }
+        Pr += wr_tot;
+        Pi += wi_tot;
+        if (__ballot(!done) == 0) break;
+      }
+    }
+    __syncthreads();
+    // flush: one thread per staged Gaussian with any processed hit in this tile
+    if ((int)threadIdx.x < nb && sflag[threadIdx.x]) {
+      const uint32_t g = a.val[base + threadIdx.x];
+      float *src = sacc + NACC * threadIdx.x;
+      const float *pg = a.prep + (size_t)kPrep * g;
+      const double qx = (double)pg[0] - pr.tx[0], qy = (double)pg[1] - pr.tx[1], qz = (double)pg[2] - pr.tx[2];
+      const double dn = sqrt((qx * qx + qy * qy) + qz * qz);
+      const double inv = dn > 0.0 ? 1.0 / dn : 0.0;
+      const float gtx = src[SLOT_T];
+      src[6] = fmaf(gtx, (float)(qx * inv), src[6]);
+      src[7] = fmaf(gtx, (float)(qy * inv), src[7]);
+      src[8] = fmaf(gtx, (float)(qz * inv), src[8]);
+#pragma unroll
+      for (int f = 0; f < SLOT_T; ++f) unsafeAtomicAdd(acc + (size_t)f * n_gauss + g, src[f]);
+#pragma unroll
+      for (int f = 0; f < NACC; ++f) src[f] = 0.f;
+      sflag[threadIdx.x] = 0;
+    }
+    if (__syncthreads_and(done ? 1 : 0)) break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a8: chain rule per Gaussian from (dL/dM, dL/dmu, dL/dN, dL/do, dL/dc) to the
+// stored parameters.  M = R D R^T with D = diag(exp(-2 log s)):
+//   dL/dD_ii = (R^T G R)_ii, dL/dR = 2 G R D (G = symmetric dL/dM),
+//   N = (2 pi)^-3/2 exp(-sum log s) gives dN/dlog s_i = -N,
+//   q_hat = q / |q| gives dL/dq = (g - q_hat (q_hat . g)) / |q|,
+//   o = sigmoid(a) gives do/da = o (1 - o).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chain(const float *__restrict__ log_scales, const float *__restrict__ quats,
+                                               const float *__restrict__ logits, const float *__restrict__ acc,
+                                               int32_t K, int64_t G, float *__restrict__ d_means,
+                                               float *__restrict__ d_ls, float *__restrict__ d_q,
+                                               float *__restrict__ d_a, float *__restrict__ d_c) {
+  const int64_t g0 = (int64_t)blockIdx.x * 256;
+  const int64_t g = g0 + threadIdx.x;
+  // coefficient gradients: coalesced writes of this block's contiguous [256][2K] slab
+  {
+    const int64_t n_here = min((int64_t)256, G - g0);
+    const int64_t total = n_here * 2 * K;
+    for (int64_t e = threadIdx.x; e < total; e += 256) {
+      const int64_t gi = g0 + e / (2 * K);
+      const int comp = (int)(e % (2 * K));
+      d_c[g0 * 2 * K + e] = acc[(size_t)(11 + comp) * G + gi];
+    }
+  }
+  if (g >= G) return;
+  auto A = [&](int f) { return acc[(size_t)f * G + g]; };
+  const float Gm[3][3] = {{A(0), A(3), A(4)}, {A(3), A(1), A(5)}, {A(4), A(5), A(2)}};
+  d_means[3 * g + 0] = A(6);
+  d_means[3 * g + 1] = A(7);
+  d_means[3 * g + 2] = A(8);
+  const float dN = A(9), dO = A(10);
+  float qw = quats[4 * g + 0], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
+  const float qn = sqrtf(fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz))));
+  qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+  float R[3][3];
+  R[0][0] = 1.f - 2.f * (qy * qy + qz * qz); R[0][1] = 2.f * (qx * qy - qw * qz); R[0][2] = 2.f * (qx * qz + qw * qy);
+  R[1][0] = 2.f * (qx * qy + qw * qz); R[1][1] = 1.f - 2.f * (qx * qx + qz * qz); R[1][2] = 2.f * (qy * qz - qw * qx);
+  R[2][0] = 2.f * (qx * qz - qw * qy); R[2][1] = 2.f * (qy * qz + qw * qx); R[2][2] = 1.f - 2.f * (qx * qx + qy * qy);
+  const float l0 = log_scales[3 * g + 0], l1 = log_scales[3 * g + 1], l2 = log_scales[3 * g + 2];
+  const float d[3] = {expf(-2.f * l0), expf(-2.f * l1), expf(-2.f * l2)};
+  const float Nn = (float)0.063493635934240969 * expf(-(l0 + l1 + l2));
+  float GR[3][3];
+  for (int a_ = 0; a_ < 3; ++a_)
+    for (int i = 0; i < 3; ++i) GR[a_][i] = fmaf(Gm[a_][0], R[0][i], fmaf(Gm[a_][1], R[1][i], Gm[a_][2] * R[2][i]));
+  for (int i = 0; i < 3; ++i) {
+    const float gd = fmaf(R[0][i], GR[0][i], fmaf(R[1][i], GR[1][i], R[2][i] * GR[2][i]));
+    d_ls[3 * g + i] = fmaf(-2.f * d[i], gd, -Nn * dN);
+  }
+  float gR[3][3];
+  for (int a_ = 0; a_ < 3; ++a_)
+    for (int i = 0; i < 3; ++i) gR[a_][i] = 2.f * GR[a_][i] * d[i];
+  const float gw = 2.f * (-qz * gR[0][1] + qy * gR[0][2] + qz * gR[1][0] - qx * gR[1][2] - qy * gR[2][0] + qx * gR[2][1]);
+  const float gx = 2.f * (qy * gR[0][1] + qz * gR[0][2] + qy * gR[1][0] - 2.f * qx * gR[1][1] - qw * gR[1][2] +
+                          qz * gR[2][0] + qw * gR[2][1] - 2.f * qx * gR[2][2]);
+  const float gy = 2.f * (-2.f * qy * gR[0][0] + qx * gR[0][1] + qw * gR[0][2] + qx * gR[1][0] + qz * gR[1][2] -
+                          qw * gR[2][0] + qz * gR[2][1] - 2.f * qy * gR[2][2]);
+  const float gz = 2.f * (-2.f * qz * gR[0][0] - qw * gR[0][1] + qx * gR[0][2] + qw * gR[1][0] - 2.f * qz * gR[1][1] +
+                          qy * gR[1][2] + qx * gR[2][0] + qy * gR[2][1]);
+  const float dot = fmaf(qw, gw, fmaf(qx, gx, fmaf(qy, gy, qz * gz)));
+  d_q[4 * g + 0] = (gw - qw * dot) / qn;
+  d_q[4 * g + 1] = (gx - qx * dot) / qn;
+  d_q[4 * g + 2] = (gy - qy * dot) / qn;
+  d_q[4 * g + 3] = (gz - qz * dot) / qn;
+  const float o = 1.f / (1.f + expf(-logits[g]));
+  d_a[g] = dO * o * (1.f - o);
+}
+
+template <int L, int NT, int G>
+static hipError_t bwd_launch(const RenderArgs &a, int64_t nblocks, const float2 *sig, const float2 *gsig,
+                             const float2 *gsum, int64_t n_gauss, float *acc, hipStream_t s) {
+  constexpr int K = (L + 1) * (L + 1);
+  constexpr int B = lds_batch(L, NT, true);
+  const size_t lds = (size_t)B * (kGeo * 16 + 2 * K * 4 + n_acc(L) * 4 + 4);
+  hipLaunchKernelGGL((k_render_bwd<L, NT, G>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, gsig, gsum, n_gauss,
+                     acc);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t bwd_dispatch(int area, int G, const RenderArgs &a, int64_t nblocks, const float2 *sig,
+                               const float2 *gsig, const float2 *gsum, int64_t n, float *acc, hipStream_t s) {
+  switch (area * 8 + G) {
+    case 64 * 8 + 1: return bwd_launch<L, 64, 1>(a, nblocks, sig, gsig, gsum, n, acc, s);
+    case 64 * 8 + 2: return bwd_launch<L, 128, 2>(a, nblocks, sig, gsig, gsum, n, acc, s);
+    case 64 * 8 + 4: return bwd_launch<L, 256, 4>(a, nblocks, sig, gsig, gsum, n, acc, s);
+    case 128 * 8 + 1: return bwd_launch<L, 128, 1>(a, nblocks, sig, gsig, gsum, n, acc, s);
+    case 128 * 8 + 2: return bwd_launch<L, 256, 2>(a, nblocks, sig, gsig, gsum, n, acc, s);
+    case 128 * 8 + 4: return bwd_launch<L, 512, 4>(a, nblocks, sig, gsig, gsum, n, acc, s);
+    case 256 * 8 + 1: return bwd_launch<L, 256, 1>(a, nblocks, sig, gsig, gsum, n, acc, s);
+    case 256 * 8 + 2: return bwd_launch<L, 512, 2>(a, nblocks, sig, gsig, gsum, n, acc, s);
+    default: return bwd_launch<L, 1024, 4>(a, nblocks, sig, gsig, gsum, n, acc, s);
+  }
+}
+
+hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws, const float *signal,
+                             const float *grad_signal, const float *grad_sum, float *d_means, float *d_log_scales,
+                             float *d_quats, float *d_logits, float *d_coeffs, hipStream_t s) {
+  float *acc = (float *)(ws + lay.grad_acc);
+  hipError_t e = fill<float>(acc, 0.f, p->n_gauss * lay.acc_stride, s);
+  if (e != hipSuccess) return e;
+  if (p->n_pairs > 0) {
+    const RenderArgs a = make_render_args(p, lay, ws);
+    const int area = p->grid.tile_w * p->grid.tile_h;
+    const int G = lanes_per_ray(p->grid);
+    const int64_t nb = (int64_t)p->n_pairs * lay.T;
+    const float2 *sg = (const float2 *)signal, *gs = (const float2 *)grad_signal, *gm = (const float2 *)grad_sum;
+    mark_kernel_event(2, s);
+    switch (p->grid.fle_L) {
+      case 0: e = bwd_dispatch<0>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
+      case 1: e = bwd_dispatch<1>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
+      case 2: e = bwd_dispatch<2>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
+      case 3: e = bwd_dispatch<3>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
+      case 4: e = bwd_dispatch<4>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
+      case 5: e = bwd_dispatch<5>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
+      default: e = bwd_dispatch<6>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
+    }
+    mark_kernel_event(3, s);
+    if (e != hipSuccess) return e;
+  }
+  if (p->n_gauss > 0) {
+    hipLaunchKernelGGL(k_chain, dim3((unsigned)((p->n_gauss + 255) / 256)), dim3(256), 0, s, p->log_scales, p->quats,
+                       p->opacity_logits, (const float *)acc, lay.K, p->n_gauss, d_means, d_log_scales, d_quats,
+                       d_logits, d_coeffs);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsrf

@@ -1,0 +1,297 @@
+// Device code shared by the forward and adjoint renderers (Sec. 3.4 eq.
+// rendering; App. A; App. D.3).  Both kernels call the same inline functions
+// for the hit test, the per-hit terms and the transmittance scan, so their
+// hit decisions, transmittances and termination points agree bit for bit.
+//
+// Per staged Gaussian the receiver-relative geometry is formed once in FP64
+// (distance D, unit direction e as an FP32 hi+lo pair, base phase
+// frac((|mu-tx| + D)/lambda)); per (ray, Gaussian) everything is FP32 in the
+// Gaussian's local frame:
+//   eps = v - e,  w = M v,  A = v.w,  b = eps.w,  c = eps^T M eps,
+//   Q = D^2 (c - b^2/A)  (= C - B^2/A, the Mahalanobis^2 at the chord midpoint)
+//   t = D (1 - b/A)      (= -B/A, the chord midpoint)
+// which avoids the cancellation of C - B^2/A at D ~ 10 m and keeps the phase
+// accurate: phase/(2 pi) = frac((|mu-tx| + D)/lambda) - (D/lambda) (b/A).
+//
+// A ray may be served by G lanes (G = 1, 2, 4): the G lanes of a ray test G
+// consecutive entries of the depth-ordered list at once, and an exclusive
+// product scan over the group gives each hit its incoming transmittance
+// T_j = T * prod_{i<j}(1 - alpha_i), so "process hit j iff T_j >= t_min" is
+// decided per hit exactly as in the sequential definition.
+#pragma once
+
+#include "gsrf_internal.h"
+
+namespace gsrf {
+
+struct RenderArgs {
+  const gsrf_pair *pairs;
+  const float *prep;        // [G][kPrep]
+  const float *coeffs;      // [G][K][2]
+  const uint32_t *val;      // sorted Gaussian ids
+  const uint32_t *tstart;   // [P*T]
+  const uint32_t *tend;     // [P*T]
+  int32_t T, nta, n_az, n_el, tw;
+  float el_lo, el_hi, r_rx, t_min, amax;
+};
+
+// Geometry record per staged Gaussian: five float4
+//   g0 = (e_hi, D)  g1 = (e_lo, D/lambda)  g2 = (M00, M11, M22, M01)
+//   g3 = (M02, M12, N, o)  g4 = (phase0, D^2, 0, 0)
+constexpr int kGeo = 5;
+
+// Number of accumulator slots the adjoint reduces per (ray, hit):
+// dL/dM (6), dL/dmu through delta (3), dL/dN, dL/do, dL/dt, dL/dc (2K).
+constexpr int n_acc(int L) { return 12 + 2 * (L + 1) * (L + 1); }
+constexpr int pow2_at_least(int n) { return n <= 32 ? 32 : (n <= 64 ? 64 : 128); }
+
+constexpr int lds_batch(int L, int NT, bool bwd) {
+  // floats per staged entry: geometry + coefficients (+ accumulators for bwd)
+  int K = (L + 1) * (L + 1);
+  int per = 4 * kGeo + 2 * K + (bwd ? n_acc(L) + 1 : 0);
+  int budget = 60 * 1024 / 4;
+  int b = NT < 256 ? NT : 256;
+  while (b > 32 && b * per > budget) b >>= 1;
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Per-ray setup: direction (FP64 -> FP32) and the FLE basis
+// Y_i = e^{j m alpha} P_l^m(sin beta), i = l^2 + l + m (Sec. 3.2 eq. FLE).
+// ---------------------------------------------------------------------------
+template <int L>
+__device__ void ray_setup(int u, int v, const RenderArgs &a, float &vx, float &vy, float &vz, float *Yr,
+                          float *Yi) {
+  const double pi = 3.14159265358979323846;
+  const double al = 2.0 * pi * (u + 0.5) / a.n_az;
+  const double be = (double)a.el_lo + ((double)a.el_hi - (double)a.el_lo) * (v + 0.5) / a.n_el;
+  const double cb = cos(be), sb = sin(be);
+  vx = (float)(cb * cos(al));
+  vy = (float)(cb * sin(al));
+  vz = (float)sb;
+  // associated Legendre P_l^m(x), m >= 0, Condon-Shortley phase, textbook recurrences
+  double P[L + 1][L + 1];
+  const double x = sb;
+  const double s = sqrt(fmax(0.0, 1.0 - x * x));
+  double pmm = 1.0;
+#pragma unroll
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) pmm = -pmm * (2 * m - 1) * s;
+    P[m][m] = pmm;
+    if (m + 1 <= L) P[m + 1][m] = x * (2 * m + 1) * pmm;
+#pragma unroll
+    for (int l = m + 2; l <= L; ++l) P[l][m] = ((2 * l - 1) * x * P[l - 1][m] - (l + m - 1) * P[l - 2][m]) / (l - m);
+  }
+#pragma unroll
+  for (int l = 0; l <= L; ++l) {
+#pragma unroll
+    for (int m = 0; m <= l; ++m) {
+      const double c = cos(m * al), sn = sin(m * al);
+      const double pl = P[l][m];
+      Yr[l * l + l + m] = (float)(pl * c);
+      Yi[l * l + l + m] = (float)(pl * sn);
+      if (m > 0) {
+        double f = 1.0;  // (l+m)! / (l-m)!
+        for (int t = l - m + 1; t <= l + m; ++t) f *= t;
+        const double pn = ((m & 1) ? -pl : pl) / f;   // P_l^{-m}
+        Yr[l * l + l - m] = (float)(pn * c);
+        Yi[l * l + l - m] = (float)(-pn * sn);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stage Gaussian g into an LDS slot (FP64 geometry relative to RX and TX).
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ void stage_entry(const RenderArgs &a, uint32_t g, double rx, double ry, double rz, double tx,
+                            double ty, double tz, double lam, float4 *geo, float *cf) {
+  const float *pg = a.prep + (size_t)kPrep * g;
+  // prep record (64-byte aligned): (mu, N) (M00, M11, M22, M01) (M02, M12, o, -)
+  const float4 *p4 = (const float4 *)pg;
+  const float4 q0 = p4[0], q1 = p4[1], q2 = p4[2];
+  const double mx = q0.x, my = q0.y, mz = q0.z;
+  const double ex = mx - rx, ey = my - ry, ez = mz - rz;
+  const double D2 = (ex * ex + ey * ey) + ez * ez;
+  const double D = sqrt(D2);
+  const double inv = D > 0.0 ? 1.0 / D : 0.0;
+  const double e0 = ex * inv, e1 = ey * inv, e2 = ez * inv;
+  const float h0 = (float)e0, h1 = (float)e1, h2 = (float)e2;
+  const double qx = mx - tx, qy = my - ty, qz = mz - tz;
+  const double dtx = sqrt((qx * qx + qy * qy) + qz * qz);
+  const double ph = (dtx + D) / lam;
+  geo[0] = make_float4(h0, h1, h2, (float)D);
+  geo[1] = make_float4((float)(e0 - (double)h0), (float)(e1 - (double)h1), (float)(e2 - (double)h2), (float)(D / lam));
+  geo[2] = q1;
+  geo[3] = make_float4(q2.x, q2.y, q0.w, q2.z);
+  geo[4] = make_float4((float)(ph - floor(ph)), (float)D2, 0.f, 0.f);
+  const float4 *c4 = (const float4 *)(a.coeffs + (size_t)2 * K * g);
+  if ((K & 1) == 0) {   // 2K floats per Gaussian: 16-byte aligned rows when K is even
+#pragma unroll
+    for (int i = 0; i < K / 2; ++i) ((float4 *)cf)[i] = c4[i];
+  } else {
+    const float2 *c2 = (const float2 *)(a.coeffs + (size_t)2 * K * g);
+#pragma unroll
+    for (int i = 0; i < K; ++i) ((float2 *)cf)[i] = c2[i];
+  }
+}
+
+// sin and cos of 2 pi x (x in revolutions): reduce to |f| <= 1/8 turn, then the
+// Taylor series of sin/cos to degree 9/10 (truncation < 2e-9 on |theta| <= pi/4).
+__device__ __forceinline__ void sincos_rev(float x, float &sn, float &cs) {
+  const float r = x - rintf(x);
+  const float q = rintf(4.0f * r);
+  const float f = fmaf(-0.25f, q, r);
+  const float th = f * 6.28318530717958648f;
+  const float t2 = th * th;
+  float ps = fmaf(t2, 2.7557319223985893e-6f, -1.9841269841269841e-4f);
+  ps = fmaf(t2, ps, 8.3333333333333333e-3f);
+  ps = fmaf(t2, ps, -1.6666666666666667e-1f);
+  ps = fmaf(t2 * th, ps, th);
+  float pc = fmaf(t2, -2.7557319223985891e-7f, 2.4801587301587302e-5f);
+  pc = fmaf(t2, pc, -1.3888888888888889e-3f);
+  pc = fmaf(t2, pc, 4.1666666666666667e-2f);
+  pc = fmaf(t2, pc, -0.5f);
+  pc = fmaf(t2, pc, 1.0f);
+  // quarter turns: swap sin/cos on odd quadrants, then flip signs (branch free)
+  const int iq = ((int)q) & 3;
+  const bool swap = (iq & 1) != 0;
+  const float s0 = swap ? pc : ps, c0 = swap ? ps : pc;
+  sn = __int_as_float(__float_as_int(s0) ^ ((iq & 2) << 30));
+  cs = __int_as_float(__float_as_int(c0) ^ (((iq + 1) & 2) << 30));
+}
+
+struct Terms {
+  float ex, ey, ez;     // eps = v - e
+  float w0, w1, w2;     // M v
+  float m0, m1, m2;     // M eps
+  float rA, bA, Q;
+  float G, alpha, p;
+  float sn, cs;         // sin/cos of the phase
+  float pr, pi;         // psi
+  float pzr, pzi;       // psi e^{-j phase}
+  bool clamped;
+};
+
+__device__ __forceinline__ bool test_hit(float vx, float vy, float vz, const float4 *geo, float r_rx, Terms &h) {
+  const float4 g0 = geo[0], g1 = geo[1], g2 = geo[2], g3 = geo[3];
+  h.ex = (vx - g0.x) - g1.x;
+  h.ey = (vy - g0.y) - g1.y;
+  h.ez = (vz - g0.z) - g1.z;
+  const float m00 = g2.x, m11 = g2.y, m22 = g2.z, m01 = g2.w, m02 = g3.x, m12 = g3.y;
+  h.w0 = fmaf(m00, vx, fmaf(m01, vy, m02 * vz));
+  h.w1 = fmaf(m01, vx, fmaf(m11, vy, m12 * vz));
+  h.w2 = fmaf(m02, vx, fmaf(m12, vy, m22 * vz));
+  const float A = fmaf(vx, h.w0, fmaf(vy, h.w1, vz * h.w2));
+  const float b = fmaf(h.ex, h.w0, fmaf(h.ey, h.w1, h.ez * h.w2));
+  h.m0 = fmaf(m00, h.ex, fmaf(m01, h.ey, m02 * h.ez));
+  h.m1 = fmaf(m01, h.ex, fmaf(m11, h.ey, m12 * h.ez));
+  h.m2 = fmaf(m02, h.ex, fmaf(m12, h.ey, m22 * h.ez));
+  const float c = fmaf(h.ex, h.m0, fmaf(h.ey, h.m1, h.ez * h.m2));
+  h.rA = __builtin_amdgcn_rcpf(A);
+  h.bA = b * h.rA;
+  h.Q = geo[4].y * fmaf(-b, h.bA, c);
+  const float t = fmaf(-g0.w, h.bA, g0.w);
+  return (h.Q <= kLevel) && (t >= r_rx);
+}
+
+template <int K>
+__device__ __forceinline__ void hit_terms(const float4 *geo, const float *cf, const float *Yr, const float *Yi,
+                                          float amax, Terms &h) {
+  const float4 g1 = geo[1], g3 = geo[3], g4 = geo[4];
+  h.G = __builtin_amdgcn_exp2f(-0.72134752044448170f * h.Q);   // exp(-Q/2)
+  const float oG = g3.w * h.G;
+  h.clamped = oG > amax;
+  h.alpha = fminf(oG, amax);
+  h.p = g3.z * h.G;
+  sincos_rev(fmaf(-g1.w, h.bA, g4.x), h.sn, h.cs);
+  float pr = 0.f, pi = 0.f;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const float cr = cf[2 * i], ci = cf[2 * i + 1];
+    pr = fmaf(cr, Yr[i], fmaf(-ci, Yi[i], pr));
+    pi = fmaf(cr, Yi[i], fmaf(ci, Yr[i], pi));
+  }
+  h.pr = pr;
+  h.pi = pi;
+  h.pzr = fmaf(pr, h.cs, pi * h.sn);
+  h.pzi = fmaf(pi, h.cs, -(pr * h.sn));
+}
+
+// Exclusive product and total of f over the G lanes of a ray (lanes q = 0..G-1
+// adjacent in the wave).  Every lane of the wave must call it.
+template <int G>
+__device__ __forceinline__ void group_prod(float f, int q, float &excl, float &total) {
+  if constexpr (G == 1) {
+    excl = 1.f;
+    total = f;
+  } else {
+    float incl = f;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const float o = __shfl_up(incl, d, G);
+      if (q >= d) incl *= o;
+    }
+    const float e = __shfl_up(incl, 1, G);
+    excl = (q == 0) ? 1.f : e;
+    total = __shfl(incl, G - 1, G);
+  }
+}
+
+// Inclusive sum and total of x over the G lanes of a ray.
+template <int G>
+__device__ __forceinline__ void group_sum(float x, int q, float &incl, float &total) {
+  if constexpr (G == 1) {
+    incl = x;
+    total = x;
+  } else {
+    incl = x;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const float o = __shfl_up(incl, d, G);
+      if (q >= d) incl += o;
+    }
+    total = __shfl(incl, G - 1, G);
+  }
+}
+
+// Reduce-scatter across the lanes of a wave that share q = lane % G (the rays
+// of the wave), by recursive halving: at lane distance D the lane keeps half of
+// its live slots and adds the partner's copy of them.  On return the lane holds
+// slots [first, first + NV*G/64) of its group's entry, summed over all 64/G
+// rays.  When NV*G < 64 the last halvings have a single live slot left: the
+// pair of lanes then both hold it and only the one without bit D writes it.
+// Every index is a compile-time constant, so v stays in registers.
+template <int NV, int G, int D>
+__device__ __forceinline__ void rs_step(float (&v)[NV], int lane, int &first, bool &writer) {
+  if constexpr (D >= G) {
+    constexpr int LIVE = (NV * D / 32 >= 1) ? NV * D / 32 : 1;
+    if constexpr (LIVE > 1) {
+      constexpr int H = LIVE / 2;
+      const bool up = (lane & D) != 0;
+#pragma unroll
+      for (int i = 0; i < H; ++i) {
+        const float send = up ? v[i] : v[i + H];
+        const float keep = up ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, D, 64);
+      }
+      if (up) first += H;
+    } else {
+      v[0] += __shfl_xor(v[0], D, 64);
+      if (lane & D) writer = false;
+    }
+    rs_step<NV, G, D / 2>(v, lane, first, writer);
+  }
+}
+
+template <int NV, int G>
+__device__ __forceinline__ void reduce_scatter(float (&v)[NV], int lane, int *first, bool *writer) {
+  int f = 0;
+  bool w = true;
+  rs_step<NV, G, 32>(v, lane, f, w);
+  *first = f;
+  *writer = w;
+}
+
+}  // namespace gsrf

@@ -1,0 +1,232 @@
+// Steps a5-a6: complex front-to-back ray accumulation (Sec. 3.4 eq. rendering;
+// App. A; Alg. 1 Blend) and the single-antenna sum (Sec. 3.4).
+//
+// One workgroup renders one (pair, tile); each ray is served by G lanes (see
+// render_common.h).  The tile's depth-sorted Gaussian list is staged through
+// LDS in batches; rays stop individually when their transmittance falls below
+// t_min and the workgroup stops when all of its rays have.  Tile partials of
+// S_hat are reduced in a fixed order, so the forward pass is deterministic.
+#include "render_common.h"
+
+namespace gsrf {
+
+template <int L, int NT, int G, bool STATS>
+__global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restrict__ signal,
+                                                   float2 *__restrict__ tile_sum,
+                                                   unsigned long long *__restrict__ stats) {
+  constexpr int K = (L + 1) * (L + 1);
+  constexpr int B = lds_batch(L, NT, false);
+  constexpr int RAYS = NT / G;
+  extern __shared__ float4 smem[];
+  float4 *sgeo = smem;                          // [B][kGeo]
+  float *scf = (float *)(smem + kGeo * B);      // [B][2K]
+  const int gt = blockIdx.x;
+  const int k = gt / a.T;
+  const int tile = gt - k * a.T;
+  const int tv = tile / a.nta, tu = tile - tv * a.nta;
+  const int r = (int)threadIdx.x / G, q = (int)threadIdx.x % G;
+  const int th_ = RAYS / a.tw;
+  const int u = tu * a.tw + r % a.tw;
+  const int v = tv * th_ + r / a.tw;
+  const bool valid = (u < a.n_az) && (v < a.n_el);
+  const gsrf_pair pr = a.pairs[k];
+  const double lam = kC0 / pr.freq_hz;
+  float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
+  ray_setup<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
+  const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
+  float T = 1.f, Sr = 0.f, Si = 0.f;
+  bool done = !valid || (1.0f < a.t_min);
+  unsigned long long n_test = 0, n_hit = 0, n_staged = 0;
+  for (uint32_t base = s0; base < s1; base += B) {
+    const int nb = (int)min((uint32_t)B, s1 - base);
+    __syncthreads();
+    if ((int)threadIdx.x < nb)
+      stage_entry<K>(a, a.val[base + threadIdx.x], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], lam,
+                     sgeo + kGeo * threadIdx.x, scf + 2 * K * threadIdx.x);
+    if (STATS && threadIdx.x == 0) n_staged += nb;
+    __syncthreads();
+    if (__ballot(!done) != 0) {              // wave-uniform
+      for (int m = 0; m < nb; m += G) {
+        const int j = m + q;
+        Terms h;
+        bool hit = false;
+        float f = 1.f, ctr = 0.f, cti = 0.f;
+        if (!done && j < nb) {
+          if (STATS) ++n_test;
+          hit = test_hit(vx, vy, vz, sgeo + kGeo * j, a.r_rx, h);
+          if (hit) {
+            hit_terms<K>(sgeo + kGeo * j, scf + 2 * K * j, Yr, Yi, a.amax, h);
+            f = 1.0f - h.alpha;
+            ctr = h.p * h.pzr;
+            cti = h.p * h.pzi;
+          }
+        }
+        float excl, total;
+        group_prod<G>(f, q, excl, total);
+        const float Tj = T * excl;
+        if (hit && Tj >= a.t_min) {
+          Sr = fmaf(Tj, ctr, Sr);
+          Si = fmaf(Tj, cti, Si);
+          if (STATS) ++n_hit;
+        }
+        T = T * total;
+        done = done || (T < a.t_min);
+        if (__ballot(!done) == 0) break;
+      }
+    }
+    if (__syncthreads_and(done ? 1 : 0)) break;
+  }
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      Sr += __shfl_xor(Sr, d, G);
+      Si += __shfl_xor(Si, d, G);
+    }
+  }
+  if (STATS) {
+    // instrumentation: tests, processed hits, staged entries, rays
+    if (n_test) atomicAdd(stats + 0, n_test);
+    if (n_hit) atomicAdd(stats + 1, n_hit);
+    if (n_staged) atomicAdd(stats + 2, n_staged);
+    if (valid && q == 0) atomicAdd(stats + 3, 1ull);
+    return;
+  }
+  if (valid && q == 0) signal[((size_t)k * a.n_el + v) * a.n_az + u] = make_float2(Sr, Si);
+  // deterministic tile partial of S_hat (fixed tree order)
+  __syncthreads();
+  float *red = (float *)smem;
+  red[threadIdx.x] = (q == 0) ? Sr : 0.f;
+  red[NT + threadIdx.x] = (q == 0) ? Si : 0.f;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[threadIdx.x] += red[threadIdx.x + off];
+      red[NT + threadIdx.x] += red[NT + threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tile_sum[gt] = make_float2(red[0], red[NT]);
+}
+
+// a6: S_hat per pair (tiles summed in fixed order, FP64) and RSSI in dBm.
+__global__ void k_rssi(const float2 *__restrict__ tile_sum, int32_t T, float *__restrict__ signal_sum,
+                       float *__restrict__ rssi) {
+  __shared__ double sr[256], si[256];
+  const int k = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int t = threadIdx.x; t < T; t += 256) {
+    const float2 v = tile_sum[(size_t)k * T + t];
+    a += v.x;
+    b += v.y;
+  }
+  sr[threadIdx.x] = a;
+  si[threadIdx.x] = b;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      sr[threadIdx.x] += sr[threadIdx.x + off];
+      si[threadIdx.x] += si[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    signal_sum[2 * k] = (float)sr[0];
+    signal_sum[2 * k + 1] = (float)si[0];
+    if (rssi) {
+      const double pw = sr[0] * sr[0] + si[0] * si[0];
+      rssi[k] = pw > 0.0 ? (float)(10.0 * log10(pw)) : -INFINITY;
+    }
+  }
+}
+
+template <int L, int NT, int G>
+static hipError_t fwd_launch(const RenderArgs &a, int64_t nblocks, float2 *sig, float2 *tsum,
+                             unsigned long long *stats, hipStream_t s) {
+  constexpr int K = (L + 1) * (L + 1);
+  constexpr int B = lds_batch(L, NT, false);
+  size_t lds = (size_t)B * (kGeo * 16 + 2 * K * 4);
+  if (lds < (size_t)NT * 8) lds = (size_t)NT * 8;
+  if (stats)
+    hipLaunchKernelGGL((k_render_fwd<L, NT, G, true>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, tsum, stats);
+  else
+    hipLaunchKernelGGL((k_render_fwd<L, NT, G, false>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, tsum,
+                       stats);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t fwd_dispatch(int area, int G, const RenderArgs &a, int64_t nblocks, float2 *sig, float2 *tsum,
+                               unsigned long long *stats, hipStream_t s) {
+  switch (area * 8 + G) {
+    case 64 * 8 + 1: return fwd_launch<L, 64, 1>(a, nblocks, sig, tsum, stats, s);
+    case 64 * 8 + 2: return fwd_launch<L, 128, 2>(a, nblocks, sig, tsum, stats, s);
+    case 64 * 8 + 4: return fwd_launch<L, 256, 4>(a, nblocks, sig, tsum, stats, s);
+    case 128 * 8 + 1: return fwd_launch<L, 128, 1>(a, nblocks, sig, tsum, stats, s);
+    case 128 * 8 + 2: return fwd_launch<L, 256, 2>(a, nblocks, sig, tsum, stats, s);
+    case 128 * 8 + 4: return fwd_launch<L, 512, 4>(a, nblocks, sig, tsum, stats, s);
+    case 256 * 8 + 1: return fwd_launch<L, 256, 1>(a, nblocks, sig, tsum, stats, s);
+    case 256 * 8 + 2: return fwd_launch<L, 512, 2>(a, nblocks, sig, tsum, stats, s);
+    default: return fwd_launch<L, 1024, 4>(a, nblocks, sig, tsum, stats, s);
+  }
+}
+
+static hipError_t fwd_any(const gsrf_problem *p, const RenderArgs &a, int64_t nblocks, float2 *sig, float2 *tsum,
+                          unsigned long long *stats, hipStream_t s) {
+  const int area = p->grid.tile_w * p->grid.tile_h;
+  const int G = lanes_per_ray(p->grid);
+  switch (p->grid.fle_L) {
+    case 0: return fwd_dispatch<0>(area, G, a, nblocks, sig, tsum, stats, s);
+    case 1: return fwd_dispatch<1>(area, G, a, nblocks, sig, tsum, stats, s);
+    case 2: return fwd_dispatch<2>(area, G, a, nblocks, sig, tsum, stats, s);
+    case 3: return fwd_dispatch<3>(area, G, a, nblocks, sig, tsum, stats, s);
+    case 4: return fwd_dispatch<4>(area, G, a, nblocks, sig, tsum, stats, s);
+    case 5: return fwd_dispatch<5>(area, G, a, nblocks, sig, tsum, stats, s);
+    default: return fwd_dispatch<6>(area, G, a, nblocks, sig, tsum, stats, s);
+  }
+}
+
+RenderArgs make_render_args(const gsrf_problem *p, const Layout &lay, char *ws) {
+  RenderArgs a;
+  const int cur = lay.sort_passes & 1;
+  a.pairs = p->pairs;
+  a.prep = (const float *)(ws + lay.prep);
+  a.coeffs = p->coeffs;
+  a.val = (const uint32_t *)(ws + lay.val[cur]);
+  a.tstart = (const uint32_t *)(ws + lay.tile_start);
+  a.tend = (const uint32_t *)(ws + lay.tile_end);
+  a.T = lay.T;
+  a.nta = lay.nta;
+  a.n_az = p->grid.n_az;
+  a.n_el = p->grid.n_el;
+  a.tw = p->grid.tile_w;
+  a.el_lo = p->grid.el_lo;
+  a.el_hi = p->grid.el_hi;
+  a.r_rx = p->grid.r_rx;
+  a.t_min = p->grid.t_min;
+  a.amax = p->grid.alpha_max;
+  return a;
+}
+
+hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws, float *signal, float *signal_sum,
+                             float *rssi_dbm, hipStream_t s) {
+  if (p->n_pairs == 0) return hipSuccess;
+  const RenderArgs a = make_render_args(p, lay, ws);
+  const int64_t nblocks = (int64_t)p->n_pairs * lay.T;
+  float2 *tsum = (float2 *)(ws + lay.tile_sum);
+  mark_kernel_event(0, s);
+  hipError_t e = fwd_any(p, a, nblocks, (float2 *)signal, tsum, nullptr, s);
+  mark_kernel_event(1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rssi, dim3(p->n_pairs), dim3(256), 0, s, tsum, lay.T, signal_sum, rssi_dbm);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *ws, int64_t *counts, hipStream_t s) {
+  hipError_t e = fill<int64_t>(counts, 0, 4, s);
+  if (e != hipSuccess || p->n_pairs == 0) return e;
+  const RenderArgs a = make_render_args(p, lay, ws);
+  const int64_t nblocks = (int64_t)p->n_pairs * lay.T;
+  return fwd_any(p, a, nblocks, nullptr, nullptr, (unsigned long long *)counts, s);
+}
+
+}  // namespace gsrf

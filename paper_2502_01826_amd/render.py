@@ -34,14 +34,16 @@ class GridSpec:
     alpha_max: float = 0.99
     tile_w: int = 16
     tile_h: int = 16
+    lanes_per_ray: int = 1
 
     @staticmethod
     def of(g) -> "GridSpec":
-        return GridSpec(**{k: getattr(g, k) for k in GridSpec.__dataclass_fields__})
+        return GridSpec(**{k: getattr(g, k, GridSpec.__dataclass_fields__[k].default)
+                           for k in GridSpec.__dataclass_fields__})
 
     def c(self) -> GsrfGrid:
         return GsrfGrid(self.n_az, self.n_el, self.el_lo, self.el_hi, self.fle_L, self.r_rx, self.t_min,
-                        self.alpha_max, self.tile_w, self.tile_h)
+                        self.alpha_max, self.tile_w, self.tile_h, self.lanes_per_ray)
 
     @property
     def K(self) -> int:

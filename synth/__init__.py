@@ -39,6 +39,7 @@ class Grid:
     alpha_max: float = 0.99
     tile_w: int = 16
     tile_h: int = 16
+    lanes_per_ray: int = 1
 
     @property
     def K(self) -> int:

@@ -77,7 +77,7 @@ def _host_problem(n_gauss=10, n_pairs=2, grid=None, cap=1000):
     p.scene_offsets = offs.ctypes.data
     p.pair_scene = ps.ctypes.data
     p.n_pairs = n_pairs
-    p.grid = grid or GsrfGrid(360, 90, 0.0, 1.5707963, 2, 1.0, 1e-4, 0.99, 16, 16)
+    p.grid = grid or GsrfGrid(360, 90, 0.0, 1.5707963, 2, 1.0, 1e-4, 0.99, 16, 16, 1)
     p.splat_capacity = cap
     return p, (offs, ps)
 
@@ -103,6 +103,7 @@ def test_workspace_size_and_layout():
 @pytest.mark.parametrize("mutate,needle", [
     (lambda p: setattr(p.grid, "tile_w", 5), "tile"),
     (lambda p: setattr(p.grid, "fle_L", 7), "fle_L"),
+    (lambda p: setattr(p.grid, "lanes_per_ray", 3), "lanes_per_ray"),
     (lambda p: setattr(p.grid, "n_az", 0), "grid size"),
     (lambda p: setattr(p.grid, "alpha_max", 1.0), "alpha_max"),
     (lambda p: setattr(p.grid, "el_hi", -0.5), "elevation"),

@@ -31,8 +31,9 @@ def _compare(gg, gr, tol=GTOL):
         assert num <= tol * den, n
 
 
-def test_tiny_gradients_match_oracle():
-    b = synth.tiny()
+@pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (16, 8, 2)])
+def test_tiny_gradients_match_oracle(tw, th, G):
+    b = synth.tiny(grid=Grid(n_az=36, n_el=9, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G))
     sc, p, g = b.scenes[0], b.pairs[0], b.grid
     prob = gpu_problem(b)
     sig, ssum, _ = prob.forward()
@@ -119,10 +120,11 @@ def test_autograd_function_l2_step():
     _compare({n: t.grad.cpu().numpy().astype(np.float64) for n, t in zip(NAMES, ps)}, gr, tol=2e-3)
 
 
-def test_paper_scale_gradients_on_sampled_rays():
+@pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4)])
+def test_paper_scale_gradients_on_sampled_rays(tw, th, G):
     """200k Gaussians, 360x90: cotangent on 48 sampled rays only, compared with
     the oracle's gradient of the same rays."""
-    b = synth.paper_scale()
+    b = synth.paper_scale(grid=Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G))
     sc, p, g = b.scenes[0], b.pairs[0], b.grid
     prob = gpu_problem(b)
     sig, _, _ = prob.forward()

@@ -54,21 +54,22 @@ def test_forward_is_deterministic():
     assert np.array_equal(S1.view(np.float64), S2.view(np.float64)) and np.array_equal(s1, s2)
 
 
-@pytest.mark.parametrize("tw,th", [(8, 8), (16, 8), (32, 8), (16, 16)])
-def test_ragged_tiles_and_seam(tw, th):
+@pytest.mark.parametrize("tw,th,G", [(8, 8, 1), (16, 8, 2), (32, 8, 1), (16, 16, 1), (8, 8, 4), (16, 16, 4),
+                                     (16, 8, 4), (8, 8, 2)])
+def test_ragged_tiles_and_seam(tw, th, G):
     # 37 x 11 rays do not divide by any tile shape: ragged last column and row
-    g = Grid(n_az=37, n_el=11, fle_L=2, tile_w=tw, tile_h=th)
+    g = Grid(n_az=37, n_el=11, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G)
     b = synth.tiny(grid=g, n=1500)
     sc, p = b.scenes[0], b.pairs[0]
-    say("ragged", tw, th)
+    say("ragged", tw, th, "lanes", G)
     S, Ssum, _ = gpu_forward(gpu_problem(b))
     ref = oracle.render(sc, p, g)
     compare_rays(S[0].ravel(), ref, sc, p, g)
 
 
-@pytest.mark.parametrize("L", [0, 1, 3, 4, 6])
-def test_fle_degrees(L):
-    g = Grid(n_az=24, n_el=8, fle_L=L, tile_w=8, tile_h=8)
+@pytest.mark.parametrize("L,G", [(0, 1), (1, 2), (3, 4), (4, 1), (6, 4), (5, 2)])
+def test_fle_degrees(L, G):
+    g = Grid(n_az=24, n_el=8, fle_L=L, tile_w=8, tile_h=8, lanes_per_ray=G)
     rng = np.random.default_rng([100, L])
     sc = synth.draw_scene(rng, 800, (4.0, 4.0, 3.0), g.K)
     p = Pair(np.array([2.0, 2.1, 1.0], np.float32), np.array([0.5, 3.0, 2.0], np.float32), 5.8e9)
@@ -135,13 +136,14 @@ def test_multi_scene_multi_pair_batch():
         assert abs(Ssum[k] - S[k].sum()) <= 1e-5 * np.abs(S[k]).sum() + 1e-30
 
 
-def test_paper_scale_sampled_rays_and_tiles():
-    """200k Gaussians, 360x90 rays, 5 GHz, at the launch configuration the
+@pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (16, 8, 2)])
+def test_paper_scale_sampled_rays_and_tiles(tw, th, G):
+    """200k Gaussians, 360x90 rays, 5 GHz, at the launch configurations the
     benchmark times: sampled rays against the oracle, sampled tile lists bit
     exact, and S_hat equal to the sum of the spectrum."""
-    b = synth.paper_scale()
+    b = synth.paper_scale(grid=Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G))
     sc, p, g = b.scenes[0], b.pairs[0], b.grid
-    say("paper scale: 200k gaussians, 360x90")
+    say("paper scale: 200k gaussians, 360x90, tile", tw, th, "lanes", G)
     prob = gpu_problem(b)
     S, Ssum, rssi = gpu_forward(prob)
     rng = np.random.default_rng(5)
