@@ -115,14 +115,15 @@ typedef struct gsrf_problem {
   size_t workspace_bytes;
 } gsrf_problem;
 
-/* Byte offsets of the workspace arrays that tests and tools may read. */
+/* Byte offsets of the workspace arrays that tests and tools may read.  Tile
+ * tt of pair k (global tile k * n_tiles + tt) owns sorted entries
+ * [tile_start[.], tile_end[.]) of sorted_klo / sorted_val. */
 typedef struct gsrf_layout {
   size_t rec_key;      /* uint32 [R]      per (pair, Gaussian) depth key bits(fp32(|mu-r|^2)) */
   size_t rec_rect;     /* uint16 [R][4]   tile rectangle (tu0, ntu, tv0, ntv) */
   size_t rec_base;     /* int64  [P+1]    first record of each pair; R = rec_base[P] */
   size_t counters;     /* int64  [4]      [0] splat count, [1] = count if over capacity else 0 */
-  size_t sorted_khi;   /* uint32 [cap]    sorted splat key, high word = pair * T + tile */
-  size_t sorted_klo;   /* uint32 [cap]    sorted splat key, low word = depth key */
+  size_t sorted_klo;   /* uint32 [cap]    depth key of each sorted splat */
   size_t sorted_val;   /* uint32 [cap]    Gaussian index of each sorted splat */
   size_t tile_start;   /* uint32 [P*T]    first sorted splat of each tile */
   size_t tile_end;     /* uint32 [P*T]    one past the last */
@@ -165,13 +166,13 @@ gsrf_status gsrf_project(const gsrf_problem *p, void *stream);
 gsrf_status gsrf_splat_count(const gsrf_problem *p, int64_t *n_splats, void *stream);
 
 /*
- * Steps a3 + a4 (Alg. 1 sphericalSplatting, the radix sort of App. E,
- * computeGridRange): emit one (key64, Gaussian) splat per covered tile with
- * key64 = (pair * T + tile) << 32 | depth key, stable LSD radix sort on key64,
- * then the [start, end) range of each tile.  Within a tile, Gaussians end up
- * in (depth key, index) order.  If the splat count exceeds splat_capacity the
- * device-side overflow counter is set and only the first splat_capacity
- * splats are sorted; results are then invalid (see gsrf_splat_count).
+ * Steps a3 + a4 (Alg. 1 sphericalSplatting, the 64-bit key sort of App. E,
+ * computeGridRange): one splat per covered tile, placed in its tile's range
+ * (counted by gsrf_project), then each tile's list sorted by depth key with
+ * ties broken by Gaussian index -- the order a sort of all splats by
+ * (tile << 32 | depth key) would give.  If the splat count exceeds
+ * splat_capacity the device-side overflow counter is set, every tile list is
+ * left empty and renders give zeros; gsrf_splat_count reports it.
  */
 gsrf_status gsrf_bin_sort(const gsrf_problem *p, void *stream);
 

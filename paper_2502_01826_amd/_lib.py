@@ -41,7 +41,7 @@ class GsrfProblem(ctypes.Structure):
 
 class GsrfLayout(ctypes.Structure):
     _fields_ = [("rec_key", c_sz), ("rec_rect", c_sz), ("rec_base", c_sz), ("counters", c_sz),
-                ("sorted_khi", c_sz), ("sorted_klo", c_sz), ("sorted_val", c_sz), ("tile_start", c_sz),
+                ("sorted_klo", c_sz), ("sorted_val", c_sz), ("tile_start", c_sz),
                 ("tile_end", c_sz), ("n_records", c_i64), ("n_tiles", c_i32), ("n_tiles_az", c_i32)]
 
 

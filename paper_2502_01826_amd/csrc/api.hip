@@ -34,15 +34,6 @@ void mark_kernel_event(int i, hipStream_t s) {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int bits_for(int64_t x) {  // bits needed to represent 0..x
-  int b = 0;
-  while (x > 0) {
-    ++b;
-    x >>= 1;
-  }
-  return b;
-}
-
 // Validates the host-readable parts of a problem and computes its layout.
 static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   if (!p || !lay) return fail(GSRF_EINVAL, "null problem or output");
@@ -94,6 +85,7 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
     if (!p->workspace) return fail(GSRF_EINVAL, "workspace is NULL");
     if ((uintptr_t)p->workspace & 255) return fail(GSRF_EINVAL, "workspace must be 256-byte aligned");
   }
+  if (T > kMaxTiles) return fail(GSRF_EINVAL, "%lld tiles per pair exceed %d", (long long)T, kMaxTiles);
   Layout L{};
   L.n_records = R;
   L.max_scene = max_used;
@@ -103,11 +95,7 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.nte = nte;
   L.K = fle_K(g.fle_L);
   L.acc_stride = 11 + 2 * L.K;
-  L.n_rec_blocks = (int32_t)((R + kScanTile - 1) / kScanTile);
-  L.n_sort_blocks = (int32_t)((L.cap + kSortTile - 1) / kSortTile);
-  L.n_hist_blocks = (int32_t)(((int64_t)256 * L.n_sort_blocks + kScanTile - 1) / kScanTile);
   const int64_t PT = (int64_t)p->n_pairs * T;
-  L.sort_passes = 4 + (bits_for(PT > 0 ? PT - 1 : 0) + 7) / 8;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -119,20 +107,17 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.rec_base = take((size_t)(p->n_pairs + 1) * 8);
   L.rec_key = take((size_t)R * 4);
   L.rec_rect = take((size_t)R * 8);
-  L.rec_cnt = take((size_t)R * 4);
-  L.rec_off = take((size_t)R * 8);
-  L.scan_tmp = take((size_t)(L.n_rec_blocks + 1) * 8);
   L.counters = take(4 * 8);
-  for (int b = 0; b < 2; ++b) {
-    L.khi[b] = take((size_t)L.cap * 4);
-    L.klo[b] = take((size_t)L.cap * 4);
-    L.val[b] = take((size_t)L.cap * 4);
-  }
-  L.hist = take((size_t)256 * L.n_sort_blocks * 4);
-  L.hist_scan = take((size_t)256 * L.n_sort_blocks * 4);
-  L.hist_tmp = take((size_t)(L.n_hist_blocks + 1) * 4);
+  L.tile_cnt = take((size_t)PT * 4);
   L.tile_start = take((size_t)PT * 4);
   L.tile_end = take((size_t)PT * 4);
+  L.tile_cur = take((size_t)PT * 4);
+  L.ekey = take((size_t)L.cap * 4);
+  L.eval = take((size_t)L.cap * 4);
+  L.klo = take((size_t)L.cap * 4);
+  L.val = take((size_t)L.cap * 4);
+  L.tkey = take((size_t)L.cap * 4);
+  L.tval = take((size_t)L.cap * 4);
   L.tile_sum = take((size_t)PT * 8);
   L.grad_acc = take((size_t)G * L.acc_stride * 4);
   L.total = o;
@@ -175,14 +160,12 @@ gsrf_status gsrf_layout_of(const gsrf_problem *p, gsrf_layout *out) {
   Layout L;
   gsrf_status st = plan(p, &L, false);
   if (st != GSRF_OK) return st;
-  const int cur = L.sort_passes & 1;
   out->rec_key = L.rec_key;
   out->rec_rect = L.rec_rect;
   out->rec_base = L.rec_base;
   out->counters = L.counters;
-  out->sorted_khi = L.khi[cur];
-  out->sorted_klo = L.klo[cur];
-  out->sorted_val = L.val[cur];
+  out->sorted_klo = L.klo;
+  out->sorted_val = L.val;
   out->tile_start = L.tile_start;
   out->tile_end = L.tile_end;
   out->n_records = L.n_records;

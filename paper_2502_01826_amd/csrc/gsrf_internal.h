@@ -19,29 +19,28 @@ constexpr float kLevel = 9.0f;
 // Per-Gaussian prepared record: mu(3), N, M00 M11 M22 M01 M02 M12, o, pad(5).
 constexpr int kPrep = 16;
 
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kScanThreads * kScanItems;   // elements per scan block
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kSortThreads * kSortItems;   // keys per radix-sort block
+// Binning: splats are emitted into per-tile buckets (key, Gaussian) and each
+// tile's bucket is sorted by one workgroup of kTileSortThreads threads, in LDS
+// chunks of at most `sort_chunk` entries (merged in global memory if longer).
+constexpr int kTileSortThreads = 512;
+constexpr int kMaxTiles = 8192;           // per pair; LDS histograms in project/emit
 
 // Byte offsets of every workspace array plus derived sizes.
 struct Layout {
-  size_t prep, rec_base, rec_key, rec_rect, rec_cnt, rec_off, scan_tmp, counters;
-  size_t khi[2], klo[2], val[2];
-  size_t hist, hist_scan, hist_tmp;
-  size_t tile_start, tile_end, tile_sum, grad_acc;
+  size_t prep, rec_base, rec_key, rec_rect, counters;
+  size_t tile_cnt, tile_start, tile_end, tile_cur;
+  size_t ekey, eval;      // emitted buckets (unsorted)
+  size_t klo, val;        // sorted tile lists: depth key, Gaussian id
+  size_t tkey, tval;      // merge scratch
+  size_t tile_sum, grad_acc;
   size_t total;
   int64_t n_records;
   int64_t max_scene;
   int64_t cap;
-  int32_t n_rec_blocks;   // scan blocks over records
-  int32_t n_sort_blocks;  // radix-sort blocks over capacity
-  int32_t n_hist_blocks;  // scan blocks over the radix histogram
   int32_t T, nta, nte;
   int32_t K, acc_stride;
-  int32_t sort_passes;
+  int32_t sort_chunk;     // entries sorted in LDS at once
+  size_t sort_lds;        // dynamic LDS bytes of the tile sort
 };
 
 inline int fle_K(int L) { return (L + 1) * (L + 1); }
@@ -67,12 +66,8 @@ hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws,
                              float *d_log_scales, float *d_quats, float *d_logits, float *d_coeffs,
                              hipStream_t s);
 
-// Exclusive scan of n inputs (uint32) into int64 or uint32 outputs; writes the
-// grand total to *total (device) when total != nullptr.  n is host-known.
-hipError_t scan_u32_to_i64(const uint32_t *in, int64_t n, int64_t *out, int64_t *tmp, int32_t nblocks,
-                           int64_t *total, int64_t cap_for_flag, int64_t *flag, hipStream_t s);
-hipError_t scan_u32_to_u32(const uint32_t *in, int64_t n, uint32_t *out, uint32_t *tmp, int32_t nblocks,
-                           hipStream_t s);
+// Dynamic LDS available to one workgroup on the current device (bytes).
+size_t max_lds_per_block();
 
 template <typename T>
 __global__ void k_fill(T *p, T v, int64_t n) {

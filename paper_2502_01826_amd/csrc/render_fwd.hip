@@ -187,11 +187,10 @@ static hipError_t fwd_any(const gsrf_problem *p, const RenderArgs &a, int64_t nb
 
 RenderArgs make_render_args(const gsrf_problem *p, const Layout &lay, char *ws) {
   RenderArgs a;
-  const int cur = lay.sort_passes & 1;
   a.pairs = p->pairs;
   a.prep = (const float *)(ws + lay.prep);
   a.coeffs = p->coeffs;
-  a.val = (const uint32_t *)(ws + lay.val[cur]);
+  a.val = (const uint32_t *)(ws + lay.val);
   a.tstart = (const uint32_t *)(ws + lay.tile_start);
   a.tend = (const uint32_t *)(ws + lay.tile_end);
   a.T = lay.T;

@@ -1,112 +1,132 @@
-// Steps a3-a4: splat emission, stable LSD radix sort on 64-bit
-// (tile | depth) keys, and per-tile ranges (App. E: one sort of all splats
-// with the tile index in the high 32 bits and the distance key in the low 32;
-// Alg. 1 sphericalSplatting and computeGridRange).
+// Steps a3-a4: splat emission into per-tile buckets and the per-tile depth
+// sort (App. E: every splat carries the tile index and the distance key; the
+// paper sorts them all at once by a 64-bit key, Alg. 1 sphericalSplatting and
+// computeGridRange).  Here the tile part of the key is applied by bucketing
+// (the tile ranges come from the counts made during projection) and the
+// distance part by sorting each bucket in its own workgroup, which gives the
+// same order -- (distance key, Gaussian index) within each tile -- with one
+// pass over the splats instead of one per key byte.
 //
-// The sort is a classic three-kernel LSD pass per 8-bit digit: per-block
-// digit histograms, an exclusive scan over (digit, block), and a stable
-// scatter whose in-block ranks come from wave64 ballots.  There is no
-// cross-block spin-waiting, so every wave always finishes.
+// A bucket of up to `chunk` entries is sorted in LDS by a four-pass stable LSD
+// radix sort on the 32-bit distance key (wave64 ballots rank equal digits),
+// after which runs of equal keys are ordered by Gaussian index.  A longer
+// bucket is sorted chunk by chunk and the sorted runs are merged pairwise in
+// global memory (merge-path partitioning across the workgroup).  No
+// workgroup ever waits on another, so every wave finishes.
 #include "gsrf_internal.h"
 
 namespace gsrf {
 
-// a3: one splat per tile of each record's rectangle, in (tile row, tile column)
-// order; value = global Gaussian index.
-__global__ void k_emit(const gsrf_pair *__restrict__ pairs, const int64_t *__restrict__ scene_off,
-                       const int64_t *__restrict__ rec_base, const uint32_t *__restrict__ rec_key,
-                       const ushort4 *__restrict__ rec_rect, const uint32_t *__restrict__ rec_cnt,
-                       const int64_t *__restrict__ rec_off, int32_t T, int32_t nta, int64_t cap,
-                       const int64_t *__restrict__ counters,
-                       uint32_t *__restrict__ khi, uint32_t *__restrict__ klo, uint32_t *__restrict__ val) {
-  if (counters[1] != 0) return;  // over capacity: nothing is emitted
+// a3: one splat per covered tile.  The workgroup (256 records of one pair)
+// counts its splats per tile in LDS, reserves each tile's share of the bucket
+// with one global atomic, then writes (key, Gaussian) at its reserved slots.
+__global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pairs,
+                                              const int64_t *__restrict__ scene_off,
+                                              const int64_t *__restrict__ rec_base,
+                                              const uint32_t *__restrict__ rec_key,
+                                              const ushort4 *__restrict__ rec_rect, int32_t T, int32_t nta,
+                                              const int64_t *__restrict__ counters,
+                                              const uint32_t *__restrict__ tstart, uint32_t *__restrict__ tcur,
+                                              uint32_t *__restrict__ ekey, uint32_t *__restrict__ eval) {
+  if (counters[1] != 0) return;  // over capacity: every range is empty, nothing is emitted
+  extern __shared__ uint32_t sm[];
+  uint32_t *cnt = sm;        // [T]
+  uint32_t *base = sm + T;   // [T]
   const int k = blockIdx.y;
+  for (int t = threadIdx.x; t < T; t += blockDim.x) cnt[t] = 0;
+  __syncthreads();
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int s = pairs[k].scene;
   const int64_t g0 = scene_off[s];
   const int64_t n = scene_off[s + 1] - g0;
-  if (j >= n) return;
-  const int64_t r = rec_base[k] + j;
-  const uint32_t cnt = rec_cnt[r];
-  if (cnt == 0) return;
-  const int64_t off = rec_off[r];
-  if (off + (int64_t)cnt > cap) return;  // over capacity: reported through the counters
-  const ushort4 rc = rec_rect[r];
-  const uint32_t key = rec_key[r];
-  const uint32_t gid = (uint32_t)(g0 + j);
-  const uint32_t tbase = (uint32_t)k * (uint32_t)T;
-  int64_t o = off;
+  ushort4 rc = make_ushort4(0, 0, 0, 0);
+  uint32_t key = 0;
+  if (j < n) {
+    const int64_t r = rec_base[k] + j;
+    rc = rec_rect[r];
+    key = rec_key[r];
+  }
   for (int tv = rc.z; tv < rc.z + rc.w; ++tv) {
     int tu = rc.x;
     for (int c = 0; c < rc.y; ++c) {
-      khi[o] = tbase + (uint32_t)(tv * nta + tu);
-      klo[o] = key;
-      val[o] = gid;
-      ++o;
+      atomicAdd(&cnt[tv * nta + tu], 1u);
+      if (++tu == nta) tu = 0;
+    }
+  }
+  __syncthreads();
+  const size_t tb = (size_t)k * T;
+  for (int t = threadIdx.x; t < T; t += blockDim.x) {
+    const uint32_t c = cnt[t];
+    if (c) base[t] = tstart[tb + t] + atomicAdd(&tcur[tb + t], c);
+    cnt[t] = 0;
+  }
+  __syncthreads();
+  const uint32_t gid = (uint32_t)(g0 + j);
+  for (int tv = rc.z; tv < rc.z + rc.w; ++tv) {
+    int tu = rc.x;
+    for (int c = 0; c < rc.y; ++c) {
+      const int t = tv * nta + tu;
+      const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
+      ekey[pos] = key;
+      eval[pos] = gid;
       if (++tu == nta) tu = 0;
     }
   }
 }
 
-// Number of valid splats; zero when the count overflowed the capacity, so an
-// over-full workspace is never read past what emission wrote.
-__device__ __forceinline__ int64_t splat_n(const int64_t *counters, int64_t cap) {
-  return counters[1] != 0 ? 0 : min(counters[0], cap);
+// ---------------------------------------------------------------------------
+// Workgroup-level pieces of the tile sort (kTileSortThreads = 512 threads).
+// ---------------------------------------------------------------------------
+struct SortLds {
+  uint32_t *ak, *av, *bk, *bv;    // ping-pong buffers [chunk]
+  uint32_t *hist, *run;           // [256] each
+  uint32_t *wcnt, *wpre;          // [8][256] each
+};
+
+__device__ __forceinline__ SortLds sort_lds_of(uint32_t *sm, int chunk) {
+  SortLds L;
+  L.ak = sm;
+  L.av = sm + chunk;
+  L.bk = sm + 2 * chunk;
+  L.bv = sm + 3 * chunk;
+  L.hist = sm + 4 * chunk;
+  L.run = L.hist + 256;
+  L.wcnt = L.run + 256;
+  L.wpre = L.wcnt + 8 * 256;
+  return L;
 }
 
-__device__ __forceinline__ uint32_t digit_of(uint32_t hi, uint32_t lo, int pass) {
-  return pass < 4 ? (lo >> (8 * pass)) & 255u : (hi >> (8 * (pass - 4))) & 255u;
-}
-
-__global__ void k_radix_hist(const uint32_t *__restrict__ khi, const uint32_t *__restrict__ klo,
-                             const int64_t *__restrict__ counters, int64_t cap, int pass, int nblk,
-                             uint32_t *__restrict__ hist) {
-  __shared__ uint32_t cnt[256];
-  const int tid = threadIdx.x;
-  cnt[tid] = 0;
+// One stable counting pass on the byte at `shift` of the keys: src -> dst.
+__device__ void lsd_pass(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv, int n, int shift,
+                         const SortLds &L) {
+  constexpr int NT = kTileSortThreads;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid < 256) L.hist[tid] = 0;
   __syncthreads();
-  const int64_t n = splat_n(counters, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll
-  for (int it = 0; it < kSortItems; ++it) {
-    const int64_t i = base + it * kSortThreads + tid;
-    if (i < n) atomicAdd(&cnt[digit_of(khi[i], klo[i], pass)], 1u);
+  for (int i = tid; i < n; i += NT) atomicAdd(&L.hist[(sk[i] >> shift) & 255u], 1u);
+  __syncthreads();
+  // exclusive scan of the 256 digit counts (Hillis-Steele in LDS)
+  uint32_t x = tid < 256 ? L.hist[tid] : 0u;
+  if (tid < 256) L.run[tid] = x;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    uint32_t y = 0;
+    if (tid < 256 && tid >= off) y = L.run[tid - off];
+    __syncthreads();
+    if (tid < 256) L.run[tid] += y;
+    __syncthreads();
   }
+  if (tid < 256) L.run[tid] -= x;
   __syncthreads();
-  hist[(int64_t)tid * nblk + blockIdx.x] = cnt[tid];
-}
-
-// Stable scatter.  Items are visited in index order (iteration-major, then
-// wave, then lane); each wave finds the lanes sharing its digit with eight
-// ballots, and per-digit running offsets carry order across waves/iterations.
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint32_t *__restrict__ khi_in, const uint32_t *__restrict__ klo_in, const uint32_t *__restrict__ val_in,
-    uint32_t *__restrict__ khi_out, uint32_t *__restrict__ klo_out, uint32_t *__restrict__ val_out,
-    const int64_t *__restrict__ counters, int64_t cap, int pass, int nblk, const uint32_t *__restrict__ hist_scan) {
-  __shared__ uint32_t goff[256];
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[4][256];
-  __shared__ uint32_t wpre[4][256];
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6;
-  const int lane = tid & 63;
-  goff[tid] = hist_scan[(int64_t)tid * nblk + blockIdx.x];
-  run[tid] = 0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
-  __syncthreads();
-  const int64_t n = splat_n(counters, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int it = 0; it < kSortItems; ++it) {
-    const int64_t i = base + it * kSortThreads + tid;
+  for (int b0 = 0; b0 < n; b0 += NT) {
+    const int i = b0 + tid;
     const bool valid = i < n;
-    uint32_t hi = 0, lo = 0, vv = 0, d = 0;
+    uint32_t key = 0, val = 0, d = 0;
     if (valid) {
-      hi = khi_in[i];
-      lo = klo_in[i];
-      vv = val_in[i];
-      d = digit_of(hi, lo, pass);
+      key = sk[i];
+      val = sv[i];
+      d = (key >> shift) & 255u;
     }
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -116,81 +136,185 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       peers &= bit ? m : ~m;
     }
     const uint32_t rank = __popcll(peers & lt_mask);
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+    if (valid && rank == 0) L.wcnt[wave * 256 + d] = __popcll(peers);
     __syncthreads();
-    {
-      uint32_t r = run[tid];
+    if (tid < 256) {
+      uint32_t r = L.run[tid];
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        wpre[w][tid] = r;
-        r += wcnt[w][tid];
-        wcnt[w][tid] = 0;
+      for (int w = 0; w < NT / 64; ++w) {
+        L.wpre[w * 256 + tid] = r;
+        r += L.wcnt[w * 256 + tid];
+        L.wcnt[w * 256 + tid] = 0;
       }
-      run[tid] = r;
+      L.run[tid] = r;
     }
     __syncthreads();
     if (valid) {
-      const uint32_t pos = goff[d] + wpre[wave][d] + rank;
-      khi_out[pos] = hi;
-      klo_out[pos] = lo;
-      val_out[pos] = vv;
+      const uint32_t pos = L.wpre[wave * 256 + d] + rank;
+      dk[pos] = key;
+      dv[pos] = val;
+    }
+  }
+  __syncthreads();
+}
+
+// Sort n <= chunk entries held in (L.ak, L.av) by (key, value); result in place.
+__device__ void lds_sort(int n, const SortLds &L) {
+  lsd_pass(L.ak, L.av, L.bk, L.bv, n, 0, L);
+  lsd_pass(L.bk, L.bv, L.ak, L.av, n, 8, L);
+  lsd_pass(L.ak, L.av, L.bk, L.bv, n, 16, L);
+  lsd_pass(L.bk, L.bv, L.ak, L.av, n, 24, L);
+  // equal keys: order by Gaussian index (runs are short; the run's first
+  // element's thread insertion-sorts it)
+  for (int i = threadIdx.x; i < n; i += kTileSortThreads) {
+    const uint32_t k0 = L.ak[i];
+    if ((i > 0 && L.ak[i - 1] == k0) || i + 1 >= n || L.ak[i + 1] != k0) continue;
+    int e = i + 1;
+    while (e < n && L.ak[e] == k0) ++e;
+    for (int a = i + 1; a < e; ++a) {
+      const uint32_t v = L.av[a];
+      int b = a - 1;
+      while (b >= i && L.av[b] > v) {
+        L.av[b + 1] = L.av[b];
+        --b;
+      }
+      L.av[b + 1] = v;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool kv_less(uint32_t ka, uint32_t va, uint32_t kb, uint32_t vb) {
+  return ka < kb || (ka == kb && va < vb);
+}
+
+// Merge sorted runs A[0, la) and B[0, lb) (given as key/value arrays) into
+// out[0, la + lb); the workgroup splits the output by merge-path diagonals.
+__device__ void merge_runs(const uint32_t *Ak, const uint32_t *Av, int la, const uint32_t *Bk, const uint32_t *Bv,
+                           int lb, uint32_t *ok, uint32_t *ov) {
+  const int total = la + lb;
+  const int per = (total + kTileSortThreads - 1) / kTileSortThreads;
+  const int d0 = min(total, (int)threadIdx.x * per);
+  const int d1 = min(total, d0 + per);
+  if (d0 >= d1) return;
+  // number of A elements among the d0 smallest
+  int lo = max(0, d0 - lb), hi = min(d0, la);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;     // take mid from A, d0 - mid from B
+    const int jb = d0 - mid - 1;
+    if (jb < 0 || kv_less(Bk[jb], Bv[jb], Ak[mid], Av[mid]))
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  int i = lo, j = d0 - lo;
+  for (int d = d0; d < d1; ++d) {
+    const bool takeA = (j >= lb) || (i < la && kv_less(Ak[i], Av[i], Bk[j], Bv[j]));
+    if (takeA) {
+      ok[d] = Ak[i];
+      ov[d] = Av[i];
+      ++i;
+    } else {
+      ok[d] = Bk[j];
+      ov[d] = Bv[j];
+      ++j;
     }
   }
 }
 
-// computeGridRange: [start, end) of each global tile in the sorted array.
-__global__ void k_ranges(const uint32_t *__restrict__ khi, const int64_t *__restrict__ counters, int64_t cap,
-                         uint32_t *__restrict__ tstart, uint32_t *__restrict__ tend) {
-  const int64_t n = splat_n(counters, cap);
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) {
-    const uint32_t t = khi[i];
-    if (i == 0 || khi[i - 1] != t) tstart[t] = (uint32_t)i;
-    if (i == n - 1 || khi[i + 1] != t) tend[t] = (uint32_t)(i + 1);
+// a4: sort every tile's bucket; writes the sorted depth keys and Gaussian ids.
+__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint32_t *__restrict__ tstart,
+                                                                const uint32_t *__restrict__ tend, int chunk,
+                                                                const uint32_t *__restrict__ ekey,
+                                                                const uint32_t *__restrict__ eval,
+                                                                uint32_t *__restrict__ klo, uint32_t *__restrict__ val,
+                                                                uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval) {
+  extern __shared__ uint32_t sm[];
+  const SortLds L = sort_lds_of(sm, chunk);
+  const int gt = blockIdx.x;
+  const uint32_t s0 = tstart[gt];
+  const int n = (int)(tend[gt] - s0);
+  if (n <= 0) return;
+  for (int i = threadIdx.x; i < 8 * 256; i += kTileSortThreads) L.wcnt[i] = 0;
+  const int nruns = (n + chunk - 1) / chunk;
+  int passes = 0;
+  while ((1 << passes) < nruns) ++passes;
+  // runs go to the buffer from which an even number of merge passes ends in (klo, val)
+  uint32_t *rk = (passes & 1) ? tkey : klo, *rv = (passes & 1) ? tval : val;
+  uint32_t *ok_ = (passes & 1) ? klo : tkey, *ov_ = (passes & 1) ? val : tval;
+  for (int c = 0; c < nruns; ++c) {
+    const int b = c * chunk;
+    const int m = min(chunk, n - b);
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += kTileSortThreads) {
+      L.ak[i] = ekey[s0 + b + i];
+      L.av[i] = eval[s0 + b + i];
+    }
+    __syncthreads();
+    lds_sort(m, L);
+    for (int i = threadIdx.x; i < m; i += kTileSortThreads) {
+      rk[s0 + b + i] = L.ak[i];
+      rv[s0 + b + i] = L.av[i];
+    }
   }
+  for (int w = chunk; w < n; w *= 2) {
+    __syncthreads();   // the previous pass's (or the runs') writes are visible to the workgroup
+    __threadfence_block();
+    for (int a0 = 0; a0 < n; a0 += 2 * w) {
+      const int la = min(w, n - a0);
+      const int lb = max(0, min(w, n - a0 - la));
+      merge_runs(rk + s0 + a0, rv + s0 + a0, la, rk + s0 + a0 + la, rv + s0 + a0 + la, lb, ok_ + s0 + a0,
+                 ov_ + s0 + a0);
+    }
+    uint32_t *t1 = rk, *t2 = rv;
+    rk = ok_; rv = ov_;
+    ok_ = t1; ov_ = t2;
+  }
+}
+
+static int g_sort_chunk = 0;
+static size_t g_sort_lds = 0;
+
+size_t max_lds_per_block() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) return 65536;
+  return (size_t)v;
+}
+
+static void choose_sort_chunk() {
+  if (g_sort_chunk) return;
+  const size_t fixed = (2 * 256 + 2 * 8 * 256) * 4;
+  size_t lds = max_lds_per_block();
+  if (lds > 160 * 1024) lds = 160 * 1024;
+  int chunk = (int)((lds - fixed) / 16);
+  chunk = (chunk / kTileSortThreads) * kTileSortThreads;
+  if (chunk > 8192) chunk = 8192;
+  if (chunk < kTileSortThreads) chunk = kTileSortThreads;
+  g_sort_lds = fixed + (size_t)16 * chunk;
+  if (g_sort_lds > 65536)
+    (void)hipFuncSetAttribute((const void *)k_tile_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g_sort_lds);
+  g_sort_chunk = chunk;
 }
 
 hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, hipStream_t s) {
   const int64_t PT = (int64_t)p->n_pairs * lay.T;
-  uint32_t *tstart = (uint32_t *)(ws + lay.tile_start);
-  uint32_t *tend = (uint32_t *)(ws + lay.tile_end);
-  hipError_t e = fill<uint32_t>(tstart, 0u, PT, s);
-  if (e != hipSuccess) return e;
-  e = fill<uint32_t>(tend, 0u, PT, s);
-  if (e != hipSuccess) return e;
-  if (lay.n_records == 0 || lay.cap == 0) return hipGetLastError();
+  if (lay.n_records == 0 || PT == 0) return hipSuccess;
   const int64_t *counters = (const int64_t *)(ws + lay.counters);
-  uint32_t *khi[2] = {(uint32_t *)(ws + lay.khi[0]), (uint32_t *)(ws + lay.khi[1])};
-  uint32_t *klo[2] = {(uint32_t *)(ws + lay.klo[0]), (uint32_t *)(ws + lay.klo[1])};
-  uint32_t *val[2] = {(uint32_t *)(ws + lay.val[0]), (uint32_t *)(ws + lay.val[1])};
+  const uint32_t *tstart = (const uint32_t *)(ws + lay.tile_start);
+  const uint32_t *tend = (const uint32_t *)(ws + lay.tile_end);
   {
     dim3 grid((unsigned)((lay.max_scene + 255) / 256), (unsigned)p->n_pairs);
-    hipLaunchKernelGGL(k_emit, grid, dim3(256), 0, s, p->pairs, p->scene_offsets_dev,
+    hipLaunchKernelGGL(k_emit, grid, dim3(256), (size_t)lay.T * 8, s, p->pairs, p->scene_offsets_dev,
                        (const int64_t *)(ws + lay.rec_base), (const uint32_t *)(ws + lay.rec_key),
-                       (const ushort4 *)(ws + lay.rec_rect), (const uint32_t *)(ws + lay.rec_cnt),
-                       (const int64_t *)(ws + lay.rec_off), lay.T, lay.nta, lay.cap, counters, khi[0], klo[0],
-                       val[0]);
+                       (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, counters, tstart,
+                       (uint32_t *)(ws + lay.tile_cur), (uint32_t *)(ws + lay.ekey), (uint32_t *)(ws + lay.eval));
   }
-  uint32_t *hist = (uint32_t *)(ws + lay.hist);
-  uint32_t *hist_scan = (uint32_t *)(ws + lay.hist_scan);
-  uint32_t *hist_tmp = (uint32_t *)(ws + lay.hist_tmp);
-  const int nblk = lay.n_sort_blocks;
-  int cur = 0;
-  for (int pass = 0; pass < lay.sort_passes; ++pass) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, s, khi[cur], klo[cur], counters, lay.cap,
-                       pass, nblk, hist);
-    e = scan_u32_to_u32(hist, (int64_t)256 * nblk, hist_scan, hist_tmp, lay.n_hist_blocks, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortThreads), 0, s, khi[cur], klo[cur], val[cur],
-                       khi[cur ^ 1], klo[cur ^ 1], val[cur ^ 1], counters, lay.cap, pass, nblk, hist_scan);
-    cur ^= 1;
-  }
-  {
-    int64_t blocks = (lay.cap + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, s, khi[cur], counters, lay.cap, tstart, tend);
-  }
+  choose_sort_chunk();
+  hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)PT), dim3(kTileSortThreads), g_sort_lds, s, tstart, tend,
+                     g_sort_chunk, (const uint32_t *)(ws + lay.ekey), (const uint32_t *)(ws + lay.eval),
+                     (uint32_t *)(ws + lay.klo), (uint32_t *)(ws + lay.val), (uint32_t *)(ws + lay.tkey),
+                     (uint32_t *)(ws + lay.tval));
   return hipGetLastError();
 }
 

@@ -50,7 +50,6 @@ def gpu_lists(prob: Problem):
     cnt = prob.view(lay.counters, torch.int64, 4).cpu().numpy()
     n = int(cnt[0])
     PT = prob.n_pairs * lay.n_tiles
-    khi = u32(prob.view(lay.sorted_khi, torch.int32, n))
     klo = u32(prob.view(lay.sorted_klo, torch.int32, n))
     val = u32(prob.view(lay.sorted_val, torch.int32, n))
     ts = u32(prob.view(lay.tile_start, torch.int32, PT)).astype(np.int64)
@@ -58,7 +57,7 @@ def gpu_lists(prob: Problem):
     base = prob.view(lay.rec_base, torch.int64, prob.n_pairs + 1).cpu().numpy()
     rkey = u32(prob.view(lay.rec_key, torch.int32, int(lay.n_records)))
     rrect = prob.view(lay.rec_rect, torch.int16, int(lay.n_records) * 4).cpu().numpy().view(np.uint16)
-    return dict(n=n, overflow=int(cnt[1]), khi=khi, klo=klo, val=val, ts=ts, te=te, T=lay.n_tiles, base=base,
+    return dict(n=n, overflow=int(cnt[1]), klo=klo, val=val, ts=ts, te=te, T=lay.n_tiles, base=base,
                 rec_key=rkey, rec_rect=rrect.reshape(-1, 4).astype(np.int64))
 
 

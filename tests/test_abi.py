@@ -90,7 +90,7 @@ def test_workspace_size_and_layout():
     lay = GsrfLayout()
     assert L.gsrf_layout_of(ctypes.byref(p), ctypes.byref(lay)) == 0
     assert lay.n_records == 20 and lay.n_tiles == 23 * 6 and lay.n_tiles_az == 23
-    offs = [lay.rec_key, lay.rec_rect, lay.rec_base, lay.counters, lay.sorted_khi, lay.sorted_klo, lay.sorted_val,
+    offs = [lay.rec_key, lay.rec_rect, lay.rec_base, lay.counters, lay.sorted_klo, lay.sorted_val,
             lay.tile_start, lay.tile_end]
     assert all(o % 256 == 0 and o < n.value for o in offs)
     # bigger capacity, bigger workspace
