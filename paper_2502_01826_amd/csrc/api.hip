@@ -108,10 +108,10 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.rec_key = take((size_t)R * 4);
   L.rec_rect = take((size_t)R * 8);
   L.counters = take(4 * 8);
-  L.tile_cnt = take((size_t)PT * 4);
+  L.tile_cnt = take((size_t)PT * kSub * 4);
   L.tile_start = take((size_t)PT * 4);
   L.tile_end = take((size_t)PT * 4);
-  L.tile_cur = take((size_t)PT * 4);
+  L.tile_cur = take((size_t)PT * kSub * 4);
   L.ekey = take((size_t)L.cap * 4);
   L.eval = take((size_t)L.cap * 4);
   L.klo = take((size_t)L.cap * 4);

@@ -22,8 +22,54 @@ constexpr int kPrep = 16;
 // Binning: splats are emitted into per-tile buckets (key, Gaussian) and each
 // tile's bucket is sorted by one workgroup of kTileSortThreads threads, in LDS
 // chunks of at most `sort_chunk` entries (merged in global memory if longer).
-constexpr int kTileSortThreads = 512;
+constexpr int kTileSortThreads = 1024;
 constexpr int kMaxTiles = 8192;           // per pair; LDS histograms in project/emit
+constexpr int kRecPerThread = 1;          // records per thread in project/emit
+constexpr int kRecPerBlock = 256 * kRecPerThread;
+// Each tile's bucket is split into kSub contiguous sub-buckets; workgroup b of
+// project/emit counts into and reserves from sub-bucket (b % kSub), which
+// divides the atomic traffic per counter by kSub.  Counters and cursors are
+// stored sub-major: [kSub][P * T].
+constexpr int kSub = 8;
+
+// Balanced expansion of the tile rectangles of a workgroup's records: the
+// rectangles' splat counts are scanned in LDS and every thread takes splats
+// s = tid, tid + 256, ..., locating the owning record by binary search.
+struct RectScan {
+  ushort4 rect[256];
+  uint32_t off[257];
+};
+
+__device__ __forceinline__ void rect_scan(RectScan &rs, ushort4 rc) {
+  const int tid = threadIdx.x;
+  const uint32_t c = (uint32_t)rc.y * rc.w;
+  rs.rect[tid] = rc;
+  rs.off[tid + 1] = c;
+  if (tid == 0) rs.off[0] = 0;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {
+    const uint32_t v = tid >= d ? rs.off[tid + 1 - d] : 0u;
+    __syncthreads();
+    rs.off[tid + 1] += v;
+    __syncthreads();
+  }
+}
+
+// splat s of the workgroup: owning record (thread slot) and its tile id
+__device__ __forceinline__ int rect_splat(const RectScan &rs, uint32_t s, int nta, int *tile) {
+  int lo = 0, hi = 255;
+  while (lo < hi) {                 // last record whose offset is <= s
+    const int mid = (lo + hi + 1) >> 1;
+    if (rs.off[mid] <= s) lo = mid; else hi = mid - 1;
+  }
+  const ushort4 rc = rs.rect[lo];
+  const uint32_t local = s - rs.off[lo];
+  const int tv = rc.z + (int)(local / rc.y);
+  int tu = rc.x + (int)(local % rc.y);
+  if (tu >= nta) tu -= nta;
+  *tile = tv * nta + tu;
+  return lo;
+}
 
 // Byte offsets of every workspace array plus derived sizes.
 struct Layout {

@@ -85,102 +85,111 @@ __global__ void k_rec_base(const gsrf_pair *__restrict__ pairs, const int64_t *_
 // and adds the counts to tile_cnt with one atomic per touched tile.
 // ---------------------------------------------------------------------------
 #pragma clang fp contract(off)
+// One record: depth key and rectangle (all FP64, operation order as documented above).
+__device__ __forceinline__ ushort4 project_record(const gsrf_pair &pr, const float *__restrict__ means,
+                                                  const float *__restrict__ log_scales, int64_t g,
+                                                  const gsrf_grid &grid, int32_t nta, uint32_t *key_out) {
+  const double ex = (double)means[3 * g + 0] - (double)pr.rx[0];
+  const double ey = (double)means[3 * g + 1] - (double)pr.rx[1];
+  const double ez = (double)means[3 * g + 2] - (double)pr.rx[2];
+  const double D2 = (ex * ex + ey * ey) + ez * ez;
+  *key_out = __float_as_uint((float)D2);
+  const double D = sqrt(D2);
+  const double lmax = fmax(fmax((double)log_scales[3 * g + 0], (double)log_scales[3 * g + 1]),
+                           (double)log_scales[3 * g + 2]);
+  const double Rb = 3.0 * exp(lmax);
+  const int n_az = grid.n_az, n_el = grid.n_el, tw = grid.tile_w, th = grid.tile_h;
+  const double el_lo = (double)grid.el_lo, el_hi = (double)grid.el_hi;
+  const double pi = 3.14159265358979323846;
+  if (D + Rb < (double)grid.r_rx * (1.0 - 1e-6)) return make_ushort4(0, 0, 0, 0);
+  const bool inside = D <= Rb * (1.0 + 1e-6);
+  long v_lo, v_hi, u_lo, u_hi;
+  bool full;
+  if (inside) {
+    v_lo = 0; v_hi = n_el - 1; full = true; u_lo = 0; u_hi = n_az - 1;
+  } else {
+    const double theta = asin(fmin(Rb / D, 1.0)) + kCapSlack;
+    const double bc = atan2(ez, sqrt(ex * ex + ey * ey));
+    const double lo = bc - theta, hi = bc + theta;
+    const double dbeta = (el_hi - el_lo) / n_el;
+    v_lo = (long)ceil((lo - el_lo) / dbeta - 0.5);
+    v_hi = (long)floor((hi - el_lo) / dbeta - 0.5);
+    if (v_lo < 0) v_lo = 0;
+    if (v_hi > n_el - 1) v_hi = n_el - 1;
+    full = (hi >= pi / 2) || (lo <= -pi / 2);
+    if (!full) {
+      const double dalpha = 2.0 * pi / n_az;
+      const double ac = atan2(ey, ex);
+      const double da = asin(fmin(sin(theta) / cos(bc), 1.0));
+      u_lo = (long)ceil((ac - da) / dalpha - 0.5);
+      u_hi = (long)floor((ac + da) / dalpha - 0.5);
+      if (u_hi - u_lo + 1 >= n_az) full = true;
+    }
+    if (full) { u_lo = 0; u_hi = n_az - 1; }
+  }
+  if (!((v_lo <= v_hi) && (full || u_hi >= u_lo))) return make_ushort4(0, 0, 0, 0);
+  if (u_lo < 0) { u_lo += n_az; u_hi += n_az; }
+  long tu0 = u_lo / tw;
+  long ntu = (u_hi < n_az) ? (u_hi / tw - tu0 + 1) : ((nta - tu0) + (u_hi - n_az) / tw + 1);
+  if (ntu >= nta) { tu0 = 0; ntu = nta; }
+  const long tv0 = v_lo / th;
+  const long ntv = v_hi / th - tv0 + 1;
+  return make_ushort4((unsigned short)tu0, (unsigned short)ntu, (unsigned short)tv0, (unsigned short)ntv);
+}
+
+// Workgroup = 256 consecutive records of one pair; per-tile counts gathered
+// in LDS by a balanced expansion of the rectangles, then one atomic per
+// touched tile on the workgroup's sub-bucket counter.
 __global__ __launch_bounds__(256) void k_project(const gsrf_pair *__restrict__ pairs,
                                                  const int64_t *__restrict__ scene_off,
                                                  const int64_t *__restrict__ rec_base, const float *__restrict__ means,
                                                  const float *__restrict__ log_scales, gsrf_grid grid, int32_t nta,
-                                                 int32_t T, uint32_t *__restrict__ rec_key,
+                                                 int32_t T, int64_t PT, uint32_t *__restrict__ rec_key,
                                                  ushort4 *__restrict__ rec_rect, uint32_t *__restrict__ tile_cnt) {
   extern __shared__ uint32_t hist[];   // [T]
+  __shared__ RectScan rs;
   const int k = blockIdx.y;
   for (int t = threadIdx.x; t < T; t += blockDim.x) hist[t] = 0;
-  __syncthreads();
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const gsrf_pair pr = pairs[k];
   const int64_t g0 = scene_off[pr.scene];
   const int64_t n = scene_off[pr.scene + 1] - g0;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  ushort4 rc = make_ushort4(0, 0, 0, 0);
   if (j < n) {
-    const int64_t g = g0 + j;
     const int64_t r = rec_base[k] + j;
-    const double ex = (double)means[3 * g + 0] - (double)pr.rx[0];
-    const double ey = (double)means[3 * g + 1] - (double)pr.rx[1];
-    const double ez = (double)means[3 * g + 2] - (double)pr.rx[2];
-    const double D2 = (ex * ex + ey * ey) + ez * ez;
-    rec_key[r] = __float_as_uint((float)D2);
-    const double D = sqrt(D2);
-    const double lmax = fmax(fmax((double)log_scales[3 * g + 0], (double)log_scales[3 * g + 1]),
-                             (double)log_scales[3 * g + 2]);
-    const double Rb = 3.0 * exp(lmax);
-    const int n_az = grid.n_az, n_el = grid.n_el, tw = grid.tile_w, th = grid.tile_h;
-    const double el_lo = (double)grid.el_lo, el_hi = (double)grid.el_hi;
-    const double pi = 3.14159265358979323846;
-    ushort4 rect = make_ushort4(0, 0, 0, 0);
-    bool visible = !(D + Rb < (double)grid.r_rx * (1.0 - 1e-6));
-    if (visible) {
-      const bool inside = D <= Rb * (1.0 + 1e-6);
-      long v_lo, v_hi, u_lo, u_hi;
-      bool full;
-      if (inside) {
-        v_lo = 0; v_hi = n_el - 1; full = true; u_lo = 0; u_hi = n_az - 1;
-      } else {
-        const double theta = asin(fmin(Rb / D, 1.0)) + kCapSlack;
-        const double bc = atan2(ez, sqrt(ex * ex + ey * ey));
-        const double lo = bc - theta, hi = bc + theta;
-        const double dbeta = (el_hi - el_lo) / n_el;
-        v_lo = (long)ceil((lo - el_lo) / dbeta - 0.5);
-        v_hi = (long)floor((hi - el_lo) / dbeta - 0.5);
-        if (v_lo < 0) v_lo = 0;
-        if (v_hi > n_el - 1) v_hi = n_el - 1;
-        full = (hi >= pi / 2) || (lo <= -pi / 2);
-        if (!full) {
-          const double dalpha = 2.0 * pi / n_az;
-          const double ac = atan2(ey, ex);
-          const double da = asin(fmin(sin(theta) / cos(bc), 1.0));
-          u_lo = (long)ceil((ac - da) / dalpha - 0.5);
-          u_hi = (long)floor((ac + da) / dalpha - 0.5);
-          if (u_hi - u_lo + 1 >= n_az) full = true;
-        }
-        if (full) { u_lo = 0; u_hi = n_az - 1; }
-      }
-      visible = (v_lo <= v_hi) && (full || u_hi >= u_lo);
-      if (visible) {
-        if (u_lo < 0) { u_lo += n_az; u_hi += n_az; }
-        long tu0 = u_lo / tw;
-        long ntu = (u_hi < n_az) ? (u_hi / tw - tu0 + 1) : ((nta - tu0) + (u_hi - n_az) / tw + 1);
-        if (ntu >= nta) { tu0 = 0; ntu = nta; }
-        const long tv0 = v_lo / th;
-        const long ntv = v_hi / th - tv0 + 1;
-        rect = make_ushort4((unsigned short)tu0, (unsigned short)ntu, (unsigned short)tv0, (unsigned short)ntv);
-        for (int tv = (int)tv0; tv < tv0 + ntv; ++tv) {
-          int tu = (int)tu0;
-          for (int c = 0; c < ntu; ++c) {
-            atomicAdd(&hist[tv * nta + tu], 1u);
-            if (++tu == nta) tu = 0;
-          }
-        }
-      }
-    }
-    rec_rect[r] = rect;
+    uint32_t key;
+    rc = project_record(pr, means, log_scales, g0 + j, grid, nta, &key);
+    rec_key[r] = key;
+    rec_rect[r] = rc;
+  }
+  rect_scan(rs, rc);
+  const uint32_t total = rs.off[256];
+  for (uint32_t sp = threadIdx.x; sp < total; sp += 256) {
+    int t;
+    rect_splat(rs, sp, nta, &t);
+    atomicAdd(&hist[t], 1u);
   }
   __syncthreads();
-  uint32_t *dst = tile_cnt + (size_t)k * T;
+  uint32_t *dst = tile_cnt + (size_t)(blockIdx.x % kSub) * PT + (size_t)k * T;
   for (int t = threadIdx.x; t < T; t += blockDim.x)
     if (hist[t]) atomicAdd(dst + t, hist[t]);
 }
 #pragma clang fp contract(on)
 
-// Exclusive scan of the per-tile counts of all pairs (one workgroup): tile
-// ranges, the splat total and the overflow flag.  When the total exceeds the
-// capacity every range is left empty, so nothing downstream reads past it.
+// Exclusive scan of the per-(tile, sub-bucket) counts of all pairs (one
+// workgroup): tile ranges, sub-bucket starts (emission cursors), the splat
+// total and the overflow flag.  When the total exceeds the capacity every
+// range is left empty, so nothing downstream reads past it.
 __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t *__restrict__ tile_cnt, int64_t PT, int64_t cap,
                                                     uint32_t *__restrict__ tstart, uint32_t *__restrict__ tend,
                                                     uint32_t *__restrict__ tcur, int64_t *__restrict__ counters) {
   __shared__ int64_t sh[1024];
   const int tid = threadIdx.x;
-  const int64_t per = (PT + 1023) / 1024;
+  const int64_t per = (PT + 1023) / 1024;       // tiles per thread
   const int64_t lo = tid * per, hi = min(PT, lo + per);
   int64_t local = 0;
-  for (int64_t t = lo; t < hi; ++t) local += tile_cnt[t];
+  for (int64_t t = lo; t < hi; ++t)
+    for (int b = 0; b < kSub; ++b) local += tile_cnt[(size_t)b * PT + t];
   sh[tid] = local;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -193,11 +202,12 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t *__restrict__
   const bool over = total > cap;
   int64_t run = sh[tid] - local;
   for (int64_t t = lo; t < hi; ++t) {
-    const int64_t c = tile_cnt[t];
     tstart[t] = over ? 0u : (uint32_t)run;
-    tend[t] = over ? 0u : (uint32_t)(run + c);
-    tcur[t] = 0u;
-    run += c;
+    for (int b = 0; b < kSub; ++b) {
+      tcur[(size_t)b * PT + t] = over ? 0u : (uint32_t)run;   // emission cursor of the sub-bucket
+      run += tile_cnt[(size_t)b * PT + t];
+    }
+    tend[t] = over ? 0u : (uint32_t)run;
   }
   if (tid == 0) {
     counters[0] = total;
@@ -210,7 +220,7 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
   int64_t *rec_base = (int64_t *)(ws + lay.rec_base);
   const int64_t PT = (int64_t)p->n_pairs * lay.T;
   uint32_t *tile_cnt = (uint32_t *)(ws + lay.tile_cnt);
-  hipError_t e = fill<uint32_t>(tile_cnt, 0u, PT, s);
+  hipError_t e = fill<uint32_t>(tile_cnt, 0u, PT * kSub, s);
   if (e != hipSuccess) return e;
   if (p->n_gauss > 0) {
     hipLaunchKernelGGL(k_activate, dim3((unsigned)((p->n_gauss + 255) / 256)), dim3(256), 0, s, p->means,
@@ -223,7 +233,7 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
   if (lay.n_records > 0) {
     dim3 grid((unsigned)((lay.max_scene + 255) / 256), (unsigned)p->n_pairs);
     hipLaunchKernelGGL(k_project, grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev, rec_base,
-                       p->means, p->log_scales, p->grid, lay.nta, lay.T, (uint32_t *)(ws + lay.rec_key),
+                       p->means, p->log_scales, p->grid, lay.nta, lay.T, PT, (uint32_t *)(ws + lay.rec_key),
                        (ushort4 *)(ws + lay.rec_rect), tile_cnt);
   }
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, tile_cnt, PT, lay.cap, (uint32_t *)(ws + lay.tile_start),

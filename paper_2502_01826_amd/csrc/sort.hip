@@ -18,27 +18,28 @@
 namespace gsrf {
 
 // a3: one splat per covered tile.  The workgroup (256 records of one pair)
-// counts its splats per tile in LDS, reserves each tile's share of the bucket
-// with one global atomic, then writes (key, Gaussian) at its reserved slots.
+// counts its splats per tile in LDS, reserves each tile's share with one
+// global atomic on its sub-bucket's cursor, then writes (key, Gaussian) at its
+// reserved slots.
 __global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pairs,
                                               const int64_t *__restrict__ scene_off,
                                               const int64_t *__restrict__ rec_base,
                                               const uint32_t *__restrict__ rec_key,
-                                              const ushort4 *__restrict__ rec_rect, int32_t T, int32_t nta,
-                                              const int64_t *__restrict__ counters,
-                                              const uint32_t *__restrict__ tstart, uint32_t *__restrict__ tcur,
+                                              const ushort4 *__restrict__ rec_rect, int32_t T, int32_t nta, int64_t PT,
+                                              const int64_t *__restrict__ counters, uint32_t *__restrict__ tcur,
                                               uint32_t *__restrict__ ekey, uint32_t *__restrict__ eval) {
   if (counters[1] != 0) return;  // over capacity: every range is empty, nothing is emitted
   extern __shared__ uint32_t sm[];
   uint32_t *cnt = sm;        // [T]
   uint32_t *base = sm + T;   // [T]
+  __shared__ RectScan rs;
+  __shared__ uint32_t keys[256];
   const int k = blockIdx.y;
   for (int t = threadIdx.x; t < T; t += blockDim.x) cnt[t] = 0;
-  __syncthreads();
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int s = pairs[k].scene;
   const int64_t g0 = scene_off[s];
   const int64_t n = scene_off[s + 1] - g0;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   ushort4 rc = make_ushort4(0, 0, 0, 0);
   uint32_t key = 0;
   if (j < n) {
@@ -46,41 +47,42 @@ __global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pair
     rc = rec_rect[r];
     key = rec_key[r];
   }
-  for (int tv = rc.z; tv < rc.z + rc.w; ++tv) {
-    int tu = rc.x;
-    for (int c = 0; c < rc.y; ++c) {
-      atomicAdd(&cnt[tv * nta + tu], 1u);
-      if (++tu == nta) tu = 0;
-    }
+  keys[threadIdx.x] = key;
+  rect_scan(rs, rc);
+  const uint32_t total = rs.off[256];
+  for (uint32_t sp = threadIdx.x; sp < total; sp += 256) {
+    int t;
+    rect_splat(rs, sp, nta, &t);
+    atomicAdd(&cnt[t], 1u);
   }
   __syncthreads();
-  const size_t tb = (size_t)k * T;
+  // reserve this workgroup's share of each touched tile in sub-bucket b % kSub
+  uint32_t *cur = tcur + (size_t)(blockIdx.x % kSub) * PT + (size_t)k * T;
   for (int t = threadIdx.x; t < T; t += blockDim.x) {
     const uint32_t c = cnt[t];
-    if (c) base[t] = tstart[tb + t] + atomicAdd(&tcur[tb + t], c);
+    if (c) base[t] = atomicAdd(cur + t, c);
     cnt[t] = 0;
   }
   __syncthreads();
-  const uint32_t gid = (uint32_t)(g0 + j);
-  for (int tv = rc.z; tv < rc.z + rc.w; ++tv) {
-    int tu = rc.x;
-    for (int c = 0; c < rc.y; ++c) {
-      const int t = tv * nta + tu;
-      const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
-      ekey[pos] = key;
-      eval[pos] = gid;
-      if (++tu == nta) tu = 0;
-    }
+  const uint32_t gbase = (uint32_t)(g0 + (int64_t)blockIdx.x * 256);
+  for (uint32_t sp = threadIdx.x; sp < total; sp += 256) {
+    int t;
+    const int slot = rect_splat(rs, sp, nta, &t);
+    const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
+    ekey[pos] = keys[slot];
+    eval[pos] = gbase + (uint32_t)slot;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Workgroup-level pieces of the tile sort (kTileSortThreads = 512 threads).
+// Workgroup-level pieces of the tile sort (kTileSortThreads threads).
 // ---------------------------------------------------------------------------
+constexpr int kSortWaves = kTileSortThreads / 64;
+
 struct SortLds {
   uint32_t *ak, *av, *bk, *bv;    // ping-pong buffers [chunk]
   uint32_t *hist, *run;           // [256] each
-  uint32_t *wcnt, *wpre;          // [8][256] each
+  uint32_t *wcnt, *wpre;          // [kSortWaves][256] each
 };
 
 __device__ __forceinline__ SortLds sort_lds_of(uint32_t *sm, int chunk) {
@@ -92,7 +94,7 @@ __device__ __forceinline__ SortLds sort_lds_of(uint32_t *sm, int chunk) {
   L.hist = sm + 4 * chunk;
   L.run = L.hist + 256;
   L.wcnt = L.run + 256;
-  L.wpre = L.wcnt + 8 * 256;
+  L.wpre = L.wcnt + kSortWaves * 256;
   return L;
 }
 
@@ -105,18 +107,23 @@ __device__ void lsd_pass(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, u
   __syncthreads();
   for (int i = tid; i < n; i += NT) atomicAdd(&L.hist[(sk[i] >> shift) & 255u], 1u);
   __syncthreads();
-  // exclusive scan of the 256 digit counts (Hillis-Steele in LDS)
-  uint32_t x = tid < 256 ? L.hist[tid] : 0u;
-  if (tid < 256) L.run[tid] = x;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    uint32_t y = 0;
-    if (tid < 256 && tid >= off) y = L.run[tid - off];
-    __syncthreads();
-    if (tid < 256) L.run[tid] += y;
-    __syncthreads();
+  // exclusive scan of the 256 digit counts by the first wave (4 bins per lane)
+  if (wave == 0) {
+    const uint32_t a0 = L.hist[4 * lane], a1 = L.hist[4 * lane + 1], a2 = L.hist[4 * lane + 2],
+                   a3 = L.hist[4 * lane + 3];
+    const uint32_t sum = a0 + a1 + a2 + a3;
+    uint32_t inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += y;
+    }
+    const uint32_t ex = inc - sum;
+    L.run[4 * lane] = ex;
+    L.run[4 * lane + 1] = ex + a0;
+    L.run[4 * lane + 2] = ex + a0 + a1;
+    L.run[4 * lane + 3] = ex + a0 + a1 + a2;
   }
-  if (tid < 256) L.run[tid] -= x;
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int b0 = 0; b0 < n; b0 += NT) {
@@ -141,7 +148,7 @@ __device__ void lsd_pass(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, u
     if (tid < 256) {
       uint32_t r = L.run[tid];
 #pragma unroll
-      for (int w = 0; w < NT / 64; ++w) {
+      for (int w = 0; w < kSortWaves; ++w) {
         L.wpre[w * 256 + tid] = r;
         r += L.wcnt[w * 256 + tid];
         L.wcnt[w * 256 + tid] = 0;
@@ -235,7 +242,7 @@ __global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint32_t *
   const uint32_t s0 = tstart[gt];
   const int n = (int)(tend[gt] - s0);
   if (n <= 0) return;
-  for (int i = threadIdx.x; i < 8 * 256; i += kTileSortThreads) L.wcnt[i] = 0;
+  for (int i = threadIdx.x; i < kSortWaves * 256; i += kTileSortThreads) L.wcnt[i] = 0;
   const int nruns = (n + chunk - 1) / chunk;
   int passes = 0;
   while ((1 << passes) < nruns) ++passes;
@@ -284,11 +291,11 @@ size_t max_lds_per_block() {
 
 static void choose_sort_chunk() {
   if (g_sort_chunk) return;
-  const size_t fixed = (2 * 256 + 2 * 8 * 256) * 4;
+  const size_t fixed = (2 * 256 + 2 * kSortWaves * 256) * 4;
   size_t lds = max_lds_per_block();
   if (lds > 160 * 1024) lds = 160 * 1024;
   int chunk = (int)((lds - fixed) / 16);
-  chunk = (chunk / kTileSortThreads) * kTileSortThreads;
+  chunk = (chunk / 512) * 512;
   if (chunk > 8192) chunk = 8192;
   if (chunk < kTileSortThreads) chunk = kTileSortThreads;
   g_sort_lds = fixed + (size_t)16 * chunk;
@@ -307,7 +314,7 @@ hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, h
     dim3 grid((unsigned)((lay.max_scene + 255) / 256), (unsigned)p->n_pairs);
     hipLaunchKernelGGL(k_emit, grid, dim3(256), (size_t)lay.T * 8, s, p->pairs, p->scene_offsets_dev,
                        (const int64_t *)(ws + lay.rec_base), (const uint32_t *)(ws + lay.rec_key),
-                       (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, counters, tstart,
+                       (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, PT, counters,
                        (uint32_t *)(ws + lay.tile_cur), (uint32_t *)(ws + lay.ekey), (uint32_t *)(ws + lay.eval));
   }
   choose_sort_chunk();
