@@ -80,7 +80,8 @@ def main() -> int:
     ap.add_argument("--gaussians", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="8x8", help="tile_w x tile_h (64, 128 or 256 rays)")
-    ap.add_argument("--lanes", type=int, default=4, help="lanes per ray (1, 2 or 4)")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="render traversal: 0 two-phase, or 1, 2, 4 lanes per ray (direct)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

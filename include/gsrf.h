@@ -57,9 +57,13 @@ typedef enum gsrf_status {
  *   alpha_max  opacity clamp, in (0, 1).
  *   tile_w/h   rays per tile (App. E uses 16 x 16); tile_w * tile_h must be
  *              64, 128 or 256.
- *   lanes_per_ray  1, 2 or 4 (0 means 1): lanes that share one ray, each
- *              testing a different entry of the depth-ordered list; results
- *              agree to rounding for every value.
+ *   lanes_per_ray  traversal of a tile's depth-ordered list by the render
+ *              kernels.  0 (recommended): two-phase traversal per staged
+ *              batch, all (ray, entry) hit tests first, then the per-hit work
+ *              on hits only, by 256 / (tile_w * tile_h) lanes per ray.
+ *              1, 2 or 4: direct traversal, that many lanes per ray, each
+ *              testing and processing a different entry.  Every value gives
+ *              the same hit decisions; the results agree to rounding.
  */
 typedef struct gsrf_grid {
   int32_t n_az, n_el;
@@ -211,8 +215,10 @@ gsrf_status gsrf_render_bwd(const gsrf_problem *p, const float *signal, const fl
 /*
  * Instrumentation for the roofline: replays the render_fwd traversal of a
  * problem prepared by gsrf_project + gsrf_bin_sort without writing any
- * output, and stores (DEVICE, int64 [4], overwritten) the number of
- * (ray, Gaussian) hit tests, processed hits, staged list entries and rays.
+ * output, and stores (DEVICE, int64 [5], overwritten) the number of
+ * (ray, Gaussian) hit tests made, processed hits, staged list entries, rays,
+ * and tile tests (sum over tiles of rays in the tile times list entries up to
+ * the tile's termination: the tests the tiled method implies).
  */
 gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stream);
 

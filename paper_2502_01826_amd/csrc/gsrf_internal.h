@@ -31,6 +31,8 @@ constexpr int kRecPerBlock = 256 * kRecPerThread;
 // divides the atomic traffic per counter by kSub.  Counters and cursors are
 // stored sub-major: [kSub][P * T].
 constexpr int kSub = 8;
+// Tiles per block of the three-pass tile-count scan (256 threads x 4).
+constexpr int kScanTiles = 1024;
 
 // Balanced expansion of the tile rectangles of a workgroup's records: the
 // rectangles' splat counts are scanned in LDS and every thread takes splats
@@ -75,6 +77,7 @@ __device__ __forceinline__ int rect_splat(const RectScan &rs, uint32_t s, int nt
 struct Layout {
   size_t prep, rec_base, rec_key, rec_rect, counters;
   size_t tile_cnt, tile_start, tile_end, tile_cur;
+  size_t scan_blk;        // per-block totals of the tile-count scan
   size_t ekey, eval;      // emitted buckets (unsorted)
   size_t klo, val;        // sorted tile lists: depth key, Gaussian id
   size_t tkey, tval;      // merge scratch
@@ -90,7 +93,6 @@ struct Layout {
 };
 
 inline int fle_K(int L) { return (L + 1) * (L + 1); }
-inline int lanes_per_ray(const gsrf_grid &g) { return g.lanes_per_ray <= 0 ? 1 : g.lanes_per_ray; }
 
 // Instrumentation events (set by gsrf_set_kernel_events): 0/1 around the
 // forward render kernel, 2/3 around the adjoint kernel.

@@ -176,42 +176,103 @@ __global__ __launch_bounds__(256) void k_project(const gsrf_pair *__restrict__ p
 }
 #pragma clang fp contract(on)
 
-// Exclusive scan of the per-(tile, sub-bucket) counts of all pairs (one
-// workgroup): tile ranges, sub-bucket starts (emission cursors), the splat
-// total and the overflow flag.  When the total exceeds the capacity every
-// range is left empty, so nothing downstream reads past it.
-__global__ __launch_bounds__(1024) void k_tile_scan(const uint32_t *__restrict__ tile_cnt, int64_t PT, int64_t cap,
-                                                    uint32_t *__restrict__ tstart, uint32_t *__restrict__ tend,
-                                                    uint32_t *__restrict__ tcur, int64_t *__restrict__ counters) {
+// Exclusive scan of the per-(tile, sub-bucket) counts of all pairs, in three
+// launches over blocks of kScanTiles tiles: block totals, a scan of the block
+// totals (which also stores the splat total and the overflow flag), and the
+// per-block scan that writes the tile ranges and the sub-bucket starts
+// (emission cursors).  When the total exceeds the capacity every range is
+// left empty, so nothing downstream reads past it.
+__device__ __forceinline__ int64_t block_sum_256(int64_t x, int64_t *sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = x;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) sh[tid] += sh[tid + off];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ tile_cnt, int64_t PT,
+                                                     int64_t *__restrict__ blk) {
+  __shared__ int64_t sh[256];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTiles;
+  int64_t local = 0;
+#pragma unroll
+  for (int i = 0; i < kScanTiles / 256; ++i) {
+    const int64_t t = t0 + i * 256 + threadIdx.x;
+    if (t < PT)
+      for (int b = 0; b < kSub; ++b) local += tile_cnt[(size_t)b * PT + t];
+  }
+  const int64_t tot = block_sum_256(local, sh);
+  if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(int64_t *__restrict__ blk, int64_t nblk, int64_t cap,
+                                                      int64_t *__restrict__ counters) {
   __shared__ int64_t sh[1024];
   const int tid = threadIdx.x;
-  const int64_t per = (PT + 1023) / 1024;       // tiles per thread
-  const int64_t lo = tid * per, hi = min(PT, lo + per);
-  int64_t local = 0;
-  for (int64_t t = lo; t < hi; ++t)
-    for (int b = 0; b < kSub; ++b) local += tile_cnt[(size_t)b * PT + t];
-  sh[tid] = local;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int64_t v = tid >= off ? sh[tid - off] : 0;
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nblk; c0 += 1024) {
+    const int64_t i = c0 + tid;
+    const int64_t x = i < nblk ? blk[i] : 0;
+    sh[tid] = x;
     __syncthreads();
-    sh[tid] += v;
-    __syncthreads();
-  }
-  const int64_t total = sh[1023];
-  const bool over = total > cap;
-  int64_t run = sh[tid] - local;
-  for (int64_t t = lo; t < hi; ++t) {
-    tstart[t] = over ? 0u : (uint32_t)run;
-    for (int b = 0; b < kSub; ++b) {
-      tcur[(size_t)b * PT + t] = over ? 0u : (uint32_t)run;   // emission cursor of the sub-bucket
-      run += tile_cnt[(size_t)b * PT + t];
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int64_t y = tid >= off ? sh[tid - off] : 0;
+      __syncthreads();
+      sh[tid] += y;
+      __syncthreads();
     }
-    tend[t] = over ? 0u : (uint32_t)run;
+    if (i < nblk) blk[i] = carry + sh[tid] - x;
+    carry += sh[1023];
+    __syncthreads();
   }
   if (tid == 0) {
-    counters[0] = total;
-    counters[1] = over ? total : 0;
+    counters[0] = carry;
+    counters[1] = carry > cap ? carry : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ tile_cnt, int64_t PT,
+                                                    const int64_t *__restrict__ blk,
+                                                    const int64_t *__restrict__ counters,
+                                                    uint32_t *__restrict__ tstart, uint32_t *__restrict__ tend,
+                                                    uint32_t *__restrict__ tcur) {
+  __shared__ int64_t sh[256];
+  constexpr int PER = kScanTiles / 256;
+  const int tid = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTiles + (int64_t)tid * PER;
+  uint32_t cnt[PER][kSub];
+  int64_t local = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i)
+#pragma unroll
+    for (int b = 0; b < kSub; ++b) {
+      cnt[i][b] = (t0 + i < PT) ? tile_cnt[(size_t)b * PT + t0 + i] : 0u;
+      local += cnt[i][b];
+    }
+  sh[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t y = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += y;
+    __syncthreads();
+  }
+  const bool over = counters[1] != 0;
+  int64_t run = blk[blockIdx.x] + sh[tid] - local;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int64_t t = t0 + i;
+    if (t >= PT) break;
+    tstart[t] = over ? 0u : (uint32_t)run;
+#pragma unroll
+    for (int b = 0; b < kSub; ++b) {
+      tcur[(size_t)b * PT + t] = over ? 0u : (uint32_t)run;   // emission cursor of the sub-bucket
+      run += cnt[i][b];
+    }
+    tend[t] = over ? 0u : (uint32_t)run;
   }
 }
 
@@ -236,8 +297,16 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
                        p->means, p->log_scales, p->grid, lay.nta, lay.T, PT, (uint32_t *)(ws + lay.rec_key),
                        (ushort4 *)(ws + lay.rec_rect), tile_cnt);
   }
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, tile_cnt, PT, lay.cap, (uint32_t *)(ws + lay.tile_start),
-                     (uint32_t *)(ws + lay.tile_end), (uint32_t *)(ws + lay.tile_cur), (int64_t *)(ws + lay.counters));
+  int64_t *blk = (int64_t *)(ws + lay.scan_blk);
+  int64_t *counters = (int64_t *)(ws + lay.counters);
+  const int64_t nblk = (PT + kScanTiles - 1) / kScanTiles;
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(256), 0, s, tile_cnt, PT, blk);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, nblk, lay.cap, counters);
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(256), 0, s, tile_cnt, PT, (const int64_t *)blk,
+                       (const int64_t *)counters, (uint32_t *)(ws + lay.tile_start), (uint32_t *)(ws + lay.tile_end),
+                       (uint32_t *)(ws + lay.tile_cur));
   return hipGetLastError();
 }
 

@@ -9,14 +9,10 @@
 // to the Gaussian's accumulators; the rays of a wave are summed by a
 // reduce-scatter (recursive halving over lanes), the waves meet in LDS, and
 // one burst of global atomics per (tile, Gaussian) flushes them.
-#include "render_common.h"
+#include "render_two_phase.h"
 
 namespace gsrf {
 
-// Accumulator slots (SoA in global memory, acc[f * G + g]):
-//   0-5 dL/dM (M00 M11 M22 M01 M02 M12), 6-8 dL/dmu, 9 dL/dN, 10 dL/do,
-//   11.. dL/dc (2K); the LDS copy adds slot 11 + 2K = sum of dL/dt, whose TX leg
-//   (mu - tx)/|mu - tx| is folded into dL/dmu at the flush.
 template <int L, int NT, int G>
 __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *__restrict__ signal,
                                                    const float2 *__restrict__ grad_signal,
@@ -27,7 +23,6 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
   constexpr int NACC = n_acc(L);               // 12 + 2K
   constexpr int NV = pow2_at_least(NACC);
   constexpr int RAYS = NT / G;
-  constexpr int SLOT_T = 11 + 2 * K;           // LDS slot of sum dL/dt
   extern __shared__ float4 smem[];
   float4 *sgeo = smem;                          // [B][kGeo]
   float *scf = (float *)(smem + kGeo * B);      // [B][2K]
@@ -103,40 +98,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
           for (int i = 0; i < NV; ++i) c[i] = 0.f;
           if (proc) {
             const float Rr = Sfr - (Pr + wr_in), Ri = Sfi - (Pi + wi_in);
-            const float dLdp = Tj * fmaf(Gr, h.pzr, Gi * h.pzi);
-            const float dLdphi = Tj * fmaf(Gr, cti, -(Gi * ctr));
-            const float dLda = h.clamped ? 0.f : -fmaf(Gr, Rr, Gi * Ri) / (1.0f - h.alpha);
-            const float4 g0 = geo[0], g3 = geo[3];
-            const float D = g0.w;
-            const float dLdG = fmaf(dLdp, g3.z, dLda * g3.w);
-            const float gQ = -0.5f * h.G * dLdG;
-            const float gt_ = dLdphi * twopi_lam;
-            const float gtA = gt_ * h.rA;
-            // x_mid - mu = D (eps - (b/A) v), M (x_mid - mu) = D (M eps - (b/A) M v)
-            const float px = D * fmaf(-h.bA, vx, h.ex), py = D * fmaf(-h.bA, vy, h.ey),
-                        pz = D * fmaf(-h.bA, vz, h.ez);
-            const float qx = D * fmaf(-h.bA, h.w0, h.m0), qy = D * fmaf(-h.bA, h.w1, h.m1),
-                        qz = D * fmaf(-h.bA, h.w2, h.m2);
-            c[0] = fmaf(gQ * px, px, -(gtA * vx * px));
-            c[1] = fmaf(gQ * py, py, -(gtA * vy * py));
-            c[2] = fmaf(gQ * pz, pz, -(gtA * vz * pz));
-            c[3] = fmaf(gQ * px, py, -0.5f * gtA * fmaf(vx, py, px * vy));
-            c[4] = fmaf(gQ * px, pz, -0.5f * gtA * fmaf(vx, pz, px * vz));
-            c[5] = fmaf(gQ * py, pz, -0.5f * gtA * fmaf(vy, pz, py * vz));
-            c[6] = fmaf(-2.0f * gQ, qx, gtA * h.w0);
-            c[7] = fmaf(-2.0f * gQ, qy, gtA * h.w1);
-            c[8] = fmaf(-2.0f * gQ, qz, gtA * h.w2);
-            c[9] = dLdp * h.G;     // dL/dN
-            c[10] = dLda * h.G;    // dL/do
-            const float Tp = Tj * h.p;
-            const float dpr = Tp * fmaf(Gr, h.cs, -(Gi * h.sn));
-            const float dpi = Tp * fmaf(Gi, h.cs, Gr * h.sn);
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-              c[11 + 2 * i] = fmaf(dpr, Yr[i], dpi * Yi[i]);
-              c[12 + 2 * i] = fmaf(dpi, Yr[i], -(dpr * Yi[i]));
-            }
-            c[SLOT_T] = gt_;       // dL/dt; TX leg applied at the flush
+            hit_adjoint<K, NV>(h, geo, Tj, ctr, cti, Rr, Ri, Gr, Gi, vx, vy, vz, Yr, Yi, twopi_lam, c);
             sflag[j] = 1;
           }
           int first;
@@ -158,25 +120,13 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
     __syncthreads();
     // flush: one thread per staged Gaussian with any processed hit in this tile
     if ((int)threadIdx.x < nb && sflag[threadIdx.x]) {
-      const uint32_t g = a.val[base + threadIdx.x];
-      float *src = sacc + NACC * threadIdx.x;
-      const float *pg = a.prep + (size_t)kPrep * g;
-      const double qx = (double)pg[0] - pr.tx[0], qy = (double)pg[1] - pr.tx[1], qz = (double)pg[2] - pr.tx[2];
-      const double dn = sqrt((qx * qx + qy * qy) + qz * qz);
-      const double inv = dn > 0.0 ? 1.0 / dn : 0.0;
-      const float gtx = src[SLOT_T];
-      src[6] = fmaf(gtx, (float)(qx * inv), src[6]);
-      src[7] = fmaf(gtx, (float)(qy * inv), src[7]);
-      src[8] = fmaf(gtx, (float)(qz * inv), src[8]);
-#pragma unroll
-      for (int f = 0; f < SLOT_T; ++f) unsafeAtomicAdd(acc + (size_t)f * n_gauss + g, src[f]);
-#pragma unroll
-      for (int f = 0; f < NACC; ++f) src[f] = 0.f;
+      flush_entry<K>(a, a.val[base + threadIdx.x], pr, sacc + NACC * threadIdx.x, n_gauss, acc);
       sflag[threadIdx.x] = 0;
     }
     if (__syncthreads_and(done ? 1 : 0)) break;
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // a8: chain rule per Gaussian from (dL/dM, dL/dmu, dL/dN, dL/do, dL/dc) to the
@@ -257,9 +207,19 @@ static hipError_t bwd_launch(const RenderArgs &a, int64_t nblocks, const float2 
   return hipGetLastError();
 }
 
+
 template <int L>
 static hipError_t bwd_dispatch(int area, int G, const RenderArgs &a, int64_t nblocks, const float2 *sig,
                                const float2 *gsig, const float2 *gsum, int64_t n, float *acc, hipStream_t s) {
+  if (G == 0) {
+    TpIO io{};
+    io.signal = const_cast<float2 *>(sig);
+    io.grad_signal = gsig;
+    io.grad_sum = gsum;
+    io.n_gauss = n;
+    io.acc = acc;
+    return tp_dispatch<L, kTpBwd>(area, a, io, nblocks, s);
+  }
   switch (area * 8 + G) {
     case 64 * 8 + 1: return bwd_launch<L, 64, 1>(a, nblocks, sig, gsig, gsum, n, acc, s);
     case 64 * 8 + 2: return bwd_launch<L, 128, 2>(a, nblocks, sig, gsig, gsum, n, acc, s);
@@ -282,7 +242,7 @@ hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws,
   if (p->n_pairs > 0) {
     const RenderArgs a = make_render_args(p, lay, ws);
     const int area = p->grid.tile_w * p->grid.tile_h;
-    const int G = lanes_per_ray(p->grid);
+    const int G = p->grid.lanes_per_ray;   // 0: two-phase traversal
     const int64_t nb = (int64_t)p->n_pairs * lay.T;
     const float2 *sg = (const float2 *)signal, *gs = (const float2 *)grad_signal, *gm = (const float2 *)grad_sum;
     mark_kernel_event(2, s);

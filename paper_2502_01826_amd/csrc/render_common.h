@@ -59,16 +59,25 @@ constexpr int lds_batch(int L, int NT, bool bwd) {
 // Per-ray setup: direction (FP64 -> FP32) and the FLE basis
 // Y_i = e^{j m alpha} P_l^m(sin beta), i = l^2 + l + m (Sec. 3.2 eq. FLE).
 // ---------------------------------------------------------------------------
-template <int L>
-__device__ void ray_setup(int u, int v, const RenderArgs &a, float &vx, float &vy, float &vz, float *Yr,
-                          float *Yi) {
+// Ray (u, v): azimuth alpha_u = 2 pi (u + 1/2) / n_az, elevation
+// beta_v = el_lo + (el_hi - el_lo) (v + 1/2) / n_el, direction rounded to FP32.
+__device__ __forceinline__ void ray_dir(int u, int v, const RenderArgs &a, float &vx, float &vy, float &vz,
+                                        double &al, double &sb) {
   const double pi = 3.14159265358979323846;
-  const double al = 2.0 * pi * (u + 0.5) / a.n_az;
+  al = 2.0 * pi * (u + 0.5) / a.n_az;
   const double be = (double)a.el_lo + ((double)a.el_hi - (double)a.el_lo) * (v + 0.5) / a.n_el;
-  const double cb = cos(be), sb = sin(be);
+  const double cb = cos(be);
+  sb = sin(be);
   vx = (float)(cb * cos(al));
   vy = (float)(cb * sin(al));
   vz = (float)sb;
+}
+
+template <int L>
+__device__ void ray_setup(int u, int v, const RenderArgs &a, float &vx, float &vy, float &vz, float *Yr,
+                          float *Yi) {
+  double al, sb;
+  ray_dir(u, v, a, vx, vy, vz, al, sb);
   // associated Legendre P_l^m(x), m >= 0, Condon-Shortley phase, textbook recurrences
   double P[L + 1][L + 1];
   const double x = sb;
@@ -219,6 +228,59 @@ __device__ __forceinline__ void hit_terms(const float4 *geo, const float *cf, co
   h.pzi = fmaf(pi, h.cs, -(pr * h.sn));
 }
 
+// ---------------------------------------------------------------------------
+// Cross-lane primitives without LDS traffic.  The G lanes of a ray are
+// adjacent and G <= 4, so a ray's group never leaves a DPP quad; the
+// reduce-scatter over the rays of a wave pairs lanes at distance 32 and 16
+// with the gfx950 permlane swaps and at 8, 4, 2, 1 with row rotation,
+// swizzle and quad permutations.
+// ---------------------------------------------------------------------------
+constexpr int quad_perm(int l0, int l1, int l2, int l3) { return l0 | (l1 << 2) | (l2 << 4) | (l3 << 6); }
+constexpr int kDppRowRor8 = 0x128;        // lane i of a 16-lane row reads lane (i + 8) mod 16 = i ^ 8
+constexpr int kSwizzleXor4 = 0x101F;      // bit-mask swizzle: and 0x1f, or 0, xor 4
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// value of lane (lane ^ D)
+template <int D>
+__device__ __forceinline__ float xor_lane(float x, int lane) {
+  if constexpr (D == 32 || D == 16) {
+    const auto r = (D == 32) ? __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false)
+                             : __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float((lane & D) ? r[0] : r[1]);
+  } else if constexpr (D == 8) {
+    return dpp<kDppRowRor8>(x);
+  } else if constexpr (D == 4) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), kSwizzleXor4));
+  } else if constexpr (D == 2) {
+    return dpp<quad_perm(2, 3, 0, 1)>(x);
+  } else {
+    return dpp<quad_perm(1, 0, 3, 2)>(x);
+  }
+}
+
+// One reduce-scatter exchange at lane distance D of the slot pair (a, b):
+// on return a holds a summed over the lane pair in the lane without bit D
+// and b summed in the lane with bit D.
+template <int D>
+__device__ __forceinline__ void pair_sum(float &a, float b, int lane) {
+  if constexpr (D == 32 || D == 16) {
+    // swap: a' = (a of the low lane, b of the low lane), b' = (a of the high
+    // lane, b of the high lane) per pair, so a' + b' is the pair sum of a in
+    // the low lane and of b in the high lane
+    const auto r = (D == 32) ? __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false)
+                             : __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  } else {
+    const float as = a + xor_lane<D>(a, lane);
+    const float bs = b + xor_lane<D>(b, lane);
+    a = (lane & D) ? bs : as;
+  }
+}
+
 // Exclusive product and total of f over the G lanes of a ray (lanes q = 0..G-1
 // adjacent in the wave).  Every lane of the wave must call it.
 template <int G>
@@ -226,16 +288,19 @@ __device__ __forceinline__ void group_prod(float f, int q, float &excl, float &t
   if constexpr (G == 1) {
     excl = 1.f;
     total = f;
+  } else if constexpr (G == 2) {
+    const float lo = dpp<quad_perm(0, 0, 2, 2)>(f);
+    const float incl = (q >= 1) ? f * lo : f;
+    excl = (q == 0) ? 1.f : lo;
+    total = dpp<quad_perm(1, 1, 3, 3)>(incl);
   } else {
-    float incl = f;
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      const float o = __shfl_up(incl, d, G);
-      if (q >= d) incl *= o;
-    }
-    const float e = __shfl_up(incl, 1, G);
+    const float s1 = dpp<quad_perm(0, 0, 1, 2)>(f);
+    const float x = (q >= 1) ? f * s1 : f;
+    const float s2 = dpp<quad_perm(0, 1, 0, 1)>(x);
+    const float incl = (q >= 2) ? x * s2 : x;
+    const float e = dpp<quad_perm(0, 0, 1, 2)>(incl);
     excl = (q == 0) ? 1.f : e;
-    total = __shfl(incl, G - 1, G);
+    total = dpp<quad_perm(3, 3, 3, 3)>(incl);
   }
 }
 
@@ -245,14 +310,16 @@ __device__ __forceinline__ void group_sum(float x, int q, float &incl, float &to
   if constexpr (G == 1) {
     incl = x;
     total = x;
+  } else if constexpr (G == 2) {
+    const float lo = dpp<quad_perm(0, 0, 2, 2)>(x);
+    incl = (q >= 1) ? x + lo : x;
+    total = dpp<quad_perm(1, 1, 3, 3)>(incl);
   } else {
-    incl = x;
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      const float o = __shfl_up(incl, d, G);
-      if (q >= d) incl += o;
-    }
-    total = __shfl(incl, G - 1, G);
+    const float s1 = dpp<quad_perm(0, 0, 1, 2)>(x);
+    const float y = (q >= 1) ? x + s1 : x;
+    const float s2 = dpp<quad_perm(0, 1, 0, 1)>(y);
+    incl = (q >= 2) ? y + s2 : y;
+    total = dpp<quad_perm(3, 3, 3, 3)>(incl);
   }
 }
 
@@ -269,16 +336,11 @@ __device__ __forceinline__ void rs_step(float (&v)[NV], int lane, int &first, bo
     constexpr int LIVE = (NV * D / 32 >= 1) ? NV * D / 32 : 1;
     if constexpr (LIVE > 1) {
       constexpr int H = LIVE / 2;
-      const bool up = (lane & D) != 0;
 #pragma unroll
-      for (int i = 0; i < H; ++i) {
-        const float send = up ? v[i] : v[i + H];
-        const float keep = up ? v[i + H] : v[i];
-        v[i] = keep + __shfl_xor(send, D, 64);
-      }
-      if (up) first += H;
+      for (int i = 0; i < H; ++i) pair_sum<D>(v[i], v[i + H], lane);
+      if (lane & D) first += H;
     } else {
-      v[0] += __shfl_xor(v[0], D, 64);
+      v[0] += xor_lane<D>(v[0], lane);
       if (lane & D) writer = false;
     }
     rs_step<NV, G, D / 2>(v, lane, first, writer);
@@ -292,6 +354,72 @@ __device__ __forceinline__ void reduce_scatter(float (&v)[NV], int lane, int *fi
   rs_step<NV, G, 32>(v, lane, f, w);
   *first = f;
   *writer = w;
+}
+
+// Accumulator slots of the adjoint (SoA in global memory, acc[f * n_gauss + g]):
+//   0-5 dL/dM (M00 M11 M22 M01 M02 M12), 6-8 dL/dmu, 9 dL/dN, 10 dL/do,
+//   11.. dL/dc (2K); the LDS copy adds slot 11 + 2K = sum of dL/dt, whose TX leg
+//   (mu - tx)/|mu - tx| is folded into dL/dmu at the flush.
+// Contributions of one processed hit j to the Gaussian's accumulator slots.
+// Rr, Ri: remainder sum_{i>j} T_i c~_i; (Gr, Gi): dL/dS of the ray.
+template <int K, int NV>
+__device__ __forceinline__ void hit_adjoint(const Terms &h, const float4 *geo, float Tj, float ctr, float cti,
+                                            float Rr, float Ri, float Gr, float Gi, float vx, float vy, float vz,
+                                            const float *Yr, const float *Yi, float twopi_lam, float (&c)[NV]) {
+  constexpr int SLOT_T = 11 + 2 * K;
+  const float dLdp = Tj * fmaf(Gr, h.pzr, Gi * h.pzi);
+  const float dLdphi = Tj * fmaf(Gr, cti, -(Gi * ctr));
+  const float dLda = h.clamped ? 0.f : -fmaf(Gr, Rr, Gi * Ri) / (1.0f - h.alpha);
+  const float4 g0 = geo[0], g3 = geo[3];
+  const float D = g0.w;
+  const float dLdG = fmaf(dLdp, g3.z, dLda * g3.w);
+  const float gQ = -0.5f * h.G * dLdG;
+  const float gt_ = dLdphi * twopi_lam;
+  const float gtA = gt_ * h.rA;
+  // x_mid - mu = D (eps - (b/A) v), M (x_mid - mu) = D (M eps - (b/A) M v)
+  const float px = D * fmaf(-h.bA, vx, h.ex), py = D * fmaf(-h.bA, vy, h.ey), pz = D * fmaf(-h.bA, vz, h.ez);
+  const float qx = D * fmaf(-h.bA, h.w0, h.m0), qy = D * fmaf(-h.bA, h.w1, h.m1), qz = D * fmaf(-h.bA, h.w2, h.m2);
+  c[0] = fmaf(gQ * px, px, -(gtA * vx * px));
+  c[1] = fmaf(gQ * py, py, -(gtA * vy * py));
+  c[2] = fmaf(gQ * pz, pz, -(gtA * vz * pz));
+  c[3] = fmaf(gQ * px, py, -0.5f * gtA * fmaf(vx, py, px * vy));
+  c[4] = fmaf(gQ * px, pz, -0.5f * gtA * fmaf(vx, pz, px * vz));
+  c[5] = fmaf(gQ * py, pz, -0.5f * gtA * fmaf(vy, pz, py * vz));
+  c[6] = fmaf(-2.0f * gQ, qx, gtA * h.w0);
+  c[7] = fmaf(-2.0f * gQ, qy, gtA * h.w1);
+  c[8] = fmaf(-2.0f * gQ, qz, gtA * h.w2);
+  c[9] = dLdp * h.G;     // dL/dN
+  c[10] = dLda * h.G;    // dL/do
+  const float Tp = Tj * h.p;
+  const float dpr = Tp * fmaf(Gr, h.cs, -(Gi * h.sn));
+  const float dpi = Tp * fmaf(Gi, h.cs, Gr * h.sn);
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    c[11 + 2 * i] = fmaf(dpr, Yr[i], dpi * Yi[i]);
+    c[12 + 2 * i] = fmaf(dpi, Yr[i], -(dpr * Yi[i]));
+  }
+  c[SLOT_T] = gt_;       // dL/dt; TX leg applied at the flush
+}
+
+// Flush of one staged Gaussian's LDS accumulators to the global SoA
+// accumulators, folding dL/dt's TX leg (mu - tx)/|mu - tx| into dL/dmu.
+template <int K>
+__device__ __forceinline__ void flush_entry(const RenderArgs &a, uint32_t g, const gsrf_pair &pr, float *src,
+                                            int64_t n_gauss, float *__restrict__ acc) {
+  constexpr int SLOT_T = 11 + 2 * K;
+  constexpr int NACC = 12 + 2 * K;
+  const float *pg = a.prep + (size_t)kPrep * g;
+  const double qx = (double)pg[0] - pr.tx[0], qy = (double)pg[1] - pr.tx[1], qz = (double)pg[2] - pr.tx[2];
+  const double dn = sqrt((qx * qx + qy * qy) + qz * qz);
+  const double inv = dn > 0.0 ? 1.0 / dn : 0.0;
+  const float gtx = src[SLOT_T];
+  src[6] = fmaf(gtx, (float)(qx * inv), src[6]);
+  src[7] = fmaf(gtx, (float)(qy * inv), src[7]);
+  src[8] = fmaf(gtx, (float)(qz * inv), src[8]);
+#pragma unroll
+  for (int f = 0; f < SLOT_T; ++f) unsafeAtomicAdd(acc + (size_t)f * n_gauss + g, src[f]);
+#pragma unroll
+  for (int f = 0; f < NACC; ++f) src[f] = 0.f;
 }
 
 }  // namespace gsrf

@@ -1,12 +1,14 @@
 // Steps a5-a6: complex front-to-back ray accumulation (Sec. 3.4 eq. rendering;
 // App. A; Alg. 1 Blend) and the single-antenna sum (Sec. 3.4).
 //
-// One workgroup renders one (pair, tile); each ray is served by G lanes (see
-// render_common.h).  The tile's depth-sorted Gaussian list is staged through
-// LDS in batches; rays stop individually when their transmittance falls below
-// t_min and the workgroup stops when all of its rays have.  Tile partials of
-// S_hat are reduced in a fixed order, so the forward pass is deterministic.
-#include "render_common.h"
+// One workgroup renders one (pair, tile).  The tile's depth-sorted Gaussian
+// list is staged through LDS in batches; rays stop individually when their
+// transmittance falls below t_min and the workgroup stops when all of its rays
+// have.  Two traversals of a batch: the two-phase one (render_two_phase.h,
+// lanes_per_ray = 0) and the direct one below, where each ray is served by G
+// lanes that test and process consecutive entries.  Tile partials of S_hat are
+// reduced in a fixed order, so the forward pass is deterministic.
+#include "render_two_phase.h"
 
 namespace gsrf {
 
@@ -36,14 +38,17 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
   const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
   float T = 1.f, Sr = 0.f, Si = 0.f;
   bool done = !valid || (1.0f < a.t_min);
-  unsigned long long n_test = 0, n_hit = 0, n_staged = 0;
+  unsigned long long n_test = 0, n_hit = 0, n_staged = 0, n_tile_tests = 0;
   for (uint32_t base = s0; base < s1; base += B) {
     const int nb = (int)min((uint32_t)B, s1 - base);
     __syncthreads();
     if ((int)threadIdx.x < nb)
       stage_entry<K>(a, a.val[base + threadIdx.x], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], lam,
                      sgeo + kGeo * threadIdx.x, scf + 2 * K * threadIdx.x);
-    if (STATS && threadIdx.x == 0) n_staged += nb;
+    if (STATS && threadIdx.x == 0) {
+      n_staged += nb;
+      n_tile_tests += (unsigned long long)nb * min(a.tw, a.n_az - tu * a.tw) * min(th_, a.n_el - tv * th_);
+    }
     __syncthreads();
     if (__ballot(!done) != 0) {              // wave-uniform
       for (int m = 0; m < nb; m += G) {
@@ -84,11 +89,12 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
     }
   }
   if (STATS) {
-    // instrumentation: tests, processed hits, staged entries, rays
+    // instrumentation: tests, processed hits, staged entries, rays, tile tests
     if (n_test) atomicAdd(stats + 0, n_test);
     if (n_hit) atomicAdd(stats + 1, n_hit);
     if (n_staged) atomicAdd(stats + 2, n_staged);
     if (valid && q == 0) atomicAdd(stats + 3, 1ull);
+    if (n_tile_tests) atomicAdd(stats + 4, n_tile_tests);
     return;
   }
   if (valid && q == 0) signal[((size_t)k * a.n_el + v) * a.n_az + u] = make_float2(Sr, Si);
@@ -107,6 +113,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
   }
   if (threadIdx.x == 0) tile_sum[gt] = make_float2(red[0], red[NT]);
 }
+
 
 // a6: S_hat per pair (tiles summed in fixed order, FP64) and RSSI in dBm.
 __global__ void k_rssi(const float2 *__restrict__ tile_sum, int32_t T, float *__restrict__ signal_sum,
@@ -154,9 +161,17 @@ static hipError_t fwd_launch(const RenderArgs &a, int64_t nblocks, float2 *sig, 
   return hipGetLastError();
 }
 
+
 template <int L>
 static hipError_t fwd_dispatch(int area, int G, const RenderArgs &a, int64_t nblocks, float2 *sig, float2 *tsum,
                                unsigned long long *stats, hipStream_t s) {
+  if (G == 0) {
+    TpIO io{};
+    io.signal = sig;
+    io.tile_sum = tsum;
+    io.stats = stats;
+    return stats ? tp_dispatch<L, kTpFwdStats>(area, a, io, nblocks, s) : tp_dispatch<L, kTpFwd>(area, a, io, nblocks, s);
+  }
   switch (area * 8 + G) {
     case 64 * 8 + 1: return fwd_launch<L, 64, 1>(a, nblocks, sig, tsum, stats, s);
     case 64 * 8 + 2: return fwd_launch<L, 128, 2>(a, nblocks, sig, tsum, stats, s);
@@ -173,7 +188,7 @@ static hipError_t fwd_dispatch(int area, int G, const RenderArgs &a, int64_t nbl
 static hipError_t fwd_any(const gsrf_problem *p, const RenderArgs &a, int64_t nblocks, float2 *sig, float2 *tsum,
                           unsigned long long *stats, hipStream_t s) {
   const int area = p->grid.tile_w * p->grid.tile_h;
-  const int G = lanes_per_ray(p->grid);
+  const int G = p->grid.lanes_per_ray;   // 0: two-phase traversal
   switch (p->grid.fle_L) {
     case 0: return fwd_dispatch<0>(area, G, a, nblocks, sig, tsum, stats, s);
     case 1: return fwd_dispatch<1>(area, G, a, nblocks, sig, tsum, stats, s);
@@ -221,7 +236,7 @@ hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws,
 }
 
 hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *ws, int64_t *counts, hipStream_t s) {
-  hipError_t e = fill<int64_t>(counts, 0, 4, s);
+  hipError_t e = fill<int64_t>(counts, 0, 5, s);
   if (e != hipSuccess || p->n_pairs == 0) return e;
   const RenderArgs a = make_render_args(p, lay, ws);
   const int64_t nblocks = (int64_t)p->n_pairs * lay.T;

@@ -1,0 +1,317 @@
+// Two-phase traversal of a tile's depth-ordered list (256 threads per
+// (pair, tile), R = 64, 128 or 256 rays), used by both the forward renderer
+// (Sec. 3.4 eq. rendering; App. A) and its adjoint (App. C; App. D).
+//
+// Only about one in six (ray, list entry) tests is a processed hit, so doing
+// the per-hit work where the test is made leaves most lanes idle.  Per staged
+// batch:
+//   phase 1  dense hit tests: wave w takes the 64 rays (w % RC) * 64 + lane
+//            against entries e, e + EP, ... (e = w / RC) and ORs the hits into
+//            per-ray bit rows in LDS, and into the union row of the phase-2
+//            wave that serves the ray;
+//   phase 2  each wave serves 64 / G rays with G = 256 / R adjacent lanes per
+//            ray and walks the union of its rays' hit bits in depth order, G
+//            entries per step (a wave-uniform scalar cursor).  A lane does the
+//            per-hit work only where its ray hits its entry; the G-lane
+//            product scan gives each hit its incoming transmittance
+//            T_j = T * prod(1 - alpha) over the earlier hits, so "process hit
+//            j iff T_j >= t_min" is decided per hit as in the sequential
+//            definition.  Because the lanes sharing q meet the same entry,
+//            the adjoint sums a step's contributions over the wave's rays by
+//            a register reduce-scatter instead of LDS atomics (walking each
+//            ray's own bits would put neighbouring rays on one Gaussian in
+//            the same step).
+#pragma once
+
+#include "render_common.h"
+
+namespace gsrf {
+
+enum TpMode { kTpFwd = 0, kTpFwdStats = 1, kTpBwd = 2 };
+
+template <int R>
+struct TwoPhase {
+  static constexpr int NT = 256;
+  static constexpr int RC = R / 64;        // ray chunks of 64 (phase 1)
+  static constexpr int EP = 4 / RC;        // entry phases per ray chunk (phase 1)
+  static constexpr int G = NT / R;         // lanes per ray (phase 2)
+  static constexpr int RPW = 64 / G;       // rays per wave (phase 2)
+};
+
+struct TpIO {
+  float2 *signal;                 // forward output S [P, n_el, n_az]; read by the adjoint
+  float2 *tile_sum;               // forward: per-(pair, tile) partial of S_hat
+  unsigned long long *stats;      // forward with counters: tests, hits, staged, rays, tile tests
+  const float2 *grad_signal;      // adjoint: dL/dS
+  const float2 *grad_sum;         // adjoint: dL/dS_hat per pair, or null
+  int64_t n_gauss;
+  float *acc;                     // adjoint accumulators [n_acc - 1][n_gauss]
+};
+
+template <int L, int R, int MODE>
+struct TpShape {
+  static constexpr bool BWD = MODE == kTpBwd;
+  static constexpr int K = (L + 1) * (L + 1);
+  static constexpr int B = lds_batch(L, 256, BWD);
+  static constexpr int NACC = n_acc(L);
+  static constexpr int MW = (B + 31) / 32;       // mask words per row
+  static constexpr int MWS = MW + 1;             // odd row stride: conflict-free column reads
+  // LDS: geometry, coefficients, [accumulators, flags], ray rows, union rows, done flags
+  static constexpr size_t kLds = (size_t)B * (kGeo * 16 + 2 * K * 4) + (BWD ? (size_t)B * (NACC * 4 + 4) : 0) +
+                                 (size_t)R * MWS * 4 + (size_t)4 * MW * 4 + (size_t)R * 4;
+  static constexpr size_t lds() { return kLds < 256 * 8 ? 256 * 8 : kLds; }
+};
+
+// Phase 1: hit bits of ray r1 against entries e, e + EP, ... < nb.
+template <int EP>
+__device__ __forceinline__ unsigned phase1_tests(float vx, float vy, float vz, const float4 *sgeo, int nb, int e,
+                                                 float r_rx, uint32_t *mask_row, uint32_t *uni_row) {
+  uint32_t bits = 0;
+  int cw = e >> 5;
+  unsigned n_test = 0;
+  for (int jj = e; jj < nb; jj += EP) {
+    Terms h;
+    const bool hit = test_hit(vx, vy, vz, sgeo + kGeo * jj, r_rx, h);
+    ++n_test;
+    const int w = jj >> 5;
+    if (w != cw) {
+      if (bits) {
+        atomicOr(mask_row + cw, bits);
+        atomicOr(uni_row + cw, bits);
+      }
+      bits = 0;
+      cw = w;
+    }
+    if (hit) bits |= 1u << (jj & 31);
+  }
+  if (bits) {
+    atomicOr(mask_row + cw, bits);
+    atomicOr(uni_row + cw, bits);
+  }
+  return n_test;
+}
+
+template <int L, int R, int MODE>
+__global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
+  using TP = TwoPhase<R>;
+  using SH = TpShape<L, R, MODE>;
+  constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats;
+  constexpr int NT = TP::NT, G = TP::G, RC = TP::RC, EP = TP::EP, RPW = TP::RPW;
+  constexpr int K = SH::K, B = SH::B, NACC = SH::NACC, MW = SH::MW, MWS = SH::MWS;
+  constexpr int NV = pow2_at_least(NACC);
+  extern __shared__ float4 smem[];
+  float4 *sgeo = smem;                                      // [B][kGeo]
+  float *scf = (float *)(smem + kGeo * B);                  // [B][2K]
+  float *sacc = scf + 2 * K * B;                            // [B][NACC]   (adjoint)
+  int *sflag = (int *)(sacc + (BWD ? NACC * B : 0));        // [B]         (adjoint)
+  uint32_t *smask = (uint32_t *)(sflag + (BWD ? B : 0));    // [R][MWS]
+  uint32_t *suni = smask + R * MWS;                         // [4][MW]
+  int *sdone = (int *)(suni + 4 * MW);                      // [R]
+  const int gt = blockIdx.x;
+  const int k = gt / a.T;
+  const int tile = gt - k * a.T;
+  const int tv = tile / a.nta, tu = tile - tv * a.nta;
+  const int th_ = R / a.tw;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // phase-2 identity: ray r, lane q of its group
+  const int r = tid / G, q = tid % G;
+  const int u = tu * a.tw + r % a.tw, v = tv * th_ + r / a.tw;
+  const bool valid = (u < a.n_az) && (v < a.n_el);
+  // phase-1 identity: ray r1, entry phase e
+  const int r1 = (wave % RC) * 64 + lane, e = wave / RC;
+  const int u1 = tu * a.tw + r1 % a.tw, v1 = tv * th_ + r1 / a.tw;
+  const bool valid1 = (u1 < a.n_az) && (v1 < a.n_el);
+  const gsrf_pair pr = a.pairs[k];
+  const double lam = kC0 / pr.freq_hz;
+  float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
+  ray_setup<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
+  float wx, wy, wz;
+  {
+    double al, sb;
+    ray_dir(valid1 ? u1 : 0, valid1 ? v1 : 0, a, wx, wy, wz, al, sb);
+  }
+  float twopi_lam = 0.f, Sfr = 0.f, Sfi = 0.f, Gr = 0.f, Gi = 0.f;
+  if constexpr (BWD) {
+    twopi_lam = (float)(2.0 * 3.14159265358979323846 / lam);
+    if (valid) {
+      const size_t ri = ((size_t)k * a.n_el + v) * a.n_az + u;
+      const float2 sf = io.signal[ri], gg = io.grad_signal[ri];
+      Sfr = sf.x; Sfi = sf.y; Gr = gg.x; Gi = gg.y;
+      if (io.grad_sum) {
+        const float2 gs = io.grad_sum[k];
+        Gr += gs.x;
+        Gi += gs.y;
+      }
+    }
+    for (int i = tid; i < NACC * B; i += NT) sacc[i] = 0.f;
+    for (int i = tid; i < B; i += NT) sflag[i] = 0;
+  }
+  const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
+  float T = 1.f, Sr = 0.f, Si = 0.f, Pr = 0.f, Pi = 0.f;
+  bool done = !valid || (1.0f < a.t_min);
+  if (q == 0) sdone[r] = done ? 1 : 0;
+  unsigned long long n_test = 0, n_hit = 0, n_staged = 0, n_tile_tests = 0;
+  int n_valid_rays = 0;
+  if constexpr (STATS) {
+    const int tu_w = min(a.tw, a.n_az - tu * a.tw), tv_h = min(th_, a.n_el - tv * th_);
+    n_valid_rays = tu_w * tv_h;
+  }
+  for (uint32_t base = s0; base < s1; base += B) {
+    const int nb = (int)min((uint32_t)B, s1 - base);
+    __syncthreads();
+    if (tid < nb)
+      stage_entry<K>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], lam,
+                     sgeo + kGeo * tid, scf + 2 * K * tid);
+    for (int i = tid; i < R * MWS + 4 * MW; i += NT) smask[i] = 0u;   // ray rows and union rows
+    if (STATS && tid == 0) {
+      n_staged += nb;
+      n_tile_tests += (unsigned long long)nb * n_valid_rays;
+    }
+    __syncthreads();
+    // ---- phase 1 ----
+    if (valid1 && !sdone[r1]) {
+      const unsigned nt = phase1_tests<EP>(wx, wy, wz, sgeo, nb, e, a.r_rx, smask + r1 * MWS, suni + (r1 / RPW) * MW);
+      if (STATS) n_test += nt;
+    }
+    __syncthreads();
+    // ---- phase 2: walk the wave's union, G entries per step ----
+    if (__ballot(!done) != 0) {                              // wave-uniform
+      const uint32_t *uw = suni + wave * MW;
+      const uint32_t *mine = smask + r * MWS;
+      int wi = 0;
+      uint32_t rb = __builtin_amdgcn_readfirstlane(uw[0]);
+      while (true) {
+        int j = -1, first = -1;
+#pragma unroll
+        for (int i = 0; i < G; ++i) {                        // scalar: the cursor is wave-uniform
+          while (rb == 0 && wi + 1 < MW) rb = __builtin_amdgcn_readfirstlane(uw[++wi]);
+          int jj = -1;
+          if (rb != 0) {
+            jj = wi * 32 + __builtin_ctz(rb);
+            rb &= rb - 1;
+          }
+          if (i == 0) first = jj;
+          if (q == i) j = jj;
+        }
+        if (first < 0) break;
+        const bool hit = !done && j >= 0 && ((mine[j >> 5] >> (j & 31)) & 1u);
+        const float4 *geo = sgeo + kGeo * (j >= 0 ? j : 0);
+        Terms h;
+        float f = 1.f, ctr = 0.f, cti = 0.f;
+        if (hit) {
+          test_hit(vx, vy, vz, geo, a.r_rx, h);               // the terms of the phase-1 hit
+          hit_terms<K>(geo, scf + 2 * K * j, Yr, Yi, a.amax, h);
+          f = 1.0f - h.alpha;
+          ctr = h.p * h.pzr;
+          cti = h.p * h.pzi;
+        }
+        float excl, total;
+        group_prod<G>(f, q, excl, total);
+        const float Tj = T * excl;
+        const bool proc = hit && (Tj >= a.t_min);
+        if constexpr (!BWD) {
+          if (proc) {
+            Sr = fmaf(Tj, ctr, Sr);
+            Si = fmaf(Tj, cti, Si);
+            if (STATS) ++n_hit;
+          }
+          T = T * total;
+          done = done || (T < a.t_min);
+        } else {
+          const float wr = proc ? Tj * ctr : 0.f, wi_ = proc ? Tj * cti : 0.f;
+          float wr_in, wi_in, wr_tot, wi_tot;
+          group_sum<G>(wr, q, wr_in, wr_tot);
+          group_sum<G>(wi_, q, wi_in, wi_tot);
+          T = T * total;
+          done = done || (T < a.t_min);
+          if (__ballot(proc) != 0) {
+            float c[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) c[i] = 0.f;
+            if (proc) {
+              const float Rr = Sfr - (Pr + wr_in), Ri = Sfi - (Pi + wi_in);
+              hit_adjoint<K, NV>(h, geo, Tj, ctr, cti, Rr, Ri, Gr, Gi, vx, vy, vz, Yr, Yi, twopi_lam, c);
+              sflag[j] = 1;
+            }
+            int first_slot;
+            bool writer;
+            reduce_scatter<NV, G>(c, lane, &first_slot, &writer);
+            constexpr int NF = (NV * G >= 64) ? NV * G / 64 : 1;
+            if (writer && j >= 0) {
+              float *dst = sacc + NACC * j;
+#pragma unroll
+              for (int i = 0; i < NF; ++i)
+                if (first_slot + i < NACC) atomicAdd(dst + first_slot + i, c[i]);
+            }
+          }
+          Pr += wr_tot;
+          Pi += wi_tot;
+        }
+        if (__ballot(!done) == 0) break;
+      }
+      if (q == 0 && done) sdone[r] = 1;
+    }
+    if constexpr (BWD) {
+      __syncthreads();
+      if (tid < nb && sflag[tid]) {
+        flush_entry<K>(a, a.val[base + tid], pr, sacc + NACC * tid, io.n_gauss, io.acc);
+        sflag[tid] = 0;
+      }
+    }
+    if (__syncthreads_and(done ? 1 : 0)) break;
+  }
+  if constexpr (!BWD) {
+    if constexpr (G > 1) {   // the ray's total over its G lanes
+#pragma unroll
+      for (int d = 1; d < G; d <<= 1) {
+        Sr += __shfl_xor(Sr, d, G);
+        Si += __shfl_xor(Si, d, G);
+      }
+    }
+    if constexpr (STATS) {
+      if (n_test) atomicAdd(io.stats + 0, n_test);
+      if (n_hit) atomicAdd(io.stats + 1, n_hit);
+      if (n_staged) atomicAdd(io.stats + 2, n_staged);
+      if (valid && q == 0) atomicAdd(io.stats + 3, 1ull);
+      if (n_tile_tests) atomicAdd(io.stats + 4, n_tile_tests);
+      return;
+    }
+    if (valid && q == 0) io.signal[((size_t)k * a.n_el + v) * a.n_az + u] = make_float2(Sr, Si);
+    __syncthreads();
+    float *red = (float *)smem;
+    red[tid] = (q == 0) ? Sr : 0.f;
+    red[NT + tid] = (q == 0) ? Si : 0.f;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+        red[tid] += red[tid + off];
+        red[NT + tid] += red[NT + tid + off];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) io.tile_sum[gt] = make_float2(red[0], red[NT]);
+  }
+}
+
+template <int L, int R, int MODE>
+hipError_t tp_launch(const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
+  constexpr size_t lds = TpShape<L, R, MODE>::lds();
+  if constexpr (lds > 65536) {   // high FLE degrees: opt in to more than 64 KB of LDS
+    const hipError_t e =
+        hipFuncSetAttribute((const void *)k_render_tp<L, R, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_render_tp<L, R, MODE>), dim3((unsigned)nblocks), dim3(256), lds, s, a, io);
+  return hipGetLastError();
+}
+
+template <int L, int MODE>
+hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
+  switch (area) {
+    case 64: return tp_launch<L, 64, MODE>(a, io, nblocks, s);
+    case 128: return tp_launch<L, 128, MODE>(a, io, nblocks, s);
+    default: return tp_launch<L, 256, MODE>(a, io, nblocks, s);
+  }
+}
+
+}  // namespace gsrf

@@ -39,7 +39,7 @@ class Grid:
     alpha_max: float = 0.99
     tile_w: int = 16
     tile_h: int = 16
-    lanes_per_ray: int = 1
+    lanes_per_ray: int = 0
 
     @property
     def K(self) -> int:

@@ -93,11 +93,12 @@ def test_workspace_size_and_layout():
     offs = [lay.rec_key, lay.rec_rect, lay.rec_base, lay.counters, lay.sorted_klo, lay.sorted_val,
             lay.tile_start, lay.tile_end]
     assert all(o % 256 == 0 and o < n.value for o in offs)
-    # bigger capacity, bigger workspace
+    # bigger capacity, bigger workspace: six 4-byte arrays per splat (emitted
+    # key/id, sorted key/id, merge ping-pong key/id)
     p2, keep2 = _host_problem(cap=100000)
     n2 = ctypes.c_size_t()
     assert L.gsrf_workspace_size(ctypes.byref(p2), ctypes.byref(n2)) == 0
-    assert n2.value > n.value + 100000 * 24
+    assert n2.value - n.value >= (100000 - 1000) * 24
 
 
 @pytest.mark.parametrize("mutate,needle", [
