@@ -76,7 +76,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batched-pairs", type=int, default=32)
+    ap.add_argument("--batched", choices=("full", "small", "none"), default="full",
+                    help="batched workloads: full (256 pairs x 500k; 16 uneven scenes), small, or none")
+    ap.add_argument("--batched-pairs", type=int, default=256)
+    ap.add_argument("--batched-iters", type=int, default=5)
     ap.add_argument("--gaussians", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="8x8", help="tile_w x tile_h (64, 128 or 256 rays)")
@@ -150,6 +153,58 @@ def main() -> int:
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    def roofline(prob, bufs, bwd, pairs_timed=1):
+        """Eager instrumented pass: render kernel times (HIP events around the
+        kernels on their stream) and the algorithmic FLOPs of the traversal."""
+        ev1 = {k: [new_event()] for k in ("f0", "f1", "b0", "b1")}
+        run(prob, bufs, 1, bwd, ev1)
+        torch.cuda.synchronize()
+        t_f = ev1["f0"][0].elapsed_time(ev1["f1"][0]) * 1e-3
+        t_b = ev1["b0"][0].elapsed_time(ev1["b1"][0]) * 1e-3 if bwd else 0.0
+        st = prob.render_stats()
+        fp = flops_per(grid.K)
+        fl_f = st["tile_tests"] * fp["test"] + st["hits"] * fp["hit_fwd"]
+        fl_b = st["tile_tests"] * fp["test"] + st["hits"] * fp["hit_bwd"]
+        dom, fl, tk = ("render_bwd", fl_b, t_b) if (bwd and t_b >= t_f) else ("render_fwd", fl_f, t_f)
+        ach = fl / tk
+        return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP32_VALU, "traffic": None, "kernel": dom, "kernel_ms": tk * 1e3,
+                "flop_per_launch": fl, "counts": st}
+
+    def run_batched(b, grad, label):
+        from paper_2502_01826_amd.batch import GraphStep, autotune
+        cat, offs = b.concat()
+        prm = dict(means=cat.means, log_scales=cat.log_scales, quats=cat.quats, logits=cat.logits,
+                   coeffs=cat.coeffs)
+        P = len(b.pairs)
+
+        def build(g):
+            return Problem(prm, b.pairs, g, scene_offsets=offs)
+
+        def make_grad(prob):
+            return (torch.from_numpy(synth.cotangent((P, grid.n_el, grid.n_az), seed=13)).to(dev),
+                    torch.from_numpy(synth.cotangent((P,), seed=14)).to(dev))
+
+        tune = autotune(build, grid, grad=grad, make_grad=make_grad, iters=2)
+        tw, th, lanes = tune.best
+        g = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=lanes)
+        prob = build(g)
+        gs, gsum = make_grad(prob) if grad else (None, None)
+        step = GraphStep(prob, grad, gs, gsum)
+        t = step.time(iters=args.batched_iters, warmup=1)
+        bufs = dict(sig=step.signal, ssum=step.signal_sum, rssi=step.rssi, G=gs, gsum=gsum, grads=step.grads)
+        roof = roofline(prob, bufs, grad)
+        n_splats, _ = prob.splat_count()
+        roof["counts"]["splats"] = n_splats
+        del step, prob
+        torch.cuda.empty_cache()
+        return {"workload": label, "pairs": P, "gaussians": int(cat.means.shape[0]),
+                "spectra_per_s": P / t, "ms_per_replay": t * 1e3, "timing": "median of hipGraph replays "
+                "(project+bin_sort+render_fwd" + ("+render_bwd" if grad else "") + " for all pairs)",
+                "tile": f"{tw}x{th}", "lanes_per_ray": lanes,
+                "autotune_ms": {f"{a}x{b_}/{c}": v * 1e3 for (a, b_, c), v in tune.seconds.items()},
+                "roofline": roof}
+
     # ---- plain: one pair per launch sequence (the headline step) -------------
     prob, bufs = make([pair])
     ev = {k: [new_event() for _ in range(args.steps)] for k in ("f0", "f1", "b0", "b1")}
@@ -162,8 +217,8 @@ def main() -> int:
     n_splats, _ = prob.splat_count()
     K = grid.K
     f = flops_per(K)
-    fl_fwd = stats["tests"] * f["test"] + stats["hits"] * f["hit_fwd"]
-    fl_bwd = stats["tests"] * f["test"] + stats["hits"] * f["hit_bwd"]
+    fl_fwd = stats["tile_tests"] * f["test"] + stats["hits"] * f["hit_fwd"]
+    fl_bwd = stats["tile_tests"] * f["test"] + stats["hits"] * f["hit_bwd"]
     if t_bwd_k >= t_fwd_k:
         dom, fl, tk = "render_bwd", fl_bwd, t_bwd_k
     else:
@@ -175,18 +230,22 @@ def main() -> int:
             "immediately around the render kernel on its stream, averaged over the timed steps",
             "counts": {**stats, "splats": n_splats}}
 
-    # ---- batched: many pairs of the same scene in one launch sequence --------
+    # ---- batched: all pairs of a batch in one hipGraph replay -----------------
     batched = None
-    if args.batched_pairs > 1:
-        rng = np.random.default_rng([4, 1])
-        pairs = [synth.draw_pair(rng, (10.0, 8.0, 3.0), 5.0e9) for _ in range(args.batched_pairs)]
-        bprob, bbufs = make(pairs)
-        bsteps = max(2, args.steps // 4)
-        tb_fb = timed(bprob, bbufs, bsteps, 1, True)
-        tb_f = timed(bprob, bbufs, bsteps, 1, False)
-        batched = {"pairs": args.batched_pairs, "fwd_bwd_spectra_per_s": args.batched_pairs / tb_fb,
-                   "fwd_spectra_per_s": args.batched_pairs / tb_f, "ms_per_launch_fwd_bwd": tb_fb * 1e3}
-        del bprob, bbufs
+    if args.batched != "none":
+        batched = {}
+        small = args.batched == "small"
+        b4 = synth.batched(n=100_000 if small else 500_000, n_pairs=16 if small else args.batched_pairs)
+        batched["fwd_500k"] = run_batched(b4, grad=False, label="batched forward: {} pairs over one {}-Gaussian "
+                                          "room, 360x90 rays, 5 GHz".format(len(b4.pairs), b4.scenes[0].n))
+        del b4
+        b5 = synth.batched_uneven(n_scenes=4 if small else 16, n_hi=100_000 if small else 1_000_000,
+                                  pairs_hi=8 if small else 64)
+        batched["uneven_fwd_bwd"] = run_batched(
+            b5, grad=True, label="batched uneven fwd+bwd: {} scenes ({}-{} Gaussians), {} pairs, carriers "
+            "2.4/5/5.8 GHz, 360x90 rays".format(len(b5.scenes), min(s_.n for s_ in b5.scenes),
+                                                max(s_.n for s_ in b5.scenes), len(b5.pairs)))
+        del b5
 
     cpu = None
     if not args.no_cpu_baseline:

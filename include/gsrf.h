@@ -56,11 +56,12 @@ typedef enum gsrf_status {
  *   t_min      a ray stops before the first hit whose transmittance < t_min.
  *   alpha_max  opacity clamp, in (0, 1).
  *   tile_w/h   rays per tile (App. E uses 16 x 16); tile_w * tile_h must be
- *              64, 128 or 256.
+ *              32 (two-phase traversal only), 64, 128 or 256.
  *   lanes_per_ray  traversal of a tile's depth-ordered list by the render
  *              kernels.  0 (recommended): two-phase traversal per staged
  *              batch, all (ray, entry) hit tests first, then the per-hit work
- *              on hits only, by 256 / (tile_w * tile_h) lanes per ray.
+ *              on hits only, by 256 / (tile_w * tile_h) lanes per ray (8, 4,
+ *              2 or 1).
  *              1, 2 or 4: direct traversal, that many lanes per ray, each
  *              testing and processing a different entry.  Every value gives
  *              the same hit decisions; the results agree to rounding.

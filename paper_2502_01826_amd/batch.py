@@ -1,0 +1,108 @@
+"""Batched execution: a whole batch of (pair, scene) work items as one
+hipGraph replay, and a tile-shape autotuner that picks the launch
+configuration by timing replays on the actual workload.
+
+A batch is one ``Problem`` holding every scene (CSR-concatenated) and every
+TX/RX pair; project, bin_sort, render_fwd and (optionally) render_bwd each
+cover all pairs in one launch sequence, and the sequence is captured once
+into a graph.  The splat capacity is fixed before capture (one eager pass
+measures it), so a replay never synchronises with the host; a caller whose
+inputs change between replays checks ``Problem.splat_count()`` afterwards.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import torch
+
+from .render import GridSpec, Problem
+
+# Launch configurations the tuner tries: (tile_w, tile_h, lanes_per_ray).
+DEFAULT_CANDIDATES = ((8, 4, 0), (8, 8, 0), (16, 8, 0))
+
+
+class GraphStep:
+    """project -> bin_sort -> render_fwd [-> render_bwd] of a Problem, captured in a graph.
+
+    Outputs live in preallocated tensors (``signal``, ``signal_sum``, ``rssi``,
+    ``grads``) that every replay overwrites.
+    """
+
+    def __init__(self, prob: Problem, grad: bool = False, grad_signal=None, grad_sum=None):
+        self.prob, self.grad = prob, grad
+        dev, g, P = prob.device, prob.grid, prob.n_pairs
+        prob.prepare()                       # sizes the splat buffers (one host sync)
+        prob.auto_capacity = False
+        self.signal = torch.empty((P, g.n_el, g.n_az, 2), dtype=torch.float32, device=dev)
+        self.signal_sum = torch.empty((P, 2), dtype=torch.float32, device=dev)
+        self.rssi = torch.empty((P,), dtype=torch.float32, device=dev)
+        self.grads = None
+        if grad:
+            G, K = prob.n_gauss, g.K
+            e = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+            self.grads = (e(G, 3), e(G, 3), e(G, 4), e(G), e(G, K, 2))
+            self.grad_signal = grad_signal if grad_signal is not None else torch.zeros_like(self.signal)
+            self.grad_sum = grad_sum
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):        # one eager pass off the default stream before capture
+            self._launch()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._launch()
+
+    def _launch(self):
+        p = self.prob
+        p.project()
+        p.bin_sort()
+        p.render_fwd(self.signal, self.signal_sum, self.rssi)
+        if self.grad:
+            p.render_bwd(self.signal, self.grad_signal, self.grad_sum, out=self.grads)
+
+    def replay(self):
+        self.graph.replay()
+
+    def time(self, iters: int = 5, warmup: int = 1) -> float:
+        """Median seconds per replay, bracketed by device synchronisation."""
+        for _ in range(warmup):
+            self.replay()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(iters):
+            t0 = time.perf_counter()
+            self.replay()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        return ts[len(ts) // 2]
+
+
+@dataclass
+class TuneResult:
+    best: tuple
+    seconds: dict = field(default_factory=dict)     # candidate -> median seconds per replay
+
+
+def autotune(build, grid, candidates=DEFAULT_CANDIDATES, grad: bool = False, iters: int = 3,
+             make_grad=None) -> TuneResult:
+    """Time one graph replay per launch configuration and return the fastest.
+
+    ``build(grid)`` returns a fresh Problem for a grid; ``make_grad(prob)``
+    returns (grad_signal, grad_sum) when ``grad``.  Each candidate's problem is
+    released before the next is built, so peak memory is one batch.
+    """
+    res = TuneResult(best=None)
+    base = GridSpec.of(grid)
+    for tw, th, lanes in candidates:
+        g = GridSpec(**{**base.__dict__, "tile_w": tw, "tile_h": th, "lanes_per_ray": lanes})
+        prob = build(g)
+        gs, gsum = make_grad(prob) if (grad and make_grad) else (None, None)
+        step = GraphStep(prob, grad, gs, gsum)
+        res.seconds[(tw, th, lanes)] = step.time(iters=iters)
+        del step, prob
+        torch.cuda.empty_cache()
+    res.best = min(res.seconds, key=res.seconds.get)
+    return res

@@ -42,10 +42,12 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
     return fail(GSRF_EINVAL, "grid size %d x %d out of range [1, 65535]", g.n_az, g.n_el);
   if (g.fle_L < 0 || g.fle_L > 6) return fail(GSRF_EINVAL, "fle_L = %d outside [0, 6]", g.fle_L);
   const int nt = g.tile_w * g.tile_h;
-  if (g.tile_w <= 0 || g.tile_h <= 0 || (nt != 64 && nt != 128 && nt != 256))
-    return fail(GSRF_EINVAL, "tile %d x %d: tile_w * tile_h must be 64, 128 or 256", g.tile_w, g.tile_h);
+  if (g.tile_w <= 0 || g.tile_h <= 0 || (nt != 32 && nt != 64 && nt != 128 && nt != 256))
+    return fail(GSRF_EINVAL, "tile %d x %d: tile_w * tile_h must be 32, 64, 128 or 256", g.tile_w, g.tile_h);
   if (g.lanes_per_ray != 0 && g.lanes_per_ray != 1 && g.lanes_per_ray != 2 && g.lanes_per_ray != 4)
     return fail(GSRF_EINVAL, "lanes_per_ray = %d: must be 0, 1, 2 or 4", g.lanes_per_ray);
+  if (nt == 32 && g.lanes_per_ray != 0)
+    return fail(GSRF_EINVAL, "32-ray tiles need the two-phase traversal (lanes_per_ray = 0)");
   if (!(g.el_lo < g.el_hi) || g.el_lo < -1.5707964f || g.el_hi > 1.5707964f)
     return fail(GSRF_EINVAL, "elevation span [%g, %g] invalid", (double)g.el_lo, (double)g.el_hi);
   if (!(g.r_rx >= 0.f) || !(g.t_min >= 0.f) || !(g.alpha_max > 0.f && g.alpha_max < 1.f))

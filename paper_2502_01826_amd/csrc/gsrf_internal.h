@@ -20,8 +20,8 @@ constexpr float kLevel = 9.0f;
 constexpr int kPrep = 16;
 
 // Binning: splats are emitted into per-tile buckets (key, Gaussian) and each
-// tile's bucket is sorted by one workgroup of kTileSortThreads threads, in LDS
-// chunks of at most `sort_chunk` entries (merged in global memory if longer).
+// tile's bucket is sorted by one workgroup of kTileSortThreads threads, through
+// LDS for buckets of at most `sort_chunk` entries, else through global scratch.
 constexpr int kTileSortThreads = 1024;
 constexpr int kMaxTiles = 8192;           // per pair; LDS histograms in project/emit
 constexpr int kRecPerThread = 1;          // records per thread in project/emit
@@ -80,7 +80,7 @@ struct Layout {
   size_t scan_blk;        // per-block totals of the tile-count scan
   size_t ekey, eval;      // emitted buckets (unsorted)
   size_t klo, val;        // sorted tile lists: depth key, Gaussian id
-  size_t tkey, tval;      // merge scratch
+  size_t tkey, tval;      // sort scratch for buckets longer than the LDS chunk
   size_t tile_sum, grad_acc;
   size_t total;
   int64_t n_records;
@@ -88,8 +88,6 @@ struct Layout {
   int64_t cap;
   int32_t T, nta, nte;
   int32_t K, acc_stride;
-  int32_t sort_chunk;     // entries sorted in LDS at once
-  size_t sort_lds;        // dynamic LDS bytes of the tile sort
 };
 
 inline int fle_K(int L) { return (L + 1) * (L + 1); }

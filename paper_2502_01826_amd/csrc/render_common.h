@@ -230,14 +230,18 @@ __device__ __forceinline__ void hit_terms(const float4 *geo, const float *cf, co
 
 // ---------------------------------------------------------------------------
 // Cross-lane primitives without LDS traffic.  The G lanes of a ray are
-// adjacent and G <= 4, so a ray's group never leaves a DPP quad; the
-// reduce-scatter over the rays of a wave pairs lanes at distance 32 and 16
-// with the gfx950 permlane swaps and at 8, 4, 2, 1 with row rotation,
-// swizzle and quad permutations.
+// adjacent and G <= 8, so a ray's group stays inside a DPP quad (G <= 4) or
+// a half row (G = 8); the reduce-scatter over the rays of a wave pairs lanes
+// at distance 32 and 16 with the gfx950 permlane swaps and at 8, 4, 2, 1
+// with row rotation, swizzle and quad permutations.
 // ---------------------------------------------------------------------------
 constexpr int quad_perm(int l0, int l1, int l2, int l3) { return l0 | (l1 << 2) | (l2 << 4) | (l3 << 6); }
 constexpr int kDppRowRor8 = 0x128;        // lane i of a 16-lane row reads lane (i + 8) mod 16 = i ^ 8
+constexpr int kDppRowShr1 = 0x111;        // lane i of a row reads lane i - 1 (row_shr:1)
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShr4 = 0x114;
 constexpr int kSwizzleXor4 = 0x101F;      // bit-mask swizzle: and 0x1f, or 0, xor 4
+constexpr int kSwizzleLast8 = 0x00F8;     // bit-mask swizzle: and 0x18, or 7 (last lane of the 8-lane group)
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
@@ -293,7 +297,7 @@ __device__ __forceinline__ void group_prod(float f, int q, float &excl, float &t
     const float incl = (q >= 1) ? f * lo : f;
     excl = (q == 0) ? 1.f : lo;
     total = dpp<quad_perm(1, 1, 3, 3)>(incl);
-  } else {
+  } else if constexpr (G == 4) {
     const float s1 = dpp<quad_perm(0, 0, 1, 2)>(f);
     const float x = (q >= 1) ? f * s1 : f;
     const float s2 = dpp<quad_perm(0, 1, 0, 1)>(x);
@@ -301,6 +305,17 @@ __device__ __forceinline__ void group_prod(float f, int q, float &excl, float &t
     const float e = dpp<quad_perm(0, 0, 1, 2)>(incl);
     excl = (q == 0) ? 1.f : e;
     total = dpp<quad_perm(3, 3, 3, 3)>(incl);
+  } else {
+    static_assert(G == 8, "lanes per ray: 1, 2, 4 or 8");
+    const float s1 = dpp<kDppRowShr1>(f);
+    const float x = (q >= 1) ? f * s1 : f;
+    const float s2 = dpp<kDppRowShr2>(x);
+    const float y = (q >= 2) ? x * s2 : x;
+    const float s4 = dpp<kDppRowShr4>(y);
+    const float incl = (q >= 4) ? y * s4 : y;
+    const float e = dpp<kDppRowShr1>(incl);
+    excl = (q == 0) ? 1.f : e;
+    total = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(incl), kSwizzleLast8));
   }
 }
 
@@ -314,12 +329,21 @@ __device__ __forceinline__ void group_sum(float x, int q, float &incl, float &to
     const float lo = dpp<quad_perm(0, 0, 2, 2)>(x);
     incl = (q >= 1) ? x + lo : x;
     total = dpp<quad_perm(1, 1, 3, 3)>(incl);
-  } else {
+  } else if constexpr (G == 4) {
     const float s1 = dpp<quad_perm(0, 0, 1, 2)>(x);
     const float y = (q >= 1) ? x + s1 : x;
     const float s2 = dpp<quad_perm(0, 1, 0, 1)>(y);
     incl = (q >= 2) ? y + s2 : y;
     total = dpp<quad_perm(3, 3, 3, 3)>(incl);
+  } else {
+    static_assert(G == 8, "lanes per ray: 1, 2, 4 or 8");
+    const float s1 = dpp<kDppRowShr1>(x);
+    const float y = (q >= 1) ? x + s1 : x;
+    const float s2 = dpp<kDppRowShr2>(y);
+    const float z = (q >= 2) ? y + s2 : y;
+    const float s4 = dpp<kDppRowShr4>(z);
+    incl = (q >= 4) ? z + s4 : z;
+    total = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(incl), kSwizzleLast8));
   }
 }
 

@@ -1,12 +1,12 @@
 // Two-phase traversal of a tile's depth-ordered list (256 threads per
-// (pair, tile), R = 64, 128 or 256 rays), used by both the forward renderer
+// (pair, tile), R = 32, 64, 128 or 256 rays), used by both the forward renderer
 // (Sec. 3.4 eq. rendering; App. A) and its adjoint (App. C; App. D).
 //
 // Only about one in six (ray, list entry) tests is a processed hit, so doing
 // the per-hit work where the test is made leaves most lanes idle.  Per staged
 // batch:
-//   phase 1  dense hit tests: wave w takes the 64 rays (w % RC) * 64 + lane
-//            against entries e, e + EP, ... (e = w / RC) and ORs the hits into
+//   phase 1  dense hit tests: thread t takes ray t % R against entries
+//            e, e + EP, ... (e = t / R, EP = 256 / R) and ORs the hits into
 //            per-ray bit rows in LDS, and into the union row of the phase-2
 //            wave that serves the ray;
 //   phase 2  each wave serves 64 / G rays with G = 256 / R adjacent lanes per
@@ -32,8 +32,7 @@ enum TpMode { kTpFwd = 0, kTpFwdStats = 1, kTpBwd = 2 };
 template <int R>
 struct TwoPhase {
   static constexpr int NT = 256;
-  static constexpr int RC = R / 64;        // ray chunks of 64 (phase 1)
-  static constexpr int EP = 4 / RC;        // entry phases per ray chunk (phase 1)
+  static constexpr int EP = NT / R;        // entry phases (phase 1): thread t takes ray t % R, entries t / R + k EP
   static constexpr int G = NT / R;         // lanes per ray (phase 2)
   static constexpr int RPW = 64 / G;       // rays per wave (phase 2)
 };
@@ -96,7 +95,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   using TP = TwoPhase<R>;
   using SH = TpShape<L, R, MODE>;
   constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats;
-  constexpr int NT = TP::NT, G = TP::G, RC = TP::RC, EP = TP::EP, RPW = TP::RPW;
+  constexpr int NT = TP::NT, G = TP::G, EP = TP::EP, RPW = TP::RPW;
   constexpr int K = SH::K, B = SH::B, NACC = SH::NACC, MW = SH::MW, MWS = SH::MWS;
   constexpr int NV = pow2_at_least(NACC);
   extern __shared__ float4 smem[];
@@ -118,7 +117,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   const int u = tu * a.tw + r % a.tw, v = tv * th_ + r / a.tw;
   const bool valid = (u < a.n_az) && (v < a.n_el);
   // phase-1 identity: ray r1, entry phase e
-  const int r1 = (wave % RC) * 64 + lane, e = wave / RC;
+  const int r1 = tid % R, e = tid / R;
   const int u1 = tu * a.tw + r1 % a.tw, v1 = tv * th_ + r1 / a.tw;
   const bool valid1 = (u1 < a.n_az) && (v1 < a.n_el);
   const gsrf_pair pr = a.pairs[k];
@@ -308,6 +307,7 @@ hipError_t tp_launch(const RenderArgs &a, const TpIO &io, int64_t nblocks, hipSt
 template <int L, int MODE>
 hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
   switch (area) {
+    case 32: return tp_launch<L, 32, MODE>(a, io, nblocks, s);
     case 64: return tp_launch<L, 64, MODE>(a, io, nblocks, s);
     case 128: return tp_launch<L, 128, MODE>(a, io, nblocks, s);
     default: return tp_launch<L, 256, MODE>(a, io, nblocks, s);

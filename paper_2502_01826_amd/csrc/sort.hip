@@ -7,12 +7,10 @@
 // same order -- (distance key, Gaussian index) within each tile -- with one
 // pass over the splats instead of one per key byte.
 //
-// A bucket of up to `chunk` entries is sorted in LDS by a four-pass stable LSD
-// radix sort on the 32-bit distance key (wave64 ballots rank equal digits),
-// after which runs of equal keys are ordered by Gaussian index.  A longer
-// bucket is sorted chunk by chunk and the sorted runs are merged pairwise in
-// global memory (merge-path partitioning across the workgroup).  No
-// workgroup ever waits on another, so every wave finishes.
+// Each bucket is sorted by one MSD counting pass and a rank within the small
+// sub-buckets it makes (below), in LDS for buckets of up to `chunk` entries
+// and through global scratch for longer ones.  No workgroup ever waits on
+// another, so every wave finishes.
 #include "gsrf_internal.h"
 
 namespace gsrf {
@@ -75,208 +73,152 @@ __global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pair
 }
 
 // ---------------------------------------------------------------------------
-// Workgroup-level pieces of the tile sort (kTileSortThreads threads).
+// a4: per-tile sort by (distance key, Gaussian index), one workgroup per tile.
+//
+// Each entry is the 64-bit composite c = key << 32 | index (unique within a
+// tile).  One MSD counting pass splits the bucket into 2^b sub-buckets of
+// c - c_min (about eight entries each, b <= 11): histogram, exclusive scan and
+// scatter.  Each entry's final place is then its sub-bucket's start plus its
+// rank among the sub-bucket's entries, found by comparing with all of them;
+// sub-buckets are small, so this costs a few comparisons per entry and no
+// further passes.  The scatter buffer is LDS for buckets of up to `chunk`
+// entries and global scratch for longer ones.  The result does not depend on
+// the (atomic) scatter order, so it is deterministic.
 // ---------------------------------------------------------------------------
 constexpr int kSortWaves = kTileSortThreads / 64;
+constexpr int kSortBitsMax = 11;
+constexpr int kSortBins = 1 << kSortBitsMax;
 
-struct SortLds {
-  uint32_t *ak, *av, *bk, *bv;    // ping-pong buffers [chunk]
-  uint32_t *hist, *run;           // [256] each
-  uint32_t *wcnt, *wpre;          // [kSortWaves][256] each
-};
+__device__ __forceinline__ uint64_t composite(uint32_t k, uint32_t v) { return ((uint64_t)k << 32) | v; }
 
-__device__ __forceinline__ SortLds sort_lds_of(uint32_t *sm, int chunk) {
-  SortLds L;
-  L.ak = sm;
-  L.av = sm + chunk;
-  L.bk = sm + 2 * chunk;
-  L.bv = sm + 3 * chunk;
-  L.hist = sm + 4 * chunk;
-  L.run = L.hist + 256;
-  L.wcnt = L.run + 256;
-  L.wpre = L.wcnt + kSortWaves * 256;
-  return L;
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int d) {
+  const uint32_t lo = __shfl_xor((uint32_t)x, d, 64), hi = __shfl_xor((uint32_t)(x >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
 }
 
-// One stable counting pass on the byte at `shift` of the keys: src -> dst.
-__device__ void lsd_pass(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv, int n, int shift,
-                         const SortLds &L) {
+// Exclusive scan of cnt[0, nbins) into start[0, nbins) (nbins <= 2 * threads).
+__device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint32_t *wsum) {
   constexpr int NT = kTileSortThreads;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (tid < 256) L.hist[tid] = 0;
-  __syncthreads();
-  for (int i = tid; i < n; i += NT) atomicAdd(&L.hist[(sk[i] >> shift) & 255u], 1u);
-  __syncthreads();
-  // exclusive scan of the 256 digit counts by the first wave (4 bins per lane)
-  if (wave == 0) {
-    const uint32_t a0 = L.hist[4 * lane], a1 = L.hist[4 * lane + 1], a2 = L.hist[4 * lane + 2],
-                   a3 = L.hist[4 * lane + 3];
-    const uint32_t sum = a0 + a1 + a2 + a3;
-    uint32_t inc = sum;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (nbins + NT - 1) / NT;
+  const int lo = min(nbins, tid * per), hi = min(nbins, lo + per);
+  uint32_t local = 0;
+  for (int i = lo; i < hi; ++i) local += cnt[i];
+  uint32_t inc = local;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t y = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += y;
-    }
-    const uint32_t ex = inc - sum;
-    L.run[4 * lane] = ex;
-    L.run[4 * lane + 1] = ex + a0;
-    L.run[4 * lane + 2] = ex + a0 + a1;
-    L.run[4 * lane + 3] = ex + a0 + a1 + a2;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
   }
+  if (lane == 63) wsum[wave] = inc;
   __syncthreads();
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int b0 = 0; b0 < n; b0 += NT) {
-    const int i = b0 + tid;
-    const bool valid = i < n;
-    uint32_t key = 0, val = 0, d = 0;
-    if (valid) {
-      key = sk[i];
-      val = sv[i];
-      d = (key >> shift) & 255u;
-    }
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(valid && bit);
-      peers &= bit ? m : ~m;
-    }
-    const uint32_t rank = __popcll(peers & lt_mask);
-    if (valid && rank == 0) L.wcnt[wave * 256 + d] = __popcll(peers);
-    __syncthreads();
-    if (tid < 256) {
-      uint32_t r = L.run[tid];
-#pragma unroll
-      for (int w = 0; w < kSortWaves; ++w) {
-        L.wpre[w * 256 + tid] = r;
-        r += L.wcnt[w * 256 + tid];
-        L.wcnt[w * 256 + tid] = 0;
-      }
-      L.run[tid] = r;
-    }
-    __syncthreads();
-    if (valid) {
-      const uint32_t pos = L.wpre[wave * 256 + d] + rank;
-      dk[pos] = key;
-      dv[pos] = val;
-    }
+  uint32_t off = 0;
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+  uint32_t run = off + inc - local;
+  for (int i = lo; i < hi; ++i) {
+    start[i] = run;
+    run += cnt[i];
   }
-  __syncthreads();
 }
 
-// Sort n <= chunk entries held in (L.ak, L.av) by (key, value); result in place.
-__device__ void lds_sort(int n, const SortLds &L) {
-  lsd_pass(L.ak, L.av, L.bk, L.bv, n, 0, L);
-  lsd_pass(L.bk, L.bv, L.ak, L.av, n, 8, L);
-  lsd_pass(L.ak, L.av, L.bk, L.bv, n, 16, L);
-  lsd_pass(L.bk, L.bv, L.ak, L.av, n, 24, L);
-  // equal keys: order by Gaussian index (runs are short; the run's first
-  // element's thread insertion-sorts it)
-  for (int i = threadIdx.x; i < n; i += kTileSortThreads) {
-    const uint32_t k0 = L.ak[i];
-    if ((i > 0 && L.ak[i - 1] == k0) || i + 1 >= n || L.ak[i + 1] != k0) continue;
-    int e = i + 1;
-    while (e < n && L.ak[e] == k0) ++e;
-    for (int a = i + 1; a < e; ++a) {
-      const uint32_t v = L.av[a];
-      int b = a - 1;
-      while (b >= i && L.av[b] > v) {
-        L.av[b + 1] = L.av[b];
-        --b;
-      }
-      L.av[b + 1] = v;
+// Sort the n entries (ek, ev) by composite into (ok, ov) through the scatter
+// buffer (bk, bv); SH: the buffer is in LDS.
+template <bool SH>
+__device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *__restrict__ ev, int n, uint32_t *bk,
+                              uint32_t *bv, uint32_t *__restrict__ ok, uint32_t *__restrict__ ov, uint32_t *hist,
+                              uint32_t *start, uint64_t *red) {
+  constexpr int NT = kTileSortThreads;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t cmin = ~0ull, cmax = 0;
+  for (int i = tid; i < n; i += NT) {
+    const uint64_t c = composite(ek[i], ev[i]);
+    cmin = c < cmin ? c : cmin;
+    cmax = c > cmax ? c : cmax;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t a = shfl_xor_u64(cmin, d), b = shfl_xor_u64(cmax, d);
+    cmin = a < cmin ? a : cmin;
+    cmax = b > cmax ? b : cmax;
+  }
+  if (lane == 0) {
+    red[wave] = cmin;
+    red[kSortWaves + wave] = cmax;
+  }
+  __syncthreads();
+  if (wave == 0) {   // lanes 0..15 fold the wave results
+    uint64_t a = lane < kSortWaves ? red[lane] : ~0ull, b = lane < kSortWaves ? red[kSortWaves + lane] : 0ull;
+#pragma unroll
+    for (int d = kSortWaves / 2; d >= 1; d >>= 1) {
+      const uint64_t x = shfl_xor_u64(a, d), y = shfl_xor_u64(b, d);
+      a = x < a ? x : a;
+      b = y > b ? y : b;
+    }
+    if (lane == 0) {
+      red[2 * kSortWaves] = a;
+      red[2 * kSortWaves + 1] = b;
     }
   }
   __syncthreads();
-}
-
-__device__ __forceinline__ bool kv_less(uint32_t ka, uint32_t va, uint32_t kb, uint32_t vb) {
-  return ka < kb || (ka == kb && va < vb);
-}
-
-// Merge sorted runs A[0, la) and B[0, lb) (given as key/value arrays) into
-// out[0, la + lb); the workgroup splits the output by merge-path diagonals.
-__device__ void merge_runs(const uint32_t *Ak, const uint32_t *Av, int la, const uint32_t *Bk, const uint32_t *Bv,
-                           int lb, uint32_t *ok, uint32_t *ov) {
-  const int total = la + lb;
-  const int per = (total + kTileSortThreads - 1) / kTileSortThreads;
-  const int d0 = min(total, (int)threadIdx.x * per);
-  const int d1 = min(total, d0 + per);
-  if (d0 >= d1) return;
-  // number of A elements among the d0 smallest
-  int lo = max(0, d0 - lb), hi = min(d0, la);
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;     // take mid from A, d0 - mid from B
-    const int jb = d0 - mid - 1;
-    if (jb < 0 || kv_less(Bk[jb], Bv[jb], Ak[mid], Av[mid]))
-      hi = mid;
-    else
-      lo = mid + 1;
+  cmin = red[2 * kSortWaves];
+  cmax = red[2 * kSortWaves + 1];
+  int bits = 1;
+  while (bits < kSortBitsMax && (8 << bits) < n) ++bits;
+  const uint64_t span = cmax - cmin;
+  const int nbits = span ? 64 - __clzll(span) : 0;
+  const int shift = nbits > bits ? nbits - bits : 0;
+  const int nbins = 1 << bits;
+  for (int i = tid; i < nbins; i += NT) hist[i] = 0;
+  __syncthreads();
+  for (int i = tid; i < n; i += NT) atomicAdd(&hist[(uint32_t)((composite(ek[i], ev[i]) - cmin) >> shift)], 1u);
+  __syncthreads();
+  bins_scan(hist, start, nbins, (uint32_t *)(red + 2 * kSortWaves + 2));
+  __syncthreads();
+  for (int i = tid; i < nbins; i += NT) hist[i] = start[i];     // scatter cursors
+  __syncthreads();
+  for (int i = tid; i < n; i += NT) {
+    const uint32_t k = ek[i], v = ev[i];
+    const uint32_t p = atomicAdd(&hist[(uint32_t)((composite(k, v) - cmin) >> shift)], 1u);
+    bk[p] = k;
+    bv[p] = v;
   }
-  int i = lo, j = d0 - lo;
-  for (int d = d0; d < d1; ++d) {
-    const bool takeA = (j >= lb) || (i < la && kv_less(Ak[i], Av[i], Bk[j], Bv[j]));
-    if (takeA) {
-      ok[d] = Ak[i];
-      ov[d] = Av[i];
-      ++i;
-    } else {
-      ok[d] = Bk[j];
-      ov[d] = Bv[j];
-      ++j;
-    }
+  if (!SH) __threadfence_block();
+  __syncthreads();
+  // hist[d] is now the end of sub-bucket d
+  for (int p = tid; p < n; p += NT) {
+    const uint32_t k = bk[p], v = bv[p];
+    const uint64_t c = composite(k, v);
+    const uint32_t d = (uint32_t)((c - cmin) >> shift);
+    const int a = (int)start[d], e = (int)hist[d];
+    int rank = 0;
+#pragma unroll 2
+    for (int j = a; j < e; ++j) rank += composite(bk[j], bv[j]) < c ? 1 : 0;
+    ok[a + rank] = k;
+    ov[a + rank] = v;
   }
 }
 
 // a4: sort every tile's bucket; writes the sorted depth keys and Gaussian ids.
-__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(const uint32_t *__restrict__ tstart,
+__global__ __launch_bounds__(kTileSortThreads, 8) void k_tile_sort(const uint32_t *__restrict__ tstart,
                                                                 const uint32_t *__restrict__ tend, int chunk,
                                                                 const uint32_t *__restrict__ ekey,
                                                                 const uint32_t *__restrict__ eval,
                                                                 uint32_t *__restrict__ klo, uint32_t *__restrict__ val,
                                                                 uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval) {
-  extern __shared__ uint32_t sm[];
-  const SortLds L = sort_lds_of(sm, chunk);
+  extern __shared__ uint64_t sm64[];
+  uint64_t *red = sm64;                                     // wave min/max, totals, wave sums
+  uint32_t *hist = (uint32_t *)(sm64 + 4 * kSortWaves);     // [kSortBins]
+  uint32_t *start = hist + kSortBins;                       // [kSortBins]
+  uint32_t *sk = start + kSortBins;                         // [chunk]
+  uint32_t *sv = sk + chunk;                                // [chunk]
   const int gt = blockIdx.x;
   const uint32_t s0 = tstart[gt];
   const int n = (int)(tend[gt] - s0);
   if (n <= 0) return;
-  for (int i = threadIdx.x; i < kSortWaves * 256; i += kTileSortThreads) L.wcnt[i] = 0;
-  const int nruns = (n + chunk - 1) / chunk;
-  int passes = 0;
-  while ((1 << passes) < nruns) ++passes;
-  // runs go to the buffer from which an even number of merge passes ends in (klo, val)
-  uint32_t *rk = (passes & 1) ? tkey : klo, *rv = (passes & 1) ? tval : val;
-  uint32_t *ok_ = (passes & 1) ? klo : tkey, *ov_ = (passes & 1) ? val : tval;
-  for (int c = 0; c < nruns; ++c) {
-    const int b = c * chunk;
-    const int m = min(chunk, n - b);
-    __syncthreads();
-    for (int i = threadIdx.x; i < m; i += kTileSortThreads) {
-      L.ak[i] = ekey[s0 + b + i];
-      L.av[i] = eval[s0 + b + i];
-    }
-    __syncthreads();
-    lds_sort(m, L);
-    for (int i = threadIdx.x; i < m; i += kTileSortThreads) {
-      rk[s0 + b + i] = L.ak[i];
-      rv[s0 + b + i] = L.av[i];
-    }
-  }
-  for (int w = chunk; w < n; w *= 2) {
-    __syncthreads();   // the previous pass's (or the runs') writes are visible to the workgroup
-    __threadfence_block();
-    for (int a0 = 0; a0 < n; a0 += 2 * w) {
-      const int la = min(w, n - a0);
-      const int lb = max(0, min(w, n - a0 - la));
-      merge_runs(rk + s0 + a0, rv + s0 + a0, la, rk + s0 + a0 + la, rv + s0 + a0 + la, lb, ok_ + s0 + a0,
-                 ov_ + s0 + a0);
-    }
-    uint32_t *t1 = rk, *t2 = rv;
-    rk = ok_; rv = ov_;
-    ok_ = t1; ov_ = t2;
-  }
+  if (n <= chunk)
+    msd_rank_sort<true>(ekey + s0, eval + s0, n, sk, sv, klo + s0, val + s0, hist, start, red);
+  else
+    msd_rank_sort<false>(ekey + s0, eval + s0, n, tkey + s0, tval + s0, klo + s0, val + s0, hist, start, red);
 }
 
 static int g_sort_chunk = 0;
@@ -289,16 +231,16 @@ size_t max_lds_per_block() {
   return (size_t)v;
 }
 
+// Largest LDS chunk that still lets two 1024-thread workgroups share a CU.
 static void choose_sort_chunk() {
   if (g_sort_chunk) return;
-  const size_t fixed = (2 * 256 + 2 * kSortWaves * 256) * 4;
+  const size_t fixed = (size_t)4 * kSortWaves * 8 + (size_t)2 * kSortBins * 4;
   size_t lds = max_lds_per_block();
   if (lds > 160 * 1024) lds = 160 * 1024;
-  int chunk = (int)((lds - fixed) / 16);
-  chunk = (chunk / 512) * 512;
-  if (chunk > 8192) chunk = 8192;
+  int chunk = (int)((lds / 2 - fixed) / 8);
+  chunk = (chunk / 32) * 32;
   if (chunk < kTileSortThreads) chunk = kTileSortThreads;
-  g_sort_lds = fixed + (size_t)16 * chunk;
+  g_sort_lds = fixed + (size_t)8 * chunk;
   if (g_sort_lds > 65536)
     (void)hipFuncSetAttribute((const void *)k_tile_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g_sort_lds);
   g_sort_chunk = chunk;

@@ -103,6 +103,8 @@ def test_workspace_size_and_layout():
 
 @pytest.mark.parametrize("mutate,needle", [
     (lambda p: setattr(p.grid, "tile_w", 5), "tile"),
+    (lambda p: (setattr(p.grid, "tile_w", 8), setattr(p.grid, "tile_h", 4), setattr(p.grid, "lanes_per_ray", 1)),
+     "32-ray tiles"),
     (lambda p: setattr(p.grid, "fle_L", 7), "fle_L"),
     (lambda p: setattr(p.grid, "lanes_per_ray", 3), "lanes_per_ray"),
     (lambda p: setattr(p.grid, "n_az", 0), "grid size"),

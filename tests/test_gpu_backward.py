@@ -31,7 +31,8 @@ def _compare(gg, gr, tol=GTOL):
         assert num <= tol * den, n
 
 
-@pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (16, 8, 2), (8, 8, 0), (16, 8, 0), (16, 16, 0)])
+@pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (16, 8, 2), (8, 8, 0), (16, 8, 0), (16, 16, 0),
+                                     (8, 4, 0), (4, 8, 0)])
 def test_tiny_gradients_match_oracle(tw, th, G):
     b = synth.tiny(grid=Grid(n_az=36, n_el=9, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G))
     sc, p, g = b.scenes[0], b.pairs[0], b.grid
@@ -56,10 +57,10 @@ def test_tiny_gradients_match_oracle(tw, th, G):
     _compare(gg, gr)
 
 
-@pytest.mark.parametrize("L,G", [(0, 0), (1, 4), (3, 0), (6, 0), (6, 1)])
-def test_gradients_across_fle_degrees(L, G):
+@pytest.mark.parametrize("L,G,th", [(0, 0, 8), (1, 4, 8), (3, 0, 8), (6, 0, 8), (6, 1, 8), (0, 0, 4), (6, 0, 4)])
+def test_gradients_across_fle_degrees(L, G, th):
     """Adjoint at every FLE degree the kernels instantiate (K = 1 .. 49)."""
-    g = Grid(n_az=24, n_el=8, fle_L=L, tile_w=8, tile_h=8, lanes_per_ray=G)
+    g = Grid(n_az=24, n_el=8, fle_L=L, tile_w=8, tile_h=th, lanes_per_ray=G)
     rng = np.random.default_rng([101, L])
     sc = synth.draw_scene(rng, 800, (4.0, 4.0, 3.0), g.K)
     p = Pair(np.array([2.0, 2.1, 1.0], np.float32), np.array([0.5, 3.0, 2.0], np.float32), 5.8e9)
@@ -137,7 +138,7 @@ def test_autograd_function_l2_step():
     _compare({n: t.grad.cpu().numpy().astype(np.float64) for n, t in zip(NAMES, ps)}, gr, tol=2e-3)
 
 
-@pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (8, 8, 0), (16, 16, 0)])
+@pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (8, 8, 0), (16, 16, 0), (8, 4, 0)])
 def test_paper_scale_gradients_on_sampled_rays(tw, th, G):
     """200k Gaussians, 360x90: cotangent on 48 sampled rays only, compared with
     the oracle's gradient of the same rays."""

@@ -55,7 +55,8 @@ def test_forward_is_deterministic():
 
 
 @pytest.mark.parametrize("tw,th,G", [(8, 8, 1), (16, 8, 2), (32, 8, 1), (16, 16, 1), (8, 8, 4), (16, 16, 4),
-                                     (16, 8, 4), (8, 8, 2), (8, 8, 0), (16, 8, 0), (16, 16, 0), (32, 8, 0)])
+                                     (16, 8, 4), (8, 8, 2), (8, 8, 0), (16, 8, 0), (16, 16, 0), (32, 8, 0),
+                                     (8, 4, 0), (4, 8, 0)])
 def test_ragged_tiles_and_seam(tw, th, G):
     # 37 x 11 rays do not divide by any tile shape: ragged last column and row
     g = Grid(n_az=37, n_el=11, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G)
@@ -67,9 +68,10 @@ def test_ragged_tiles_and_seam(tw, th, G):
     compare_rays(S[0].ravel(), ref, sc, p, g)
 
 
-@pytest.mark.parametrize("L,G", [(0, 1), (1, 2), (3, 4), (4, 1), (6, 4), (5, 2), (0, 0), (1, 0), (3, 0), (6, 0)])
-def test_fle_degrees(L, G):
-    g = Grid(n_az=24, n_el=8, fle_L=L, tile_w=8, tile_h=8, lanes_per_ray=G)
+@pytest.mark.parametrize("L,G,th", [(0, 1, 8), (1, 2, 8), (3, 4, 8), (4, 1, 8), (6, 4, 8), (5, 2, 8), (0, 0, 8),
+                                    (1, 0, 8), (3, 0, 8), (6, 0, 8), (2, 0, 4), (6, 0, 4)])
+def test_fle_degrees(L, G, th):
+    g = Grid(n_az=24, n_el=8, fle_L=L, tile_w=8, tile_h=th, lanes_per_ray=G)
     rng = np.random.default_rng([100, L])
     sc = synth.draw_scene(rng, 800, (4.0, 4.0, 3.0), g.K)
     p = Pair(np.array([2.0, 2.1, 1.0], np.float32), np.array([0.5, 3.0, 2.0], np.float32), 5.8e9)
@@ -136,7 +138,7 @@ def test_multi_scene_multi_pair_batch():
         assert abs(Ssum[k] - S[k].sum()) <= 1e-5 * np.abs(S[k]).sum() + 1e-30
 
 
-@pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (16, 8, 2), (8, 8, 0), (16, 16, 0)])
+@pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (16, 8, 2), (8, 8, 0), (16, 16, 0), (8, 4, 0)])
 def test_paper_scale_sampled_rays_and_tiles(tw, th, G):
     """200k Gaussians, 360x90 rays, 5 GHz, at the launch configurations the
     benchmark times: sampled rays against the oracle, sampled tile lists bit
