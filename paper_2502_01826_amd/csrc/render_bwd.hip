@@ -39,7 +39,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
   const bool valid = (u < a.n_az) && (v < a.n_el);
   const int lane = threadIdx.x & 63;
   const gsrf_pair pr = a.pairs[k];
-  const double lam = kC0 / pr.freq_hz;
+  const double lam = kC0 / pr.freq_hz, inv_lam = pr.freq_hz / kC0;
   const float twopi_lam = (float)(2.0 * 3.14159265358979323846 / lam);
   float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
   ray_setup<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
     const int nb = (int)min((uint32_t)B, s1 - base);
     __syncthreads();
     if ((int)threadIdx.x < nb)
-      stage_entry<K>(a, a.val[base + threadIdx.x], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], lam,
+      stage_entry<K>(a, a.val[base + threadIdx.x], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                      sgeo + kGeo * threadIdx.x, scf + 2 * K * threadIdx.x);
     __syncthreads();
     if (__ballot(!done) != 0) {              // wave-uniform

@@ -115,7 +115,7 @@ __device__ void ray_setup(int u, int v, const RenderArgs &a, float &vx, float &v
 // ---------------------------------------------------------------------------
 template <int K>
 __device__ void stage_entry(const RenderArgs &a, uint32_t g, double rx, double ry, double rz, double tx,
-                            double ty, double tz, double lam, float4 *geo, float *cf) {
+                            double ty, double tz, double inv_lam, float4 *geo, float *cf) {
   const float *pg = a.prep + (size_t)kPrep * g;
   // prep record (64-byte aligned): (mu, N) (M00, M11, M22, M01) (M02, M12, o, -)
   const float4 *p4 = (const float4 *)pg;
@@ -129,9 +129,10 @@ __device__ void stage_entry(const RenderArgs &a, uint32_t g, double rx, double r
   const float h0 = (float)e0, h1 = (float)e1, h2 = (float)e2;
   const double qx = mx - tx, qy = my - ty, qz = mz - tz;
   const double dtx = sqrt((qx * qx + qy * qy) + qz * qz);
-  const double ph = (dtx + D) / lam;
+  const double ph = (dtx + D) * inv_lam;
   geo[0] = make_float4(h0, h1, h2, (float)D);
-  geo[1] = make_float4((float)(e0 - (double)h0), (float)(e1 - (double)h1), (float)(e2 - (double)h2), (float)(D / lam));
+  geo[1] = make_float4((float)(e0 - (double)h0), (float)(e1 - (double)h1), (float)(e2 - (double)h2),
+                       (float)(D * inv_lam));
   geo[2] = q1;
   geo[3] = make_float4(q2.x, q2.y, q0.w, q2.z);
   geo[4] = make_float4((float)(ph - floor(ph)), (float)D2, 0.f, 0.f);

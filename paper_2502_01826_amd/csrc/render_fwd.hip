@@ -32,7 +32,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
   const int v = tv * th_ + r / a.tw;
   const bool valid = (u < a.n_az) && (v < a.n_el);
   const gsrf_pair pr = a.pairs[k];
-  const double lam = kC0 / pr.freq_hz;
+  const double inv_lam = pr.freq_hz / kC0;
   float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
   ray_setup<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
   const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
     const int nb = (int)min((uint32_t)B, s1 - base);
     __syncthreads();
     if ((int)threadIdx.x < nb)
-      stage_entry<K>(a, a.val[base + threadIdx.x], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], lam,
+      stage_entry<K>(a, a.val[base + threadIdx.x], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                      sgeo + kGeo * threadIdx.x, scf + 2 * K * threadIdx.x);
     if (STATS && threadIdx.x == 0) {
       n_staged += nb;

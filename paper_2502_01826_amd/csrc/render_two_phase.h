@@ -61,31 +61,59 @@ struct TpShape {
   static constexpr size_t lds() { return kLds < 256 * 8 ? 256 * 8 : kLds; }
 };
 
-// Phase 1: hit bits of ray r1 against entries e, e + EP, ... < nb.
-template <int EP>
-__device__ __forceinline__ unsigned phase1_tests(float vx, float vy, float vz, const float4 *sgeo, int nb, int e,
-                                                 float r_rx, uint32_t *mask_row, uint32_t *uni_row) {
-  uint32_t bits = 0;
-  int cw = e >> 5;
+// Phase-1 hit test of ray v against a staged Gaussian: the decision of
+// test_hit (Q <= 9 and t >= r_rx) with A = v^T M v taken from the ray's
+// quadratic monomials and b = v . (M eps), which needs no M v (34 VALU
+// operations instead of 40).  The per-hit terms are recomputed by test_hit
+// in phase 2; only the decision is taken here, in both the forward and the
+// adjoint, so the two passes agree on every hit.
+struct RayMono {
+  float x, y, z, xx, yy, zz, xy2, xz2, yz2;
+};
+
+__device__ __forceinline__ RayMono ray_mono(float x, float y, float z) {
+  return RayMono{x, y, z, x * x, y * y, z * z, 2.f * x * y, 2.f * x * z, 2.f * y * z};
+}
+
+__device__ __forceinline__ bool hit_decision(const RayMono &v, const float4 *geo, float r_rx) {
+  const float4 g0 = geo[0], g1 = geo[1], g2 = geo[2], g3 = geo[3];
+  const float ex = (v.x - g0.x) - g1.x, ey = (v.y - g0.y) - g1.y, ez = (v.z - g0.z) - g1.z;
+  const float m00 = g2.x, m11 = g2.y, m22 = g2.z, m01 = g2.w, m02 = g3.x, m12 = g3.y;
+  const float n0 = fmaf(m00, ex, fmaf(m01, ey, m02 * ez));
+  const float n1 = fmaf(m01, ex, fmaf(m11, ey, m12 * ez));
+  const float n2 = fmaf(m02, ex, fmaf(m12, ey, m22 * ez));
+  const float A = fmaf(m00, v.xx, fmaf(m11, v.yy, fmaf(m22, v.zz, fmaf(m01, v.xy2, fmaf(m02, v.xz2, m12 * v.yz2)))));
+  const float b = fmaf(v.x, n0, fmaf(v.y, n1, v.z * n2));
+  const float c = fmaf(ex, n0, fmaf(ey, n1, ez * n2));
+  const float bA = b * __builtin_amdgcn_rcpf(A);
+  const float Q = geo[4].y * fmaf(-b, bA, c);
+  const float t = fmaf(-g0.w, bA, g0.w);
+  return (Q <= kLevel) && (t >= r_rx);
+}
+
+// Phase 1: hit bits of ray v against entries e, e + EP, ... < nb, one 32-entry
+// word at a time (32 / EP tests unrolled per word).
+template <int EP, int MW>
+__device__ __forceinline__ unsigned phase1_tests(const RayMono &v, const float4 *sgeo, int nb, int e, float r_rx,
+                                                 uint32_t *mask_row, uint32_t *uni_row) {
   unsigned n_test = 0;
-  for (int jj = e; jj < nb; jj += EP) {
-    Terms h;
-    const bool hit = test_hit(vx, vy, vz, sgeo + kGeo * jj, r_rx, h);
-    ++n_test;
-    const int w = jj >> 5;
-    if (w != cw) {
-      if (bits) {
-        atomicOr(mask_row + cw, bits);
-        atomicOr(uni_row + cw, bits);
+#pragma unroll 1
+  for (int w = 0; w < MW; ++w) {
+    const int j0 = w * 32;
+    if (j0 >= nb) break;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int i = 0; i < 32 / EP; ++i) {
+      const int jj = j0 + e + i * EP;
+      if (jj < nb) {
+        ++n_test;
+        if (hit_decision(v, sgeo + kGeo * jj, r_rx)) bits |= 1u << (jj & 31);
       }
-      bits = 0;
-      cw = w;
     }
-    if (hit) bits |= 1u << (jj & 31);
-  }
-  if (bits) {
-    atomicOr(mask_row + cw, bits);
-    atomicOr(uni_row + cw, bits);
+    if (bits) {
+      atomicOr(mask_row + w, bits);
+      atomicOr(uni_row + w, bits);
+    }
   }
   return n_test;
 }
@@ -121,13 +149,15 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   const int u1 = tu * a.tw + r1 % a.tw, v1 = tv * th_ + r1 / a.tw;
   const bool valid1 = (u1 < a.n_az) && (v1 < a.n_el);
   const gsrf_pair pr = a.pairs[k];
-  const double lam = kC0 / pr.freq_hz;
+  const double lam = kC0 / pr.freq_hz, inv_lam = pr.freq_hz / kC0;
   float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
   ray_setup<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
-  float wx, wy, wz;
+  RayMono w1;
   {
+    float wx, wy, wz;
     double al, sb;
     ray_dir(valid1 ? u1 : 0, valid1 ? v1 : 0, a, wx, wy, wz, al, sb);
+    w1 = ray_mono(wx, wy, wz);
   }
   float twopi_lam = 0.f, Sfr = 0.f, Sfi = 0.f, Gr = 0.f, Gi = 0.f;
   if constexpr (BWD) {
@@ -159,7 +189,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     const int nb = (int)min((uint32_t)B, s1 - base);
     __syncthreads();
     if (tid < nb)
-      stage_entry<K>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], lam,
+      stage_entry<K>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                      sgeo + kGeo * tid, scf + 2 * K * tid);
     for (int i = tid; i < R * MWS + 4 * MW; i += NT) smask[i] = 0u;   // ray rows and union rows
     if (STATS && tid == 0) {
@@ -169,7 +199,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     __syncthreads();
     // ---- phase 1 ----
     if (valid1 && !sdone[r1]) {
-      const unsigned nt = phase1_tests<EP>(wx, wy, wz, sgeo, nb, e, a.r_rx, smask + r1 * MWS, suni + (r1 / RPW) * MW);
+      const unsigned nt = phase1_tests<EP, MW>(w1, sgeo, nb, e, a.r_rx, smask + r1 * MWS, suni + (r1 / RPW) * MW);
       if (STATS) n_test += nt;
     }
     __syncthreads();
