@@ -8,8 +8,11 @@ RSSI (gsrf_render_fwd) and the adjoint + chain rule (gsrf_render_bwd) with a
 seeded upstream gradient.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line (rank 0).  Extra fields report the forward-only rate,
-a batched launch over many pairs of the same scene, the roofline of the
-dominant kernel and the FP64 oracle timed on the host's cores.
+the two batched workloads -- 256 pairs over one 500k-Gaussian room (forward)
+and 16 scenes of 20k-1M Gaussians with 8-64 pairs each (forward + adjoint) --
+each as hipGraph replays with an autotuned tile shape, the roofline of the
+dominant kernel of each workload and the FP64 oracle timed on the host's
+cores.  ``--workloads`` restricts the run (profiling).
 """
 from __future__ import annotations
 
@@ -42,6 +45,25 @@ def flops_per(K: int) -> dict:
           = 107 + 8K
     """
     return dict(test=60.0, hit_fwd=52.0 + 8 * K, hit_bwd=52.0 + 8 * K + 107.0 + 8 * K)
+
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "render_traffic.json")
+
+
+def measured_traffic(kernel: str, config: str):
+    """HBM bytes per launch of `kernel` at `config` from the committed PMC record
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel's readings), or None when
+    there is no record or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    from paper_2502_01826_amd.profiling import sources_hash
+    if rec.get("sources_sha256") != sources_hash():
+        return None
+    ent = rec.get("kernels", {}).get(kernel, {}).get(config)
+    return None if ent is None else float(ent["bytes_per_launch"])
 
 
 def cpu_baseline(scene, pair, grid, min_seconds: float = 8.0) -> dict:
@@ -78,6 +100,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batched", choices=("full", "small", "none"), default="full",
                     help="batched workloads: full (256 pairs x 500k; 16 uneven scenes), small, or none")
+    ap.add_argument("--workloads", default="plain,fwd_500k,uneven",
+                    help="comma list of plain, fwd_500k, uneven (profiling runs pick one)")
     ap.add_argument("--batched-pairs", type=int, default=256)
     ap.add_argument("--batched-iters", type=int, default=5)
     ap.add_argument("--gaussians", type=int, default=200_000)
@@ -205,60 +229,73 @@ def main() -> int:
                 "autotune_ms": {f"{a}x{b_}/{c}": v * 1e3 for (a, b_, c), v in tune.seconds.items()},
                 "roofline": roof}
 
+    def run_plain():
+        prob, bufs = make([pair])
+        ev = {k: [new_event() for _ in range(args.steps)] for k in ("f0", "f1", "b0", "b1")}
+        torch.cuda.synchronize()
+        t_step = timed(prob, bufs, args.steps, args.warmup, True, ev)
+        t_fwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["f0"], ev["f1"])) / args.steps * 1e-3
+        t_bwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["b0"], ev["b1"])) / args.steps * 1e-3
+        t_fwd_only = timed(prob, bufs, args.steps, 1, False)
+        stats = prob.render_stats()
+        n_splats, _ = prob.splat_count()
+        K = grid.K
+        f = flops_per(K)
+        fl_fwd = stats["tile_tests"] * f["test"] + stats["hits"] * f["hit_fwd"]
+        fl_bwd = stats["tile_tests"] * f["test"] + stats["hits"] * f["hit_bwd"]
+        if t_bwd_k >= t_fwd_k:
+            dom, fl, tk = "render_bwd", fl_bwd, t_bwd_k
+        else:
+            dom, fl, tk = "render_fwd", fl_fwd, t_fwd_k
+        achieved = fl / tk
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VALU,
+                "traffic": measured_traffic(dom, f"{args.tile}/{args.lanes}/{args.gaussians}"), "kernel": dom,
+                "kernel_ms": tk * 1e3, "flop_per_launch": fl, "timing": "HIP events recorded by the library "
+                "immediately around the render kernel on its stream, averaged over the timed steps",
+                "counts": {**stats, "splats": n_splats}}
+        del prob, bufs
+        torch.cuda.empty_cache()
+        return t_step, t_fwd_only, t_fwd_k, t_bwd_k, roof
+
+    work = set(args.workloads.split(","))
     # ---- plain: one pair per launch sequence (the headline step) -------------
-    prob, bufs = make([pair])
-    ev = {k: [new_event() for _ in range(args.steps)] for k in ("f0", "f1", "b0", "b1")}
-    torch.cuda.synchronize()
-    t_step = timed(prob, bufs, args.steps, args.warmup, True, ev)
-    t_fwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["f0"], ev["f1"])) / args.steps * 1e-3
-    t_bwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["b0"], ev["b1"])) / args.steps * 1e-3
-    t_fwd_only = timed(prob, bufs, args.steps, 1, False)
-    stats = prob.render_stats()
-    n_splats, _ = prob.splat_count()
-    K = grid.K
-    f = flops_per(K)
-    fl_fwd = stats["tile_tests"] * f["test"] + stats["hits"] * f["hit_fwd"]
-    fl_bwd = stats["tile_tests"] * f["test"] + stats["hits"] * f["hit_bwd"]
-    if t_bwd_k >= t_fwd_k:
-        dom, fl, tk = "render_bwd", fl_bwd, t_bwd_k
-    else:
-        dom, fl, tk = "render_fwd", fl_fwd, t_fwd_k
-    achieved = fl / tk
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VALU, "traffic": None, "kernel": dom,
-            "kernel_ms": tk * 1e3, "flop_per_launch": fl, "timing": "HIP events recorded by the library "
-            "immediately around the render kernel on its stream, averaged over the timed steps",
-            "counts": {**stats, "splats": n_splats}}
+    t_step = t_fwd_only = t_fwd_k = t_bwd_k = None
+    roof = None
+    if "plain" in work:
+        t_step, t_fwd_only, t_fwd_k, t_bwd_k, roof = run_plain()
 
     # ---- batched: all pairs of a batch in one hipGraph replay -----------------
     batched = None
     if args.batched != "none":
         batched = {}
         small = args.batched == "small"
-        b4 = synth.batched(n=100_000 if small else 500_000, n_pairs=16 if small else args.batched_pairs)
-        batched["fwd_500k"] = run_batched(b4, grad=False, label="batched forward: {} pairs over one {}-Gaussian "
-                                          "room, 360x90 rays, 5 GHz".format(len(b4.pairs), b4.scenes[0].n))
-        del b4
-        b5 = synth.batched_uneven(n_scenes=4 if small else 16, n_hi=100_000 if small else 1_000_000,
-                                  pairs_hi=8 if small else 64)
-        batched["uneven_fwd_bwd"] = run_batched(
-            b5, grad=True, label="batched uneven fwd+bwd: {} scenes ({}-{} Gaussians), {} pairs, carriers "
-            "2.4/5/5.8 GHz, 360x90 rays".format(len(b5.scenes), min(s_.n for s_ in b5.scenes),
-                                                max(s_.n for s_ in b5.scenes), len(b5.pairs)))
-        del b5
+        if "fwd_500k" in work:
+            b4 = synth.batched(n=100_000 if small else 500_000, n_pairs=16 if small else args.batched_pairs)
+            batched["fwd_500k"] = run_batched(b4, grad=False, label="batched forward: {} pairs over one {}-Gaussian "
+                                              "room, 360x90 rays, 5 GHz".format(len(b4.pairs), b4.scenes[0].n))
+            del b4
+        if "uneven" in work:
+            b5 = synth.batched_uneven(n_scenes=4 if small else 16, n_hi=100_000 if small else 1_000_000,
+                                      pairs_hi=8 if small else 64)
+            batched["uneven_fwd_bwd"] = run_batched(
+                b5, grad=True, label="batched uneven fwd+bwd: {} scenes ({}-{} Gaussians), {} pairs, carriers "
+                "2.4/5/5.8 GHz, 360x90 rays".format(len(b5.scenes), min(s_.n for s_ in b5.scenes),
+                                                    max(s_.n for s_ in b5.scenes), len(b5.pairs)))
+            del b5
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and "plain" in work:
         cpu = cpu_baseline(scene, pair, grid)
 
     out = {
         "metric": METRIC,
-        "value": 1.0 / t_step,
+        "value": None if t_step is None else 1.0 / t_step,
         "unit": "spectra/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t_step * 1e3,
+        "ms_per_step": None if t_step is None else t_step * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -268,8 +305,8 @@ def main() -> int:
                                "pair, 360x90 rays, 5 GHz, FLE L=2; project+bin_sort+render_fwd+render_bwd",
                    "gaussians": args.gaussians, "rays": "360x90", "pairs": 1, "tile": args.tile,
                    "lanes_per_ray": args.lanes},
-        "fwd_only": {"spectra_per_s": 1.0 / t_fwd_only, "ms": t_fwd_only * 1e3},
-        "kernels_ms": {"render_fwd": t_fwd_k * 1e3, "render_bwd": t_bwd_k * 1e3},
+        "fwd_only": None if t_fwd_only is None else {"spectra_per_s": 1.0 / t_fwd_only, "ms": t_fwd_only * 1e3},
+        "kernels_ms": None if t_fwd_k is None else {"render_fwd": t_fwd_k * 1e3, "render_bwd": t_bwd_k * 1e3},
         "batched": batched,
         "roofline": roof,
         "cpu_baseline": cpu,

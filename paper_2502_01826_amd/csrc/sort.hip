@@ -82,8 +82,9 @@ __global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pair
 // rank among the sub-bucket's entries, found by comparing with all of them;
 // sub-buckets are small, so this costs a few comparisons per entry and no
 // further passes.  The scatter buffer is LDS for buckets of up to `chunk`
-// entries and global scratch for longer ones.  The result does not depend on
-// the (atomic) scatter order, so it is deterministic.
+// entries; longer buckets scatter to global scratch and are ranked in LDS
+// windows of whole sub-buckets.  The result does not depend on the (atomic)
+// scatter order, so it is deterministic.
 // ---------------------------------------------------------------------------
 constexpr int kSortWaves = kTileSortThreads / 64;
 constexpr int kSortBitsMax = 11;
@@ -126,7 +127,7 @@ __device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint3
 template <bool SH>
 __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *__restrict__ ev, int n, uint32_t *bk,
                               uint32_t *bv, uint32_t *__restrict__ ok, uint32_t *__restrict__ ov, uint32_t *hist,
-                              uint32_t *start, uint64_t *red) {
+                              uint32_t *start, uint64_t *red, uint32_t *sk, uint32_t *sv, int chunk) {
   constexpr int NT = kTileSortThreads;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint64_t cmin = ~0ull, cmax = 0;
@@ -185,16 +186,70 @@ __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *_
   if (!SH) __threadfence_block();
   __syncthreads();
   // hist[d] is now the end of sub-bucket d
-  for (int p = tid; p < n; p += NT) {
-    const uint32_t k = bk[p], v = bv[p];
-    const uint64_t c = composite(k, v);
-    const uint32_t d = (uint32_t)((c - cmin) >> shift);
-    const int a = (int)start[d], e = (int)hist[d];
-    int rank = 0;
+  if constexpr (SH) {
+    for (int p = tid; p < n; p += NT) {
+      const uint32_t k = bk[p], v = bv[p];
+      const uint64_t c = composite(k, v);
+      const uint32_t d = (uint32_t)((c - cmin) >> shift);
+      const int a = (int)start[d], e = (int)hist[d];
+      int rank = 0;
 #pragma unroll 2
-    for (int j = a; j < e; ++j) rank += composite(bk[j], bv[j]) < c ? 1 : 0;
-    ok[a + rank] = k;
-    ov[a + rank] = v;
+      for (int j = a; j < e; ++j) rank += composite(bk[j], bv[j]) < c ? 1 : 0;
+      ok[a + rank] = k;
+      ov[a + rank] = v;
+    }
+  } else {
+    // rank in LDS windows of whole sub-buckets (at most `chunk` entries each);
+    // a single sub-bucket longer than that is ranked in global memory
+    int w0 = 0;
+    while (w0 < n) {
+      const int lim = min(n, w0 + chunk);
+      // last sub-bucket end <= lim (ends are non-decreasing in the digit)
+      int lo = 0, hi = nbins - 1, w1 = w0;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int e = (int)hist[mid];
+        if (e <= lim) {
+          w1 = max(w1, e);
+          lo = mid + 1;
+        } else {
+          hi = mid - 1;
+        }
+      }
+      if (w1 > w0) {
+        for (int i = tid; i < w1 - w0; i += NT) {
+          sk[i] = bk[w0 + i];
+          sv[i] = bv[w0 + i];
+        }
+        __syncthreads();
+        for (int p = tid; p < w1 - w0; p += NT) {
+          const uint32_t k = sk[p], v = sv[p];
+          const uint64_t c = composite(k, v);
+          const uint32_t d = (uint32_t)((c - cmin) >> shift);
+          const int a = (int)start[d] - w0, e = (int)hist[d] - w0;
+          int rank = 0;
+#pragma unroll 2
+          for (int j = a; j < e; ++j) rank += composite(sk[j], sv[j]) < c ? 1 : 0;
+          ok[w0 + a + rank] = k;
+          ov[w0 + a + rank] = v;
+        }
+        __syncthreads();
+      } else {
+        // the sub-bucket starting at w0 exceeds the window
+        const uint64_t c0 = composite(bk[w0], bv[w0]);
+        const uint32_t d0 = (uint32_t)((c0 - cmin) >> shift);
+        w1 = (int)hist[d0];
+        for (int p = w0 + tid; p < w1; p += NT) {
+          const uint32_t k = bk[p], v = bv[p];
+          const uint64_t c = composite(k, v);
+          int rank = 0;
+          for (int j = w0; j < w1; ++j) rank += composite(bk[j], bv[j]) < c ? 1 : 0;
+          ok[w0 + rank] = k;
+          ov[w0 + rank] = v;
+        }
+      }
+      w0 = w1;
+    }
   }
 }
 
@@ -216,9 +271,10 @@ __global__ __launch_bounds__(kTileSortThreads, 8) void k_tile_sort(const uint32_
   const int n = (int)(tend[gt] - s0);
   if (n <= 0) return;
   if (n <= chunk)
-    msd_rank_sort<true>(ekey + s0, eval + s0, n, sk, sv, klo + s0, val + s0, hist, start, red);
+    msd_rank_sort<true>(ekey + s0, eval + s0, n, sk, sv, klo + s0, val + s0, hist, start, red, sk, sv, chunk);
   else
-    msd_rank_sort<false>(ekey + s0, eval + s0, n, tkey + s0, tval + s0, klo + s0, val + s0, hist, start, red);
+    msd_rank_sort<false>(ekey + s0, eval + s0, n, tkey + s0, tval + s0, klo + s0, val + s0, hist, start, red, sk, sv,
+                         chunk);
 }
 
 static int g_sort_chunk = 0;
