@@ -85,28 +85,99 @@ __global__ void k_rec_base(const gsrf_pair *__restrict__ pairs, const int64_t *_
 // and adds the counts to tile_cnt with one atomic per touched tile.
 // ---------------------------------------------------------------------------
 #pragma clang fp contract(off)
-// One record: depth key and rectangle (all FP64, operation order as documented above).
-__device__ __forceinline__ ushort4 project_record(const gsrf_pair &pr, const float *__restrict__ means,
-                                                  const float *__restrict__ log_scales, int64_t g,
-                                                  const gsrf_grid &grid, int32_t nta, uint32_t *key_out) {
-  const double ex = (double)means[3 * g + 0] - (double)pr.rx[0];
-  const double ey = (double)means[3 * g + 1] - (double)pr.rx[1];
-  const double ez = (double)means[3 * g + 2] - (double)pr.rx[2];
+// Ray index ranges -> tile rectangle (integer tail shared by both evaluations).
+__device__ __forceinline__ ushort4 tile_rect(long v_lo, long v_hi, long u_lo, long u_hi, bool full, int n_az, int tw,
+                                             int th, int32_t nta) {
+  if (full) { u_lo = 0; u_hi = n_az - 1; }
+  if (!((v_lo <= v_hi) && (full || u_hi >= u_lo))) return make_ushort4(0, 0, 0, 0);
+  if (u_lo < 0) { u_lo += n_az; u_hi += n_az; }
+  long tu0 = u_lo / tw;
+  long ntu = (u_hi < n_az) ? (u_hi / tw - tu0 + 1) : ((nta - tu0) + (u_hi - n_az) / tw + 1);
+  if (ntu >= nta) { tu0 = 0; ntu = nta; }
+  const long tv0 = v_lo / th;
+  const long ntv = v_hi / th - tv0 + 1;
+  return make_ushort4((unsigned short)tu0, (unsigned short)ntu, (unsigned short)tv0, (unsigned short)ntv);
+}
+
+// The same rectangle evaluated in FP32, accepted only when every discrete
+// decision (cull, inside, pole, and the four ceil/floor of ray indices) lies
+// farther from its threshold than kFastAngTol (in angle, or that angle in index
+// units).  The FP32 errors of the quantities involved stay below 2e-5 rad
+// under the guards used here (Rb/D <= 0.9, cos beta_c >= 0.2,
+// sin theta / cos beta_c <= 0.9), so an accepted result equals the FP64 one;
+// otherwise the caller evaluates the FP64 definition.
+constexpr float kFastAngTol = 2e-4f;
+
+__device__ __forceinline__ bool near_int(float x, float tol) { return fabsf(x - rintf(x)) <= tol; }
+
+__device__ __forceinline__ bool cap_rect_fp32(float ex, float ey, float ez, float D, float Rb, const gsrf_grid &grid,
+                                              int32_t nta, ushort4 *out) {
+  const float DR = D + Rb;
+  if (fabsf(DR - grid.r_rx) <= 1e-5f * (DR + grid.r_rx)) return false;
+  if (DR < grid.r_rx) {
+    *out = make_ushort4(0, 0, 0, 0);
+    return true;
+  }
+  if (fabsf(D - Rb) <= 1e-5f * DR) return false;
+  if (D <= Rb) {
+    *out = tile_rect(0, grid.n_el - 1, 0, grid.n_az - 1, true, grid.n_az, grid.tile_w, grid.tile_h, nta);
+    return true;
+  }
+  const float sr = Rb / D;
+  if (sr > 0.9f) return false;
+  const float theta = asinf(sr) + (float)kCapSlack;
+  const float bc = atan2f(ez, sqrtf(ex * ex + ey * ey));
+  const float lo = bc - theta, hi = bc + theta;
+  const float halfpi = 1.57079632679489662f;
+  if (fabsf(hi - halfpi) <= kFastAngTol || fabsf(lo + halfpi) <= kFastAngTol) return false;
+  const float dbeta = (grid.el_hi - grid.el_lo) / (float)grid.n_el;
+  const float xl = (lo - grid.el_lo) / dbeta - 0.5f, xh = (hi - grid.el_lo) / dbeta - 0.5f;
+  const float tolv = kFastAngTol / dbeta;
+  if (near_int(xl, tolv + 1e-5f * (fabsf(xl) + 1.f)) || near_int(xh, tolv + 1e-5f * (fabsf(xh) + 1.f))) return false;
+  long v_lo = (long)ceilf(xl), v_hi = (long)floorf(xh);
+  if (v_lo < 0) v_lo = 0;
+  if (v_hi > grid.n_el - 1) v_hi = grid.n_el - 1;
+  bool full = (hi >= halfpi) || (lo <= -halfpi);
+  long u_lo = 0, u_hi = grid.n_az - 1;
+  if (!full) {
+    const float cb = cosf(bc);
+    if (cb < 0.2f) return false;
+    const float r = sinf(theta) / cb;
+    if (r > 0.9f) return false;
+    const float da = asinf(r);
+    const float ac = atan2f(ey, ex);
+    const float dalpha = 6.28318530717958648f / (float)grid.n_az;
+    const float ul = (ac - da) / dalpha - 0.5f, uh = (ac + da) / dalpha - 0.5f;
+    const float tolu = kFastAngTol / dalpha;
+    if (near_int(ul, tolu + 1e-5f * (fabsf(ul) + 1.f)) || near_int(uh, tolu + 1e-5f * (fabsf(uh) + 1.f)))
+      return false;
+    u_lo = (long)ceilf(ul);
+    u_hi = (long)floorf(uh);
+    if (u_hi - u_lo + 1 >= grid.n_az) full = true;
+  }
+  *out = tile_rect(v_lo, v_hi, u_lo, u_hi, full, grid.n_az, grid.tile_w, grid.tile_h, nta);
+  return true;
+}
+
+// FP64 evaluation of the rectangle, in the operation order documented above
+// (scalar arguments: not inlined, and nothing of the caller's needs memory).
+__device__ __noinline__ ushort4 cap_rect_fp64(float mx, float my, float mz, float rx, float ry, float rz, float lmaxf,
+                                              int n_az, int n_el, float el_lo_f, float el_hi_f, float r_rx, int tw,
+                                              int th, int32_t nta) {
+  const double ex = (double)mx - (double)rx;
+  const double ey = (double)my - (double)ry;
+  const double ez = (double)mz - (double)rz;
   const double D2 = (ex * ex + ey * ey) + ez * ez;
-  *key_out = __float_as_uint((float)D2);
   const double D = sqrt(D2);
-  const double lmax = fmax(fmax((double)log_scales[3 * g + 0], (double)log_scales[3 * g + 1]),
-                           (double)log_scales[3 * g + 2]);
-  const double Rb = 3.0 * exp(lmax);
-  const int n_az = grid.n_az, n_el = grid.n_el, tw = grid.tile_w, th = grid.tile_h;
-  const double el_lo = (double)grid.el_lo, el_hi = (double)grid.el_hi;
+  const double Rb = 3.0 * exp((double)lmaxf);
+  const double el_lo = (double)el_lo_f, el_hi = (double)el_hi_f;
   const double pi = 3.14159265358979323846;
-  if (D + Rb < (double)grid.r_rx * (1.0 - 1e-6)) return make_ushort4(0, 0, 0, 0);
+  if (D + Rb < (double)r_rx * (1.0 - 1e-6)) return make_ushort4(0, 0, 0, 0);
   const bool inside = D <= Rb * (1.0 + 1e-6);
-  long v_lo, v_hi, u_lo, u_hi;
+  long v_lo, v_hi, u_lo = 0, u_hi = n_az - 1;
   bool full;
   if (inside) {
-    v_lo = 0; v_hi = n_el - 1; full = true; u_lo = 0; u_hi = n_az - 1;
+    v_lo = 0; v_hi = n_el - 1; full = true;
   } else {
     const double theta = asin(fmin(Rb / D, 1.0)) + kCapSlack;
     const double bc = atan2(ez, sqrt(ex * ex + ey * ey));
@@ -125,16 +196,22 @@ __device__ __forceinline__ ushort4 project_record(const gsrf_pair &pr, const flo
       u_hi = (long)floor((ac + da) / dalpha - 0.5);
       if (u_hi - u_lo + 1 >= n_az) full = true;
     }
-    if (full) { u_lo = 0; u_hi = n_az - 1; }
   }
-  if (!((v_lo <= v_hi) && (full || u_hi >= u_lo))) return make_ushort4(0, 0, 0, 0);
-  if (u_lo < 0) { u_lo += n_az; u_hi += n_az; }
-  long tu0 = u_lo / tw;
-  long ntu = (u_hi < n_az) ? (u_hi / tw - tu0 + 1) : ((nta - tu0) + (u_hi - n_az) / tw + 1);
-  if (ntu >= nta) { tu0 = 0; ntu = nta; }
-  const long tv0 = v_lo / th;
-  const long ntv = v_hi / th - tv0 + 1;
-  return make_ushort4((unsigned short)tu0, (unsigned short)ntu, (unsigned short)tv0, (unsigned short)ntv);
+  return tile_rect(v_lo, v_hi, u_lo, u_hi, full, n_az, tw, th, nta);
+}
+
+// One record: depth key (always FP64: bits of fp32(D^2), D^2 without FMA)
+// and an attempt at the rectangle in FP32; false when the FP64 evaluation
+// is needed.
+__device__ __forceinline__ bool project_record_fast(const gsrf_pair &pr, const float *__restrict__ means,
+                                                    float lmaxf, int64_t g, const gsrf_grid &grid, int32_t nta,
+                                                    uint32_t *key_out, ushort4 *rect) {
+  const double ex = (double)means[3 * g + 0] - (double)pr.rx[0];
+  const double ey = (double)means[3 * g + 1] - (double)pr.rx[1];
+  const double ez = (double)means[3 * g + 2] - (double)pr.rx[2];
+  const double D2 = (ex * ex + ey * ey) + ez * ez;
+  *key_out = __float_as_uint((float)D2);
+  return cap_rect_fp32((float)ex, (float)ey, (float)ez, sqrtf((float)D2), 3.0f * expf(lmaxf), grid, nta, rect);
 }
 
 // Workgroup = 256 consecutive records of one pair; per-tile counts gathered
@@ -148,20 +225,40 @@ __global__ __launch_bounds__(256) void k_project(const gsrf_pair *__restrict__ p
                                                  ushort4 *__restrict__ rec_rect, uint32_t *__restrict__ tile_cnt) {
   extern __shared__ uint32_t hist[];   // [T]
   __shared__ RectScan rs;
+  __shared__ ushort4 rects[256];
+  __shared__ int fallback[256];
+  __shared__ int n_fallback;
   const int k = blockIdx.y;
   for (int t = threadIdx.x; t < T; t += blockDim.x) hist[t] = 0;
+  if (threadIdx.x == 0) n_fallback = 0;
   const gsrf_pair pr = pairs[k];
   const int64_t g0 = scene_off[pr.scene];
   const int64_t n = scene_off[pr.scene + 1] - g0;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t j = j0 + threadIdx.x;
+  __syncthreads();
   ushort4 rc = make_ushort4(0, 0, 0, 0);
   if (j < n) {
-    const int64_t r = rec_base[k] + j;
     uint32_t key;
-    rc = project_record(pr, means, log_scales, g0 + j, grid, nta, &key);
-    rec_key[r] = key;
-    rec_rect[r] = rc;
+    const int64_t g = g0 + j;
+    if (!project_record_fast(pr, means, fmaxf(fmaxf(log_scales[3 * g], log_scales[3 * g + 1]), log_scales[3 * g + 2]),
+                             g, grid, nta, &key, &rc))
+      fallback[atomicAdd(&n_fallback, 1)] = threadIdx.x;
+    rec_key[rec_base[k] + j] = key;
   }
+  rects[threadIdx.x] = rc;
+  __syncthreads();
+  // records the FP32 evaluation could not decide, packed onto the first lanes
+  for (int i = threadIdx.x; i < n_fallback; i += 256) {
+    const int slot = fallback[i];
+    const int64_t g = g0 + j0 + slot;
+    rects[slot] = cap_rect_fp64(means[3 * g], means[3 * g + 1], means[3 * g + 2], pr.rx[0], pr.rx[1], pr.rx[2],
+                                fmaxf(fmaxf(log_scales[3 * g], log_scales[3 * g + 1]), log_scales[3 * g + 2]),
+                                grid.n_az, grid.n_el, grid.el_lo, grid.el_hi, grid.r_rx, grid.tile_w, grid.tile_h, nta);
+  }
+  __syncthreads();
+  rc = rects[threadIdx.x];
+  if (j < n) rec_rect[rec_base[k] + j] = rc;
   rect_scan(rs, rc);
   const uint32_t total = rs.off[256];
   for (uint32_t sp = threadIdx.x; sp < total; sp += 256) {
