@@ -39,38 +39,49 @@ constexpr int kScanTiles = 1024;
 // s = tid, tid + 256, ..., locating the owning record by binary search.
 struct RectScan {
   ushort4 rect[256];
+  float inv_ntu[256];      // 1 / (tile columns) of each rectangle
   uint32_t off[257];
+  uint32_t wsum[4];
 };
 
 __device__ __forceinline__ void rect_scan(RectScan &rs, ushort4 rc) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t c = (uint32_t)rc.y * rc.w;
   rs.rect[tid] = rc;
-  rs.off[tid + 1] = c;
+  rs.inv_ntu[tid] = 1.0f / (float)(rc.y > 0 ? rc.y : 1);
+  uint32_t inc = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) rs.wsum[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+#pragma unroll
+  for (int w = 0; w < 3; ++w) base += (w < wave) ? rs.wsum[w] : 0u;
+  rs.off[tid + 1] = base + inc;
   if (tid == 0) rs.off[0] = 0;
   __syncthreads();
-  for (int d = 1; d < 256; d <<= 1) {
-    const uint32_t v = tid >= d ? rs.off[tid + 1 - d] : 0u;
-    __syncthreads();
-    rs.off[tid + 1] += v;
-    __syncthreads();
-  }
 }
 
 // splat s of the workgroup: owning record (thread slot) and its tile id
 __device__ __forceinline__ int rect_splat(const RectScan &rs, uint32_t s, int nta, int *tile) {
-  int lo = 0, hi = 255;
-  while (lo < hi) {                 // last record whose offset is <= s
-    const int mid = (lo + hi + 1) >> 1;
-    if (rs.off[mid] <= s) lo = mid; else hi = mid - 1;
-  }
-  const ushort4 rc = rs.rect[lo];
-  const uint32_t local = s - rs.off[lo];
-  const int tv = rc.z + (int)(local / rc.y);
-  int tu = rc.x + (int)(local % rc.y);
+  int pos = 0;                      // last record whose offset is <= s (off[0] = 0)
+#pragma unroll
+  for (int step = 128; step >= 1; step >>= 1)
+    if (rs.off[pos + step] <= s) pos += step;
+  const ushort4 rc = rs.rect[pos];
+  const uint32_t local = s - rs.off[pos];
+  // row = floor((local + 1/2) / ntu): the quotient is at most ntv + 1 and at
+  // least 1/(2 ntu) from an integer, and ntu * ntv <= kMaxTiles keeps its FP32
+  // error two orders of magnitude below that distance
+  const uint32_t q = (uint32_t)(((float)local + 0.5f) * rs.inv_ntu[pos]);
+  const int tv = rc.z + (int)q;
+  int tu = rc.x + (int)(local - q * rc.y);
   if (tu >= nta) tu -= nta;
   *tile = tv * nta + tu;
-  return lo;
+  return pos;
 }
 
 // Byte offsets of every workspace array plus derived sizes.

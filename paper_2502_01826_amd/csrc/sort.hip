@@ -87,6 +87,7 @@ __global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pair
 // scatter order, so it is deterministic.
 // ---------------------------------------------------------------------------
 constexpr int kSortWaves = kTileSortThreads / 64;
+constexpr int kSortRegs = 8;              // entries per thread held in registers (LDS path)
 constexpr int kSortBitsMax = 11;
 constexpr int kSortBins = 1 << kSortBitsMax;
 
@@ -130,11 +131,32 @@ __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *_
                               uint32_t *start, uint64_t *red, uint32_t *sk, uint32_t *sv, int chunk) {
   constexpr int NT = kTileSortThreads;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // LDS path (n <= kSortRegs * NT): each thread keeps its entries in registers
+  // across the passes, so the bucket is read from global memory once
+  uint32_t rk[SH ? kSortRegs : 1], rv[SH ? kSortRegs : 1];
+  if constexpr (SH) {
+#pragma unroll
+    for (int e = 0; e < kSortRegs; ++e) {
+      const int i = tid + e * NT;
+      rk[e] = i < n ? ek[i] : 0u;
+      rv[e] = i < n ? ev[i] : 0u;
+    }
+  }
   uint64_t cmin = ~0ull, cmax = 0;
-  for (int i = tid; i < n; i += NT) {
-    const uint64_t c = composite(ek[i], ev[i]);
-    cmin = c < cmin ? c : cmin;
-    cmax = c > cmax ? c : cmax;
+  if constexpr (SH) {
+#pragma unroll
+    for (int e = 0; e < kSortRegs; ++e)
+      if (tid + e * NT < n) {
+        const uint64_t c = composite(rk[e], rv[e]);
+        cmin = c < cmin ? c : cmin;
+        cmax = c > cmax ? c : cmax;
+      }
+  } else {
+    for (int i = tid; i < n; i += NT) {
+      const uint64_t c = composite(ek[i], ev[i]);
+      cmin = c < cmin ? c : cmin;
+      cmax = c > cmax ? c : cmax;
+    }
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
@@ -171,17 +193,33 @@ __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *_
   const int nbins = 1 << bits;
   for (int i = tid; i < nbins; i += NT) hist[i] = 0;
   __syncthreads();
-  for (int i = tid; i < n; i += NT) atomicAdd(&hist[(uint32_t)((composite(ek[i], ev[i]) - cmin) >> shift)], 1u);
+  if constexpr (SH) {
+#pragma unroll
+    for (int e = 0; e < kSortRegs; ++e)
+      if (tid + e * NT < n) atomicAdd(&hist[(uint32_t)((composite(rk[e], rv[e]) - cmin) >> shift)], 1u);
+  } else {
+    for (int i = tid; i < n; i += NT) atomicAdd(&hist[(uint32_t)((composite(ek[i], ev[i]) - cmin) >> shift)], 1u);
+  }
   __syncthreads();
   bins_scan(hist, start, nbins, (uint32_t *)(red + 2 * kSortWaves + 2));
   __syncthreads();
   for (int i = tid; i < nbins; i += NT) hist[i] = start[i];     // scatter cursors
   __syncthreads();
-  for (int i = tid; i < n; i += NT) {
-    const uint32_t k = ek[i], v = ev[i];
-    const uint32_t p = atomicAdd(&hist[(uint32_t)((composite(k, v) - cmin) >> shift)], 1u);
-    bk[p] = k;
-    bv[p] = v;
+  if constexpr (SH) {
+#pragma unroll
+    for (int e = 0; e < kSortRegs; ++e)
+      if (tid + e * NT < n) {
+        const uint32_t p = atomicAdd(&hist[(uint32_t)((composite(rk[e], rv[e]) - cmin) >> shift)], 1u);
+        bk[p] = rk[e];
+        bv[p] = rv[e];
+      }
+  } else {
+    for (int i = tid; i < n; i += NT) {
+      const uint32_t k = ek[i], v = ev[i];
+      const uint32_t p = atomicAdd(&hist[(uint32_t)((composite(k, v) - cmin) >> shift)], 1u);
+      bk[p] = k;
+      bv[p] = v;
+    }
   }
   if (!SH) __threadfence_block();
   __syncthreads();
@@ -295,6 +333,7 @@ static void choose_sort_chunk() {
   if (lds > 160 * 1024) lds = 160 * 1024;
   int chunk = (int)((lds / 2 - fixed) / 8);
   chunk = (chunk / 32) * 32;
+  if (chunk > kSortRegs * kTileSortThreads) chunk = kSortRegs * kTileSortThreads;
   if (chunk < kTileSortThreads) chunk = kTileSortThreads;
   g_sort_lds = fixed + (size_t)8 * chunk;
   if (g_sort_lds > 65536)
