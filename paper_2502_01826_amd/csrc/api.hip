@@ -90,6 +90,7 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   if (T > kMaxTiles) return fail(GSRF_EINVAL, "%lld tiles per pair exceed %d", (long long)T, kMaxTiles);
   Layout L{};
   L.n_records = R;
+  L.rec_block = R >= kBigBatchRecords ? 1024 : 256;
   L.max_scene = max_used;
   L.cap = p->splat_capacity;
   L.T = (int32_t)T;

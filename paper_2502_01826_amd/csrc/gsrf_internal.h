@@ -24,27 +24,33 @@ constexpr int kPrep = 16;
 // LDS for buckets of at most `sort_chunk` entries, else through global scratch.
 constexpr int kTileSortThreads = 1024;
 constexpr int kMaxTiles = 8192;           // per pair; LDS histograms in project/emit
-constexpr int kRecPerThread = 1;          // records per thread in project/emit
-constexpr int kRecPerBlock = 256 * kRecPerThread;
-// Each tile's bucket is split into kSub contiguous sub-buckets; workgroup b of
-// project/emit counts into and reserves from sub-bucket (b % kSub), which
+// Records per workgroup in emit: 256, or 1024 for large batches (fewer
+// workgroups per tile means fewer global cursor atomics per record); project
+// always uses 256 and counts into the sub-bucket of emit's workgroup.
+constexpr int64_t kBigBatchRecords = (int64_t)1 << 22;
+// Each tile's bucket is split into kSub contiguous sub-buckets; emit's
+// workgroup b (and project's workgroups of the same records) counts into and
+// reserves from sub-bucket (b % kSub), which
 // divides the atomic traffic per counter by kSub.  Counters and cursors are
 // stored sub-major: [kSub][P * T].
 constexpr int kSub = 8;
 // Tiles per block of the three-pass tile-count scan (256 threads x 4).
 constexpr int kScanTiles = 1024;
 
-// Balanced expansion of the tile rectangles of a workgroup's records: the
-// rectangles' splat counts are scanned in LDS and every thread takes splats
-// s = tid, tid + 256, ..., locating the owning record by binary search.
+// Balanced expansion of the tile rectangles of a workgroup's RB records
+// (RB = 256 or 1024, one per thread): the rectangles' splat counts are scanned
+// and every thread takes splats s = tid, tid + RB, ..., locating the owning
+// record by binary search.
+template <int RB>
 struct RectScan {
-  ushort4 rect[256];
-  float inv_ntu[256];      // 1 / (tile columns) of each rectangle
-  uint32_t off[257];
-  uint32_t wsum[4];
+  ushort4 rect[RB];
+  float inv_ntu[RB];       // 1 / (tile columns) of each rectangle
+  uint32_t off[RB + 1];
+  uint32_t wsum[RB / 64];
 };
 
-__device__ __forceinline__ void rect_scan(RectScan &rs, ushort4 rc) {
+template <int RB>
+__device__ __forceinline__ void rect_scan(RectScan<RB> &rs, ushort4 rc) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t c = (uint32_t)rc.y * rc.w;
   rs.rect[tid] = rc;
@@ -59,17 +65,18 @@ __device__ __forceinline__ void rect_scan(RectScan &rs, ushort4 rc) {
   __syncthreads();
   uint32_t base = 0;
 #pragma unroll
-  for (int w = 0; w < 3; ++w) base += (w < wave) ? rs.wsum[w] : 0u;
+  for (int w = 0; w < RB / 64 - 1; ++w) base += (w < wave) ? rs.wsum[w] : 0u;
   rs.off[tid + 1] = base + inc;
   if (tid == 0) rs.off[0] = 0;
   __syncthreads();
 }
 
 // splat s of the workgroup: owning record (thread slot) and its tile id
-__device__ __forceinline__ int rect_splat(const RectScan &rs, uint32_t s, int nta, int *tile) {
+template <int RB>
+__device__ __forceinline__ int rect_splat(const RectScan<RB> &rs, uint32_t s, int nta, int *tile) {
   int pos = 0;                      // last record whose offset is <= s (off[0] = 0)
 #pragma unroll
-  for (int step = 128; step >= 1; step >>= 1)
+  for (int step = RB / 2; step >= 1; step >>= 1)
     if (rs.off[pos + step] <= s) pos += step;
   const ushort4 rc = rs.rect[pos];
   const uint32_t local = s - rs.off[pos];
@@ -95,6 +102,7 @@ struct Layout {
   size_t tile_sum, grad_acc;
   size_t total;
   int64_t n_records;
+  int32_t rec_block;      // records per workgroup in emit (256 or 1024)
   int64_t max_scene;
   int64_t cap;
   int32_t T, nta, nte;

@@ -16,9 +16,46 @@ namespace gsrf {
 //   M = Sigma^-1 = R diag(exp(-2 log s)) R^T, N = (2 pi)^-3/2 exp(-sum log s),
 //   o = sigmoid(logit).  The quaternion (w,x,y,z) is normalised first.
 // ---------------------------------------------------------------------------
-__global__ void k_activate(const float *__restrict__ means, const float *__restrict__ log_scales,
-                           const float *__restrict__ quats, const float *__restrict__ logits, int64_t G,
-                           float *__restrict__ prep) {
+// The same launch also clears the per-(tile, sub-bucket) counters (grid
+// stride) and, in workgroup 0, makes the record base of every pair:
+// rec_base[k] = sum_{k'<k} |scene(k')|, rec_base[P] = R.
+__device__ void rec_base_scan(const gsrf_pair *__restrict__ pairs, const int64_t *__restrict__ scene_off, int32_t P,
+                              int64_t *__restrict__ rec_base) {
+  __shared__ int64_t sh[256];
+  const int tid = threadIdx.x;
+  const int per = (P + 255) / 256;
+  const int lo = tid * per, hi = min(P, lo + per);
+  int64_t local = 0;
+  for (int k = lo; k < hi; ++k) {
+    const int s = pairs[k].scene;
+    local += scene_off[s + 1] - scene_off[s];
+  }
+  sh[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t v = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += v;
+    __syncthreads();
+  }
+  int64_t run = sh[tid] - local;
+  for (int k = lo; k < hi; ++k) {
+    rec_base[k] = run;
+    const int s = pairs[k].scene;
+    run += scene_off[s + 1] - scene_off[s];
+  }
+  if (tid == 255) rec_base[P] = sh[255];
+}
+
+__global__ __launch_bounds__(256) void k_activate(const float *__restrict__ means, const float *__restrict__ log_scales,
+                                                  const float *__restrict__ quats, const float *__restrict__ logits,
+                                                  int64_t G, float *__restrict__ prep, uint32_t *__restrict__ tile_cnt,
+                                                  int64_t n_cnt, const gsrf_pair *__restrict__ pairs,
+                                                  const int64_t *__restrict__ scene_off, int32_t P,
+                                                  int64_t *__restrict__ rec_base) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_cnt; i += stride) tile_cnt[i] = 0u;
+  if (blockIdx.x == 0 && P > 0) rec_base_scan(pairs, scene_off, P, rec_base);
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   float qw = quats[4 * g + 0], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
@@ -44,35 +81,6 @@ __global__ void k_activate(const float *__restrict__ means, const float *__restr
   o[3] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// Record base of each pair: rec_base[k] = sum_{k'<k} |scene(k')|, rec_base[P] = R.
-__global__ void k_rec_base(const gsrf_pair *__restrict__ pairs, const int64_t *__restrict__ scene_off,
-                           int32_t P, int64_t *__restrict__ rec_base) {
-  __shared__ int64_t sh[1024];
-  const int tid = threadIdx.x;
-  const int per = (P + 1023) / 1024;
-  const int lo = tid * per, hi = min(P, lo + per);
-  int64_t local = 0;
-  for (int k = lo; k < hi; ++k) {
-    int s = pairs[k].scene;
-    local += scene_off[s + 1] - scene_off[s];
-  }
-  sh[tid] = local;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int64_t v = tid >= off ? sh[tid - off] : 0;
-    __syncthreads();
-    sh[tid] += v;
-    __syncthreads();
-  }
-  int64_t run = sh[tid] - local;
-  for (int k = lo; k < hi; ++k) {
-    rec_base[k] = run;
-    int s = pairs[k].scene;
-    run += scene_off[s + 1] - scene_off[s];
-  }
-  if (tid == 1023) rec_base[P] = sh[1023];
-}
-
 // ---------------------------------------------------------------------------
 // a2: per (pair, Gaussian) depth key and conservative tile rectangle, FP64.
 //   e = mu - r, D^2 = (ex ex + ey ey) + ez ez (no FMA), key = bits(fp32(D^2)).
@@ -81,7 +89,7 @@ __global__ void k_rec_base(const gsrf_pair *__restrict__ pairs, const int64_t *_
 //   rows with centre elevation in [beta_c - theta, beta_c + theta], and columns
 //   with centre azimuth within asin(sin theta / cos beta_c) of alpha_c unless
 //   the band reaches a pole.  Columns wrap at the azimuth seam.
-// The workgroup (256 records of one pair) counts its splats per tile in LDS
+// The workgroup (RB records of one pair) counts its splats per tile in LDS
 // and adds the counts to tile_cnt with one atomic per touched tile.
 // ---------------------------------------------------------------------------
 #pragma clang fp contract(off)
@@ -214,19 +222,24 @@ __device__ __forceinline__ bool project_record_fast(const gsrf_pair &pr, const f
   return cap_rect_fp32((float)ex, (float)ey, (float)ez, sqrtf((float)D2), 3.0f * expf(lmaxf), grid, nta, rect);
 }
 
-// Workgroup = 256 consecutive records of one pair; per-tile counts gathered
+// Workgroup = RB consecutive records of one pair; per-tile counts gathered
 // in LDS by a balanced expansion of the rectangles, then one atomic per
 // touched tile on the workgroup's sub-bucket counter.
-__global__ __launch_bounds__(256) void k_project(const gsrf_pair *__restrict__ pairs,
+// The sub-bucket of a record is (record index / emit's workgroup size) % kSub,
+// so this kernel's workgroups (RB records) count into the sub-bucket from
+// which emit's workgroup of the same records later reserves: sub_shift =
+// log2(emit workgroup / RB).
+template <int RB>
+__global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pairs,
                                                  const int64_t *__restrict__ scene_off,
                                                  const int64_t *__restrict__ rec_base, const float *__restrict__ means,
                                                  const float *__restrict__ log_scales, gsrf_grid grid, int32_t nta,
-                                                 int32_t T, int64_t PT, uint32_t *__restrict__ rec_key,
+                                                 int32_t T, int64_t PT, int sub_shift, uint32_t *__restrict__ rec_key,
                                                  ushort4 *__restrict__ rec_rect, uint32_t *__restrict__ tile_cnt) {
   extern __shared__ uint32_t hist[];   // [T]
-  __shared__ RectScan rs;
-  __shared__ ushort4 rects[256];
-  __shared__ int fallback[256];
+  __shared__ RectScan<RB> rs;
+  __shared__ ushort4 rects[RB];
+  __shared__ int fallback[RB];
   __shared__ int n_fallback;
   const int k = blockIdx.y;
   for (int t = threadIdx.x; t < T; t += blockDim.x) hist[t] = 0;
@@ -234,7 +247,7 @@ __global__ __launch_bounds__(256) void k_project(const gsrf_pair *__restrict__ p
   const gsrf_pair pr = pairs[k];
   const int64_t g0 = scene_off[pr.scene];
   const int64_t n = scene_off[pr.scene + 1] - g0;
-  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int64_t j0 = (int64_t)blockIdx.x * RB;
   const int64_t j = j0 + threadIdx.x;
   __syncthreads();
   ushort4 rc = make_ushort4(0, 0, 0, 0);
@@ -249,7 +262,7 @@ __global__ __launch_bounds__(256) void k_project(const gsrf_pair *__restrict__ p
   rects[threadIdx.x] = rc;
   __syncthreads();
   // records the FP32 evaluation could not decide, packed onto the first lanes
-  for (int i = threadIdx.x; i < n_fallback; i += 256) {
+  for (int i = threadIdx.x; i < n_fallback; i += RB) {
     const int slot = fallback[i];
     const int64_t g = g0 + j0 + slot;
     rects[slot] = cap_rect_fp64(means[3 * g], means[3 * g + 1], means[3 * g + 2], pr.rx[0], pr.rx[1], pr.rx[2],
@@ -260,14 +273,14 @@ __global__ __launch_bounds__(256) void k_project(const gsrf_pair *__restrict__ p
   rc = rects[threadIdx.x];
   if (j < n) rec_rect[rec_base[k] + j] = rc;
   rect_scan(rs, rc);
-  const uint32_t total = rs.off[256];
-  for (uint32_t sp = threadIdx.x; sp < total; sp += 256) {
+  const uint32_t total = rs.off[RB];
+  for (uint32_t sp = threadIdx.x; sp < total; sp += RB) {
     int t;
     rect_splat(rs, sp, nta, &t);
     atomicAdd(&hist[t], 1u);
   }
   __syncthreads();
-  uint32_t *dst = tile_cnt + (size_t)(blockIdx.x % kSub) * PT + (size_t)k * T;
+  uint32_t *dst = tile_cnt + (size_t)((blockIdx.x >> sub_shift) % kSub) * PT + (size_t)k * T;
   for (int t = threadIdx.x; t < T; t += blockDim.x)
     if (hist[t]) atomicAdd(dst + t, hist[t]);
 }
@@ -331,9 +344,11 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int64_t *__restrict__ blk,
   }
 }
 
+// blk == null: the only block (P * T <= kScanTiles) also makes the total and
+// the overflow flag, so the first two passes are skipped.
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ tile_cnt, int64_t PT,
-                                                    const int64_t *__restrict__ blk,
-                                                    const int64_t *__restrict__ counters,
+                                                    const int64_t *__restrict__ blk, int64_t cap,
+                                                    int64_t *__restrict__ counters,
                                                     uint32_t *__restrict__ tstart, uint32_t *__restrict__ tend,
                                                     uint32_t *__restrict__ tcur) {
   __shared__ int64_t sh[256];
@@ -357,8 +372,20 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
     sh[tid] += y;
     __syncthreads();
   }
-  const bool over = counters[1] != 0;
-  int64_t run = blk[blockIdx.x] + sh[tid] - local;
+  bool over;
+  int64_t run;
+  if (blk) {
+    over = counters[1] != 0;
+    run = blk[blockIdx.x] + sh[tid] - local;
+  } else {
+    const int64_t total = sh[255];
+    over = total > cap;
+    run = sh[tid] - local;
+    if (tid == 0) {
+      counters[0] = total;
+      counters[1] = over ? total : 0;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int64_t t = t0 + i;
@@ -378,32 +405,37 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
   int64_t *rec_base = (int64_t *)(ws + lay.rec_base);
   const int64_t PT = (int64_t)p->n_pairs * lay.T;
   uint32_t *tile_cnt = (uint32_t *)(ws + lay.tile_cnt);
-  hipError_t e = fill<uint32_t>(tile_cnt, 0u, PT * kSub, s);
-  if (e != hipSuccess) return e;
-  if (p->n_gauss > 0) {
-    hipLaunchKernelGGL(k_activate, dim3((unsigned)((p->n_gauss + 255) / 256)), dim3(256), 0, s, p->means,
-                       p->log_scales, p->quats, p->opacity_logits, p->n_gauss, prep);
-  }
-  if (p->n_pairs > 0) {
-    hipLaunchKernelGGL(k_rec_base, dim3(1), dim3(1024), 0, s, p->pairs, p->scene_offsets_dev, p->n_pairs,
-                       rec_base);
+  {
+    int64_t nb = (p->n_gauss + 255) / 256;
+    const int64_t nb_cnt = (PT * kSub + 255) / 256;
+    if (nb_cnt > nb) nb = nb_cnt < 4096 ? nb_cnt : 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_activate, dim3((unsigned)nb), dim3(256), 0, s, p->means, p->log_scales, p->quats,
+                       p->opacity_logits, p->n_gauss, prep, tile_cnt, PT * kSub, p->pairs, p->scene_offsets_dev,
+                       p->n_pairs, rec_base);
   }
   if (lay.n_records > 0) {
+    const int sub_shift = lay.rec_block == 1024 ? 2 : 0;   // emit's workgroup = 256 << sub_shift records
     dim3 grid((unsigned)((lay.max_scene + 255) / 256), (unsigned)p->n_pairs);
-    hipLaunchKernelGGL(k_project, grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev, rec_base,
-                       p->means, p->log_scales, p->grid, lay.nta, lay.T, PT, (uint32_t *)(ws + lay.rec_key),
+    hipLaunchKernelGGL(k_project<256>, grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev, rec_base,
+                       p->means, p->log_scales, p->grid, lay.nta, lay.T, PT, sub_shift, (uint32_t *)(ws + lay.rec_key),
                        (ushort4 *)(ws + lay.rec_rect), tile_cnt);
   }
   int64_t *blk = (int64_t *)(ws + lay.scan_blk);
   int64_t *counters = (int64_t *)(ws + lay.counters);
   const int64_t nblk = (PT + kScanTiles - 1) / kScanTiles;
-  if (nblk > 0)
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(256), 0, s, tile_cnt, PT, blk);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, nblk, lay.cap, counters);
-  if (nblk > 0)
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(256), 0, s, tile_cnt, PT, (const int64_t *)blk,
-                       (const int64_t *)counters, (uint32_t *)(ws + lay.tile_start), (uint32_t *)(ws + lay.tile_end),
+  if (nblk <= 1) {
+    // one block: counts, total and ranges in a single launch (also P * T = 0)
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(256), 0, s, tile_cnt, PT, (const int64_t *)nullptr, lay.cap,
+                       counters, (uint32_t *)(ws + lay.tile_start), (uint32_t *)(ws + lay.tile_end),
                        (uint32_t *)(ws + lay.tile_cur));
+  } else {
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(256), 0, s, tile_cnt, PT, blk);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, nblk, lay.cap, counters);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(256), 0, s, tile_cnt, PT, (const int64_t *)blk,
+                       lay.cap, counters, (uint32_t *)(ws + lay.tile_start), (uint32_t *)(ws + lay.tile_end),
+                       (uint32_t *)(ws + lay.tile_cur));
+  }
   return hipGetLastError();
 }
 

@@ -15,11 +15,12 @@
 
 namespace gsrf {
 
-// a3: one splat per covered tile.  The workgroup (256 records of one pair)
+// a3: one splat per covered tile.  The workgroup (RB records of one pair)
 // counts its splats per tile in LDS, reserves each tile's share with one
 // global atomic on its sub-bucket's cursor, then writes (key, Gaussian) at its
 // reserved slots.
-__global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pairs,
+template <int RB>
+__global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs,
                                               const int64_t *__restrict__ scene_off,
                                               const int64_t *__restrict__ rec_base,
                                               const uint32_t *__restrict__ rec_key,
@@ -30,14 +31,14 @@ __global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pair
   extern __shared__ uint32_t sm[];
   uint32_t *cnt = sm;        // [T]
   uint32_t *base = sm + T;   // [T]
-  __shared__ RectScan rs;
-  __shared__ uint32_t keys[256];
+  __shared__ RectScan<RB> rs;
+  __shared__ uint32_t keys[RB];
   const int k = blockIdx.y;
   for (int t = threadIdx.x; t < T; t += blockDim.x) cnt[t] = 0;
   const int s = pairs[k].scene;
   const int64_t g0 = scene_off[s];
   const int64_t n = scene_off[s + 1] - g0;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * RB + threadIdx.x;
   ushort4 rc = make_ushort4(0, 0, 0, 0);
   uint32_t key = 0;
   if (j < n) {
@@ -47,8 +48,8 @@ __global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pair
   }
   keys[threadIdx.x] = key;
   rect_scan(rs, rc);
-  const uint32_t total = rs.off[256];
-  for (uint32_t sp = threadIdx.x; sp < total; sp += 256) {
+  const uint32_t total = rs.off[RB];
+  for (uint32_t sp = threadIdx.x; sp < total; sp += RB) {
     int t;
     rect_splat(rs, sp, nta, &t);
     atomicAdd(&cnt[t], 1u);
@@ -62,8 +63,8 @@ __global__ __launch_bounds__(256) void k_emit(const gsrf_pair *__restrict__ pair
     cnt[t] = 0;
   }
   __syncthreads();
-  const uint32_t gbase = (uint32_t)(g0 + (int64_t)blockIdx.x * 256);
-  for (uint32_t sp = threadIdx.x; sp < total; sp += 256) {
+  const uint32_t gbase = (uint32_t)(g0 + (int64_t)blockIdx.x * RB);
+  for (uint32_t sp = threadIdx.x; sp < total; sp += RB) {
     int t;
     const int slot = rect_splat(rs, sp, nta, &t);
     const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
@@ -348,11 +349,18 @@ hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, h
   const uint32_t *tstart = (const uint32_t *)(ws + lay.tile_start);
   const uint32_t *tend = (const uint32_t *)(ws + lay.tile_end);
   {
-    dim3 grid((unsigned)((lay.max_scene + 255) / 256), (unsigned)p->n_pairs);
-    hipLaunchKernelGGL(k_emit, grid, dim3(256), (size_t)lay.T * 8, s, p->pairs, p->scene_offsets_dev,
-                       (const int64_t *)(ws + lay.rec_base), (const uint32_t *)(ws + lay.rec_key),
-                       (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, PT, counters,
-                       (uint32_t *)(ws + lay.tile_cur), (uint32_t *)(ws + lay.ekey), (uint32_t *)(ws + lay.eval));
+    const int RB = lay.rec_block;
+    dim3 grid((unsigned)((lay.max_scene + RB - 1) / RB), (unsigned)p->n_pairs);
+    if (RB == 1024)
+      hipLaunchKernelGGL(k_emit<1024>, grid, dim3(1024), (size_t)lay.T * 8, s, p->pairs, p->scene_offsets_dev,
+                         (const int64_t *)(ws + lay.rec_base), (const uint32_t *)(ws + lay.rec_key),
+                         (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, PT, counters,
+                         (uint32_t *)(ws + lay.tile_cur), (uint32_t *)(ws + lay.ekey), (uint32_t *)(ws + lay.eval));
+    else
+      hipLaunchKernelGGL(k_emit<256>, grid, dim3(256), (size_t)lay.T * 8, s, p->pairs, p->scene_offsets_dev,
+                         (const int64_t *)(ws + lay.rec_base), (const uint32_t *)(ws + lay.rec_key),
+                         (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, PT, counters,
+                         (uint32_t *)(ws + lay.tile_cur), (uint32_t *)(ws + lay.ekey), (uint32_t *)(ws + lay.eval));
   }
   choose_sort_chunk();
   hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)PT), dim3(kTileSortThreads), g_sort_lds, s, tstart, tend,
