@@ -45,12 +45,12 @@ constexpr int kGeo = 5;
 constexpr int n_acc(int L) { return 12 + 2 * (L + 1) * (L + 1); }
 constexpr int pow2_at_least(int n) { return n <= 32 ? 32 : (n <= 64 ? 64 : 128); }
 
-constexpr int lds_batch(int L, int NT, bool bwd) {
+constexpr int lds_batch(int L, int NT, bool bwd, int cap = 256) {
   // floats per staged entry: geometry + coefficients (+ accumulators for bwd)
   int K = (L + 1) * (L + 1);
   int per = 4 * kGeo + 2 * K + (bwd ? n_acc(L) + 1 : 0);
   int budget = 60 * 1024 / 4;
-  int b = NT < 256 ? NT : 256;
+  int b = NT < cap ? NT : cap;
   while (b > 32 && b * per > budget) b >>= 1;
   return b;
 }

@@ -47,11 +47,15 @@ struct TpIO {
   float *acc;                     // adjoint accumulators [n_acc - 1][n_gauss]
 };
 
-template <int L, int R, int MODE>
+// BCAP: largest staged batch.  Smaller batches waste fewer tests past the
+// rays' termination (the last batch is tested whole), larger ones need fewer
+// barriers: the forward uses 128, the adjoint 64 when the launch has few
+// workgroups (latency-bound) and 128 otherwise.
+template <int L, int R, int MODE, int BCAP>
 struct TpShape {
   static constexpr bool BWD = MODE == kTpBwd;
   static constexpr int K = (L + 1) * (L + 1);
-  static constexpr int B = lds_batch(L, 256, BWD);
+  static constexpr int B = lds_batch(L, 256, BWD, BCAP);
   static constexpr int NACC = n_acc(L);
   static constexpr int MW = (B + 31) / 32;       // mask words per row
   static constexpr int MWS = MW + 1;             // odd row stride: conflict-free column reads
@@ -118,10 +122,10 @@ __device__ __forceinline__ unsigned phase1_tests(const RayMono &v, const float4 
   return n_test;
 }
 
-template <int L, int R, int MODE>
+template <int L, int R, int MODE, int BCAP>
 __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   using TP = TwoPhase<R>;
-  using SH = TpShape<L, R, MODE>;
+  using SH = TpShape<L, R, MODE, BCAP>;
   constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats;
   constexpr int NT = TP::NT, G = TP::G, EP = TP::EP, RPW = TP::RPW;
   constexpr int K = SH::K, B = SH::B, NACC = SH::NACC, MW = SH::MW, MWS = SH::MWS;
@@ -322,25 +326,38 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   }
 }
 
-template <int L, int R, int MODE>
+template <int L, int R, int MODE, int BCAP>
 hipError_t tp_launch(const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
-  constexpr size_t lds = TpShape<L, R, MODE>::lds();
+  constexpr size_t lds = TpShape<L, R, MODE, BCAP>::lds();
   if constexpr (lds > 65536) {   // high FLE degrees: opt in to more than 64 KB of LDS
-    const hipError_t e =
-        hipFuncSetAttribute((const void *)k_render_tp<L, R, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute((const void *)k_render_tp<L, R, MODE, BCAP>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_render_tp<L, R, MODE>), dim3((unsigned)nblocks), dim3(256), lds, s, a, io);
+  hipLaunchKernelGGL((k_render_tp<L, R, MODE, BCAP>), dim3((unsigned)nblocks), dim3(256), lds, s, a, io);
   return hipGetLastError();
 }
 
+// Workgroups below which the adjoint launch counts as latency-bound.
+constexpr int64_t kFewBlocks = 2048;
+
 template <int L, int MODE>
 hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
+  if constexpr (MODE == kTpBwd) {
+    if (nblocks <= kFewBlocks) {
+      switch (area) {
+        case 32: return tp_launch<L, 32, MODE, 64>(a, io, nblocks, s);
+        case 64: return tp_launch<L, 64, MODE, 64>(a, io, nblocks, s);
+        case 128: return tp_launch<L, 128, MODE, 64>(a, io, nblocks, s);
+        default: return tp_launch<L, 256, MODE, 64>(a, io, nblocks, s);
+      }
+    }
+  }
   switch (area) {
-    case 32: return tp_launch<L, 32, MODE>(a, io, nblocks, s);
-    case 64: return tp_launch<L, 64, MODE>(a, io, nblocks, s);
-    case 128: return tp_launch<L, 128, MODE>(a, io, nblocks, s);
-    default: return tp_launch<L, 256, MODE>(a, io, nblocks, s);
+    case 32: return tp_launch<L, 32, MODE, 128>(a, io, nblocks, s);
+    case 64: return tp_launch<L, 64, MODE, 128>(a, io, nblocks, s);
+    case 128: return tp_launch<L, 128, MODE, 128>(a, io, nblocks, s);
+    default: return tp_launch<L, 256, MODE, 128>(a, io, nblocks, s);
   }
 }
 
