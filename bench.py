@@ -103,7 +103,8 @@ def main() -> int:
     ap.add_argument("--workloads", default="plain,fwd_500k,uneven",
                     help="comma list of plain, fwd_500k, uneven (profiling runs pick one)")
     ap.add_argument("--batched-pairs", type=int, default=256)
-    ap.add_argument("--batched-iters", type=int, default=5)
+    ap.add_argument("--batched-iters", type=int, default=50)
+    ap.add_argument("--batched-warmup", type=int, default=10)
     ap.add_argument("--gaussians", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="8x8", help="tile_w x tile_h (64, 128 or 256 rays)")
@@ -158,6 +159,8 @@ def main() -> int:
 
     def run(prob, bufs, steps, bwd, ev=None):
         for i in range(steps):
+            if ev is not None and "s0" in ev:
+                ev["s0"][i].record(stream)
             if ev is not None:
                 # the library records these around its render kernels only
                 _lib.lib().gsrf_set_kernel_events(ev["f0"][i].cuda_event, ev["f1"][i].cuda_event,
@@ -167,6 +170,8 @@ def main() -> int:
             prob.render_fwd(bufs["sig"], bufs["ssum"], bufs["rssi"])
             if bwd:
                 prob.render_bwd(bufs["sig"], bufs["G"], bufs["gsum"], out=bufs["grads"])
+            if ev is not None and "s1" in ev:
+                ev["s1"][i].record(stream)
         _lib.lib().gsrf_set_kernel_events(None, None, None, None)
 
     def timed(prob, bufs, steps, warmup, bwd, ev=None):
@@ -215,7 +220,8 @@ def main() -> int:
         prob = build(g)
         gs, gsum = make_grad(prob) if grad else (None, None)
         step = GraphStep(prob, grad, gs, gsum)
-        t = step.time(iters=args.batched_iters, warmup=1)
+        st = step.time_stats(iters=args.batched_iters, warmup=args.batched_warmup)
+        t = st["median"]
         bufs = dict(sig=step.signal, ssum=step.signal_sum, rssi=step.rssi, G=gs, gsum=gsum, grads=step.grads)
         roof = roofline(prob, bufs, grad)
         n_splats, _ = prob.splat_count()
@@ -223,19 +229,25 @@ def main() -> int:
         del step, prob
         torch.cuda.empty_cache()
         return {"workload": label, "pairs": P, "gaussians": int(cat.means.shape[0]),
-                "spectra_per_s": P / t, "ms_per_replay": t * 1e3, "timing": "median of hipGraph replays "
-                "(project+bin_sort+render_fwd" + ("+render_bwd" if grad else "") + " for all pairs)",
+                "spectra_per_s": P / t, "ms_per_replay": t * 1e3,
+                "ms_per_replay_p10_p90": [st["p10"] * 1e3, st["p90"] * 1e3],
+                "timing": f"median of {st['n']} hipGraph replays after {args.batched_warmup} warm-up replays, HIP "
+                "events around each replay (project+bin_sort+render_fwd" + ("+render_bwd" if grad else "") +
+                " for all pairs)",
                 "tile": f"{tw}x{th}", "lanes_per_ray": lanes,
                 "autotune_ms": {f"{a}x{b_}/{c}": v * 1e3 for (a, b_, c), v in tune.seconds.items()},
                 "roofline": roof}
 
     def run_plain():
         prob, bufs = make([pair])
-        ev = {k: [new_event() for _ in range(args.steps)] for k in ("f0", "f1", "b0", "b1")}
+        ev = {k: [new_event() for _ in range(args.steps)] for k in ("f0", "f1", "b0", "b1", "s0", "s1")}
         torch.cuda.synchronize()
         t_step = timed(prob, bufs, args.steps, args.warmup, True, ev)
         t_fwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["f0"], ev["f1"])) / args.steps * 1e-3
         t_bwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["b0"], ev["b1"])) / args.steps * 1e-3
+        steps_ms = sorted(a.elapsed_time(b) for a, b in zip(ev["s0"], ev["s1"]))
+        q = lambda f: steps_ms[min(len(steps_ms) - 1, int(round(f * (len(steps_ms) - 1))))]
+        step_stats.update(median=q(0.5), p10=q(0.1), p90=q(0.9))
         t_fwd_only = timed(prob, bufs, args.steps, 1, False)
         stats = prob.render_stats()
         n_splats, _ = prob.splat_count()
@@ -258,6 +270,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         return t_step, t_fwd_only, t_fwd_k, t_bwd_k, roof
 
+    step_stats = {}
     work = set(args.workloads.split(","))
     # ---- plain: one pair per launch sequence (the headline step) -------------
     t_step = t_fwd_only = t_fwd_k = t_bwd_k = None
@@ -305,6 +318,7 @@ def main() -> int:
                                "pair, 360x90 rays, 5 GHz, FLE L=2; project+bin_sort+render_fwd+render_bwd",
                    "gaussians": args.gaussians, "rays": "360x90", "pairs": 1, "tile": args.tile,
                    "lanes_per_ray": args.lanes},
+        "step_ms_events": step_stats or None,
         "fwd_only": None if t_fwd_only is None else {"spectra_per_s": 1.0 / t_fwd_only, "ms": t_fwd_only * 1e3},
         "kernels_ms": None if t_fwd_k is None else {"render_fwd": t_fwd_k * 1e3, "render_bwd": t_bwd_k * 1e3},
         "batched": batched,

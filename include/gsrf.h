@@ -200,7 +200,9 @@ gsrf_status gsrf_render_fwd(const gsrf_problem *p, float *signal, float *signal_
  * covariance chain the paper omits): recomputes each ray's transmittance
  * front to back (no per-ray state is stored by render_fwd beyond `signal`)
  * and forms the gradient of L with respect to every parameter, where the
- * caller supplies dL/dS per ray and per pair:
+ * caller supplies dL/dS per ray and per pair.  Must follow gsrf_render_fwd
+ * of the same prepared problem on the same workspace: with lanes_per_ray = 0
+ * it reuses the per-list-entry hit masks that call records there.
  *   signal       [P, n_el, n_az, 2]  the render_fwd output for this problem
  *   grad_signal  [P, n_el, n_az, 2]  dL/dRe S + j dL/dIm S
  *   grad_sum     [P, 2] or NULL      dL/dS_hat (added to every ray of the pair)

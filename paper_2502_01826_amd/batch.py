@@ -66,18 +66,26 @@ class GraphStep:
         self.graph.replay()
 
     def time(self, iters: int = 5, warmup: int = 1) -> float:
-        """Median seconds per replay, bracketed by device synchronisation."""
+        """Median seconds per replay (HIP events around each replay)."""
+        return self.time_stats(iters, warmup)["median"]
+
+    def time_stats(self, iters: int = 50, warmup: int = 10) -> dict:
+        """Per-replay seconds from HIP events recorded on the replay stream
+        around each replay: median, p10, p90 over `iters` replays after
+        `warmup` untimed ones."""
         for _ in range(warmup):
             self.replay()
+        stream = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(iters)]
         torch.cuda.synchronize()
-        ts = []
-        for _ in range(iters):
-            t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
             self.replay()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        ts.sort()
-        return ts[len(ts) // 2]
+            b.record(stream)
+        torch.cuda.synchronize()
+        ts = sorted(a.elapsed_time(b) * 1e-3 for a, b in ev)
+        q = lambda f: ts[min(len(ts) - 1, int(round(f * (len(ts) - 1))))]
+        return {"median": q(0.5), "p10": q(0.1), "p90": q(0.9), "n": len(ts)}
 
 
 @dataclass

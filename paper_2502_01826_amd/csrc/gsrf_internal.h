@@ -100,6 +100,7 @@ struct Layout {
   size_t klo, val;        // sorted tile lists: depth key, Gaussian id
   size_t tkey, tval;      // sort scratch for buckets longer than the LDS chunk
   size_t tile_sum, grad_acc;
+  size_t hitmask;         // two-phase traversal: per splat, tile-area / 32 words of forward hit bits
   size_t total;
   int64_t n_records;
   int32_t rec_block;      // records per workgroup in emit (256 or 1024)

@@ -31,6 +31,8 @@ struct RenderArgs {
   const uint32_t *val;      // sorted Gaussian ids
   const uint32_t *tstart;   // [P*T]
   const uint32_t *tend;     // [P*T]
+  uint32_t *hitmask;        // [splats][R / 32]: per list entry, its hits over the tile's rays (two-phase
+                            // traversal: written by the forward, read by the adjoint)
   int32_t T, nta, n_az, n_el, tw;
   float el_lo, el_hi, r_rx, t_min, amax;
 };

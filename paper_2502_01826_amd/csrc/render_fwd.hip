@@ -208,6 +208,7 @@ RenderArgs make_render_args(const gsrf_problem *p, const Layout &lay, char *ws) 
   a.val = (const uint32_t *)(ws + lay.val);
   a.tstart = (const uint32_t *)(ws + lay.tile_start);
   a.tend = (const uint32_t *)(ws + lay.tile_end);
+  a.hitmask = (uint32_t *)(ws + lay.hitmask);
   a.T = lay.T;
   a.nta = lay.nta;
   a.n_az = p->grid.n_az;

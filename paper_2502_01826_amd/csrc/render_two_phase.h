@@ -8,7 +8,10 @@
 //   phase 1  dense hit tests: thread t takes ray t % R against entries
 //            e, e + EP, ... (e = t / R, EP = 256 / R) and ORs the hits into
 //            per-ray bit rows in LDS, and into the union row of the phase-2
-//            wave that serves the ray;
+//            wave that serves the ray.  The forward also stores each list
+//            entry's hits as an R-bit mask in the workspace; the adjoint
+//            rebuilds its rows from those masks instead of testing again
+//            (the same decisions, for the rays still active);
 //   phase 2  each wave serves 64 / G rays with G = 256 / R adjacent lanes per
 //            ray and walks the union of its rays' hit bits in depth order, G
 //            entries per step (a wave-uniform scalar cursor).  A lane does the
@@ -59,6 +62,7 @@ struct TpShape {
   static constexpr int NACC = n_acc(L);
   static constexpr int MW = (B + 31) / 32;       // mask words per row
   static constexpr int MWS = MW + 1;             // odd row stride: conflict-free column reads
+  static constexpr int MWR = R / 32;             // hit-mask words per entry (one bit per ray)
   // LDS: geometry, coefficients, [accumulators, flags], ray rows, union rows, done flags
   static constexpr size_t kLds = (size_t)B * (kGeo * 16 + 2 * K * 4) + (BWD ? (size_t)B * (NACC * 4 + 4) : 0) +
                                  (size_t)R * MWS * 4 + (size_t)4 * MW * 4 + (size_t)R * 4;
@@ -93,6 +97,24 @@ __device__ __forceinline__ bool hit_decision(const RayMono &v, const float4 *geo
   const float Q = geo[4].y * fmaf(-b, bA, c);
   const float t = fmaf(-g0.w, bA, g0.w);
   return (Q <= kLevel) && (t >= r_rx);
+}
+
+// 32 x 32 bit transpose across the 32 lanes of a half-wave: on return lane l
+// holds, as bit i, bit l of lane i's input.  Five exchanges at lane distances
+// 16, 8, 4, 2, 1, each swapping the off-diagonal blocks of that size.
+template <int J>
+__device__ __forceinline__ uint32_t transpose_step(uint32_t x, int lane, uint32_t m) {
+  const uint32_t y = __float_as_uint(xor_lane<J>(__uint_as_float(x), lane));
+  return (lane & J) ? ((x & ~m) | ((y >> J) & m)) : ((x & m) | ((y << J) & ~m));
+}
+
+__device__ __forceinline__ uint32_t transpose32(uint32_t x, int lane) {
+  x = transpose_step<16>(x, lane, 0x0000FFFFu);
+  x = transpose_step<8>(x, lane, 0x00FF00FFu);
+  x = transpose_step<4>(x, lane, 0x0F0F0F0Fu);
+  x = transpose_step<2>(x, lane, 0x33333333u);
+  x = transpose_step<1>(x, lane, 0x55555555u);
+  return x;
 }
 
 // Phase 1: hit bits of ray v against entries e, e + EP, ... < nb, one 32-entry
@@ -138,6 +160,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   uint32_t *smask = (uint32_t *)(sflag + (BWD ? B : 0));    // [R][MWS]
   uint32_t *suni = smask + R * MWS;                         // [4][MW]
   int *sdone = (int *)(suni + 4 * MW);                      // [R]
+  constexpr int MWR = SH::MWR;
   const int gt = blockIdx.x;
   const int k = gt / a.T;
   const int tile = gt - k * a.T;
@@ -195,18 +218,56 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     if (tid < nb)
       stage_entry<K>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                      sgeo + kGeo * tid, scf + 2 * K * tid);
-    for (int i = tid; i < R * MWS + 4 * MW; i += NT) smask[i] = 0u;   // ray rows and union rows
+    if constexpr (!BWD)
+      for (int i = tid; i < R * MWS + 4 * MW; i += NT) smask[i] = 0u;   // ray rows and union rows
+
     if (STATS && tid == 0) {
       n_staged += nb;
       n_tile_tests += (unsigned long long)nb * n_valid_rays;
     }
     __syncthreads();
-    // ---- phase 1 ----
-    if (valid1 && !sdone[r1]) {
-      const unsigned nt = phase1_tests<EP, MW>(w1, sgeo, nb, e, a.r_rx, smask + r1 * MWS, suni + (r1 / RPW) * MW);
-      if (STATS) n_test += nt;
+    // ---- phase 1: the forward tests; the adjoint takes the forward's hit masks ----
+    if constexpr (!BWD) {
+      if (valid1 && !sdone[r1]) {
+        const unsigned nt = phase1_tests<EP, MW>(w1, sgeo, nb, e, a.r_rx, smask + r1 * MWS, suni + (r1 / RPW) * MW);
+        if (STATS) n_test += nt;
+      }
+      __syncthreads();
+      if constexpr (MODE == kTpFwd) {
+        // entry masks = transpose of the ray rows, one 32 x 32 bit block per
+        // half-wave: block (ray block rb, entry word w); lane l of the half
+        // reads ray 32 rb + l's row word and ends with entry 32 w + l's bits
+        constexpr int NBLK = (R / 32) * MW;
+        const int hl = lane & 31;
+        for (int blk = (tid >> 5); blk < NBLK; blk += NT / 32) {
+          const int rb = blk / MW, w = blk - rb * MW;
+          const uint32_t m = transpose32(smask[(rb * 32 + hl) * MWS + w], hl);
+          const int j = w * 32 + hl;
+          if (j < nb) a.hitmask[(size_t)(base + j) * MWR + rb] = m;
+        }
+      }
+    } else {
+      // the forward's entry masks, transposed back into the rows of the rays
+      // still active; then the union rows of the phase-2 waves
+      constexpr int NBLK = (R / 32) * MW;
+      const int hl = lane & 31;
+      for (int blk = (tid >> 5); blk < NBLK; blk += NT / 32) {
+        const int rb = blk / MW, w = blk - rb * MW;
+        const int j = w * 32 + hl;
+        const uint32_t m = j < nb ? a.hitmask[(size_t)(base + j) * MWR + rb] : 0u;
+        const uint32_t row = transpose32(m, hl);
+        const int rr = rb * 32 + hl;
+        smask[rr * MWS + w] = sdone[rr] ? 0u : row;
+      }
+      __syncthreads();
+      for (int i = tid; i < 4 * MW; i += NT) {
+        const int wv = i / MW, w = i - wv * MW;
+        uint32_t u = 0;
+        for (int rr = wv * RPW; rr < (wv + 1) * RPW; ++rr) u |= smask[rr * MWS + w];
+        suni[wv * MW + w] = u;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     // ---- phase 2: walk the wave's union, G entries per step ----
     if (__ballot(!done) != 0) {                              // wave-uniform
       const uint32_t *uw = suni + wave * MW;
