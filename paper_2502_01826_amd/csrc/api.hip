@@ -97,7 +97,7 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.nta = nta;
   L.nte = nte;
   L.K = fle_K(g.fle_L);
-  L.acc_stride = 11 + 2 * L.K;
+  L.acc_stride = (11 + 2 * L.K + 15) / 16 * 16;   // 64-byte rows of the adjoint accumulators
   const int64_t PT = (int64_t)p->n_pairs * T;
   size_t o = 0;
   auto take = [&](size_t bytes) {

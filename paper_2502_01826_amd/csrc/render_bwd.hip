@@ -16,8 +16,8 @@ namespace gsrf {
 template <int L, int NT, int G>
 __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *__restrict__ signal,
                                                    const float2 *__restrict__ grad_signal,
-                                                   const float2 *__restrict__ grad_sum, int64_t n_gauss,
-                                                   float *__restrict__ acc) {
+                                                   const float2 *__restrict__ grad_sum, float *__restrict__ acc,
+                                                   int acc_stride) {
   constexpr int K = (L + 1) * (L + 1);
   constexpr int B = lds_batch(L, NT, true);
   constexpr int NACC = n_acc(L);               // 12 + 2K
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
   float4 *sgeo = smem;                          // [B][kGeo]
   float *scf = (float *)(smem + kGeo * B);      // [B][2K]
   float *sacc = scf + 2 * K * B;                // [B][NACC]
-  int *sflag = (int *)(sacc + NACC * B);        // [B]
+  uint32_t *sflag = (uint32_t *)(sacc + NACC * B);   // [B]
   const int gt = blockIdx.x;
   const int k = gt / a.T;
   const int tile = gt - k * a.T;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
     }
   }
   for (int i = threadIdx.x; i < NACC * B; i += NT) sacc[i] = 0.f;
-  for (int i = threadIdx.x; i < B; i += NT) sflag[i] = 0;
+  for (int i = threadIdx.x; i < B; i += NT) sflag[i] = 0u;
   const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
   float T = 1.f, Pr = 0.f, Pi = 0.f;
   bool done = !valid || (1.0f < a.t_min);
@@ -65,6 +65,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
     if ((int)threadIdx.x < nb)
       stage_entry<K>(a, a.val[base + threadIdx.x], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                      sgeo + kGeo * threadIdx.x, scf + 2 * K * threadIdx.x);
+    for (int i = threadIdx.x; i < nb; i += NT) sflag[i] = 0u;   // the previous batch's flush ids
     __syncthreads();
     if (__ballot(!done) != 0) {              // wave-uniform
       for (int m = 0; m < nb; m += G) {
@@ -118,11 +119,8 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
       }
     }
     __syncthreads();
-    // flush: one thread per staged Gaussian with any processed hit in this tile
-    if ((int)threadIdx.x < nb && sflag[threadIdx.x]) {
-      flush_entry<K>(a, a.val[base + threadIdx.x], pr, sacc + NACC * threadIdx.x, n_gauss, acc);
-      sflag[threadIdx.x] = 0;
-    }
+    // flush the staged Gaussians with any processed hit in this tile
+    flush_batch<K, NT>(a, pr, base, nb, sacc, sflag, acc, acc_stride);
     if (__syncthreads_and(done ? 1 : 0)) break;
   }
 }
@@ -138,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chain(const float *__restrict__ log_scales, const float *__restrict__ quats,
                                                const float *__restrict__ logits, const float *__restrict__ acc,
-                                               int32_t K, int64_t G, float *__restrict__ d_means,
+                                               int32_t S, int32_t K, int64_t G, float *__restrict__ d_means,
                                                float *__restrict__ d_ls, float *__restrict__ d_q,
                                                float *__restrict__ d_a, float *__restrict__ d_c) {
   const int64_t g0 = (int64_t)blockIdx.x * 256;
@@ -150,11 +148,12 @@ __global__ __launch_bounds__(256) void k_chain(const float *__restrict__ log_sca
     for (int64_t e = threadIdx.x; e < total; e += 256) {
       const int64_t gi = g0 + e / (2 * K);
       const int comp = (int)(e % (2 * K));
-      d_c[g0 * 2 * K + e] = acc[(size_t)(11 + comp) * G + gi];
+      d_c[g0 * 2 * K + e] = acc[(size_t)gi * S + 11 + comp];
     }
   }
   if (g >= G) return;
-  auto A = [&](int f) { return acc[(size_t)f * G + g]; };
+  const float *row = acc + (size_t)g * S;
+  auto A = [&](int f) { return row[f]; };
   const float Gm[3][3] = {{A(0), A(3), A(4)}, {A(3), A(1), A(5)}, {A(4), A(5), A(2)}};
   d_means[3 * g + 0] = A(6);
   d_means[3 * g + 1] = A(7);
@@ -198,38 +197,37 @@ __global__ __launch_bounds__(256) void k_chain(const float *__restrict__ log_sca
 
 template <int L, int NT, int G>
 static hipError_t bwd_launch(const RenderArgs &a, int64_t nblocks, const float2 *sig, const float2 *gsig,
-                             const float2 *gsum, int64_t n_gauss, float *acc, hipStream_t s) {
+                             const float2 *gsum, float *acc, int S, hipStream_t s) {
   constexpr int K = (L + 1) * (L + 1);
   constexpr int B = lds_batch(L, NT, true);
   const size_t lds = (size_t)B * (kGeo * 16 + 2 * K * 4 + n_acc(L) * 4 + 4);
-  hipLaunchKernelGGL((k_render_bwd<L, NT, G>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, gsig, gsum, n_gauss,
-                     acc);
+  hipLaunchKernelGGL((k_render_bwd<L, NT, G>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, gsig, gsum, acc, S);
   return hipGetLastError();
 }
 
 
 template <int L>
 static hipError_t bwd_dispatch(int area, int G, const RenderArgs &a, int64_t nblocks, const float2 *sig,
-                               const float2 *gsig, const float2 *gsum, int64_t n, float *acc, hipStream_t s) {
+                               const float2 *gsig, const float2 *gsum, float *acc, int S, hipStream_t s) {
   if (G == 0) {
     TpIO io{};
     io.signal = const_cast<float2 *>(sig);
     io.grad_signal = gsig;
     io.grad_sum = gsum;
-    io.n_gauss = n;
     io.acc = acc;
+    io.acc_stride = S;
     return tp_dispatch<L, kTpBwd>(area, a, io, nblocks, s);
   }
   switch (area * 8 + G) {
-    case 64 * 8 + 1: return bwd_launch<L, 64, 1>(a, nblocks, sig, gsig, gsum, n, acc, s);
-    case 64 * 8 + 2: return bwd_launch<L, 128, 2>(a, nblocks, sig, gsig, gsum, n, acc, s);
-    case 64 * 8 + 4: return bwd_launch<L, 256, 4>(a, nblocks, sig, gsig, gsum, n, acc, s);
-    case 128 * 8 + 1: return bwd_launch<L, 128, 1>(a, nblocks, sig, gsig, gsum, n, acc, s);
-    case 128 * 8 + 2: return bwd_launch<L, 256, 2>(a, nblocks, sig, gsig, gsum, n, acc, s);
-    case 128 * 8 + 4: return bwd_launch<L, 512, 4>(a, nblocks, sig, gsig, gsum, n, acc, s);
-    case 256 * 8 + 1: return bwd_launch<L, 256, 1>(a, nblocks, sig, gsig, gsum, n, acc, s);
-    case 256 * 8 + 2: return bwd_launch<L, 512, 2>(a, nblocks, sig, gsig, gsum, n, acc, s);
-    default: return bwd_launch<L, 1024, 4>(a, nblocks, sig, gsig, gsum, n, acc, s);
+    case 64 * 8 + 1: return bwd_launch<L, 64, 1>(a, nblocks, sig, gsig, gsum, acc, S, s);
+    case 64 * 8 + 2: return bwd_launch<L, 128, 2>(a, nblocks, sig, gsig, gsum, acc, S, s);
+    case 64 * 8 + 4: return bwd_launch<L, 256, 4>(a, nblocks, sig, gsig, gsum, acc, S, s);
+    case 128 * 8 + 1: return bwd_launch<L, 128, 1>(a, nblocks, sig, gsig, gsum, acc, S, s);
+    case 128 * 8 + 2: return bwd_launch<L, 256, 2>(a, nblocks, sig, gsig, gsum, acc, S, s);
+    case 128 * 8 + 4: return bwd_launch<L, 512, 4>(a, nblocks, sig, gsig, gsum, acc, S, s);
+    case 256 * 8 + 1: return bwd_launch<L, 256, 1>(a, nblocks, sig, gsig, gsum, acc, S, s);
+    case 256 * 8 + 2: return bwd_launch<L, 512, 2>(a, nblocks, sig, gsig, gsum, acc, S, s);
+    default: return bwd_launch<L, 1024, 4>(a, nblocks, sig, gsig, gsum, acc, S, s);
   }
 }
 
@@ -247,20 +245,20 @@ hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws,
     const float2 *sg = (const float2 *)signal, *gs = (const float2 *)grad_signal, *gm = (const float2 *)grad_sum;
     mark_kernel_event(2, s);
     switch (p->grid.fle_L) {
-      case 0: e = bwd_dispatch<0>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
-      case 1: e = bwd_dispatch<1>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
-      case 2: e = bwd_dispatch<2>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
-      case 3: e = bwd_dispatch<3>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
-      case 4: e = bwd_dispatch<4>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
-      case 5: e = bwd_dispatch<5>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
-      default: e = bwd_dispatch<6>(area, G, a, nb, sg, gs, gm, p->n_gauss, acc, s); break;
+      case 0: e = bwd_dispatch<0>(area, G, a, nb, sg, gs, gm, acc, lay.acc_stride, s); break;
+      case 1: e = bwd_dispatch<1>(area, G, a, nb, sg, gs, gm, acc, lay.acc_stride, s); break;
+      case 2: e = bwd_dispatch<2>(area, G, a, nb, sg, gs, gm, acc, lay.acc_stride, s); break;
+      case 3: e = bwd_dispatch<3>(area, G, a, nb, sg, gs, gm, acc, lay.acc_stride, s); break;
+      case 4: e = bwd_dispatch<4>(area, G, a, nb, sg, gs, gm, acc, lay.acc_stride, s); break;
+      case 5: e = bwd_dispatch<5>(area, G, a, nb, sg, gs, gm, acc, lay.acc_stride, s); break;
+      default: e = bwd_dispatch<6>(area, G, a, nb, sg, gs, gm, acc, lay.acc_stride, s); break;
     }
     mark_kernel_event(3, s);
     if (e != hipSuccess) return e;
   }
   if (p->n_gauss > 0) {
     hipLaunchKernelGGL(k_chain, dim3((unsigned)((p->n_gauss + 255) / 256)), dim3(256), 0, s, p->log_scales, p->quats,
-                       p->opacity_logits, (const float *)acc, lay.K, p->n_gauss, d_means, d_log_scales, d_quats,
+                       p->opacity_logits, (const float *)acc, lay.acc_stride, lay.K, p->n_gauss, d_means, d_log_scales, d_quats,
                        d_logits, d_coeffs);
   }
   return hipGetLastError();

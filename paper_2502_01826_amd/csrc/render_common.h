@@ -428,25 +428,49 @@ __device__ __forceinline__ void hit_adjoint(const Terms &h, const float4 *geo, f
   c[SLOT_T] = gt_;       // dL/dt; TX leg applied at the flush
 }
 
-// Flush of one staged Gaussian's LDS accumulators to the global SoA
-// accumulators, folding dL/dt's TX leg (mu - tx)/|mu - tx| into dL/dmu.
-template <int K>
-__device__ __forceinline__ void flush_entry(const RenderArgs &a, uint32_t g, const gsrf_pair &pr, float *src,
-                                            int64_t n_gauss, float *__restrict__ acc) {
+// Flush of a staged batch's LDS accumulators to the global accumulators
+// acc[n_gauss][S] (row stride S >= 11 + 2K floats, 64-byte aligned rows).
+// First every flagged entry folds dL/dt's TX leg (mu - tx)/|mu - tx| into
+// dL/dmu and replaces its flag by its Gaussian id (kNoFlush if it had no
+// processed hit); then one lane per (entry, slot) adds a slot, so the atomics
+// of one wave instruction land on one or two Gaussians' rows instead of one
+// row per lane.  Every thread of the workgroup calls it; the LDS accumulators
+// are left zeroed, and the caller clears the flags before the next batch.
+constexpr uint32_t kNoFlush = 0xFFFFFFFFu;
+
+template <int K, int NT>
+__device__ __forceinline__ void flush_batch(const RenderArgs &a, const gsrf_pair &pr, uint32_t base, int nb,
+                                            float *sacc, uint32_t *sflag, float *__restrict__ acc, int S) {
   constexpr int SLOT_T = 11 + 2 * K;
   constexpr int NACC = 12 + 2 * K;
-  const float *pg = a.prep + (size_t)kPrep * g;
-  const double qx = (double)pg[0] - pr.tx[0], qy = (double)pg[1] - pr.tx[1], qz = (double)pg[2] - pr.tx[2];
-  const double dn = sqrt((qx * qx + qy * qy) + qz * qz);
-  const double inv = dn > 0.0 ? 1.0 / dn : 0.0;
-  const float gtx = src[SLOT_T];
-  src[6] = fmaf(gtx, (float)(qx * inv), src[6]);
-  src[7] = fmaf(gtx, (float)(qy * inv), src[7]);
-  src[8] = fmaf(gtx, (float)(qz * inv), src[8]);
-#pragma unroll
-  for (int f = 0; f < SLOT_T; ++f) unsafeAtomicAdd(acc + (size_t)f * n_gauss + g, src[f]);
-#pragma unroll
-  for (int f = 0; f < NACC; ++f) src[f] = 0.f;
+  constexpr int FW = pow2_at_least(NACC);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb; e += NT) {
+    uint32_t id = kNoFlush;
+    if (sflag[e]) {
+      id = a.val[base + e];
+      float *src = sacc + NACC * e;
+      const float *pg = a.prep + (size_t)kPrep * id;
+      const double qx = (double)pg[0] - pr.tx[0], qy = (double)pg[1] - pr.tx[1], qz = (double)pg[2] - pr.tx[2];
+      const double dn = sqrt((qx * qx + qy * qy) + qz * qz);
+      const double inv = dn > 0.0 ? 1.0 / dn : 0.0;
+      const float gtx = src[SLOT_T];
+      src[6] = fmaf(gtx, (float)(qx * inv), src[6]);
+      src[7] = fmaf(gtx, (float)(qy * inv), src[7]);
+      src[8] = fmaf(gtx, (float)(qz * inv), src[8]);
+    }
+    sflag[e] = id;
+  }
+  __syncthreads();
+  for (int i = tid; i < nb * FW; i += NT) {
+    const int e = i / FW, f = i % FW;
+    if (f < NACC) {
+      const uint32_t id = sflag[e];
+      float *src = sacc + NACC * e + f;
+      if (id != kNoFlush && f < SLOT_T) unsafeAtomicAdd(acc + (size_t)id * S + f, *src);
+      *src = 0.f;
+    }
+  }
 }
 
 }  // namespace gsrf

@@ -46,8 +46,8 @@ struct TpIO {
   unsigned long long *stats;      // forward with counters: tests, hits, staged, rays, tile tests
   const float2 *grad_signal;      // adjoint: dL/dS
   const float2 *grad_sum;         // adjoint: dL/dS_hat per pair, or null
-  int64_t n_gauss;
-  float *acc;                     // adjoint accumulators [n_acc - 1][n_gauss]
+  float *acc;                     // adjoint accumulators [n_gauss][acc_stride]
+  int acc_stride;
 };
 
 // BCAP: largest staged batch.  Smaller batches waste fewer tests past the
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   float4 *sgeo = smem;                                      // [B][kGeo]
   float *scf = (float *)(smem + kGeo * B);                  // [B][2K]
   float *sacc = scf + 2 * K * B;                            // [B][NACC]   (adjoint)
-  int *sflag = (int *)(sacc + (BWD ? NACC * B : 0));        // [B]         (adjoint)
+  uint32_t *sflag = (uint32_t *)(sacc + (BWD ? NACC * B : 0));  // [B]    (adjoint)
   uint32_t *smask = (uint32_t *)(sflag + (BWD ? B : 0));    // [R][MWS]
   uint32_t *suni = smask + R * MWS;                         // [4][MW]
   int *sdone = (int *)(suni + 4 * MW);                      // [R]
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       }
     }
     for (int i = tid; i < NACC * B; i += NT) sacc[i] = 0.f;
-    for (int i = tid; i < B; i += NT) sflag[i] = 0;
+    for (int i = tid; i < B; i += NT) sflag[i] = 0u;
   }
   const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
   float T = 1.f, Sr = 0.f, Si = 0.f, Pr = 0.f, Pi = 0.f;
@@ -218,6 +218,8 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     if (tid < nb)
       stage_entry<K>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                      sgeo + kGeo * tid, scf + 2 * K * tid);
+    if constexpr (BWD)
+      for (int i = tid; i < nb; i += NT) sflag[i] = 0u;                  // the previous batch's flush ids
     if constexpr (!BWD)
       for (int i = tid; i < R * MWS + 4 * MW; i += NT) smask[i] = 0u;   // ray rows and union rows
 
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
             if (proc) {
               const float Rr = Sfr - (Pr + wr_in), Ri = Sfi - (Pi + wi_in);
               hit_adjoint<K, NV>(h, geo, Tj, ctr, cti, Rr, Ri, Gr, Gi, vx, vy, vz, Yr, Yi, twopi_lam, c);
-              sflag[j] = 1;
+              sflag[j] = 1u;
             }
             int first_slot;
             bool writer;
@@ -347,10 +349,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     }
     if constexpr (BWD) {
       __syncthreads();
-      if (tid < nb && sflag[tid]) {
-        flush_entry<K>(a, a.val[base + tid], pr, sacc + NACC * tid, io.n_gauss, io.acc);
-        sflag[tid] = 0;
-      }
+      flush_batch<K, NT>(a, pr, base, nb, sacc, sflag, io.acc, io.acc_stride);
     }
     if (__syncthreads_and(done ? 1 : 0)) break;
   }
