@@ -218,10 +218,12 @@ gsrf_status gsrf_render_bwd(const gsrf_problem *p, const float *signal, const fl
 /*
  * Instrumentation for the roofline: replays the render_fwd traversal of a
  * problem prepared by gsrf_project + gsrf_bin_sort without writing any
- * output, and stores (DEVICE, int64 [5], overwritten) the number of
+ * output, and stores (DEVICE, int64 [6], overwritten) the number of
  * (ray, Gaussian) hit tests made, processed hits, staged list entries, rays,
- * and tile tests (sum over tiles of rays in the tile times list entries up to
- * the tile's termination: the tests the tiled method implies).
+ * tile tests (sum over tiles of rays in the tile times list entries up to
+ * the tile's termination: the tests the tiled method implies), and walk
+ * slots (two-phase traversal only, else 0: 64 per step of a phase-2 wave, so
+ * processed hits / walk slots is the share of phase-2 lanes doing per-hit work).
  */
 gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stream);
 

@@ -125,6 +125,7 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.tile_sum = take((size_t)PT * 8);
   L.grad_acc = take((size_t)G * L.acc_stride * 4);
   L.hitmask = take(g.lanes_per_ray == 0 ? (size_t)L.cap * (size_t)(g.tile_w * g.tile_h / 32) * 4 : 0);
+  L.rays = take((size_t)g.n_az * g.n_el * ray_stride(L.K) * 4);
   L.total = o;
   if (need_device && p->workspace_bytes < L.total)
     return fail(GSRF_EINVAL, "workspace_bytes %zu < required %zu", p->workspace_bytes, L.total);

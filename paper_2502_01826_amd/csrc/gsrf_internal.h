@@ -36,6 +36,9 @@ constexpr int64_t kBigBatchRecords = (int64_t)1 << 22;
 constexpr int kSub = 8;
 // Tiles per block of the three-pass tile-count scan (256 threads x 4).
 constexpr int kScanTiles = 1024;
+// Ray table row (floats, 16-byte aligned): direction (3), pad, then the FLE
+// basis interleaved Yr_0, Yi_0, Yr_1, Yi_1, ... (2K).
+constexpr int ray_stride(int K) { return (4 + 2 * K + 3) / 4 * 4; }
 
 // Balanced expansion of the tile rectangles of a workgroup's RB records
 // (RB = 256 or 1024, one per thread): the rectangles' splat counts are scanned
@@ -101,6 +104,7 @@ struct Layout {
   size_t tkey, tval;      // sort scratch for buckets longer than the LDS chunk
   size_t tile_sum, grad_acc;
   size_t hitmask;         // two-phase traversal: per splat, tile-area / 32 words of forward hit bits
+  size_t rays;            // [n_el * n_az][ray_stride(K)] ray directions and FLE basis (FP32)
   size_t total;
   int64_t n_records;
   int32_t rec_block;      // records per workgroup in emit (256 or 1024)

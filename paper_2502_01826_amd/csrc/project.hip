@@ -47,15 +47,77 @@ __device__ void rec_base_scan(const gsrf_pair *__restrict__ pairs, const int64_t
   if (tid == 255) rec_base[P] = sh[255];
 }
 
+// Ray (u, v) of the receiver grid: azimuth alpha_u = 2 pi (u + 1/2) / n_az,
+// elevation beta_v = el_lo + (el_hi - el_lo) (v + 1/2) / n_el; its direction
+// rounded to FP32 and the FLE basis Y_i = e^{j m alpha} P_l^m(sin beta),
+// i = l^2 + l + m (Sec. 3.2 eq. FLE), evaluated in FP64 and rounded to FP32,
+// stored as one ray-table row: (vx, vy, vz, 0, Yr_0, Yi_0, Yr_1, Yi_1, ...).
+template <int L>
+__device__ void ray_table_row(int u, int v, int n_az, int n_el, float el_lo, float el_hi, float *row) {
+  const double pi = 3.14159265358979323846;
+  const double al = 2.0 * pi * (u + 0.5) / n_az;
+  const double be = (double)el_lo + ((double)el_hi - (double)el_lo) * (v + 0.5) / n_el;
+  const double cb = cos(be), sb = sin(be);
+  row[0] = (float)(cb * cos(al));
+  row[1] = (float)(cb * sin(al));
+  row[2] = (float)sb;
+  row[3] = 0.f;
+  float *Y = row + 4;
+  // associated Legendre P_l^m(x), m >= 0, Condon-Shortley phase, textbook recurrences
+  double P[L + 1][L + 1];
+  const double x = sb;
+  const double s = sqrt(fmax(0.0, 1.0 - x * x));
+  double pmm = 1.0;
+#pragma unroll
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) pmm = -pmm * (2 * m - 1) * s;
+    P[m][m] = pmm;
+    if (m + 1 <= L) P[m + 1][m] = x * (2 * m + 1) * pmm;
+#pragma unroll
+    for (int l = m + 2; l <= L; ++l) P[l][m] = ((2 * l - 1) * x * P[l - 1][m] - (l + m - 1) * P[l - 2][m]) / (l - m);
+  }
+#pragma unroll
+  for (int l = 0; l <= L; ++l) {
+#pragma unroll
+    for (int m = 0; m <= l; ++m) {
+      const double c = cos(m * al), sn = sin(m * al);
+      const double pl = P[l][m];
+      Y[2 * (l * l + l + m)] = (float)(pl * c);
+      Y[2 * (l * l + l + m) + 1] = (float)(pl * sn);
+      if (m > 0) {
+        double f = 1.0;  // (l+m)! / (l-m)!
+        for (int t = l - m + 1; t <= l + m; ++t) f *= t;
+        const double pn = ((m & 1) ? -pl : pl) / f;   // P_l^{-m}
+        Y[2 * (l * l + l - m)] = (float)(pn * c);
+        Y[2 * (l * l + l - m) + 1] = (float)(-pn * sn);
+      }
+    }
+  }
+  for (int i = 4 + 2 * (L + 1) * (L + 1); i < ray_stride((L + 1) * (L + 1)); ++i) row[i] = 0.f;
+}
+
+// Workgroups [0, ceil(G / 256)) activate Gaussians; the next ceil(n_rays / 256)
+// make the ray table, which depends on the grid only.
+template <int L>
 __global__ __launch_bounds__(256) void k_activate(const float *__restrict__ means, const float *__restrict__ log_scales,
                                                   const float *__restrict__ quats, const float *__restrict__ logits,
                                                   int64_t G, float *__restrict__ prep, uint32_t *__restrict__ tile_cnt,
                                                   int64_t n_cnt, const gsrf_pair *__restrict__ pairs,
                                                   const int64_t *__restrict__ scene_off, int32_t P,
-                                                  int64_t *__restrict__ rec_base) {
+                                                  int64_t *__restrict__ rec_base, int n_az, int n_el, float el_lo,
+                                                  float el_hi, float *__restrict__ rays) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_cnt; i += stride) tile_cnt[i] = 0u;
   if (blockIdx.x == 0 && P > 0) rec_base_scan(pairs, scene_off, P, rec_base);
+  const int64_t nb_g = (G + 255) / 256;
+  if ((int64_t)blockIdx.x >= nb_g) {
+    const int64_t ray = ((int64_t)blockIdx.x - nb_g) * 256 + threadIdx.x;
+    if (ray < (int64_t)n_az * n_el) {
+      const int v = (int)(ray / n_az), u = (int)(ray - (int64_t)v * n_az);
+      ray_table_row<L>(u, v, n_az, n_el, el_lo, el_hi, rays + ray * ray_stride((L + 1) * (L + 1)));
+    }
+    return;
+  }
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   float qw = quats[4 * g + 0], qx = quats[4 * g + 1], qy = quats[4 * g + 2], qz = quats[4 * g + 3];
@@ -406,13 +468,26 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
   const int64_t PT = (int64_t)p->n_pairs * lay.T;
   uint32_t *tile_cnt = (uint32_t *)(ws + lay.tile_cnt);
   {
-    int64_t nb = (p->n_gauss + 255) / 256;
-    const int64_t nb_cnt = (PT * kSub + 255) / 256;
+    const gsrf_grid &g = p->grid;
+    int64_t nb = (p->n_gauss + 255) / 256 + ((int64_t)g.n_az * g.n_el + 255) / 256;
+    const int64_t nb_cnt = (PT * kSub + 255) / 256;   // the counters are cleared grid-stride
     if (nb_cnt > nb) nb = nb_cnt < 4096 ? nb_cnt : 4096;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_activate, dim3((unsigned)nb), dim3(256), 0, s, p->means, p->log_scales, p->quats,
-                       p->opacity_logits, p->n_gauss, prep, tile_cnt, PT * kSub, p->pairs, p->scene_offsets_dev,
-                       p->n_pairs, rec_base);
+    float *rays = (float *)(ws + lay.rays);
+#define GSRF_ACTIVATE(LL)                                                                                           \
+  hipLaunchKernelGGL(k_activate<LL>, dim3((unsigned)nb), dim3(256), 0, s, p->means, p->log_scales, p->quats,         \
+                     p->opacity_logits, p->n_gauss, prep, tile_cnt, PT * kSub, p->pairs, p->scene_offsets_dev,       \
+                     p->n_pairs, rec_base, g.n_az, g.n_el, g.el_lo, g.el_hi, rays)
+    switch (g.fle_L) {
+      case 0: GSRF_ACTIVATE(0); break;
+      case 1: GSRF_ACTIVATE(1); break;
+      case 2: GSRF_ACTIVATE(2); break;
+      case 3: GSRF_ACTIVATE(3); break;
+      case 4: GSRF_ACTIVATE(4); break;
+      case 5: GSRF_ACTIVATE(5); break;
+      default: GSRF_ACTIVATE(6); break;
+    }
+#undef GSRF_ACTIVATE
   }
   if (lay.n_records > 0) {
     const int sub_shift = lay.rec_block == 1024 ? 2 : 0;   // emit's workgroup = 256 << sub_shift records

@@ -25,7 +25,8 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
   constexpr int RAYS = NT / G;
   extern __shared__ float4 smem[];
   float4 *sgeo = smem;                          // [B][kGeo]
-  float *scf = (float *)(smem + kGeo * B);      // [B][2K]
+  float4 *stx = smem + kGeo * B;                // [B] TX leg, Gaussian id
+  float *scf = (float *)(stx + B);              // [B][2K]
   float *sacc = scf + 2 * K * B;                // [B][NACC]
   uint32_t *sflag = (uint32_t *)(sacc + NACC * B);   // [B]
   const int gt = blockIdx.x;
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
   const double lam = kC0 / pr.freq_hz, inv_lam = pr.freq_hz / kC0;
   const float twopi_lam = (float)(2.0 * 3.14159265358979323846 / lam);
   float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
-  ray_setup<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
+  ray_load<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
   float Sfr = 0.f, Sfi = 0.f, Gr = 0.f, Gi = 0.f;
   if (valid) {
     const size_t ri = ((size_t)k * a.n_el + v) * a.n_az + u;
@@ -64,8 +65,11 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
     __syncthreads();
     if ((int)threadIdx.x < nb)
       stage_entry<K>(a, a.val[base + threadIdx.x], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
-                     sgeo + kGeo * threadIdx.x, scf + 2 * K * threadIdx.x);
-    for (int i = threadIdx.x; i < nb; i += NT) sflag[i] = 0u;   // the previous batch's flush ids
+                     sgeo + kGeo * threadIdx.x, scf + 2 * K * threadIdx.x, stx + threadIdx.x);
+    for (int i = threadIdx.x; i < nb; i += NT) {   // what the previous batch's flush left
+      sflag[i] = 0u;
+      sacc[NACC * i + NACC - 1] = 0.f;
+    }
     __syncthreads();
     if (__ballot(!done) != 0) {              // wave-uniform
       for (int m = 0; m < nb; m += G) {
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
     }
     __syncthreads();
     // flush the staged Gaussians with any processed hit in this tile
-    flush_batch<K, NT>(a, pr, base, nb, sacc, sflag, acc, acc_stride);
+    flush_batch<K, NT>(nb, sacc, sflag, stx, acc, acc_stride);
     if (__syncthreads_and(done ? 1 : 0)) break;
   }
 }
@@ -141,19 +145,30 @@ __global__ __launch_bounds__(256) void k_chain(const float *__restrict__ log_sca
                                                float *__restrict__ d_a, float *__restrict__ d_c) {
   const int64_t g0 = (int64_t)blockIdx.x * 256;
   const int64_t g = g0 + threadIdx.x;
-  // coefficient gradients: coalesced writes of this block's contiguous [256][2K] slab
+  // coefficient gradients: coalesced writes of this block's contiguous [256][2K] slab;
+  // element e = l * 2K + c of the slab, (l, c) advanced without a division per element
   {
-    const int64_t n_here = min((int64_t)256, G - g0);
-    const int64_t total = n_here * 2 * K;
-    for (int64_t e = threadIdx.x; e < total; e += 256) {
-      const int64_t gi = g0 + e / (2 * K);
-      const int comp = (int)(e % (2 * K));
-      d_c[g0 * 2 * K + e] = acc[(size_t)gi * S + 11 + comp];
+    const int two_k = 2 * K;
+    const int total = (int)min((int64_t)256, G - g0) * two_k;
+    const int step_l = 256 / two_k, step_c = 256 - step_l * two_k;
+    int l = (int)threadIdx.x / two_k, c = (int)threadIdx.x - l * two_k;
+    const float *src = acc + (size_t)g0 * S + 11;
+    float *dst = d_c + (size_t)g0 * two_k;
+    for (int e = threadIdx.x; e < total; e += 256) {
+      dst[e] = src[(size_t)l * S + c];
+      l += step_l;
+      c += step_c;
+      if (c >= two_k) {
+        c -= two_k;
+        ++l;
+      }
     }
   }
   if (g >= G) return;
-  const float *row = acc + (size_t)g * S;
-  auto A = [&](int f) { return row[f]; };
+  const float4 *row4 = (const float4 *)(acc + (size_t)g * S);   // rows are 64-byte aligned
+  const float4 r0 = row4[0], r1 = row4[1], r2 = row4[2];
+  const float rv[12] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
+  auto A = [&](int f) { return rv[f]; };
   const float Gm[3][3] = {{A(0), A(3), A(4)}, {A(3), A(1), A(5)}, {A(4), A(5), A(2)}};
   d_means[3 * g + 0] = A(6);
   d_means[3 * g + 1] = A(7);
@@ -200,7 +215,7 @@ static hipError_t bwd_launch(const RenderArgs &a, int64_t nblocks, const float2 
                              const float2 *gsum, float *acc, int S, hipStream_t s) {
   constexpr int K = (L + 1) * (L + 1);
   constexpr int B = lds_batch(L, NT, true);
-  const size_t lds = (size_t)B * (kGeo * 16 + 2 * K * 4 + n_acc(L) * 4 + 4);
+  const size_t lds = (size_t)B * (kGeo * 16 + 16 + 2 * K * 4 + n_acc(L) * 4 + 4);
   hipLaunchKernelGGL((k_render_bwd<L, NT, G>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, gsig, gsum, acc, S);
   return hipGetLastError();
 }

@@ -33,6 +33,7 @@ struct RenderArgs {
   const uint32_t *tend;     // [P*T]
   uint32_t *hitmask;        // [splats][R / 32]: per list entry, its hits over the tile's rays (two-phase
                             // traversal: written by the forward, read by the adjoint)
+  const float *rays;        // [n_el * n_az][ray_stride(K)] ray table made by gsrf_project
   int32_t T, nta, n_az, n_el, tw;
   float el_lo, el_hi, r_rx, t_min, amax;
 };
@@ -48,9 +49,9 @@ constexpr int n_acc(int L) { return 12 + 2 * (L + 1) * (L + 1); }
 constexpr int pow2_at_least(int n) { return n <= 32 ? 32 : (n <= 64 ? 64 : 128); }
 
 constexpr int lds_batch(int L, int NT, bool bwd, int cap = 256) {
-  // floats per staged entry: geometry + coefficients (+ accumulators for bwd)
+  // floats per staged entry: geometry + coefficients (+ TX leg, accumulators and flag for bwd)
   int K = (L + 1) * (L + 1);
-  int per = 4 * kGeo + 2 * K + (bwd ? n_acc(L) + 1 : 0);
+  int per = 4 * kGeo + 2 * K + (bwd ? 4 + n_acc(L) + 1 : 0);
   int budget = 60 * 1024 / 4;
   int b = NT < cap ? NT : cap;
   while (b > 32 && b * per > budget) b >>= 1;
@@ -58,66 +59,56 @@ constexpr int lds_batch(int L, int NT, bool bwd, int cap = 256) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-ray setup: direction (FP64 -> FP32) and the FLE basis
-// Y_i = e^{j m alpha} P_l^m(sin beta), i = l^2 + l + m (Sec. 3.2 eq. FLE).
+// Per-ray data from the ray table: the FP32 direction and FLE basis
+// Y_i = e^{j m alpha} P_l^m(sin beta), i = l^2 + l + m (Sec. 3.2 eq. FLE),
+// evaluated in FP64 once per problem by gsrf_project.
 // ---------------------------------------------------------------------------
-// Ray (u, v): azimuth alpha_u = 2 pi (u + 1/2) / n_az, elevation
-// beta_v = el_lo + (el_hi - el_lo) (v + 1/2) / n_el, direction rounded to FP32.
-__device__ __forceinline__ void ray_dir(int u, int v, const RenderArgs &a, float &vx, float &vy, float &vz,
-                                        double &al, double &sb) {
-  const double pi = 3.14159265358979323846;
-  al = 2.0 * pi * (u + 0.5) / a.n_az;
-  const double be = (double)a.el_lo + ((double)a.el_hi - (double)a.el_lo) * (v + 0.5) / a.n_el;
-  const double cb = cos(be);
-  sb = sin(be);
-  vx = (float)(cb * cos(al));
-  vy = (float)(cb * sin(al));
-  vz = (float)sb;
+__device__ __forceinline__ const float4 *ray_row(int u, int v, const RenderArgs &a, int K) {
+  return (const float4 *)(a.rays + (size_t)(v * a.n_az + u) * ray_stride(K));
+}
+
+__device__ __forceinline__ void ray_load_dir(int u, int v, const RenderArgs &a, int K, float &vx, float &vy,
+                                             float &vz) {
+  const float4 d = ray_row(u, v, a, K)[0];
+  vx = d.x;
+  vy = d.y;
+  vz = d.z;
 }
 
 template <int L>
-__device__ void ray_setup(int u, int v, const RenderArgs &a, float &vx, float &vy, float &vz, float *Yr,
-                          float *Yi) {
-  double al, sb;
-  ray_dir(u, v, a, vx, vy, vz, al, sb);
-  // associated Legendre P_l^m(x), m >= 0, Condon-Shortley phase, textbook recurrences
-  double P[L + 1][L + 1];
-  const double x = sb;
-  const double s = sqrt(fmax(0.0, 1.0 - x * x));
-  double pmm = 1.0;
+__device__ __forceinline__ void ray_load(int u, int v, const RenderArgs &a, float &vx, float &vy, float &vz, float *Yr,
+                                         float *Yi) {
+  constexpr int K = (L + 1) * (L + 1);
+  constexpr int NQ = (2 * K + 3) / 4;
+  const float4 *r4 = ray_row(u, v, a, K);
+  const float4 d = r4[0];
+  vx = d.x;
+  vy = d.y;
+  vz = d.z;
+  float y[4 * NQ];
 #pragma unroll
-  for (int m = 0; m <= L; ++m) {
-    if (m > 0) pmm = -pmm * (2 * m - 1) * s;
-    P[m][m] = pmm;
-    if (m + 1 <= L) P[m + 1][m] = x * (2 * m + 1) * pmm;
-#pragma unroll
-    for (int l = m + 2; l <= L; ++l) P[l][m] = ((2 * l - 1) * x * P[l - 1][m] - (l + m - 1) * P[l - 2][m]) / (l - m);
+  for (int q = 0; q < NQ; ++q) {
+    const float4 c = r4[1 + q];
+    y[4 * q] = c.x;
+    y[4 * q + 1] = c.y;
+    y[4 * q + 2] = c.z;
+    y[4 * q + 3] = c.w;
   }
 #pragma unroll
-  for (int l = 0; l <= L; ++l) {
-#pragma unroll
-    for (int m = 0; m <= l; ++m) {
-      const double c = cos(m * al), sn = sin(m * al);
-      const double pl = P[l][m];
-      Yr[l * l + l + m] = (float)(pl * c);
-      Yi[l * l + l + m] = (float)(pl * sn);
-      if (m > 0) {
-        double f = 1.0;  // (l+m)! / (l-m)!
-        for (int t = l - m + 1; t <= l + m; ++t) f *= t;
-        const double pn = ((m & 1) ? -pl : pl) / f;   // P_l^{-m}
-        Yr[l * l + l - m] = (float)(pn * c);
-        Yi[l * l + l - m] = (float)(-pn * sn);
-      }
-    }
+  for (int i = 0; i < K; ++i) {
+    Yr[i] = y[2 * i];
+    Yi[i] = y[2 * i + 1];
   }
 }
 
 // ---------------------------------------------------------------------------
 // Stage Gaussian g into an LDS slot (FP64 geometry relative to RX and TX).
 // ---------------------------------------------------------------------------
+// txg (adjoint only, else null) receives the TX leg of dL/dt, the unit vector
+// (mu - tx)/|mu - tx|, and g's bits in w.
 template <int K>
 __device__ void stage_entry(const RenderArgs &a, uint32_t g, double rx, double ry, double rz, double tx,
-                            double ty, double tz, double inv_lam, float4 *geo, float *cf) {
+                            double ty, double tz, double inv_lam, float4 *geo, float *cf, float4 *txg = nullptr) {
   const float *pg = a.prep + (size_t)kPrep * g;
   // prep record (64-byte aligned): (mu, N) (M00, M11, M22, M01) (M02, M12, o, -)
   const float4 *p4 = (const float4 *)pg;
@@ -138,6 +129,10 @@ __device__ void stage_entry(const RenderArgs &a, uint32_t g, double rx, double r
   geo[2] = q1;
   geo[3] = make_float4(q2.x, q2.y, q0.w, q2.z);
   geo[4] = make_float4((float)(ph - floor(ph)), (float)D2, 0.f, 0.f);
+  if (txg) {
+    const double it = dtx > 0.0 ? 1.0 / dtx : 0.0;
+    *txg = make_float4((float)(qx * it), (float)(qy * it), (float)(qz * it), __uint_as_float(g));
+  }
   const float4 *c4 = (const float4 *)(a.coeffs + (size_t)2 * K * g);
   if ((K & 1) == 0) {   // 2K floats per Gaussian: 16-byte aligned rows when K is even
 #pragma unroll
@@ -429,45 +424,30 @@ __device__ __forceinline__ void hit_adjoint(const Terms &h, const float4 *geo, f
 }
 
 // Flush of a staged batch's LDS accumulators to the global accumulators
-// acc[n_gauss][S] (row stride S >= 11 + 2K floats, 64-byte aligned rows).
-// First every flagged entry folds dL/dt's TX leg (mu - tx)/|mu - tx| into
-// dL/dmu and replaces its flag by its Gaussian id (kNoFlush if it had no
-// processed hit); then one lane per (entry, slot) adds a slot, so the atomics
-// of one wave instruction land on one or two Gaussians' rows instead of one
-// row per lane.  Every thread of the workgroup calls it; the LDS accumulators
-// are left zeroed, and the caller clears the flags before the next batch.
-constexpr uint32_t kNoFlush = 0xFFFFFFFFu;
-
+// acc[n_gauss][S] (row stride S >= 11 + 2K floats, 64-byte aligned rows), one
+// lane per (entry, slot) so that the atomics of one wave instruction land on
+// one or two Gaussians' rows instead of one row per lane.  dL/dt's TX leg
+// (mu - tx)/|mu - tx| (txg, staged with the entry together with its Gaussian
+// id) is folded into dL/dmu on the way.  Entries whose flag is clear had no
+// processed hit.  Every thread of the workgroup calls it, after a barrier
+// that ends the batch's accumulation; it leaves every slot but dL/dt zeroed,
+// and the caller clears the flags and the dL/dt slots before the next batch.
 template <int K, int NT>
-__device__ __forceinline__ void flush_batch(const RenderArgs &a, const gsrf_pair &pr, uint32_t base, int nb,
-                                            float *sacc, uint32_t *sflag, float *__restrict__ acc, int S) {
+__device__ __forceinline__ void flush_batch(int nb, float *sacc, const uint32_t *sflag, const float4 *txg,
+                                            float *__restrict__ acc, int S) {
   constexpr int SLOT_T = 11 + 2 * K;
   constexpr int NACC = 12 + 2 * K;
   constexpr int FW = pow2_at_least(NACC);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nb; e += NT) {
-    uint32_t id = kNoFlush;
-    if (sflag[e]) {
-      id = a.val[base + e];
-      float *src = sacc + NACC * e;
-      const float *pg = a.prep + (size_t)kPrep * id;
-      const double qx = (double)pg[0] - pr.tx[0], qy = (double)pg[1] - pr.tx[1], qz = (double)pg[2] - pr.tx[2];
-      const double dn = sqrt((qx * qx + qy * qy) + qz * qz);
-      const double inv = dn > 0.0 ? 1.0 / dn : 0.0;
-      const float gtx = src[SLOT_T];
-      src[6] = fmaf(gtx, (float)(qx * inv), src[6]);
-      src[7] = fmaf(gtx, (float)(qy * inv), src[7]);
-      src[8] = fmaf(gtx, (float)(qz * inv), src[8]);
-    }
-    sflag[e] = id;
-  }
-  __syncthreads();
-  for (int i = tid; i < nb * FW; i += NT) {
+  for (int i = threadIdx.x; i < nb * FW; i += NT) {
     const int e = i / FW, f = i % FW;
-    if (f < NACC) {
-      const uint32_t id = sflag[e];
+    if (f < SLOT_T) {
       float *src = sacc + NACC * e + f;
-      if (id != kNoFlush && f < SLOT_T) unsafeAtomicAdd(acc + (size_t)id * S + f, *src);
+      if (sflag[e]) {
+        const float4 tg = txg[e];
+        float v = *src;
+        if (f >= 6 && f <= 8) v = fmaf(sacc[NACC * e + SLOT_T], f == 6 ? tg.x : (f == 7 ? tg.y : tg.z), v);
+        unsafeAtomicAdd(acc + (size_t)__float_as_uint(tg.w) * S + f, v);
+      }
       *src = 0.f;
     }
   }

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
   const gsrf_pair pr = a.pairs[k];
   const double inv_lam = pr.freq_hz / kC0;
   float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
-  ray_setup<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
+  ray_load<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
   const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
   float T = 1.f, Sr = 0.f, Si = 0.f;
   bool done = !valid || (1.0f < a.t_min);
@@ -209,6 +209,7 @@ RenderArgs make_render_args(const gsrf_problem *p, const Layout &lay, char *ws) 
   a.tstart = (const uint32_t *)(ws + lay.tile_start);
   a.tend = (const uint32_t *)(ws + lay.tile_end);
   a.hitmask = (uint32_t *)(ws + lay.hitmask);
+  a.rays = (const float *)(ws + lay.rays);
   a.T = lay.T;
   a.nta = lay.nta;
   a.n_az = p->grid.n_az;
@@ -237,7 +238,7 @@ hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws,
 }
 
 hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *ws, int64_t *counts, hipStream_t s) {
-  hipError_t e = fill<int64_t>(counts, 0, 5, s);
+  hipError_t e = fill<int64_t>(counts, 0, 6, s);
   if (e != hipSuccess || p->n_pairs == 0) return e;
   const RenderArgs a = make_render_args(p, lay, ws);
   const int64_t nblocks = (int64_t)p->n_pairs * lay.T;

@@ -43,7 +43,7 @@ struct TwoPhase {
 struct TpIO {
   float2 *signal;                 // forward output S [P, n_el, n_az]; read by the adjoint
   float2 *tile_sum;               // forward: per-(pair, tile) partial of S_hat
-  unsigned long long *stats;      // forward with counters: tests, hits, staged, rays, tile tests
+  unsigned long long *stats;      // forward with counters: tests, hits, staged, rays, tile tests, walk slots
   const float2 *grad_signal;      // adjoint: dL/dS
   const float2 *grad_sum;         // adjoint: dL/dS_hat per pair, or null
   float *acc;                     // adjoint accumulators [n_gauss][acc_stride]
@@ -63,8 +63,8 @@ struct TpShape {
   static constexpr int MW = (B + 31) / 32;       // mask words per row
   static constexpr int MWS = MW + 1;             // odd row stride: conflict-free column reads
   static constexpr int MWR = R / 32;             // hit-mask words per entry (one bit per ray)
-  // LDS: geometry, coefficients, [accumulators, flags], ray rows, union rows, done flags
-  static constexpr size_t kLds = (size_t)B * (kGeo * 16 + 2 * K * 4) + (BWD ? (size_t)B * (NACC * 4 + 4) : 0) +
+  // LDS: geometry, [TX legs], coefficients, [accumulators, flags], ray rows, union rows, done flags
+  static constexpr size_t kLds = (size_t)B * (kGeo * 16 + 2 * K * 4) + (BWD ? (size_t)B * (16 + NACC * 4 + 4) : 0) +
                                  (size_t)R * MWS * 4 + (size_t)4 * MW * 4 + (size_t)R * 4;
   static constexpr size_t lds() { return kLds < 256 * 8 ? 256 * 8 : kLds; }
 };
@@ -154,7 +154,8 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   constexpr int NV = pow2_at_least(NACC);
   extern __shared__ float4 smem[];
   float4 *sgeo = smem;                                      // [B][kGeo]
-  float *scf = (float *)(smem + kGeo * B);                  // [B][2K]
+  float4 *stx = smem + kGeo * B;                            // [B]         (adjoint: TX leg, Gaussian id)
+  float *scf = (float *)(stx + (BWD ? B : 0));              // [B][2K]
   float *sacc = scf + 2 * K * B;                            // [B][NACC]   (adjoint)
   uint32_t *sflag = (uint32_t *)(sacc + (BWD ? NACC * B : 0));  // [B]    (adjoint)
   uint32_t *smask = (uint32_t *)(sflag + (BWD ? B : 0));    // [R][MWS]
@@ -178,12 +179,11 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   const gsrf_pair pr = a.pairs[k];
   const double lam = kC0 / pr.freq_hz, inv_lam = pr.freq_hz / kC0;
   float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
-  ray_setup<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
+  ray_load<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
   RayMono w1;
   {
     float wx, wy, wz;
-    double al, sb;
-    ray_dir(valid1 ? u1 : 0, valid1 ? v1 : 0, a, wx, wy, wz, al, sb);
+    ray_load_dir(valid1 ? u1 : 0, valid1 ? v1 : 0, a, K, wx, wy, wz);
     w1 = ray_mono(wx, wy, wz);
   }
   float twopi_lam = 0.f, Sfr = 0.f, Sfi = 0.f, Gr = 0.f, Gi = 0.f;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   float T = 1.f, Sr = 0.f, Si = 0.f, Pr = 0.f, Pi = 0.f;
   bool done = !valid || (1.0f < a.t_min);
   if (q == 0) sdone[r] = done ? 1 : 0;
-  unsigned long long n_test = 0, n_hit = 0, n_staged = 0, n_tile_tests = 0;
+  unsigned long long n_test = 0, n_hit = 0, n_staged = 0, n_tile_tests = 0, n_steps = 0;
   int n_valid_rays = 0;
   if constexpr (STATS) {
     const int tu_w = min(a.tw, a.n_az - tu * a.tw), tv_h = min(th_, a.n_el - tv * th_);
@@ -217,9 +217,12 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     __syncthreads();
     if (tid < nb)
       stage_entry<K>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
-                     sgeo + kGeo * tid, scf + 2 * K * tid);
+                     sgeo + kGeo * tid, scf + 2 * K * tid, BWD ? stx + tid : nullptr);
     if constexpr (BWD)
-      for (int i = tid; i < nb; i += NT) sflag[i] = 0u;                  // the previous batch's flush ids
+      for (int i = tid; i < nb; i += NT) {   // what the previous batch's flush left
+        sflag[i] = 0u;
+        sacc[NACC * i + NACC - 1] = 0.f;
+      }
     if constexpr (!BWD)
       for (int i = tid; i < R * MWS + 4 * MW; i += NT) smask[i] = 0u;   // ray rows and union rows
 
@@ -290,6 +293,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
           if (q == i) j = jj;
         }
         if (first < 0) break;
+        if (STATS) ++n_steps;
         const bool hit = !done && j >= 0 && ((mine[j >> 5] >> (j & 31)) & 1u);
         const float4 *geo = sgeo + kGeo * (j >= 0 ? j : 0);
         Terms h;
@@ -349,7 +353,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     }
     if constexpr (BWD) {
       __syncthreads();
-      flush_batch<K, NT>(a, pr, base, nb, sacc, sflag, io.acc, io.acc_stride);
+      flush_batch<K, NT>(nb, sacc, sflag, stx, io.acc, io.acc_stride);
     }
     if (__syncthreads_and(done ? 1 : 0)) break;
   }
@@ -367,6 +371,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       if (n_staged) atomicAdd(io.stats + 2, n_staged);
       if (valid && q == 0) atomicAdd(io.stats + 3, 1ull);
       if (n_tile_tests) atomicAdd(io.stats + 4, n_tile_tests);
+      if (lane == 0 && n_steps) atomicAdd(io.stats + 5, 64ull * n_steps);
       return;
     }
     if (valid && q == 0) io.signal[((size_t)k * a.n_el + v) * a.n_az + u] = make_float2(Sr, Si);

@@ -188,11 +188,11 @@ class Problem:
 
     def render_stats(self, stream=None) -> dict:
         """Counts of the forward traversal (instrumentation; run after prepare())."""
-        c = torch.zeros(5, dtype=torch.int64, device=self.device)
+        c = torch.zeros(6, dtype=torch.int64, device=self.device)
         check(_lib.lib().gsrf_render_stats(ctypes.byref(self._problem()), c.data_ptr(), _stream_handle(stream)),
               "gsrf_render_stats")
         v = c.cpu().tolist()
-        return dict(tests=v[0], hits=v[1], staged=v[2], rays=v[3], tile_tests=v[4])
+        return dict(tests=v[0], hits=v[1], staged=v[2], rays=v[3], tile_tests=v[4], walk_slots=v[5])
 
     def prepare(self, stream=None):
         """project + bin_sort, growing the splat capacity when it is too small."""

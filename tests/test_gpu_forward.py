@@ -46,6 +46,34 @@ def test_tiny_forward_matches_oracle_and_lists_are_bit_exact():
         np.testing.assert_array_equal(L["klo"][a:e], keys[t].astype(np.uint32))
 
 
+@pytest.mark.parametrize("tw,th,G", [(8, 8, 0), (8, 4, 0), (16, 8, 2)])
+def test_render_stats_counts_match_oracle(tw, th, G):
+    """The traversal counters: rays and processed hits against the oracle (hits
+    of rays with a marginal decision may differ by the flipped decisions), and
+    the orderings every traversal obeys."""
+    g = Grid(n_az=37, n_el=11, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G)
+    b = synth.tiny(grid=g, n=1500)
+    sc, p = b.scenes[0], b.pairs[0]
+    say("render_stats", tw, th, "lanes", G)
+    prob = gpu_problem(b)
+    prob.forward()
+    st = prob.render_stats()
+    torch.cuda.synchronize()
+    ref = oracle.render(sc, p, g)
+    say("  counts", st)
+    assert st["rays"] == g.n_az * g.n_el
+    n_act = ref["n_active"].astype(np.int64)
+    # a flipped hit or termination decision moves a marginal ray's count by one
+    slack = 8 * int(ref["marginal"].sum())
+    assert abs(st["hits"] - int(n_act.sum())) <= slack
+    assert st["hits"] <= st["tests"] <= st["tile_tests"]
+    assert st["staged"] > 0
+    if G == 0:
+        assert st["walk_slots"] % 64 == 0 and st["hits"] <= st["walk_slots"]
+    else:
+        assert st["walk_slots"] == 0
+
+
 def test_forward_is_deterministic():
     b = synth.tiny()
     prob = gpu_problem(b)
