@@ -375,19 +375,22 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       return;
     }
     if (valid && q == 0) io.signal[((size_t)k * a.n_el + v) * a.n_az + u] = make_float2(Sr, Si);
+    // tile partial of S_hat in a fixed order: each wave's rays by a butterfly,
+    // then the four wave totals in wave order
+    float xr = (q == 0) ? Sr : 0.f, xi = (q == 0) ? Si : 0.f;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      xr += __shfl_xor(xr, d, 64);
+      xi += __shfl_xor(xi, d, 64);
+    }
     __syncthreads();
     float *red = (float *)smem;
-    red[tid] = (q == 0) ? Sr : 0.f;
-    red[NT + tid] = (q == 0) ? Si : 0.f;
-    __syncthreads();
-    for (int off = NT / 2; off > 0; off >>= 1) {
-      if (tid < off) {
-        red[tid] += red[tid + off];
-        red[NT + tid] += red[NT + tid + off];
-      }
-      __syncthreads();
+    if (lane == 0) {
+      red[wave] = xr;
+      red[4 + wave] = xi;
     }
-    if (tid == 0) io.tile_sum[gt] = make_float2(red[0], red[NT]);
+    __syncthreads();
+    if (tid == 0) io.tile_sum[gt] = make_float2((red[0] + red[1]) + (red[2] + red[3]), (red[4] + red[5]) + (red[6] + red[7]));
   }
 }
 
