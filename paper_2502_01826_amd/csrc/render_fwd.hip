@@ -233,7 +233,9 @@ hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws,
   hipError_t e = fwd_any(p, a, nblocks, (float2 *)signal, tsum, nullptr, s);
   mark_kernel_event(1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rssi, dim3(p->n_pairs), dim3(256), 0, s, tsum, lay.T, signal_sum, rssi_dbm);
+  // partials per pair: one per render workgroup of the pair's tiles
+  const int split = p->grid.lanes_per_ray == 0 ? tp_split(p->grid.tile_w * p->grid.tile_h, nblocks) : 1;
+  hipLaunchKernelGGL(k_rssi, dim3(p->n_pairs), dim3(256), 0, s, tsum, lay.T * split, signal_sum, rssi_dbm);
   return hipGetLastError();
 }
 

@@ -144,7 +144,12 @@ __device__ __forceinline__ unsigned phase1_tests(const RayMono &v, const float4 
   return n_test;
 }
 
-template <int L, int R, int MODE, int BCAP>
+// SPLIT = 2: the bin tile (2R rays) is rendered by two workgroups, each taking
+// R rays (the upper or lower half of the tile's rows) over the whole list;
+// forward launches with few tiles use it to double the waves in flight.  The
+// hit masks have the same layout either way (ray r of the tile is bit r % 32
+// of word r / 32), so the adjoint need not split as the forward did.
+template <int L, int R, int MODE, int BCAP, int SPLIT>
 __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   using TP = TwoPhase<R>;
   using SH = TpShape<L, R, MODE, BCAP>;
@@ -162,19 +167,21 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   uint32_t *suni = smask + R * MWS;                         // [4][MW]
   int *sdone = (int *)(suni + 4 * MW);                      // [R]
   constexpr int MWR = SH::MWR;
-  const int gt = blockIdx.x;
-  const int k = gt / a.T;
-  const int tile = gt - k * a.T;
+  const int gt = blockIdx.x;                 // (pair, tile, half)
+  const int gtile = gt / SPLIT, half = gt - gtile * SPLIT;
+  const int k = gtile / a.T;
+  const int tile = gtile - k * a.T;
   const int tv = tile / a.nta, tu = tile - tv * a.nta;
-  const int th_ = R / a.tw;
+  const int th_ = R / a.tw;                  // rows of this workgroup
+  const int v0 = (tv * SPLIT + half) * th_;  // its first row
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   // phase-2 identity: ray r, lane q of its group
   const int r = tid / G, q = tid % G;
-  const int u = tu * a.tw + r % a.tw, v = tv * th_ + r / a.tw;
+  const int u = tu * a.tw + r % a.tw, v = v0 + r / a.tw;
   const bool valid = (u < a.n_az) && (v < a.n_el);
   // phase-1 identity: ray r1, entry phase e
   const int r1 = tid % R, e = tid / R;
-  const int u1 = tu * a.tw + r1 % a.tw, v1 = tv * th_ + r1 / a.tw;
+  const int u1 = tu * a.tw + r1 % a.tw, v1 = v0 + r1 / a.tw;
   const bool valid1 = (u1 < a.n_az) && (v1 < a.n_el);
   const gsrf_pair pr = a.pairs[k];
   const double lam = kC0 / pr.freq_hz, inv_lam = pr.freq_hz / kC0;
@@ -202,14 +209,14 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     for (int i = tid; i < NACC * B; i += NT) sacc[i] = 0.f;
     for (int i = tid; i < B; i += NT) sflag[i] = 0u;
   }
-  const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
+  const uint32_t s0 = a.tstart[gtile], s1 = v0 < a.n_el ? a.tend[gtile] : s0;   // a half below the grid: no rays
   float T = 1.f, Sr = 0.f, Si = 0.f, Pr = 0.f, Pi = 0.f;
   bool done = !valid || (1.0f < a.t_min);
   if (q == 0) sdone[r] = done ? 1 : 0;
   unsigned long long n_test = 0, n_hit = 0, n_staged = 0, n_tile_tests = 0, n_steps = 0;
   int n_valid_rays = 0;
   if constexpr (STATS) {
-    const int tu_w = min(a.tw, a.n_az - tu * a.tw), tv_h = min(th_, a.n_el - tv * th_);
+    const int tu_w = min(a.tw, a.n_az - tu * a.tw), tv_h = max(0, min(th_, a.n_el - v0));
     n_valid_rays = tu_w * tv_h;
   }
   for (uint32_t base = s0; base < s1; base += B) {
@@ -248,7 +255,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
           const int rb = blk / MW, w = blk - rb * MW;
           const uint32_t m = transpose32(smask[(rb * 32 + hl) * MWS + w], hl);
           const int j = w * 32 + hl;
-          if (j < nb) a.hitmask[(size_t)(base + j) * MWR + rb] = m;
+          if (j < nb) a.hitmask[(size_t)(base + j) * (MWR * SPLIT) + half * MWR + rb] = m;
         }
       }
     } else {
@@ -259,7 +266,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       for (int blk = (tid >> 5); blk < NBLK; blk += NT / 32) {
         const int rb = blk / MW, w = blk - rb * MW;
         const int j = w * 32 + hl;
-        const uint32_t m = j < nb ? a.hitmask[(size_t)(base + j) * MWR + rb] : 0u;
+        const uint32_t m = j < nb ? a.hitmask[(size_t)(base + j) * (MWR * SPLIT) + half * MWR + rb] : 0u;
         const uint32_t row = transpose32(m, hl);
         const int rr = rb * 32 + hl;
         smask[rr * MWS + w] = sdone[rr] ? 0u : row;
@@ -394,38 +401,54 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   }
 }
 
-template <int L, int R, int MODE, int BCAP>
+template <int L, int R, int MODE, int BCAP, int SPLIT>
 hipError_t tp_launch(const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
   constexpr size_t lds = TpShape<L, R, MODE, BCAP>::lds();
   if constexpr (lds > 65536) {   // high FLE degrees: opt in to more than 64 KB of LDS
-    const hipError_t e = hipFuncSetAttribute((const void *)k_render_tp<L, R, MODE, BCAP>,
+    const hipError_t e = hipFuncSetAttribute((const void *)k_render_tp<L, R, MODE, BCAP, SPLIT>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_render_tp<L, R, MODE, BCAP>), dim3((unsigned)nblocks), dim3(256), lds, s, a, io);
+  hipLaunchKernelGGL((k_render_tp<L, R, MODE, BCAP, SPLIT>), dim3((unsigned)(nblocks * SPLIT)), dim3(256), lds, s, a,
+                     io);
   return hipGetLastError();
 }
 
-// Workgroups below which the adjoint launch counts as latency-bound.
+// Workgroups below which a launch counts as latency-bound: the adjoint then
+// stages smaller batches, and the forward splits tiles of 64 rays or more in
+// two (the adjoint, with more registers per thread, would not fit the extra
+// workgroups on the chip at once).
 constexpr int64_t kFewBlocks = 2048;
+
+// Workgroups per tile of the two-phase forward (1 or 2) for a launch over
+// `tiles` (pair, tile) units.
+inline int tp_split(int area, int64_t tiles) { return (area >= 64 && tiles <= kFewBlocks) ? 2 : 1; }
 
 template <int L, int MODE>
 hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
   if constexpr (MODE == kTpBwd) {
     if (nblocks <= kFewBlocks) {
       switch (area) {
-        case 32: return tp_launch<L, 32, MODE, 64>(a, io, nblocks, s);
-        case 64: return tp_launch<L, 64, MODE, 64>(a, io, nblocks, s);
-        case 128: return tp_launch<L, 128, MODE, 64>(a, io, nblocks, s);
-        default: return tp_launch<L, 256, MODE, 64>(a, io, nblocks, s);
+        case 32: return tp_launch<L, 32, MODE, 64, 1>(a, io, nblocks, s);
+        case 64: return tp_launch<L, 64, MODE, 64, 1>(a, io, nblocks, s);
+        case 128: return tp_launch<L, 128, MODE, 64, 1>(a, io, nblocks, s);
+        default: return tp_launch<L, 256, MODE, 64, 1>(a, io, nblocks, s);
+      }
+    }
+  } else {
+    if (tp_split(area, nblocks) == 2) {
+      switch (area) {
+        case 64: return tp_launch<L, 32, MODE, 128, 2>(a, io, nblocks, s);
+        case 128: return tp_launch<L, 64, MODE, 128, 2>(a, io, nblocks, s);
+        default: return tp_launch<L, 128, MODE, 128, 2>(a, io, nblocks, s);
       }
     }
   }
   switch (area) {
-    case 32: return tp_launch<L, 32, MODE, 128>(a, io, nblocks, s);
-    case 64: return tp_launch<L, 64, MODE, 128>(a, io, nblocks, s);
-    case 128: return tp_launch<L, 128, MODE, 128>(a, io, nblocks, s);
-    default: return tp_launch<L, 256, MODE, 128>(a, io, nblocks, s);
+    case 32: return tp_launch<L, 32, MODE, 128, 1>(a, io, nblocks, s);
+    case 64: return tp_launch<L, 64, MODE, 128, 1>(a, io, nblocks, s);
+    case 128: return tp_launch<L, 128, MODE, 128, 1>(a, io, nblocks, s);
+    default: return tp_launch<L, 256, MODE, 128, 1>(a, io, nblocks, s);
   }
 }
 

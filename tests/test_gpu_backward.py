@@ -6,7 +6,7 @@ import torch
 import oracle
 import synth
 from synth import Batch, Grid, Pair
-from gpu_common import GTOL, gpu_forward, gpu_problem, params_of, say
+from gpu_common import GTOL, compare_rays, gpu_forward, gpu_problem, params_of, say
 from paper_2502_01826_amd import GSRFRender, Problem
 
 pytestmark = pytest.mark.gpu
@@ -159,3 +159,33 @@ def test_paper_scale_gradients_on_sampled_rays(tw, th, G):
     gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), G)
     gr = oracle.vjp(sc, p, g, Gs, rays_uv=uv)
     _compare(gg, gr)
+
+
+def test_many_tile_launch_gradients_match_oracle():
+    """10 pairs x 540 tiles: the forward renders each tile with one workgroup
+    and the adjoint stages full batches (the launch shape of large batches);
+    cotangent on 16 sampled rays per pair, gradients summed over the pairs."""
+    g = Grid(n_az=360, n_el=90, fle_L=2, tile_w=8, tile_h=8, lanes_per_ray=0)
+    b = synth.batched(n=20_000, n_pairs=10, grid=g)
+    sc = b.scenes[0]
+    prob = gpu_problem(b)
+    assert len(b.pairs) * g.n_tiles > 2048
+    sig, _, _ = prob.forward()
+    S = torch.view_as_complex(sig).cpu().numpy().astype(np.complex128)
+    rng = np.random.default_rng(21)
+    G = np.zeros((len(b.pairs), g.n_el, g.n_az, 2))
+    ref = None
+    for k, p in enumerate(b.pairs):
+        uv = np.unique(np.stack([rng.integers(0, g.n_az, 16), rng.integers(0, g.n_el, 16)], 1), axis=0)
+        tr = oracle.trace(sc, p, g, uv)
+        compare_rays(S[k][uv[:, 1], uv[:, 0]], tr, sc, p, g, max_marginal_frac=0.25)   # 16-ray sample
+        uv = uv[~tr["marginal"]]
+        Gs = synth.cotangent((len(uv),), seed=40 + k).astype(np.float64)
+        G[k, uv[:, 1], uv[:, 0]] = Gs
+        r = oracle.vjp(sc, p, g, Gs, rays_uv=uv)
+        ref = r if ref is None else {n: ref[n] + r[n] for n in NAMES}
+    say("many-tile launch: 10 pairs x 540 tiles")
+    gt = torch.from_numpy(G.astype(np.float32)).cuda()
+    out = prob.render_bwd(sig, gt)
+    torch.cuda.synchronize()
+    _compare({n: o.cpu().numpy().astype(np.float64) for n, o in zip(NAMES, out)}, ref)
