@@ -78,7 +78,7 @@ __global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs
 //
 // Each entry is the 64-bit composite c = key << 32 | index (unique within a
 // tile).  One MSD counting pass splits the bucket into 2^b sub-buckets of
-// c - c_min (about eight entries each, b <= 11): histogram, exclusive scan and
+// c - c_min (about four entries each, b <= 11): histogram, exclusive scan and
 // scatter.  Each entry's final place is then its sub-bucket's start plus its
 // rank among the sub-bucket's entries, found by comparing with all of them;
 // sub-buckets are small, so this costs a few comparisons per entry and no
@@ -187,7 +187,7 @@ __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *_
   cmin = red[2 * kSortWaves];
   cmax = red[2 * kSortWaves + 1];
   int bits = 1;
-  while (bits < kSortBitsMax && (8 << bits) < n) ++bits;
+  while (bits < kSortBitsMax && (4 << bits) < n) ++bits;
   const uint64_t span = cmax - cmin;
   const int nbits = span ? 64 - __clzll(span) : 0;
   const int shift = nbits > bits ? nbits - bits : 0;
