@@ -57,9 +57,9 @@ __device__ void ray_table_row(int u, int v, int n_az, int n_el, float el_lo, flo
   const double pi = 3.14159265358979323846;
   const double al = 2.0 * pi * (u + 0.5) / n_az;
   const double be = (double)el_lo + ((double)el_hi - (double)el_lo) * (v + 0.5) / n_el;
-  const double cb = cos(be), sb = sin(be);
-  row[0] = (float)(cb * cos(al));
-  row[1] = (float)(cb * sin(al));
+  const double cb = cos(be), sb = sin(be), ca = cos(al), sa = sin(al);
+  row[0] = (float)(cb * ca);
+  row[1] = (float)(cb * sa);
   row[2] = (float)sb;
   row[3] = 0.f;
   float *Y = row + 4;
@@ -76,11 +76,20 @@ __device__ void ray_table_row(int u, int v, int n_az, int n_el, float el_lo, flo
 #pragma unroll
     for (int l = m + 2; l <= L; ++l) P[l][m] = ((2 * l - 1) * x * P[l - 1][m] - (l + m - 1) * P[l - 2][m]) / (l - m);
   }
+  // cos(m alpha), sin(m alpha) by the angle-addition recurrence
+  double cm[L + 1], sm[L + 1];
+  cm[0] = 1.0;
+  sm[0] = 0.0;
+#pragma unroll
+  for (int m = 1; m <= L; ++m) {
+    cm[m] = cm[m - 1] * ca - sm[m - 1] * sa;
+    sm[m] = sm[m - 1] * ca + cm[m - 1] * sa;
+  }
 #pragma unroll
   for (int l = 0; l <= L; ++l) {
 #pragma unroll
     for (int m = 0; m <= l; ++m) {
-      const double c = cos(m * al), sn = sin(m * al);
+      const double c = cm[m], sn = sm[m];
       const double pl = P[l][m];
       Y[2 * (l * l + l + m)] = (float)(pl * c);
       Y[2 * (l * l + l + m) + 1] = (float)(pl * sn);
