@@ -116,8 +116,7 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.tile_end = take((size_t)PT * 4);
   L.tile_cur = take((size_t)PT * kSub * 4);
   L.scan_blk = take((size_t)((PT + kScanTiles - 1) / kScanTiles + 1) * 8);
-  L.ekey = take((size_t)L.cap * 4);
-  L.eval = take((size_t)L.cap * 4);
+  L.ekv = take((size_t)L.cap * 8);
   L.klo = take((size_t)L.cap * 4);
   L.val = take((size_t)L.cap * 4);
   L.tkey = take((size_t)L.cap * 4);

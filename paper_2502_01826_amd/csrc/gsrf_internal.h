@@ -99,7 +99,7 @@ struct Layout {
   size_t prep, rec_base, rec_key, rec_rect, counters;
   size_t tile_cnt, tile_start, tile_end, tile_cur;
   size_t scan_blk;        // per-block totals of the tile-count scan
-  size_t ekey, eval;      // emitted buckets (unsorted)
+  size_t ekv;             // emitted buckets (unsorted): (depth key, Gaussian id) pairs
   size_t klo, val;        // sorted tile lists: depth key, Gaussian id
   size_t tkey, tval;      // sort scratch for buckets longer than the LDS chunk
   size_t tile_sum, grad_acc;

@@ -18,7 +18,11 @@ namespace gsrf {
 // a3: one splat per covered tile.  The workgroup (RB records of one pair)
 // counts its splats per tile in LDS, reserves each tile's share with one
 // global atomic on its sub-bucket's cursor, then writes (key, Gaussian) at its
-// reserved slots.
+// reserved slots.  With 256 records and at most kEmitCache splats, the first
+// pass keeps every splat's (tile, rank in the workgroup's share, record) in
+// LDS, so the second pass neither searches nor counts again.
+constexpr int kEmitCache = 2048;
+
 template <int RB>
 __global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs,
                                               const int64_t *__restrict__ scene_off,
@@ -26,13 +30,15 @@ __global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs
                                               const uint32_t *__restrict__ rec_key,
                                               const ushort4 *__restrict__ rec_rect, int32_t T, int32_t nta, int64_t PT,
                                               const int64_t *__restrict__ counters, uint32_t *__restrict__ tcur,
-                                              uint32_t *__restrict__ ekey, uint32_t *__restrict__ eval) {
+                                              uint2 *__restrict__ ekv) {
   if (counters[1] != 0) return;  // over capacity: every range is empty, nothing is emitted
+  constexpr bool CACHE = RB == 256;   // tile < 2^16, rank < 2^8, record < 2^8
   extern __shared__ uint32_t sm[];
   uint32_t *cnt = sm;        // [T]
   uint32_t *base = sm + T;   // [T]
   __shared__ RectScan<RB> rs;
   __shared__ uint32_t keys[RB];
+  __shared__ uint32_t cache[CACHE ? kEmitCache : 1];
   const int k = blockIdx.y;
   for (int t = threadIdx.x; t < T; t += blockDim.x) cnt[t] = 0;
   const int s = pairs[k].scene;
@@ -49,10 +55,12 @@ __global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs
   keys[threadIdx.x] = key;
   rect_scan(rs, rc);
   const uint32_t total = rs.off[RB];
+  const bool cached = CACHE && total <= (uint32_t)kEmitCache;
   for (uint32_t sp = threadIdx.x; sp < total; sp += RB) {
     int t;
-    rect_splat(rs, sp, nta, &t);
-    atomicAdd(&cnt[t], 1u);
+    const int slot = rect_splat(rs, sp, nta, &t);
+    const uint32_t rank = atomicAdd(&cnt[t], 1u);
+    if (cached) cache[sp] = ((uint32_t)t << 16) | (rank << 8) | (uint32_t)slot;
   }
   __syncthreads();
   // reserve this workgroup's share of each touched tile in sub-bucket b % kSub
@@ -64,12 +72,19 @@ __global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs
   }
   __syncthreads();
   const uint32_t gbase = (uint32_t)(g0 + (int64_t)blockIdx.x * RB);
-  for (uint32_t sp = threadIdx.x; sp < total; sp += RB) {
-    int t;
-    const int slot = rect_splat(rs, sp, nta, &t);
-    const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
-    ekey[pos] = keys[slot];
-    eval[pos] = gbase + (uint32_t)slot;
+  if (cached) {
+    for (uint32_t sp = threadIdx.x; sp < total; sp += RB) {
+      const uint32_t c = cache[sp];
+      const uint32_t slot = c & 0xFFu;
+      ekv[base[c >> 16] + ((c >> 8) & 0xFFu)] = make_uint2(keys[slot], gbase + slot);
+    }
+  } else {
+    for (uint32_t sp = threadIdx.x; sp < total; sp += RB) {
+      int t;
+      const int slot = rect_splat(rs, sp, nta, &t);
+      const uint32_t pos = base[t] + atomicAdd(&cnt[t], 1u);
+      ekv[pos] = make_uint2(keys[slot], gbase + (uint32_t)slot);
+    }
   }
 }
 
@@ -124,10 +139,10 @@ __device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint3
   }
 }
 
-// Sort the n entries (ek, ev) by composite into (ok, ov) through the scatter
+// Sort the n entries ekv = (key, value) by composite into (ok, ov) through the scatter
 // buffer (bk, bv); SH: the buffer is in LDS.
 template <bool SH>
-__device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *__restrict__ ev, int n, uint32_t *bk,
+__device__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint32_t *bk,
                               uint32_t *bv, uint32_t *__restrict__ ok, uint32_t *__restrict__ ov, uint32_t *hist,
                               uint32_t *start, uint64_t *red, uint32_t *sk, uint32_t *sv, int chunk) {
   constexpr int NT = kTileSortThreads;
@@ -139,8 +154,9 @@ __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *_
 #pragma unroll
     for (int e = 0; e < kSortRegs; ++e) {
       const int i = tid + e * NT;
-      rk[e] = i < n ? ek[i] : 0u;
-      rv[e] = i < n ? ev[i] : 0u;
+      const uint2 x = i < n ? ekv[i] : make_uint2(0u, 0u);
+      rk[e] = x.x;
+      rv[e] = x.y;
     }
   }
   uint64_t cmin = ~0ull, cmax = 0;
@@ -154,7 +170,7 @@ __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *_
       }
   } else {
     for (int i = tid; i < n; i += NT) {
-      const uint64_t c = composite(ek[i], ev[i]);
+      const uint64_t c = composite(ekv[i].x, ekv[i].y);
       cmin = c < cmin ? c : cmin;
       cmax = c > cmax ? c : cmax;
     }
@@ -199,7 +215,7 @@ __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *_
     for (int e = 0; e < kSortRegs; ++e)
       if (tid + e * NT < n) atomicAdd(&hist[(uint32_t)((composite(rk[e], rv[e]) - cmin) >> shift)], 1u);
   } else {
-    for (int i = tid; i < n; i += NT) atomicAdd(&hist[(uint32_t)((composite(ek[i], ev[i]) - cmin) >> shift)], 1u);
+    for (int i = tid; i < n; i += NT) atomicAdd(&hist[(uint32_t)((composite(ekv[i].x, ekv[i].y) - cmin) >> shift)], 1u);
   }
   __syncthreads();
   bins_scan(hist, start, nbins, (uint32_t *)(red + 2 * kSortWaves + 2));
@@ -216,7 +232,7 @@ __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *_
       }
   } else {
     for (int i = tid; i < n; i += NT) {
-      const uint32_t k = ek[i], v = ev[i];
+      const uint32_t k = ekv[i].x, v = ekv[i].y;
       const uint32_t p = atomicAdd(&hist[(uint32_t)((composite(k, v) - cmin) >> shift)], 1u);
       bk[p] = k;
       bv[p] = v;
@@ -295,8 +311,7 @@ __device__ void msd_rank_sort(const uint32_t *__restrict__ ek, const uint32_t *_
 // a4: sort every tile's bucket; writes the sorted depth keys and Gaussian ids.
 __global__ __launch_bounds__(kTileSortThreads, 8) void k_tile_sort(const uint32_t *__restrict__ tstart,
                                                                 const uint32_t *__restrict__ tend, int chunk,
-                                                                const uint32_t *__restrict__ ekey,
-                                                                const uint32_t *__restrict__ eval,
+                                                                const uint2 *__restrict__ ekv,
                                                                 uint32_t *__restrict__ klo, uint32_t *__restrict__ val,
                                                                 uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval) {
   extern __shared__ uint64_t sm64[];
@@ -310,10 +325,9 @@ __global__ __launch_bounds__(kTileSortThreads, 8) void k_tile_sort(const uint32_
   const int n = (int)(tend[gt] - s0);
   if (n <= 0) return;
   if (n <= chunk)
-    msd_rank_sort<true>(ekey + s0, eval + s0, n, sk, sv, klo + s0, val + s0, hist, start, red, sk, sv, chunk);
+    msd_rank_sort<true>(ekv + s0, n, sk, sv, klo + s0, val + s0, hist, start, red, sk, sv, chunk);
   else
-    msd_rank_sort<false>(ekey + s0, eval + s0, n, tkey + s0, tval + s0, klo + s0, val + s0, hist, start, red, sk, sv,
-                         chunk);
+    msd_rank_sort<false>(ekv + s0, n, tkey + s0, tval + s0, klo + s0, val + s0, hist, start, red, sk, sv, chunk);
 }
 
 static int g_sort_chunk = 0;
@@ -355,16 +369,16 @@ hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, h
       hipLaunchKernelGGL(k_emit<1024>, grid, dim3(1024), (size_t)lay.T * 8, s, p->pairs, p->scene_offsets_dev,
                          (const int64_t *)(ws + lay.rec_base), (const uint32_t *)(ws + lay.rec_key),
                          (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, PT, counters,
-                         (uint32_t *)(ws + lay.tile_cur), (uint32_t *)(ws + lay.ekey), (uint32_t *)(ws + lay.eval));
+                         (uint32_t *)(ws + lay.tile_cur), (uint2 *)(ws + lay.ekv));
     else
       hipLaunchKernelGGL(k_emit<256>, grid, dim3(256), (size_t)lay.T * 8, s, p->pairs, p->scene_offsets_dev,
                          (const int64_t *)(ws + lay.rec_base), (const uint32_t *)(ws + lay.rec_key),
                          (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, PT, counters,
-                         (uint32_t *)(ws + lay.tile_cur), (uint32_t *)(ws + lay.ekey), (uint32_t *)(ws + lay.eval));
+                         (uint32_t *)(ws + lay.tile_cur), (uint2 *)(ws + lay.ekv));
   }
   choose_sort_chunk();
   hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)PT), dim3(kTileSortThreads), g_sort_lds, s, tstart, tend,
-                     g_sort_chunk, (const uint32_t *)(ws + lay.ekey), (const uint32_t *)(ws + lay.eval),
+                     g_sort_chunk, (const uint2 *)(ws + lay.ekv),
                      (uint32_t *)(ws + lay.klo), (uint32_t *)(ws + lay.val), (uint32_t *)(ws + lay.tkey),
                      (uint32_t *)(ws + lay.tval));
   return hipGetLastError();
