@@ -101,7 +101,7 @@ struct Layout {
   size_t scan_blk;        // per-block totals of the tile-count scan
   size_t ekv;             // emitted buckets (unsorted): (depth key, Gaussian id) pairs
   size_t klo, val;        // sorted tile lists: depth key, Gaussian id
-  size_t tkey, tval;      // sort scratch for buckets longer than the LDS chunk
+  size_t tkv;             // sort scratch for buckets longer than the LDS chunk: (key, id) pairs
   size_t tile_sum, grad_acc;
   size_t hitmask;         // two-phase traversal: per splat, tile-area / 32 words of forward hit bits
   size_t rays;            // [n_el * n_az][ray_stride(K)] ray directions and FLE basis (FP32)

@@ -92,9 +92,9 @@ __global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs
 // a4: per-tile sort by (distance key, Gaussian index), one workgroup per tile.
 //
 // Each entry is the 64-bit composite c = key << 32 | index (unique within a
-// tile).  One MSD counting pass splits the bucket into 2^b sub-buckets of
-// c - c_min (about four entries each, b <= 11): histogram, exclusive scan and
-// scatter.  Each entry's final place is then its sub-bucket's start plus its
+// tile).  One MSD counting pass splits the bucket into 2^b sub-buckets (about
+// four entries each, b <= 11) by the key's D^2 value scaled linearly between
+// the bucket's extremes: histogram, exclusive scan and scatter.  Each entry's final place is then its sub-bucket's start plus its
 // rank among the sub-bucket's entries, found by comparing with all of them;
 // sub-buckets are small, so this costs a few comparisons per entry and no
 // further passes.  The scatter buffer is LDS for buckets of up to `chunk`
@@ -102,10 +102,22 @@ __global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs
 // windows of whole sub-buckets.  The result does not depend on the (atomic)
 // scatter order, so it is deterministic.
 // ---------------------------------------------------------------------------
-constexpr int kSortWaves = kTileSortThreads / 64;
 constexpr int kSortRegs = 8;              // entries per thread held in registers (LDS path)
-constexpr int kSortBitsMax = 11;
-constexpr int kSortBins = 1 << kSortBitsMax;
+
+// Workgroup shapes: 1024 threads (any bucket; up to 2^11 sub-buckets) and 256
+// threads (buckets of at most 8 x 256 entries, held in registers; 2^9).
+template <int NT>
+struct SortShape {
+  static constexpr int kWaves = NT / 64;
+  static constexpr int kBitsMax = NT >= 1024 ? 11 : 9;
+  static constexpr int kBins = 1 << kBitsMax;
+  static constexpr int kRedWords = 4 * kWaves;    // u64: wave min/max, totals, wave sums
+};
+constexpr int kSortWaves = kTileSortThreads / 64;
+constexpr int kSortBitsMax = SortShape<kTileSortThreads>::kBitsMax;
+constexpr int kSortBins = SortShape<kTileSortThreads>::kBins;
+constexpr int kSmallSortThreads = 256;
+constexpr int kSmallSortMax = kSortRegs * kSmallSortThreads;   // 2048 entries
 
 __device__ __forceinline__ uint64_t composite(uint32_t k, uint32_t v) { return ((uint64_t)k << 32) | v; }
 
@@ -114,9 +126,46 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int d) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Exclusive scan of cnt[0, nbins) into start[0, nbins) (nbins <= 2 * threads).
+// f(entry) for every entry of a bucket in global memory, kGlobalBatch loads
+// per thread in flight at a time (a plain strided loop would wait for each load).
+constexpr int kGlobalBatch = 4;
+
+template <int NT, typename F>
+__device__ __forceinline__ void for_each_global(const uint2 *__restrict__ ekv, int n, F f) {
+  for (int b = 0; b < n; b += kGlobalBatch * NT) {
+    uint2 x[kGlobalBatch];
+#pragma unroll
+    for (int e = 0; e < kGlobalBatch; ++e) {
+      const int i = b + (int)threadIdx.x + e * NT;
+      x[e] = i < n ? ekv[i] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int e = 0; e < kGlobalBatch; ++e)
+      if (b + (int)threadIdx.x + e * NT < n) f(x[e]);
+  }
+}
+
+// dst[i] = src[i] for i < len, kGlobalBatch loads per thread in flight.
+template <int NT>
+__device__ __forceinline__ void copy_window(const uint2 *__restrict__ src, uint2 *dst, int len) {
+  for (int b = 0; b < len; b += kGlobalBatch * NT) {
+    uint2 x[kGlobalBatch];
+#pragma unroll
+    for (int e = 0; e < kGlobalBatch; ++e) {
+      const int i = b + (int)threadIdx.x + e * NT;
+      x[e] = i < len ? src[i] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int e = 0; e < kGlobalBatch; ++e) {
+      const int i = b + (int)threadIdx.x + e * NT;
+      if (i < len) dst[i] = x[e];
+    }
+  }
+}
+
+// Exclusive scan of cnt[0, nbins) into start[0, nbins) by the NT threads.
+template <int NT>
 __device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint32_t *wsum) {
-  constexpr int NT = kTileSortThreads;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (nbins + NT - 1) / NT;
   const int lo = min(nbins, tid * per), hi = min(nbins, lo + per);
@@ -140,19 +189,20 @@ __device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint3
 }
 
 // Sort the n entries ekv = (key, value) by composite into (ok, ov) through the scatter
-// buffer (bk, bv); SH: the buffer is in LDS.
-template <bool SH>
-__device__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint32_t *bk,
-                              uint32_t *bv, uint32_t *__restrict__ ok, uint32_t *__restrict__ ov, uint32_t *hist,
-                              uint32_t *start, uint64_t *red, uint32_t *sk, uint32_t *sv, int chunk) {
-  constexpr int NT = kTileSortThreads;
+// buffer bkv; SH: the buffer is in LDS, else in global memory and ranked
+// through the LDS window skv.
+template <int NT, bool SH, int REGS = kSortRegs>
+__device__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint2 *bkv, uint32_t *__restrict__ ok,
+                              uint32_t *__restrict__ ov, uint32_t *hist, uint32_t *start, uint64_t *red, uint2 *skv,
+                              int chunk) {
+  constexpr int kSortWaves = SortShape<NT>::kWaves, kSortBitsMax = SortShape<NT>::kBitsMax;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // LDS path (n <= kSortRegs * NT): each thread keeps its entries in registers
+  // LDS path (n <= REGS * NT): each thread keeps its entries in registers
   // across the passes, so the bucket is read from global memory once
-  uint32_t rk[SH ? kSortRegs : 1], rv[SH ? kSortRegs : 1];
+  uint32_t rk[SH ? REGS : 1], rv[SH ? REGS : 1];
   if constexpr (SH) {
 #pragma unroll
-    for (int e = 0; e < kSortRegs; ++e) {
+    for (int e = 0; e < REGS; ++e) {
       const int i = tid + e * NT;
       const uint2 x = i < n ? ekv[i] : make_uint2(0u, 0u);
       rk[e] = x.x;
@@ -162,18 +212,18 @@ __device__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint32_t *bk
   uint64_t cmin = ~0ull, cmax = 0;
   if constexpr (SH) {
 #pragma unroll
-    for (int e = 0; e < kSortRegs; ++e)
+    for (int e = 0; e < REGS; ++e)
       if (tid + e * NT < n) {
         const uint64_t c = composite(rk[e], rv[e]);
         cmin = c < cmin ? c : cmin;
         cmax = c > cmax ? c : cmax;
       }
   } else {
-    for (int i = tid; i < n; i += NT) {
-      const uint64_t c = composite(ekv[i].x, ekv[i].y);
+    for_each_global<NT>(ekv, n, [&](uint2 x) {
+      const uint64_t c = composite(x.x, x.y);
       cmin = c < cmin ? c : cmin;
       cmax = c > cmax ? c : cmax;
-    }
+    });
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
@@ -204,52 +254,60 @@ __device__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint32_t *bk
   cmax = red[2 * kSortWaves + 1];
   int bits = 1;
   while (bits < kSortBitsMax && (4 << bits) < n) ++bits;
-  const uint64_t span = cmax - cmin;
-  const int nbits = span ? 64 - __clzll(span) : 0;
-  const int shift = nbits > bits ? nbits - bits : 0;
+  // sub-bucket of an entry: its depth key's value (D^2) scaled linearly onto
+  // [0, nbins) -- monotone in the key, so in the composite; the density of
+  // splats grows slowly with D^2 (not like the key bits, which are
+  // logarithmic in D^2), so the sub-buckets stay balanced
   const int nbins = 1 << bits;
+  const float dlo = __uint_as_float((uint32_t)(cmin >> 32)), dhi = __uint_as_float((uint32_t)(cmax >> 32));
+  const float scale = dhi > dlo ? (float)nbins / (dhi - dlo) : 0.f;
+  auto digit = [&](uint32_t k) -> uint32_t {   // (a NaN product, from an infinite scale, lands in the last bin)
+    const float x = (__uint_as_float(k) - dlo) * scale;
+    return x < (float)nbins ? (uint32_t)x : (uint32_t)(nbins - 1);
+  };
   for (int i = tid; i < nbins; i += NT) hist[i] = 0;
   __syncthreads();
   if constexpr (SH) {
 #pragma unroll
-    for (int e = 0; e < kSortRegs; ++e)
-      if (tid + e * NT < n) atomicAdd(&hist[(uint32_t)((composite(rk[e], rv[e]) - cmin) >> shift)], 1u);
+    for (int e = 0; e < REGS; ++e)
+      if (tid + e * NT < n) atomicAdd(&hist[digit(rk[e])], 1u);
   } else {
-    for (int i = tid; i < n; i += NT) atomicAdd(&hist[(uint32_t)((composite(ekv[i].x, ekv[i].y) - cmin) >> shift)], 1u);
+    for_each_global<NT>(ekv, n, [&](uint2 x) { atomicAdd(&hist[digit(x.x)], 1u); });
   }
   __syncthreads();
-  bins_scan(hist, start, nbins, (uint32_t *)(red + 2 * kSortWaves + 2));
+  bins_scan<NT>(hist, start, nbins, (uint32_t *)(red + 2 * kSortWaves + 2));
   __syncthreads();
   for (int i = tid; i < nbins; i += NT) hist[i] = start[i];     // scatter cursors
   __syncthreads();
   if constexpr (SH) {
 #pragma unroll
-    for (int e = 0; e < kSortRegs; ++e)
+    for (int e = 0; e < REGS; ++e)
       if (tid + e * NT < n) {
-        const uint32_t p = atomicAdd(&hist[(uint32_t)((composite(rk[e], rv[e]) - cmin) >> shift)], 1u);
-        bk[p] = rk[e];
-        bv[p] = rv[e];
+        const uint32_t p = atomicAdd(&hist[digit(rk[e])], 1u);
+        bkv[p] = make_uint2(rk[e], rv[e]);
       }
   } else {
-    for (int i = tid; i < n; i += NT) {
-      const uint32_t k = ekv[i].x, v = ekv[i].y;
-      const uint32_t p = atomicAdd(&hist[(uint32_t)((composite(k, v) - cmin) >> shift)], 1u);
-      bk[p] = k;
-      bv[p] = v;
-    }
+    for_each_global<NT>(ekv, n, [&](uint2 x) {
+      const uint32_t p = atomicAdd(&hist[digit(x.x)], 1u);
+      bkv[p] = x;
+    });
   }
   if (!SH) __threadfence_block();
   __syncthreads();
   // hist[d] is now the end of sub-bucket d
   if constexpr (SH) {
     for (int p = tid; p < n; p += NT) {
-      const uint32_t k = bk[p], v = bv[p];
+      const uint2 kv = bkv[p];
+      const uint32_t k = kv.x, v = kv.y;
       const uint64_t c = composite(k, v);
-      const uint32_t d = (uint32_t)((c - cmin) >> shift);
+      const uint32_t d = digit(k);
       const int a = (int)start[d], e = (int)hist[d];
       int rank = 0;
-#pragma unroll 2
-      for (int j = a; j < e; ++j) rank += composite(bk[j], bv[j]) < c ? 1 : 0;
+#pragma unroll 4
+      for (int j = a; j < e; ++j) {
+        const uint2 o = bkv[j];
+        rank += composite(o.x, o.y) < c ? 1 : 0;
+      }
       ok[a + rank] = k;
       ov[a + rank] = v;
     }
@@ -272,33 +330,33 @@ __device__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint32_t *bk
         }
       }
       if (w1 > w0) {
-        for (int i = tid; i < w1 - w0; i += NT) {
-          sk[i] = bk[w0 + i];
-          sv[i] = bv[w0 + i];
-        }
+        copy_window<NT>(bkv + w0, skv, w1 - w0);
         __syncthreads();
         for (int p = tid; p < w1 - w0; p += NT) {
-          const uint32_t k = sk[p], v = sv[p];
+          const uint2 kv = skv[p];
+          const uint32_t k = kv.x, v = kv.y;
           const uint64_t c = composite(k, v);
-          const uint32_t d = (uint32_t)((c - cmin) >> shift);
+          const uint32_t d = digit(k);
           const int a = (int)start[d] - w0, e = (int)hist[d] - w0;
           int rank = 0;
-#pragma unroll 2
-          for (int j = a; j < e; ++j) rank += composite(sk[j], sv[j]) < c ? 1 : 0;
+#pragma unroll 4
+          for (int j = a; j < e; ++j) {
+            const uint2 o = skv[j];
+            rank += composite(o.x, o.y) < c ? 1 : 0;
+          }
           ok[w0 + a + rank] = k;
           ov[w0 + a + rank] = v;
         }
         __syncthreads();
       } else {
         // the sub-bucket starting at w0 exceeds the window
-        const uint64_t c0 = composite(bk[w0], bv[w0]);
-        const uint32_t d0 = (uint32_t)((c0 - cmin) >> shift);
+        const uint32_t d0 = digit(bkv[w0].x);
         w1 = (int)hist[d0];
         for (int p = w0 + tid; p < w1; p += NT) {
-          const uint32_t k = bk[p], v = bv[p];
+          const uint32_t k = bkv[p].x, v = bkv[p].y;
           const uint64_t c = composite(k, v);
           int rank = 0;
-          for (int j = w0; j < w1; ++j) rank += composite(bk[j], bv[j]) < c ? 1 : 0;
+          for (int j = w0; j < w1; ++j) rank += composite(bkv[j].x, bkv[j].y) < c ? 1 : 0;
           ok[w0 + rank] = k;
           ov[w0 + rank] = v;
         }
@@ -308,30 +366,104 @@ __device__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint32_t *bk
   }
 }
 
+// One bucket by the 1024-thread workgroup: in LDS up to `chunk` entries
+// (REGS * 1024 at most), else through the global scratch tkv.
+template <int REGS = kSortRegs>
+__device__ __forceinline__ void sort_bucket(const uint2 *__restrict__ ekv, uint32_t s0, int n, int chunk,
+                                            uint32_t *__restrict__ klo, uint32_t *__restrict__ val,
+                                            uint2 *__restrict__ tkv, uint32_t *hist, uint32_t *start,
+                                            uint64_t *red, uint2 *skv) {
+  if (n <= 0) return;
+  if (n <= chunk)
+    msd_rank_sort<kTileSortThreads, true, REGS>(ekv + s0, n, skv, klo + s0, val + s0, hist, start, red, skv, chunk);
+  else
+    msd_rank_sort<kTileSortThreads, false>(ekv + s0, n, tkv + s0, klo + s0, val + s0, hist, start, red, skv, chunk);
+}
+
 // a4: sort every tile's bucket; writes the sorted depth keys and Gaussian ids.
 __global__ __launch_bounds__(kTileSortThreads, 8) void k_tile_sort(const uint32_t *__restrict__ tstart,
                                                                 const uint32_t *__restrict__ tend, int chunk,
                                                                 const uint2 *__restrict__ ekv,
                                                                 uint32_t *__restrict__ klo, uint32_t *__restrict__ val,
-                                                                uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval) {
+                                                                uint2 *__restrict__ tkv) {
   extern __shared__ uint64_t sm64[];
   uint64_t *red = sm64;                                     // wave min/max, totals, wave sums
   uint32_t *hist = (uint32_t *)(sm64 + 4 * kSortWaves);     // [kSortBins]
   uint32_t *start = hist + kSortBins;                       // [kSortBins]
-  uint32_t *sk = start + kSortBins;                         // [chunk]
-  uint32_t *sv = sk + chunk;                                // [chunk]
+  uint2 *skv = (uint2 *)(start + kSortBins);                // [chunk]
   const int gt = blockIdx.x;
   const uint32_t s0 = tstart[gt];
   const int n = (int)(tend[gt] - s0);
-  if (n <= 0) return;
-  if (n <= chunk)
-    msd_rank_sort<true>(ekv + s0, n, sk, sv, klo + s0, val + s0, hist, start, red, sk, sv, chunk);
-  else
-    msd_rank_sort<false>(ekv + s0, n, tkey + s0, tval + s0, klo + s0, val + s0, hist, start, red, sk, sv, chunk);
+  sort_bucket(ekv, s0, n, chunk, klo, val, tkv, hist, start, red, skv);
 }
 
-static int g_sort_chunk = 0;
-static size_t g_sort_lds = 0;
+// a4 for launches with many tiles, in two kernels: one 256-thread workgroup
+// per tile sorts the buckets of at most 2048 entries (four times as many
+// workgroups per CU as the 1024-thread kernel, for the same waves), then a
+// fixed grid of 1024-thread workgroups sorts the longer ones: workgroup b
+// takes tiles b, b + grid, ..., finding the long ones 1024 tiles at a time.
+__global__ __launch_bounds__(kSmallSortThreads) void k_tile_sort_small(const uint32_t *__restrict__ tstart,
+                                                                      const uint32_t *__restrict__ tend,
+                                                                      const uint2 *__restrict__ ekv,
+                                                                      uint32_t *__restrict__ klo,
+                                                                      uint32_t *__restrict__ val) {
+  constexpr int NT = kSmallSortThreads, NB = SortShape<NT>::kBins;
+  __shared__ uint64_t red[SortShape<NT>::kRedWords];
+  __shared__ uint32_t hist[NB], start[NB];
+  __shared__ uint2 skv[kSmallSortMax];
+  const int gt = blockIdx.x;
+  const uint32_t s0 = tstart[gt];
+  const int n = (int)(tend[gt] - s0);
+  if (n <= 0 || n > kSmallSortMax) return;
+  msd_rank_sort<NT, true>(ekv + s0, n, skv, klo + s0, val + s0, hist, start, red, skv, kSmallSortMax);
+}
+
+// Buckets longer than `lo` entries in a fixed grid: workgroup b takes tiles
+// b, b + grid, ..., finding its long ones 1024 tiles at a time.
+__global__ __launch_bounds__(kTileSortThreads, 8) void k_tile_sort_long(
+    const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend, int64_t PT, int lo, int chunk,
+    const uint2 *__restrict__ ekv, uint32_t *__restrict__ klo, uint32_t *__restrict__ val, uint2 *__restrict__ tkv) {
+  extern __shared__ uint64_t sm64[];
+  uint64_t *red = sm64;
+  uint32_t *hist = (uint32_t *)(sm64 + 4 * kSortWaves);
+  uint32_t *start = hist + kSortBins;
+  uint2 *skv = (uint2 *)(start + kSortBins);
+  __shared__ uint32_t list[kTileSortThreads];
+  __shared__ uint32_t n_list[kSortWaves + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t stride = gridDim.x;
+  for (int64_t k0 = 0; blockIdx.x + k0 * stride < PT; k0 += kTileSortThreads) {
+    // this block's next 1024 tiles: keep the long buckets, in tile order
+    const int64_t t = blockIdx.x + (k0 + tid) * stride;
+    const int n = t < PT ? (int)(tend[t] - tstart[t]) : 0;
+    const bool longb = n > lo;
+    const uint64_t m = __ballot(longb);
+    if (lane == 0) n_list[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t run = 0;
+      for (int w = 0; w < kSortWaves; ++w) {
+        const uint32_t c = n_list[w];
+        n_list[w] = run;
+        run += c;
+      }
+      n_list[kSortWaves] = run;
+    }
+    __syncthreads();
+    if (longb) list[n_list[wave] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
+    __syncthreads();
+    const int cnt = (int)n_list[kSortWaves];
+    for (int i = 0; i < cnt; ++i) {
+      const uint32_t tt = list[i];
+      const uint32_t s0 = tstart[tt];
+      sort_bucket(ekv, s0, (int)(tend[tt] - s0), chunk, klo, val, tkv, hist, start, red, skv);
+      __syncthreads();
+    }
+  }
+}
+
+static int g_sort_chunk = 0, g_long_chunk = 0, g_n_cu = 0;
+static size_t g_sort_lds = 0, g_long_lds = 0;
 
 size_t max_lds_per_block() {
   int dev = 0, v = 0;
@@ -340,21 +472,42 @@ size_t max_lds_per_block() {
   return (size_t)v;
 }
 
-// Largest LDS chunk that still lets two 1024-thread workgroups share a CU.
-static void choose_sort_chunk() {
-  if (g_sort_chunk) return;
+// Largest LDS chunk that lets `per_cu` 1024-thread workgroups share a CU
+// (static_bytes: the kernel's own LDS besides the dynamic part), at most
+// regs * 1024 entries.
+static int sort_chunk_for(size_t static_bytes, int per_cu, int regs, size_t *dyn) {
   const size_t fixed = (size_t)4 * kSortWaves * 8 + (size_t)2 * kSortBins * 4;
   size_t lds = max_lds_per_block();
-  if (lds > 160 * 1024) lds = 160 * 1024;
-  int chunk = (int)((lds / 2 - fixed) / 8);
+  if (lds > (size_t)160 * 1024 / per_cu) lds = (size_t)160 * 1024 / per_cu;
+  int chunk = (int)((lds - fixed - static_bytes) / 8);
   chunk = (chunk / 32) * 32;
-  if (chunk > kSortRegs * kTileSortThreads) chunk = kSortRegs * kTileSortThreads;
+  if (chunk > regs * kTileSortThreads) chunk = regs * kTileSortThreads;
   if (chunk < kTileSortThreads) chunk = kTileSortThreads;
-  g_sort_lds = fixed + (size_t)8 * chunk;
-  if (g_sort_lds > 65536)
-    (void)hipFuncSetAttribute((const void *)k_tile_sort, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g_sort_lds);
-  g_sort_chunk = chunk;
+  *dyn = fixed + (size_t)8 * chunk;
+  return chunk;
 }
+
+static void set_lds(const void *f, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+static void choose_sort_chunk() {
+  if (g_sort_chunk) return;
+  const size_t list_bytes = (size_t)4 * (kTileSortThreads + kSortWaves + 1);
+  g_sort_chunk = sort_chunk_for(0, 2, kSortRegs, &g_sort_lds);
+  set_lds((const void *)k_tile_sort, g_sort_lds);
+  g_long_chunk = sort_chunk_for(list_bytes, 2, kSortRegs, &g_long_lds);
+  set_lds((const void *)k_tile_sort_long, g_long_lds);
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      n > 0)
+    g_n_cu = n;
+  else
+    g_n_cu = 256;
+}
+
+// Launches with more (pair, tile) units than this sort in two kernels.
+constexpr int64_t kSortFewTiles = 2048;
 
 hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, hipStream_t s) {
   const int64_t PT = (int64_t)p->n_pairs * lay.T;
@@ -377,10 +530,19 @@ hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, h
                          (uint32_t *)(ws + lay.tile_cur), (uint2 *)(ws + lay.ekv));
   }
   choose_sort_chunk();
-  hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)PT), dim3(kTileSortThreads), g_sort_lds, s, tstart, tend,
-                     g_sort_chunk, (const uint2 *)(ws + lay.ekv),
-                     (uint32_t *)(ws + lay.klo), (uint32_t *)(ws + lay.val), (uint32_t *)(ws + lay.tkey),
-                     (uint32_t *)(ws + lay.tval));
+  const uint2 *ekv = (const uint2 *)(ws + lay.ekv);
+  uint32_t *klo = (uint32_t *)(ws + lay.klo), *val = (uint32_t *)(ws + lay.val);
+  uint2 *tkv = (uint2 *)(ws + lay.tkv);
+  if (PT <= kSortFewTiles) {
+    hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)PT), dim3(kTileSortThreads), g_sort_lds, s, tstart, tend,
+                       g_sort_chunk, ekv, klo, val, tkv);
+  } else {
+    hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)PT), dim3(kSmallSortThreads), 0, s, tstart, tend, ekv, klo,
+                       val);
+    const int64_t grid = 2 * (int64_t)g_n_cu < PT ? 2 * (int64_t)g_n_cu : PT;   // two workgroups per CU
+    hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)grid), dim3(kTileSortThreads), g_long_lds, s, tstart, tend,
+                       PT, kSmallSortMax, g_long_chunk, ekv, klo, val, tkv);
+  }
   return hipGetLastError();
 }
 

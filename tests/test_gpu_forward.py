@@ -244,11 +244,20 @@ def test_large_batch_wide_workgroups_match_oracle():
     assert L["overflow"] == 0
     rng = np.random.default_rng(17)
     T = L["T"]
+    # every list of every pair is ordered by (key, Gaussian index)
+    comp = (L["klo"].astype(np.uint64) << np.uint64(32)) | L["val"].astype(np.uint64)
+    step_ok = comp[1:] > comp[:-1]
+    first = np.zeros(len(comp), bool)
+    first[L["ts"][L["te"] > L["ts"]]] = True
+    assert np.all(step_ok | first[1:])
+    say("longest list", int((L["te"] - L["ts"]).max()))
     for k in (0, 4, 8):
         p = b.pairs[k]
         np.testing.assert_array_equal(L["rec_key"][k * sc.n:(k + 1) * sc.n],
                                       oracle.depth_key32(sc.means, p.rx).astype(np.uint32))
-        tiles = rng.choice(T, 6, replace=False)
+        lens = L["te"][k * T:(k + 1) * T] - L["ts"][k * T:(k + 1) * T]
+        # six random tiles and the two longest (sorted by the long-bucket kernel)
+        tiles = np.unique(np.concatenate([rng.choice(T, 6, replace=False), np.argsort(lens)[-2:]]))
         ref_l, marg = oracle_tile_members(sc, p, g, tiles)
         bad = set(np.nonzero(marg)[0].tolist())
         for t in tiles:
