@@ -16,7 +16,7 @@ constexpr double kC0 = 3.0e8;
 constexpr double kCapSlack = 1e-5;
 // 3-sigma ellipsoid level (App. D.3.1).
 constexpr float kLevel = 9.0f;
-// Per-Gaussian prepared record: mu(3), N, M00 M11 M22 M01 M02 M12, o, pad(5).
+// Per-Gaussian prepared record: mu(3), N, M00 M11 M22 M01 M02 M12, o, pad, 3 max(s), max log s, pad(2).
 constexpr int kPrep = 16;
 
 // Binning: splats are emitted into per-tile buckets (key, Gaussian) and each

@@ -149,7 +149,9 @@ __global__ __launch_bounds__(256) void k_activate(const float *__restrict__ mean
   o[0] = make_float4(means[3 * g + 0], means[3 * g + 1], means[3 * g + 2], inv_2pi_15 * expf(-(l0 + l1 + l2)));
   o[1] = make_float4(M[0][0], M[1][1], M[2][2], 0.5f * (M[0][1] + M[1][0]));
   o[2] = make_float4(0.5f * (M[0][2] + M[2][0]), 0.5f * (M[1][2] + M[2][1]), 1.f / (1.f + expf(-logits[g])), 0.f);
-  o[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+  // binning: bounding-sphere radius 3 max(s) (FP32, as the cap evaluation uses it) and max log-scale
+  const float lmax = fmaxf(fmaxf(l0, l1), l2);
+  o[3] = make_float4(3.0f * expf(lmax), lmax, 0.f, 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -205,7 +207,8 @@ __device__ __forceinline__ bool cap_rect_fp32(float ex, float ey, float ez, floa
   const float sr = Rb / D;
   if (sr > 0.9f) return false;
   const float theta = asinf(sr) + (float)kCapSlack;
-  const float bc = atan2f(ez, sqrtf(ex * ex + ey * ey));
+  const float rho = sqrtf(ex * ex + ey * ey);
+  const float bc = atan2f(ez, rho);
   const float lo = bc - theta, hi = bc + theta;
   const float halfpi = 1.57079632679489662f;
   if (fabsf(hi - halfpi) <= kFastAngTol || fabsf(lo + halfpi) <= kFastAngTol) return false;
@@ -219,9 +222,10 @@ __device__ __forceinline__ bool cap_rect_fp32(float ex, float ey, float ez, floa
   bool full = (hi >= halfpi) || (lo <= -halfpi);
   long u_lo = 0, u_hi = grid.n_az - 1;
   if (!full) {
-    const float cb = cosf(bc);
+    const float cb = rho / D;                                    // cos(beta_c)
     if (cb < 0.2f) return false;
-    const float r = sinf(theta) / cb;
+    // sin(theta) = sin(asin(sr) + slack) = sr cos(slack) + cos(asin(sr)) sin(slack), cos(slack) = 1 in FP32
+    const float r = fmaf(sqrtf(fmaxf(0.f, 1.f - sr * sr)), (float)kCapSlack, sr) / cb;
     if (r > 0.9f) return false;
     const float da = asinf(r);
     const float ac = atan2f(ey, ex);
@@ -282,15 +286,14 @@ __device__ __noinline__ ushort4 cap_rect_fp64(float mx, float my, float mz, floa
 // One record: depth key (always FP64: bits of fp32(D^2), D^2 without FMA)
 // and an attempt at the rectangle in FP32; false when the FP64 evaluation
 // is needed.
-__device__ __forceinline__ bool project_record_fast(const gsrf_pair &pr, const float *__restrict__ means,
-                                                    float lmaxf, int64_t g, const gsrf_grid &grid, int32_t nta,
-                                                    uint32_t *key_out, ushort4 *rect) {
-  const double ex = (double)means[3 * g + 0] - (double)pr.rx[0];
-  const double ey = (double)means[3 * g + 1] - (double)pr.rx[1];
-  const double ez = (double)means[3 * g + 2] - (double)pr.rx[2];
+__device__ __forceinline__ bool project_record_fast(const gsrf_pair &pr, float4 mu, float Rb, const gsrf_grid &grid,
+                                                    int32_t nta, uint32_t *key_out, ushort4 *rect) {
+  const double ex = (double)mu.x - (double)pr.rx[0];
+  const double ey = (double)mu.y - (double)pr.rx[1];
+  const double ez = (double)mu.z - (double)pr.rx[2];
   const double D2 = (ex * ex + ey * ey) + ez * ez;
   *key_out = __float_as_uint((float)D2);
-  return cap_rect_fp32((float)ex, (float)ey, (float)ez, sqrtf((float)D2), 3.0f * expf(lmaxf), grid, nta, rect);
+  return cap_rect_fp32((float)ex, (float)ey, (float)ez, sqrtf((float)D2), Rb, grid, nta, rect);
 }
 
 // Workgroup = RB consecutive records of one pair; per-tile counts gathered
@@ -303,8 +306,8 @@ __device__ __forceinline__ bool project_record_fast(const gsrf_pair &pr, const f
 template <int RB>
 __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pairs,
                                                  const int64_t *__restrict__ scene_off,
-                                                 const int64_t *__restrict__ rec_base, const float *__restrict__ means,
-                                                 const float *__restrict__ log_scales, gsrf_grid grid, int32_t nta,
+                                                 const int64_t *__restrict__ rec_base, const float *__restrict__ prep,
+                                                 gsrf_grid grid, int32_t nta,
                                                  int32_t T, int64_t PT, int sub_shift, uint32_t *__restrict__ rec_key,
                                                  ushort4 *__restrict__ rec_rect, uint32_t *__restrict__ tile_cnt) {
   extern __shared__ uint32_t hist[];   // [T]
@@ -324,9 +327,8 @@ __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pa
   ushort4 rc = make_ushort4(0, 0, 0, 0);
   if (j < n) {
     uint32_t key;
-    const int64_t g = g0 + j;
-    if (!project_record_fast(pr, means, fmaxf(fmaxf(log_scales[3 * g], log_scales[3 * g + 1]), log_scales[3 * g + 2]),
-                             g, grid, nta, &key, &rc))
+    const float4 *pg = (const float4 *)(prep + (size_t)kPrep * (g0 + j));   // (mu, N) ... (3 max s, max log s)
+    if (!project_record_fast(pr, pg[0], pg[3].x, grid, nta, &key, &rc))
       fallback[atomicAdd(&n_fallback, 1)] = threadIdx.x;
     rec_key[rec_base[k] + j] = key;
   }
@@ -335,10 +337,9 @@ __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pa
   // records the FP32 evaluation could not decide, packed onto the first lanes
   for (int i = threadIdx.x; i < n_fallback; i += RB) {
     const int slot = fallback[i];
-    const int64_t g = g0 + j0 + slot;
-    rects[slot] = cap_rect_fp64(means[3 * g], means[3 * g + 1], means[3 * g + 2], pr.rx[0], pr.rx[1], pr.rx[2],
-                                fmaxf(fmaxf(log_scales[3 * g], log_scales[3 * g + 1]), log_scales[3 * g + 2]),
-                                grid.n_az, grid.n_el, grid.el_lo, grid.el_hi, grid.r_rx, grid.tile_w, grid.tile_h, nta);
+    const float *pg = prep + (size_t)kPrep * (g0 + j0 + slot);
+    rects[slot] = cap_rect_fp64(pg[0], pg[1], pg[2], pr.rx[0], pr.rx[1], pr.rx[2], pg[13], grid.n_az, grid.n_el,
+                                grid.el_lo, grid.el_hi, grid.r_rx, grid.tile_w, grid.tile_h, nta);
   }
   __syncthreads();
   rc = rects[threadIdx.x];
@@ -502,7 +503,7 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
     const int sub_shift = lay.rec_block == 1024 ? 2 : 0;   // emit's workgroup = 256 << sub_shift records
     dim3 grid((unsigned)((lay.max_scene + 255) / 256), (unsigned)p->n_pairs);
     hipLaunchKernelGGL(k_project<256>, grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev, rec_base,
-                       p->means, p->log_scales, p->grid, lay.nta, lay.T, PT, sub_shift, (uint32_t *)(ws + lay.rec_key),
+                       (const float *)prep, p->grid, lay.nta, lay.T, PT, sub_shift, (uint32_t *)(ws + lay.rec_key),
                        (ushort4 *)(ws + lay.rec_rect), tile_cnt);
   }
   int64_t *blk = (int64_t *)(ws + lay.scan_blk);

@@ -50,10 +50,9 @@ struct TpIO {
   int acc_stride;
 };
 
-// BCAP: largest staged batch.  Smaller batches waste fewer tests past the
-// rays' termination (the last batch is tested whole), larger ones need fewer
-// barriers: the forward uses 128, the adjoint 64 when the launch has few
-// workgroups (latency-bound) and 128 otherwise.
+// BCAP: largest staged batch (128).  Smaller batches waste fewer tests past
+// the rays' termination (the last batch is tested whole), larger ones need
+// fewer barriers.
 template <int L, int R, int MODE, int BCAP>
 struct TpShape {
   static constexpr bool BWD = MODE == kTpBwd;
@@ -414,10 +413,9 @@ hipError_t tp_launch(const RenderArgs &a, const TpIO &io, int64_t nblocks, hipSt
   return hipGetLastError();
 }
 
-// Workgroups below which a launch counts as latency-bound: the adjoint then
-// stages smaller batches, and the forward splits tiles of 64 rays or more in
-// two (the adjoint, with more registers per thread, would not fit the extra
-// workgroups on the chip at once).
+// Workgroups below which a launch counts as latency-bound: the forward then
+// splits tiles of 64 rays or more in two (the adjoint, with more registers per
+// thread, would not fit the extra workgroups on the chip at once).
 constexpr int64_t kFewBlocks = 2048;
 
 // Workgroups per tile of the two-phase forward (1 or 2) for a launch over
@@ -426,16 +424,7 @@ inline int tp_split(int area, int64_t tiles) { return (area >= 64 && tiles <= kF
 
 template <int L, int MODE>
 hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
-  if constexpr (MODE == kTpBwd) {
-    if (nblocks <= kFewBlocks) {
-      switch (area) {
-        case 32: return tp_launch<L, 32, MODE, 64, 1>(a, io, nblocks, s);
-        case 64: return tp_launch<L, 64, MODE, 64, 1>(a, io, nblocks, s);
-        case 128: return tp_launch<L, 128, MODE, 64, 1>(a, io, nblocks, s);
-        default: return tp_launch<L, 256, MODE, 64, 1>(a, io, nblocks, s);
-      }
-    }
-  } else {
+  if constexpr (MODE != kTpBwd) {
     if (tp_split(area, nblocks) == 2) {
       switch (area) {
         case 64: return tp_launch<L, 32, MODE, 128, 2>(a, io, nblocks, s);
