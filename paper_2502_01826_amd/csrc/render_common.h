@@ -423,6 +423,70 @@ __device__ __forceinline__ void hit_adjoint(const Terms &h, const float4 *geo, f
   c[SLOT_T] = gt_;       // dL/dt; TX leg applied at the flush
 }
 
+// The same contributions in parts of 16 slots, for a caller that reduces each
+// part before forming the next (fewer values live at once): adj_hit forms the
+// per-hit scalars, adj_slot<K>(s) slot s from them (s a compile-time index
+// after unrolling).  A zero AdjHit gives zero in every slot.
+struct AdjHit {
+  float gQ, gtA, gt, px, py, pz, qx, qy, qz, w0, w1, w2, dN, dO, dpr, dpi;
+};
+
+__device__ __forceinline__ AdjHit adj_hit(const Terms &h, const float4 *geo, float Tj, float ctr, float cti, float Rr,
+                                          float Ri, float Gr, float Gi, float vx, float vy, float vz,
+                                          float twopi_lam) {
+  AdjHit a;
+  const float dLdp = Tj * fmaf(Gr, h.pzr, Gi * h.pzi);
+  const float dLdphi = Tj * fmaf(Gr, cti, -(Gi * ctr));
+  const float dLda = h.clamped ? 0.f : -fmaf(Gr, Rr, Gi * Ri) / (1.0f - h.alpha);
+  const float4 g0 = geo[0], g3 = geo[3];
+  const float D = g0.w;
+  const float dLdG = fmaf(dLdp, g3.z, dLda * g3.w);
+  a.gQ = -0.5f * h.G * dLdG;
+  a.gt = dLdphi * twopi_lam;
+  a.gtA = a.gt * h.rA;
+  a.px = D * fmaf(-h.bA, vx, h.ex);
+  a.py = D * fmaf(-h.bA, vy, h.ey);
+  a.pz = D * fmaf(-h.bA, vz, h.ez);
+  a.qx = D * fmaf(-h.bA, h.w0, h.m0);
+  a.qy = D * fmaf(-h.bA, h.w1, h.m1);
+  a.qz = D * fmaf(-h.bA, h.w2, h.m2);
+  a.w0 = h.w0;
+  a.w1 = h.w1;
+  a.w2 = h.w2;
+  a.dN = dLdp * h.G;
+  a.dO = dLda * h.G;
+  const float Tp = Tj * h.p;
+  a.dpr = Tp * fmaf(Gr, h.cs, -(Gi * h.sn));
+  a.dpi = Tp * fmaf(Gi, h.cs, Gr * h.sn);
+  return a;
+}
+
+template <int K>
+__device__ __forceinline__ float adj_slot(int s, const AdjHit &a, float vx, float vy, float vz, const float *Yr,
+                                          const float *Yi) {
+  constexpr int SLOT_T = 11 + 2 * K;
+  switch (s) {
+    case 0: return fmaf(a.gQ * a.px, a.px, -(a.gtA * vx * a.px));
+    case 1: return fmaf(a.gQ * a.py, a.py, -(a.gtA * vy * a.py));
+    case 2: return fmaf(a.gQ * a.pz, a.pz, -(a.gtA * vz * a.pz));
+    case 3: return fmaf(a.gQ * a.px, a.py, -0.5f * a.gtA * fmaf(vx, a.py, a.px * vy));
+    case 4: return fmaf(a.gQ * a.px, a.pz, -0.5f * a.gtA * fmaf(vx, a.pz, a.px * vz));
+    case 5: return fmaf(a.gQ * a.py, a.pz, -0.5f * a.gtA * fmaf(vy, a.pz, a.py * vz));
+    case 6: return fmaf(-2.0f * a.gQ, a.qx, a.gtA * a.w0);
+    case 7: return fmaf(-2.0f * a.gQ, a.qy, a.gtA * a.w1);
+    case 8: return fmaf(-2.0f * a.gQ, a.qz, a.gtA * a.w2);
+    case 9: return a.dN;
+    case 10: return a.dO;
+    default:
+      if (s == SLOT_T) return a.gt;
+      if (s > SLOT_T) return 0.f;
+      {
+        const int i = (s - 11) >> 1;
+        return ((s - 11) & 1) ? fmaf(a.dpi, Yr[i], -(a.dpr * Yi[i])) : fmaf(a.dpr, Yr[i], a.dpi * Yi[i]);
+      }
+  }
+}
+
 // Flush of a staged batch's LDS accumulators to the global accumulators
 // acc[n_gauss][S] (row stride S >= 11 + 2K floats, 64-byte aligned rows), one
 // lane per (entry, slot) so that the atomics of one wave instruction land on

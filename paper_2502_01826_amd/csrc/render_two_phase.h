@@ -331,23 +331,28 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
           T = T * total;
           done = done || (T < a.t_min);
           if (__ballot(proc) != 0) {
-            float c[NV];
-#pragma unroll
-            for (int i = 0; i < NV; ++i) c[i] = 0.f;
+            AdjHit ah{};
             if (proc) {
               const float Rr = Sfr - (Pr + wr_in), Ri = Sfi - (Pi + wi_in);
-              hit_adjoint<K, NV>(h, geo, Tj, ctr, cti, Rr, Ri, Gr, Gi, vx, vy, vz, Yr, Yi, twopi_lam, c);
+              ah = adj_hit(h, geo, Tj, ctr, cti, Rr, Ri, Gr, Gi, vx, vy, vz, twopi_lam);
               sflag[j] = 1u;
             }
-            int first_slot;
-            bool writer;
-            reduce_scatter<NV, G>(c, lane, &first_slot, &writer);
-            constexpr int NF = (NV * G >= 64) ? NV * G / 64 : 1;
-            if (writer && j >= 0) {
-              float *dst = sacc + NACC * j;
+            // the slots in parts of 16, each reduced over the wave's rays before the next is formed
+            constexpr int NF = (16 * G >= 64) ? 16 * G / 64 : 1;
+            float *dst = sacc + NACC * (j >= 0 ? j : 0);
 #pragma unroll
-              for (int i = 0; i < NF; ++i)
-                if (first_slot + i < NACC) atomicAdd(dst + first_slot + i, c[i]);
+            for (int part = 0; part < NV / 16; ++part) {
+              float c[16];
+#pragma unroll
+              for (int i = 0; i < 16; ++i) c[i] = adj_slot<K>(part * 16 + i, ah, vx, vy, vz, Yr, Yi);
+              int first_slot;
+              bool writer;
+              reduce_scatter<16, G>(c, lane, &first_slot, &writer);
+              if (writer && j >= 0) {
+#pragma unroll
+                for (int i = 0; i < NF; ++i)
+                  if (part * 16 + first_slot + i < NACC) atomicAdd(dst + part * 16 + first_slot + i, c[i]);
+              }
             }
           }
           Pr += wr_tot;
