@@ -74,6 +74,38 @@ def test_render_stats_counts_match_oracle(tw, th, G):
         assert st["walk_slots"] == 0
 
 
+@pytest.mark.parametrize("n_pairs", [1, 12])
+def test_capacity_overflow_renders_nothing_then_recovers(n_pairs):
+    """A splat capacity below the count: gsrf_splat_count reports it, bin_sort
+    emits nothing and every tile range is empty (zero signal, overflow flag
+    set); with the capacity grown the same problem matches the oracle.  One
+    pair of 36x9 rays takes the one-launch tile scan; 12 pairs of 360x90 rays
+    (6480 tiles) the three-launch scan and the two-kernel sort."""
+    g = Grid(n_az=360, n_el=90, fle_L=2, tile_w=8, tile_h=8, lanes_per_ray=0) if n_pairs > 1 else \
+        Grid(n_az=36, n_el=9, fle_L=2, tile_w=8, tile_h=8, lanes_per_ray=0)
+    b = synth.batched(n=3000, n_pairs=n_pairs, grid=g) if n_pairs > 1 else synth.tiny(grid=g)
+    say("capacity overflow, pairs", n_pairs)
+    prob = gpu_problem(b, cap=64)
+    prob.project()
+    n, ok = prob.splat_count()
+    assert not ok and n > 64
+    prob.bin_sort()
+    sig, ssum, _ = prob.render_fwd()
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(sig).item() == 0 and torch.count_nonzero(ssum).item() == 0
+    L = gpu_lists(prob)
+    assert L["overflow"] == n and np.all(L["ts"] == 0) and np.all(L["te"] == 0)
+    prob.cap = n
+    prob._alloc()
+    S, _, _ = gpu_forward(prob)
+    sc, p = b.scenes[0], b.pairs[0]
+    if n_pairs == 1:
+        compare_rays(S[0].ravel(), oracle.render(sc, p, g), sc, p, g)
+    else:
+        uv = np.stack([np.arange(0, 360, 15), np.arange(0, 90, 90 // 24)[:24]], 1)
+        compare_rays(S[0][uv[:, 1], uv[:, 0]], oracle.trace(sc, p, g, uv), sc, p, g)
+
+
 def test_forward_is_deterministic():
     b = synth.tiny()
     prob = gpu_problem(b)
