@@ -3,9 +3,12 @@
 
 A step is one pass of the whole path over one TX/RX pair of a 200k-Gaussian
 synthetic room at 360x90 rays and 5 GHz: activation + splatting
-(gsrf_project), binning + radix sort (gsrf_bin_sort), complex rendering +
+(gsrf_project), binning + per-tile sort (gsrf_bin_sort), complex rendering +
 RSSI (gsrf_render_fwd) and the adjoint + chain rule (gsrf_render_bwd) with a
 seeded upstream gradient.  Inputs are resident in HBM before timing starts.
+The headline rate replays the step captured once as a hipGraph (the way a
+training loop over a fixed-shape problem runs it: the same kernels, launched
+without host round trips); the rate of eager launches is reported beside it.
 
 Prints one JSON line (rank 0).  Extra fields report the forward-only rate,
 the two batched workloads -- 256 pairs over one 500k-Gaussian room (forward)
@@ -242,12 +245,28 @@ def main() -> int:
         prob, bufs = make([pair])
         ev = {k: [new_event() for _ in range(args.steps)] for k in ("f0", "f1", "b0", "b1", "s0", "s1")}
         torch.cuda.synchronize()
-        t_step = timed(prob, bufs, args.steps, args.warmup, True, ev)
+        t_eager = timed(prob, bufs, args.steps, args.warmup, True, ev)
         t_fwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["f0"], ev["f1"])) / args.steps * 1e-3
         t_bwd_k = sum(a.elapsed_time(b) for a, b in zip(ev["b0"], ev["b1"])) / args.steps * 1e-3
         steps_ms = sorted(a.elapsed_time(b) for a, b in zip(ev["s0"], ev["s1"]))
         q = lambda f: steps_ms[min(len(steps_ms) - 1, int(round(f * (len(steps_ms) - 1))))]
-        step_stats.update(median=q(0.5), p10=q(0.1), p90=q(0.9))
+        eager.update(ms_per_step=t_eager * 1e3, spectra_per_s=1.0 / t_eager,
+                     step_ms_events={"median": q(0.5), "p10": q(0.1), "p90": q(0.9)})
+        # the same step captured once and replayed: W untimed replays, then K
+        # back-to-back replays bracketed by synchronisation
+        from paper_2502_01826_amd.batch import GraphStep
+        gstep = GraphStep(prob, grad=True, grad_signal=bufs["G"], grad_sum=bufs["gsum"])
+        for _ in range(args.warmup):
+            gstep.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gstep.replay()
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t0) / args.steps
+        gst = gstep.time_stats(iters=args.steps, warmup=1)
+        step_stats.update(median=gst["median"] * 1e3, p10=gst["p10"] * 1e3, p90=gst["p90"] * 1e3)
+        del gstep
         t_fwd_only = timed(prob, bufs, args.steps, 1, False)
         stats = prob.render_stats()
         n_splats, _ = prob.splat_count()
@@ -271,6 +290,7 @@ def main() -> int:
         return t_step, t_fwd_only, t_fwd_k, t_bwd_k, roof
 
     step_stats = {}
+    eager = {}
     work = set(args.workloads.split(","))
     # ---- plain: one pair per launch sequence (the headline step) -------------
     t_step = t_fwd_only = t_fwd_k = t_bwd_k = None
@@ -318,7 +338,9 @@ def main() -> int:
                                "pair, 360x90 rays, 5 GHz, FLE L=2; project+bin_sort+render_fwd+render_bwd",
                    "gaussians": args.gaussians, "rays": "360x90", "pairs": 1, "tile": args.tile,
                    "lanes_per_ray": args.lanes},
+        "step_timing": "hipGraph replays of the captured step (project, bin_sort, render_fwd, render_bwd)",
         "step_ms_events": step_stats or None,
+        "eager": eager or None,
         "fwd_only": None if t_fwd_only is None else {"spectra_per_s": 1.0 / t_fwd_only, "ms": t_fwd_only * 1e3},
         "kernels_ms": None if t_fwd_k is None else {"render_fwd": t_fwd_k * 1e3, "render_bwd": t_bwd_k * 1e3},
         "batched": batched,

@@ -429,7 +429,7 @@ inline int tp_split(int area, int64_t tiles) { return (area >= 64 && tiles <= kF
 
 template <int L, int MODE>
 hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
-  if constexpr (MODE != kTpBwd) {
+  if constexpr (MODE == kTpFwd) {   // (the counters follow whole tiles, as the adjoint does)
     if (tp_split(area, nblocks) == 2) {
       switch (area) {
         case 64: return tp_launch<L, 32, MODE, 128, 2>(a, io, nblocks, s);
