@@ -196,6 +196,24 @@ gsrf_status gsrf_render_fwd(const gsrf_problem *p, float *signal, float *signal_
                             void *stream);
 
 /*
+ * Multi-carrier forward (OFDM subcarriers, the 5G CSI synthesis of Sec. 4;
+ * each path's phase is 2 pi f tau, Sec. 2): the render of gsrf_render_fwd for
+ * n_freq carriers per pair, carrier c of pair k at
+ * pairs[k].freq_hz + c * freq_step_hz.  Hit decisions, transmittance, N G and
+ * psi do not depend on the carrier, so one traversal serves up to 16
+ * carriers and the propagation phase is the only per-carrier term.
+ *   n_freq        1 .. 4096 carriers per pair
+ *   freq_step_hz  carrier spacing, >= 0 (Hz)
+ *   signal        [P, n_freq, n_el, n_az, 2]  complex received signal (re, im)
+ *   signal_sum    [P, n_freq, 2]              S_hat per pair and carrier
+ * Needs lanes_per_ray = 0 (GSRF_ENOTSUP otherwise).  Follows gsrf_bin_sort
+ * like gsrf_render_fwd; it leaves the forward's hit masks untouched, so it
+ * may sit between gsrf_render_fwd and gsrf_render_bwd.  Deterministic.
+ */
+gsrf_status gsrf_render_fwd_multi(const gsrf_problem *p, int32_t n_freq, double freq_step_hz, float *signal,
+                                  float *signal_sum, void *stream);
+
+/*
  * Steps a7 + a8 (App. C backward kernel; App. D gradients, including the
  * covariance chain the paper omits): recomputes each ray's transmittance
  * front to back (no per-ray state is stored by render_fwd beyond `signal`)

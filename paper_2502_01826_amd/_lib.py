@@ -48,7 +48,8 @@ class GsrfLayout(ctypes.Structure):
 assert ctypes.sizeof(GsrfPair) == 40
 
 EXPORTS = ["gsrf_status_str", "gsrf_last_error", "gsrf_workspace_size", "gsrf_layout_of", "gsrf_project",
-           "gsrf_splat_count", "gsrf_bin_sort", "gsrf_render_fwd", "gsrf_render_bwd", "gsrf_render_stats",
+           "gsrf_splat_count", "gsrf_bin_sort", "gsrf_render_fwd", "gsrf_render_fwd_multi", "gsrf_render_bwd",
+           "gsrf_render_stats",
            "gsrf_set_kernel_events"]
 
 _lib = None
@@ -75,6 +76,7 @@ def lib() -> ctypes.CDLL:
     L.gsrf_render_fwd.argtypes = [P(GsrfProblem), c_vp, c_vp, c_vp, c_vp]
     L.gsrf_render_bwd.argtypes = [P(GsrfProblem), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]
     L.gsrf_render_stats.argtypes = [P(GsrfProblem), c_vp, c_vp]
+    L.gsrf_render_fwd_multi.argtypes = [P(GsrfProblem), c_i32, c_f64, c_vp, c_vp, c_vp]
     L.gsrf_set_kernel_events.argtypes = [c_vp, c_vp, c_vp, c_vp]
     for n in EXPORTS[2:]:
         getattr(L, n).restype = c_i32

@@ -216,6 +216,22 @@ gsrf_status gsrf_render_fwd(const gsrf_problem *p, float *signal, float *signal_
              "gsrf_render_fwd");
 }
 
+gsrf_status gsrf_render_fwd_multi(const gsrf_problem *p, int32_t n_freq, double freq_step_hz, float *signal,
+                                  float *signal_sum, void *stream) {
+  if (!p) return fail(GSRF_EINVAL, "problem is NULL");
+  if (n_freq < 1 || n_freq > kMaxCarriers) return fail(GSRF_EINVAL, "n_freq = %d outside [1, %d]", n_freq, kMaxCarriers);
+  if (!(freq_step_hz >= 0.0) || !(freq_step_hz < 1e12)) return fail(GSRF_EINVAL, "freq_step_hz = %g", freq_step_hz);
+  if (p->grid.lanes_per_ray != 0)
+    return fail(GSRF_ENOTSUP, "the multi-carrier forward uses the two-phase traversal (lanes_per_ray = 0)");
+  Layout L;
+  gsrf_status st = plan(p, &L, true);
+  if (st != GSRF_OK) return st;
+  if (p->n_pairs > 0 && (!signal || !signal_sum)) return fail(GSRF_EINVAL, "signal or signal_sum is NULL");
+  return dev(launch_render_fwd_multi(p, L, (char *)p->workspace, n_freq, freq_step_hz, signal, signal_sum,
+                                     (hipStream_t)stream),
+             "gsrf_render_fwd_multi");
+}
+
 gsrf_status gsrf_render_bwd(const gsrf_problem *p, const float *signal, const float *grad_signal,
                             const float *grad_sum, float *d_means, float *d_log_scales, float *d_quats,
                             float *d_logits, float *d_coeffs, void *stream) {

@@ -24,6 +24,7 @@ constexpr int kPrep = 16;
 // LDS for buckets of at most `sort_chunk` entries, else through global scratch.
 constexpr int kTileSortThreads = 1024;
 constexpr int kMaxTiles = 8192;           // per pair; LDS histograms in project/emit
+constexpr int kMaxCarriers = 4096;        // carriers of one multi-carrier forward
 // Records per workgroup in emit: 256, or 1024 for large batches (fewer
 // workgroups per tile means fewer global cursor atomics per record); project
 // always uses 256 and counts into the sub-bucket of emit's workgroup.
@@ -131,6 +132,8 @@ hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, h
 hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws, float *signal,
                              float *signal_sum, float *rssi_dbm, hipStream_t s);
 hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *ws, int64_t *counts, hipStream_t s);
+hipError_t launch_render_fwd_multi(const gsrf_problem *p, const Layout &lay, char *ws, int32_t n_freq, double f_step,
+                                   float *signal, float *signal_sum, hipStream_t s);
 hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws, const float *signal,
                              const float *grad_signal, const float *grad_sum, float *d_means,
                              float *d_log_scales, float *d_quats, float *d_logits, float *d_coeffs,

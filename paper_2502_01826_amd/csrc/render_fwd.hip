@@ -239,6 +239,64 @@ hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws,
   return hipGetLastError();
 }
 
+// S_hat of every (pair, carrier) of a multi-carrier render: one workgroup sums
+// the carrier's spectrum in FP64 in a fixed order.
+__global__ __launch_bounds__(256) void k_sum_multi(const float2 *__restrict__ multi, int64_t n_rays, int n_freq,
+                                                   float *__restrict__ signal_sum) {
+  __shared__ double sr[256], si[256];
+  const int f = blockIdx.x, k = blockIdx.y;
+  const float2 *src = multi + ((size_t)k * n_freq + f) * n_rays;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < n_rays; i += 256) {
+    const float2 x = src[i];
+    a += x.x;
+    b += x.y;
+  }
+  sr[threadIdx.x] = a;
+  si[threadIdx.x] = b;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      sr[threadIdx.x] += sr[threadIdx.x + off];
+      si[threadIdx.x] += si[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    signal_sum[2 * ((size_t)k * n_freq + f)] = (float)sr[0];
+    signal_sum[2 * ((size_t)k * n_freq + f) + 1] = (float)si[0];
+  }
+}
+
+hipError_t launch_render_fwd_multi(const gsrf_problem *p, const Layout &lay, char *ws, int32_t n_freq, double f_step,
+                                   float *signal, float *signal_sum, hipStream_t s) {
+  if (p->n_pairs == 0 || n_freq == 0) return hipSuccess;
+  const RenderArgs a = make_render_args(p, lay, ws);
+  const int64_t nblocks = (int64_t)p->n_pairs * lay.T;
+  const int area = p->grid.tile_w * p->grid.tile_h;
+  TpIO io{};
+  io.multi = (float2 *)signal;
+  io.n_freq = n_freq;
+  io.f_step = f_step;
+  hipError_t e = hipSuccess;
+  for (int f0 = 0; f0 < n_freq && e == hipSuccess; f0 += kMultiChunk) {   // one traversal per chunk of carriers
+    io.f_first = f0;
+    switch (p->grid.fle_L) {
+      case 0: e = tp_dispatch<0, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 1: e = tp_dispatch<1, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 2: e = tp_dispatch<2, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 3: e = tp_dispatch<3, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 4: e = tp_dispatch<4, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 5: e = tp_dispatch<5, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      default: e = tp_dispatch<6, kTpFwdMulti>(area, a, io, nblocks, s); break;
+    }
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_multi, dim3((unsigned)n_freq, (unsigned)p->n_pairs), dim3(256), 0, s,
+                     (const float2 *)signal, (int64_t)p->grid.n_el * p->grid.n_az, n_freq, signal_sum);
+  return hipGetLastError();
+}
+
 hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *ws, int64_t *counts, hipStream_t s) {
   hipError_t e = fill<int64_t>(counts, 0, 6, s);
   if (e != hipSuccess || p->n_pairs == 0) return e;

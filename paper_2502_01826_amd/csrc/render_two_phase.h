@@ -30,7 +30,13 @@
 
 namespace gsrf {
 
-enum TpMode { kTpFwd = 0, kTpFwdStats = 1, kTpBwd = 2 };
+// kTpFwdMulti: the forward for kMultiChunk carriers f_c = f_0 + c * step at
+// once (OFDM subcarriers; Sec. 4 5G CSI synthesis): hit decisions, alpha, p and
+// psi do not depend on the carrier, only the propagation phase does, so one
+// traversal accumulates every carrier (the phase factor of carrier c + 1 is
+// that of carrier c times the step's).
+enum TpMode { kTpFwd = 0, kTpFwdStats = 1, kTpBwd = 2, kTpFwdMulti = 3 };
+constexpr int kMultiChunk = 16;
 
 template <int R>
 struct TwoPhase {
@@ -44,6 +50,9 @@ struct TpIO {
   float2 *signal;                 // forward output S [P, n_el, n_az]; read by the adjoint
   float2 *tile_sum;               // forward: per-(pair, tile) partial of S_hat
   unsigned long long *stats;      // forward with counters: tests, hits, staged, rays, tile tests, walk slots
+  float2 *multi;                  // multi-carrier: S [P, n_freq, n_el, n_az]
+  int n_freq, f_first;            // multi-carrier: carriers in all, first carrier of this launch
+  double f_step;                  // multi-carrier: carrier step (Hz)
   const float2 *grad_signal;      // adjoint: dL/dS
   const float2 *grad_sum;         // adjoint: dL/dS_hat per pair, or null
   float *acc;                     // adjoint accumulators [n_gauss][acc_stride]
@@ -152,7 +161,8 @@ template <int L, int R, int MODE, int BCAP, int SPLIT>
 __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   using TP = TwoPhase<R>;
   using SH = TpShape<L, R, MODE, BCAP>;
-  constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats;
+  constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats, MULTI = MODE == kTpFwdMulti;
+  constexpr int FC = MULTI ? kMultiChunk : 1;
   constexpr int NT = TP::NT, G = TP::G, EP = TP::EP, RPW = TP::RPW;
   constexpr int K = SH::K, B = SH::B, NACC = SH::NACC, MW = SH::MW, MWS = SH::MWS;
   constexpr int NV = pow2_at_least(NACC);
@@ -183,7 +193,13 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   const int u1 = tu * a.tw + r1 % a.tw, v1 = v0 + r1 / a.tw;
   const bool valid1 = (u1 < a.n_az) && (v1 < a.n_el);
   const gsrf_pair pr = a.pairs[k];
-  const double lam = kC0 / pr.freq_hz, inv_lam = pr.freq_hz / kC0;
+  // (multi-carrier: the launch's first carrier)
+  const double freq = MULTI ? pr.freq_hz + io.f_first * io.f_step : pr.freq_hz;
+  const double lam = kC0 / freq, inv_lam = freq / kC0;
+  const double step_rev = MULTI ? io.f_step / kC0 : 0.0;
+  float mr[FC], mi[FC];   // multi-carrier accumulators
+#pragma unroll
+  for (int c = 0; c < FC; ++c) mr[c] = mi[c] = 0.f;
   float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
   ray_load<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
   RayMono w1;
@@ -223,7 +239,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     __syncthreads();
     if (tid < nb)
       stage_entry<K>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
-                     sgeo + kGeo * tid, scf + 2 * K * tid, BWD ? stx + tid : nullptr);
+                     sgeo + kGeo * tid, scf + 2 * K * tid, BWD ? stx + tid : nullptr, step_rev);
     if constexpr (BWD)
       for (int i = tid; i < nb; i += NT) {   // what the previous batch's flush left
         sflag[i] = 0u;
@@ -320,6 +336,22 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
             Sr = fmaf(Tj, ctr, Sr);
             Si = fmaf(Tj, cti, Si);
             if (STATS) ++n_hit;
+            if constexpr (MULTI) {
+              // carrier c: p psi e^{-j phi_c}, phi_{c+1} = phi_c + 2 pi (|mu - tx| + t) step / c0
+              float sns, css;
+              const float4 g4 = geo[4];
+              sincos_rev(fmaf(-h.bA, g4.w, g4.z), sns, css);
+              const float w = Tj * h.p;
+              float zr = h.pzr, zi = h.pzi;
+#pragma unroll
+              for (int c = 0; c < FC; ++c) {
+                mr[c] = fmaf(w, zr, mr[c]);
+                mi[c] = fmaf(w, zi, mi[c]);
+                const float nr = fmaf(zr, css, zi * sns), ni = fmaf(zi, css, -(zr * sns));
+                zr = nr;
+                zi = ni;
+              }
+            }
           }
           T = T * total;
           done = done || (T < a.t_min);
@@ -385,6 +417,23 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       if (lane == 0 && n_steps) atomicAdd(io.stats + 5, 64ull * n_steps);
       return;
     }
+    if constexpr (MULTI) {   // the ray's carriers, summed over its G lanes
+      const int nc = min(FC, io.n_freq - io.f_first);
+#pragma unroll
+      for (int c = 0; c < FC; ++c) {
+        float xr = mr[c], xi = mi[c];
+        if constexpr (G > 1) {
+#pragma unroll
+          for (int d = 1; d < G; d <<= 1) {
+            xr += __shfl_xor(xr, d, G);
+            xi += __shfl_xor(xi, d, G);
+          }
+        }
+        if (valid && q == 0 && c < nc)
+          io.multi[(((size_t)k * io.n_freq + io.f_first + c) * a.n_el + v) * a.n_az + u] = make_float2(xr, xi);
+      }
+      return;
+    }
     if (valid && q == 0) io.signal[((size_t)k * a.n_el + v) * a.n_az + u] = make_float2(Sr, Si);
     // tile partial of S_hat in a fixed order: each wave's rays by a butterfly,
     // then the four wave totals in wave order
@@ -429,7 +478,7 @@ inline int tp_split(int area, int64_t tiles) { return (area >= 64 && tiles <= kF
 
 template <int L, int MODE>
 hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
-  if constexpr (MODE == kTpFwd) {   // (the counters follow whole tiles, as the adjoint does)
+  if constexpr (MODE == kTpFwd || MODE == kTpFwdMulti) {   // (the counters follow whole tiles, as the adjoint does)
     if (tp_split(area, nblocks) == 2) {
       switch (area) {
         case 64: return tp_launch<L, 32, MODE, 128, 2>(a, io, nblocks, s);

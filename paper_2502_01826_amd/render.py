@@ -174,6 +174,19 @@ class Problem:
                                          rssi.data_ptr(), _stream_handle(stream)), "gsrf_render_fwd")
         return signal, signal_sum, rssi
 
+    def render_fwd_multi(self, n_freq: int, freq_step_hz: float, signal=None, signal_sum=None, stream=None):
+        """Forward for n_freq carriers per pair (carrier c at pair frequency + c * freq_step_hz):
+        signal [P, n_freq, n_el, n_az, 2], signal_sum [P, n_freq, 2]."""
+        g, P = self.grid, self.n_pairs
+        if signal is None:
+            signal = torch.empty((P, n_freq, g.n_el, g.n_az, 2), dtype=torch.float32, device=self.device)
+        if signal_sum is None:
+            signal_sum = torch.empty((P, n_freq, 2), dtype=torch.float32, device=self.device)
+        check(_lib.lib().gsrf_render_fwd_multi(ctypes.byref(self._problem()), int(n_freq), float(freq_step_hz),
+                                               signal.data_ptr(), signal_sum.data_ptr(), _stream_handle(stream)),
+              "gsrf_render_fwd_multi")
+        return signal, signal_sum
+
     def render_bwd(self, signal, grad_signal, grad_sum=None, out=None, stream=None):
         G, K = self.n_gauss, self.grid.K
         if out is None:

@@ -137,6 +137,20 @@ def test_entry_points_reject_missing_device_pointers_without_launching():
     assert L.gsrf_status_str(2) == b"GSRF_ECAPACITY"
 
 
+def test_multi_carrier_forward_validates_before_launching():
+    L = _lib.lib()
+    p, keep = _host_problem()
+    assert L.gsrf_render_fwd_multi(ctypes.byref(p), 0, 1e6, None, None, None) == _lib.GSRF_EINVAL
+    assert "n_freq" in L.gsrf_last_error().decode()
+    assert L.gsrf_render_fwd_multi(ctypes.byref(p), 4, -1.0, None, None, None) == _lib.GSRF_EINVAL
+    assert "freq_step" in L.gsrf_last_error().decode()
+    p.grid.lanes_per_ray = 2
+    assert L.gsrf_render_fwd_multi(ctypes.byref(p), 4, 1e6, None, None, None) == _lib.GSRF_ENOTSUP
+    p.grid.lanes_per_ray = 0
+    # valid request, but no device workspace: refused on the host
+    assert L.gsrf_render_fwd_multi(ctypes.byref(p), 4, 1e6, None, None, None) == _lib.GSRF_EINVAL
+
+
 def test_pair_packing_matches_struct():
     from paper_2502_01826_amd import pack_pairs
     import synth
