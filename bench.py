@@ -13,7 +13,8 @@ without host round trips); the rate of eager launches is reported beside it.
 Prints one JSON line (rank 0).  Extra fields report the forward-only rate,
 the two batched workloads -- 256 pairs over one 500k-Gaussian room (forward)
 and 16 scenes of 20k-1M Gaussians with 8-64 pairs each (forward + adjoint) --
-each as hipGraph replays with an autotuned tile shape, the roofline of the
+each as hipGraph replays with an autotuned tile shape, the multi-carrier
+forward (26 carriers of one OFDM block per pass), the roofline of the
 dominant kernel of each workload and the FP64 oracle timed on the host's
 cores.  ``--workloads`` restricts the run (profiling).
 """
@@ -48,6 +49,14 @@ def flops_per(K: int) -> dict:
           = 107 + 8K
     """
     return dict(test=60.0, hit_fwd=52.0 + 8 * K, hit_bwd=52.0 + 8 * K + 107.0 + 8 * K)
+
+
+def flops_multi(K: int, n_freq: int, chunks: int, tile_tests: int, hits: int) -> float:
+    """Algorithmic FP32 FLOPs of the multi-carrier forward: per traversal (one
+    per chunk of carriers) the tile tests and the single-carrier hit work plus
+    the step phasor (fma 2 + sincos 30 + weight 1 = 33); per hit and carrier
+    the two accumulating FMAs (4) and the phasor rotation (6) = 10."""
+    return chunks * tile_tests * 60.0 + hits * (chunks * (52.0 + 8 * K + 33.0) + 10.0 * n_freq)
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "render_traffic.json")
@@ -103,8 +112,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batched", choices=("full", "small", "none"), default="full",
                     help="batched workloads: full (256 pairs x 500k; 16 uneven scenes), small, or none")
-    ap.add_argument("--workloads", default="plain,fwd_500k,uneven",
-                    help="comma list of plain, fwd_500k, uneven (profiling runs pick one)")
+    ap.add_argument("--workloads", default="plain,fwd_500k,uneven,multi",
+                    help="comma list of plain, fwd_500k, uneven, multi (profiling runs pick one)")
+    ap.add_argument("--carriers", type=int, default=26, help="multi-carrier workload: carriers per pair")
+    ap.add_argument("--carrier-step", type=float, default=312.5e3, help="multi-carrier workload: spacing in Hz")
     ap.add_argument("--batched-pairs", type=int, default=256)
     ap.add_argument("--batched-iters", type=int, default=50)
     ap.add_argument("--batched-warmup", type=int, default=10)
@@ -289,6 +300,61 @@ def main() -> int:
         torch.cuda.empty_cache()
         return t_step, t_fwd_only, t_fwd_k, t_bwd_k, roof
 
+    def run_multi():
+        """One pair, n carriers per render: project + bin_sort + render_fwd_multi
+        per pass (eager), against the single-carrier forward kernel of the same
+        pair repeated once per carrier."""
+        from paper_2502_01826_amd.render import multi_chunks
+        nf, df = args.carriers, args.carrier_step
+        prob, bufs = make([pair])
+        msig = torch.empty((1, nf, grid.n_el, grid.n_az, 2), dtype=torch.float32, device=dev)
+        msum = torch.empty((1, nf, 2), dtype=torch.float32, device=dev)
+        steps = args.steps
+        ev = {k: [new_event() for _ in range(steps)] for k in ("f0", "f1")}
+
+        def passes(n, with_ev):
+            for i in range(n):
+                if with_ev:
+                    _lib.lib().gsrf_set_kernel_events(ev["f0"][i].cuda_event, ev["f1"][i].cuda_event, None, None)
+                prob.project()
+                prob.bin_sort()
+                prob.render_fwd_multi(nf, df, msig, msum)
+            _lib.lib().gsrf_set_kernel_events(None, None, None, None)
+
+        passes(args.warmup, False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        passes(steps, True)
+        torch.cuda.synchronize()
+        t_pass = (time.perf_counter() - t0) / steps
+        t_mk = sum(a.elapsed_time(b) for a, b in zip(ev["f0"], ev["f1"])) / steps * 1e-3
+        # the single-carrier forward kernel of the same pair, same instrumentation
+        ev1 = {k: [new_event() for _ in range(steps)] for k in ("f0", "f1", "b0", "b1")}
+        run(prob, bufs, 1, False)
+        torch.cuda.synchronize()
+        run(prob, bufs, steps, False, ev1)
+        torch.cuda.synchronize()
+        t_1k = sum(a.elapsed_time(b) for a, b in zip(ev1["f0"], ev1["f1"])) / steps * 1e-3
+        st = prob.render_stats()
+        fl = flops_multi(grid.K, nf, len(multi_chunks(nf)), st["tile_tests"], st["hits"])
+        ach = fl / t_mk
+        del prob, bufs, msig, msum
+        torch.cuda.empty_cache()
+        return {"workload": f"multi-carrier forward: {nf} carriers {df / 1e3:g} kHz apart (one OFDM block) on the "
+                            "plain pair, 200k Gaussians, 360x90 rays",
+                "carriers": nf, "carrier_step_hz": df,
+                "carrier_spectra_per_s": nf / t_pass, "ms_per_pass": t_pass * 1e3,
+                "timing": f"{steps} eager passes (project+bin_sort+render_fwd_multi) after {args.warmup} warm-up "
+                          "passes, wall clock between synchronisations",
+                "carriers_per_traversal": multi_chunks(nf),
+                "kernel_ms": t_mk * 1e3, "single_carrier_kernel_ms": t_1k * 1e3,
+                "speedup_vs_per_carrier_kernels": nf * t_1k / t_mk,
+                "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                             "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None,
+                             "kernel": "render_fwd_multi traversals", "flop_per_launch": fl,
+                             "timing": "HIP events recorded by the library around the carrier-chunk traversals",
+                             "counts": st}}
+
     step_stats = {}
     eager = {}
     work = set(args.workloads.split(","))
@@ -317,6 +383,8 @@ def main() -> int:
                                                     max(s_.n for s_ in b5.scenes), len(b5.pairs)))
             del b5
 
+    multi = run_multi() if "multi" in work else None
+
     cpu = None
     if not args.no_cpu_baseline and "plain" in work:
         cpu = cpu_baseline(scene, pair, grid)
@@ -344,6 +412,7 @@ def main() -> int:
         "fwd_only": None if t_fwd_only is None else {"spectra_per_s": 1.0 / t_fwd_only, "ms": t_fwd_only * 1e3},
         "kernels_ms": None if t_fwd_k is None else {"render_fwd": t_fwd_k * 1e3, "render_bwd": t_bwd_k * 1e3},
         "batched": batched,
+        "multi_carrier": multi,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -200,7 +200,7 @@ gsrf_status gsrf_render_fwd(const gsrf_problem *p, float *signal, float *signal_
  * each path's phase is 2 pi f tau, Sec. 2): the render of gsrf_render_fwd for
  * n_freq carriers per pair, carrier c of pair k at
  * pairs[k].freq_hz + c * freq_step_hz.  Hit decisions, transmittance, N G and
- * psi do not depend on the carrier, so one traversal serves up to 16
+ * psi do not depend on the carrier, so one traversal serves up to 32
  * carriers and the propagation phase is the only per-carrier term.
  *   n_freq        1 .. 4096 carriers per pair
  *   freq_step_hz  carrier spacing, >= 0 (Hz)
@@ -248,7 +248,8 @@ gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stre
 /*
  * Instrumentation for kernel timing: every later gsrf_render_fwd records
  * fwd_start / fwd_stop (hipEvent_t, caller-created; NULL = none) on its stream
- * immediately before and after its render kernel, and every gsrf_render_bwd
+ * immediately before and after its render kernel (gsrf_render_fwd_multi:
+ * around all of its carrier-chunk traversals), and every gsrf_render_bwd
  * does the same with bwd_start / bwd_stop around its adjoint kernel.  The
  * setting is process-wide; pass NULLs to switch it off.  Never fails.
  */

@@ -118,7 +118,8 @@ struct Layout {
 inline int fle_K(int L) { return (L + 1) * (L + 1); }
 
 // Instrumentation events (set by gsrf_set_kernel_events): 0/1 around the
-// forward render kernel, 2/3 around the adjoint kernel.
+// forward render kernel (the multi-carrier traversals), 2/3 around the
+// adjoint kernel.
 void mark_kernel_event(int i, hipStream_t s);
 
 

@@ -279,19 +279,30 @@ hipError_t launch_render_fwd_multi(const gsrf_problem *p, const Layout &lay, cha
   io.n_freq = n_freq;
   io.f_step = f_step;
   hipError_t e = hipSuccess;
-  for (int f0 = 0; f0 < n_freq && e == hipSuccess; f0 += kMultiChunk) {   // one traversal per chunk of carriers
+  mark_kernel_event(0, s);
+  for (int f0 = 0; f0 < n_freq && e == hipSuccess;) {   // one traversal per chunk of carriers
     io.f_first = f0;
+    const bool wide = n_freq - f0 > kMultiChunk;
     switch (p->grid.fle_L) {
-      case 0: e = tp_dispatch<0, kTpFwdMulti>(area, a, io, nblocks, s); break;
-      case 1: e = tp_dispatch<1, kTpFwdMulti>(area, a, io, nblocks, s); break;
-      case 2: e = tp_dispatch<2, kTpFwdMulti>(area, a, io, nblocks, s); break;
-      case 3: e = tp_dispatch<3, kTpFwdMulti>(area, a, io, nblocks, s); break;
-      case 4: e = tp_dispatch<4, kTpFwdMulti>(area, a, io, nblocks, s); break;
-      case 5: e = tp_dispatch<5, kTpFwdMulti>(area, a, io, nblocks, s); break;
-      default: e = tp_dispatch<6, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 0: e = wide ? tp_dispatch<0, kTpFwdMultiWide>(area, a, io, nblocks, s)
+                       : tp_dispatch<0, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 1: e = wide ? tp_dispatch<1, kTpFwdMultiWide>(area, a, io, nblocks, s)
+                       : tp_dispatch<1, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 2: e = wide ? tp_dispatch<2, kTpFwdMultiWide>(area, a, io, nblocks, s)
+                       : tp_dispatch<2, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 3: e = wide ? tp_dispatch<3, kTpFwdMultiWide>(area, a, io, nblocks, s)
+                       : tp_dispatch<3, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 4: e = wide ? tp_dispatch<4, kTpFwdMultiWide>(area, a, io, nblocks, s)
+                       : tp_dispatch<4, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      case 5: e = wide ? tp_dispatch<5, kTpFwdMultiWide>(area, a, io, nblocks, s)
+                       : tp_dispatch<5, kTpFwdMulti>(area, a, io, nblocks, s); break;
+      default: e = wide ? tp_dispatch<6, kTpFwdMultiWide>(area, a, io, nblocks, s)
+                        : tp_dispatch<6, kTpFwdMulti>(area, a, io, nblocks, s); break;
     }
+    f0 += wide ? kMultiChunkWide : kMultiChunk;
   }
   if (e != hipSuccess) return e;
+  mark_kernel_event(1, s);
   hipLaunchKernelGGL(k_sum_multi, dim3((unsigned)n_freq, (unsigned)p->n_pairs), dim3(256), 0, s,
                      (const float2 *)signal, (int64_t)p->grid.n_el * p->grid.n_az, n_freq, signal_sum);
   return hipGetLastError();

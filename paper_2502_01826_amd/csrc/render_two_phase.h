@@ -30,13 +30,18 @@
 
 namespace gsrf {
 
-// kTpFwdMulti: the forward for kMultiChunk carriers f_c = f_0 + c * step at
-// once (OFDM subcarriers; Sec. 4 5G CSI synthesis): hit decisions, alpha, p and
-// psi do not depend on the carrier, only the propagation phase does, so one
-// traversal accumulates every carrier (the phase factor of carrier c + 1 is
-// that of carrier c times the step's).
-enum TpMode { kTpFwd = 0, kTpFwdStats = 1, kTpBwd = 2, kTpFwdMulti = 3 };
-constexpr int kMultiChunk = 16;
+// kTpFwdMulti / kTpFwdMultiWide: the forward for 16 / 32 carriers
+// f_c = f_0 + c * step at once (OFDM subcarriers; Sec. 4 5G CSI synthesis):
+// hit decisions, alpha, p and psi do not depend on the carrier, only the
+// propagation phase does, so one traversal accumulates every carrier (the
+// phase factor of carrier c + 1 is that of carrier c times the step's).  The
+// wide form holds twice the accumulators at half the occupancy; it pays when
+// more than 16 carriers remain.
+enum TpMode { kTpFwd = 0, kTpFwdStats = 1, kTpBwd = 2, kTpFwdMulti = 3, kTpFwdMultiWide = 4 };
+constexpr int kMultiChunk = 16, kMultiChunkWide = 32;
+constexpr int multi_chunk(int mode) {
+  return mode == kTpFwdMulti ? kMultiChunk : mode == kTpFwdMultiWide ? kMultiChunkWide : 1;
+}
 
 template <int R>
 struct TwoPhase {
@@ -161,8 +166,8 @@ template <int L, int R, int MODE, int BCAP, int SPLIT>
 __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   using TP = TwoPhase<R>;
   using SH = TpShape<L, R, MODE, BCAP>;
-  constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats, MULTI = MODE == kTpFwdMulti;
-  constexpr int FC = MULTI ? kMultiChunk : 1;
+  constexpr int FC = multi_chunk(MODE);
+  constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats, MULTI = FC > 1;
   constexpr int NT = TP::NT, G = TP::G, EP = TP::EP, RPW = TP::RPW;
   constexpr int K = SH::K, B = SH::B, NACC = SH::NACC, MW = SH::MW, MWS = SH::MWS;
   constexpr int NV = pow2_at_least(NACC);
@@ -478,7 +483,7 @@ inline int tp_split(int area, int64_t tiles) { return (area >= 64 && tiles <= kF
 
 template <int L, int MODE>
 hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
-  if constexpr (MODE == kTpFwd || MODE == kTpFwdMulti) {   // (the counters follow whole tiles, as the adjoint does)
+  if constexpr (MODE == kTpFwd || multi_chunk(MODE) > 1) {   // (the counters follow whole tiles, as the adjoint does)
     if (tp_split(area, nblocks) == 2) {
       switch (area) {
         case 64: return tp_launch<L, 32, MODE, 128, 2>(a, io, nblocks, s);

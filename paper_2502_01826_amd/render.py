@@ -20,6 +20,17 @@ from ._lib import GsrfGrid, GsrfLayout, GsrfProblem, check
 FIELDS = ("means", "log_scales", "quats", "logits", "coeffs")
 
 
+def multi_chunks(n_freq: int) -> list:
+    """Carriers per traversal of gsrf_render_fwd_multi: 32 while more than 16
+    remain, then 16 (the last chunk may be partly unused)."""
+    out, left = [], n_freq
+    while left > 0:
+        c = 32 if left > 16 else 16
+        out.append(c)
+        left -= c
+    return out
+
+
 @dataclass
 class GridSpec:
     """Receiver ray grid and render constants (mirrors ``gsrf_grid``)."""

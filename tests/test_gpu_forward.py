@@ -107,7 +107,8 @@ def test_capacity_overflow_renders_nothing_then_recovers(n_pairs):
 
 
 def test_multi_carrier_forward_matches_oracle_per_carrier():
-    """20 carriers 40 MHz apart (two traversals of 16 and 4) on the tiny room:
+    """40 carriers 40 MHz apart (two traversals: 32 carriers, then 8 in a
+    16-carrier one) on the tiny room:
     every checked carrier against the oracle rendered at that frequency, the
     per-carrier sums against the rays, carrier 0 against the one-carrier
     forward, and a repeated call bit for bit."""
@@ -116,15 +117,15 @@ def test_multi_carrier_forward_matches_oracle_per_carrier():
     sc, p = b.scenes[0], b.pairs[0]
     prob = gpu_problem(b)
     sig1, _, _ = prob.forward()
-    F, df = 20, 40e6
-    say("multi-carrier: 20 carriers, 40 MHz apart")
+    F, df = 40, 40e6
+    say("multi-carrier: 40 carriers, 40 MHz apart")
     sig, ssum = prob.render_fwd_multi(F, df)
     sig2, ssum2 = prob.render_fwd_multi(F, df)
     torch.cuda.synchronize()
     assert torch.equal(sig, sig2) and torch.equal(ssum, ssum2)
     S = torch.view_as_complex(sig).cpu().numpy().astype(np.complex128)        # [1, F, n_el, n_az]
     Ssum = torch.view_as_complex(ssum).cpu().numpy().astype(np.complex128)    # [1, F]
-    for c in (0, 1, 7, 15, 16, 19):
+    for c in (0, 1, 15, 16, 31, 32, 39):
         pc = Pair(p.rx, p.tx, p.freq_hz + c * df, p.scene)
         ref = oracle.render(sc, pc, g)
         compare_rays(S[0, c].ravel(), ref, sc, pc, g)
@@ -136,7 +137,8 @@ def test_multi_carrier_forward_matches_oracle_per_carrier():
 
 def test_multi_carrier_forward_in_a_many_tile_launch():
     """12 pairs of 360x90 rays (6480 tiles: one workgroup per tile), 3 carriers
-    5 MHz apart, sampled rays of three pairs against the oracle."""
+    5 MHz apart (one 16-carrier traversal), sampled rays of three pairs against
+    the oracle."""
     g = Grid(n_az=360, n_el=90, fle_L=2, tile_w=8, tile_h=8, lanes_per_ray=0)
     b = synth.batched(n=5000, n_pairs=12, grid=g)
     sc = b.scenes[0]
