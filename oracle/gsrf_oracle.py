@@ -23,8 +23,7 @@ Paper passages followed (arXiv 2502.01826):
   * single-antenna sum S_hat = sum_uv S_uv           -- Sec. 3.4 (loss, single antenna)
   * 64-bit splat key (tile | distance)               -- App. E (CUDA kernel paragraph)
 
-Readings taken where the paper is silent or ambiguous (each also listed in
-DESIGN.md):
+Readings taken where the paper is silent or ambiguous:
   R1  transmittance amplitude is 1 - o*G(x_mid) with o = sigmoid(logit); its
       phase is the free-space propagation term e^{-j 2 pi d / lambda}
       (App. A's continuous model with beta = 2 pi / lambda).
@@ -50,8 +49,8 @@ Parity pinning: every function here is pinned by a CPU test in
 tests/test_oracle_*.py against closed forms, library routines, the paper's
 worked example or brute force.  The FLE conventions (R10-R13), the phase
 convention (R14) and RSSI (R17) are readings: their numerical conventions are
-pinned only up to the reading (closed forms of the chosen convention), which
-DESIGN.md records as "parity unpinned by the paper".
+pinned only up to the reading (closed forms of the chosen convention): parity
+unpinned by the paper for those conventions.
 """
 from __future__ import annotations
 

@@ -127,9 +127,9 @@ def draw_pair(rng: np.random.Generator, room, freq_hz: float, scene: int = 0) ->
 
 
 # --------------------------------------------------------------------------
-# The five workloads.  cfg ids 1..5 match the order the workloads are listed
-# in the design doc: tiny parity case, paper-scale forward, differentiated step,
-# batched forward, batched uneven forward+backward.
+# The five workloads, cfg ids 1..5 in this order: tiny parity case,
+# paper-scale forward, differentiated step, batched forward, batched uneven
+# forward+backward.
 # --------------------------------------------------------------------------
 
 def tiny(seed_stream: int = 0, n: int = 2000, grid: Grid | None = None) -> Batch:
