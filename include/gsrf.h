@@ -255,6 +255,94 @@ gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stre
  */
 gsrf_status gsrf_set_kernel_events(void *fwd_start, void *fwd_stop, void *bwd_start, void *bwd_stop);
 
+/* ------------------------------------------------------------------------
+ * Training steps either side of the render (Sec. 3.4 loss function;
+ * App. Gaussian primitive optimization).  These take plain arrays, not a
+ * problem, and follow the stream-order and validation rules above.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Device workspace (bytes) that gsrf_loss_spectrum needs for n_pairs spectra
+ * of n_el x n_az rays (per-tile FP64 partial sums).  0 when n_pairs = 0.
+ */
+gsrf_status gsrf_loss_workspace_size(int32_t n_pairs, int32_t n_el, int32_t n_az, size_t *bytes);
+
+/*
+ * Antenna-array loss (Sec. 3.4, loss function) of each pair's spatial
+ * spectrum and its gradient with respect to the rendered rays.  The predicted
+ * spectrum is the power x = |S_uv|^2 of every ray, the target y a measured
+ * spectrum of the same shape, N = n_el * n_az:
+ *   L = (1 - lambda1 - lambda2) L1 + lambda1 L_SSIM + lambda2 L_Fourier,
+ *   L1 = (1/N) sum |x - y|,  L_SSIM = 1 - mean SSIM(x, y),
+ *   L_Fourier = (1/N) sum over frequency pairs |F(x) - F(y)|^2 with F the
+ *   unnormalised 2D DFT (by Parseval equal to sum (x - y)^2, which is what
+ *   is computed).
+ * SSIM: 11 x 11 Gaussian window of sigma 1.5, zero padding outside the
+ * spectrum, C1 = 0.01^2, C2 = 0.03^2, averaged over all N pixels (the paper
+ * gives no window or constants; these are the 3D Gaussian splatting ones).
+ * The paper gives no values for lambda1, lambda2 either.
+ *   signal       [P, n_el, n_az, 2]  rendered rays (gsrf_render_fwd output)
+ *   target       [P, n_el, n_az]     target power spectra
+ *   loss         [P, 4]              per pair: L, L1, L_SSIM, L_Fourier
+ *   grad_signal  [P, n_el, n_az, 2] or NULL: dL_k/dRe S + j dL_k/dIm S for
+ *                each pair's own loss L_k (= 2 dL_k/dx * S), the form
+ *                gsrf_render_bwd takes; overwritten.  d|x - y|/dx at 0 is 0.
+ *   workspace    gsrf_loss_workspace_size bytes (device), may be NULL when
+ *                n_pairs = 0.
+ * 1 <= n_el, n_az <= 65535, 0 <= n_pairs <= 65535, lambdas finite.
+ * Deterministic (fixed-order sums).
+ */
+gsrf_status gsrf_loss_spectrum(const float *signal, const float *target, int32_t n_pairs, int32_t n_el,
+                               int32_t n_az, float lambda1, float lambda2, float *loss, float *grad_signal,
+                               void *workspace, void *stream);
+
+/* Loss kinds of gsrf_loss_single. */
+typedef enum gsrf_loss_kind {
+  GSRF_LOSS_RSSI_DB = 0,      /* |10 log10 |S_hat|^2 - t|, t an RSSI in dBm (target [P]) */
+  GSRF_LOSS_COMPLEX_L2 = 1    /* |S_hat - t|^2, t complex (target [P, 2]) */
+} gsrf_loss_kind;
+
+/*
+ * Single-antenna loss (Sec. 3.4: L1 when the measurement is a power, squared
+ * L2 when it is a complex signal) of each pair's S_hat = sum_uv S_uv.
+ *   signal_sum  [P, 2]  (gsrf_render_fwd's S_hat)
+ *   target      [P] (RSSI in dBm) or [P, 2] (complex), by kind
+ *   loss        [P]     per pair
+ *   grad_sum    [P, 2] or NULL: dL_k/dRe S_hat + j dL_k/dIm S_hat, the
+ *               grad_sum argument of gsrf_render_bwd.  For GSRF_LOSS_RSSI_DB
+ *               and S_hat = 0 the loss is +inf and the gradient 0.
+ * Computed in FP64, rounded to FP32.  0 <= n_pairs; kind one of the above.
+ */
+gsrf_status gsrf_loss_single(const float *signal_sum, const float *target, int32_t n_pairs, int32_t kind,
+                             float *loss, float *grad_sum, void *stream);
+
+/*
+ * Learning rates of gsrf_sgd_step (App. training gives mean 1.6e-4 decaying
+ * exponentially to 1.6e-6 over 30000 iterations, scaling 0.01, rotation
+ * 0.005, attenuation 0.01, emission 0.0025).
+ */
+typedef struct gsrf_sgd_lr {
+  double mean_init, mean_final;  /* > 0 */
+  int64_t mean_steps;            /* iterations of the decay; <= 0: final rate throughout */
+  double log_scale, quat, logit, coeff;   /* >= 0 */
+} gsrf_sgd_lr;
+
+/*
+ * SGD on every attribute of every Gaussian in one launch (App. attribute
+ * updating, eq. updating): w <- w - eta_w * dL/dw, rounded once (FMA), in
+ * place.  eta for the means at iteration j: exp((1 - t) ln mean_init +
+ * t ln mean_final), t = min(j / mean_steps, 1), evaluated in FP64 on the host
+ * and rounded to FP32 like the other rates.  The quaternion is updated as
+ * stored (the render normalises it).
+ *   means [G,3], log_scales [G,3], quats [G,4], logits [G], coeffs [G,K,2]
+ *   (K = (fle_L + 1)^2) and the gradients in the same layouts
+ *   (gsrf_render_bwd's outputs); lr HOST; iteration >= 0.
+ */
+gsrf_status gsrf_sgd_step(int64_t n_gauss, int32_t fle_L, float *means, float *log_scales, float *quats,
+                          float *logits, float *coeffs, const float *d_means, const float *d_log_scales,
+                          const float *d_quats, const float *d_logits, const float *d_coeffs,
+                          const gsrf_sgd_lr *lr, int64_t iteration, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

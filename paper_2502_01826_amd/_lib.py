@@ -45,12 +45,20 @@ class GsrfLayout(ctypes.Structure):
                 ("tile_end", c_sz), ("n_records", c_i64), ("n_tiles", c_i32), ("n_tiles_az", c_i32)]
 
 
+class GsrfSgdLr(ctypes.Structure):
+    _fields_ = [("mean_init", c_f64), ("mean_final", c_f64), ("mean_steps", c_i64), ("log_scale", c_f64),
+                ("quat", c_f64), ("logit", c_f64), ("coeff", c_f64)]
+
+
 assert ctypes.sizeof(GsrfPair) == 40
+
+GSRF_LOSS_RSSI_DB, GSRF_LOSS_COMPLEX_L2 = 0, 1
 
 EXPORTS = ["gsrf_status_str", "gsrf_last_error", "gsrf_workspace_size", "gsrf_layout_of", "gsrf_project",
            "gsrf_splat_count", "gsrf_bin_sort", "gsrf_render_fwd", "gsrf_render_fwd_multi", "gsrf_render_bwd",
            "gsrf_render_stats",
-           "gsrf_set_kernel_events"]
+           "gsrf_set_kernel_events", "gsrf_loss_workspace_size", "gsrf_loss_spectrum", "gsrf_loss_single",
+           "gsrf_sgd_step"]
 
 _lib = None
 
@@ -78,6 +86,10 @@ def lib() -> ctypes.CDLL:
     L.gsrf_render_stats.argtypes = [P(GsrfProblem), c_vp, c_vp]
     L.gsrf_render_fwd_multi.argtypes = [P(GsrfProblem), c_i32, c_f64, c_vp, c_vp, c_vp]
     L.gsrf_set_kernel_events.argtypes = [c_vp, c_vp, c_vp, c_vp]
+    L.gsrf_loss_workspace_size.argtypes = [c_i32, c_i32, c_i32, P(c_sz)]
+    L.gsrf_loss_spectrum.argtypes = [c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_vp, c_vp, c_vp, c_vp]
+    L.gsrf_loss_single.argtypes = [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp]
+    L.gsrf_sgd_step.argtypes = [c_i64, c_i32] + [c_vp] * 10 + [P(GsrfSgdLr), c_i64, c_vp]
     for n in EXPORTS[2:]:
         getattr(L, n).restype = c_i32
     _lib = L

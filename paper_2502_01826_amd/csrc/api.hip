@@ -254,6 +254,69 @@ gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stre
   return dev(launch_render_stats(p, L, (char *)p->workspace, counts, (hipStream_t)stream), "gsrf_render_stats");
 }
 
+static gsrf_status check_spectrum(int32_t n_pairs, int32_t n_el, int32_t n_az) {
+  if (n_pairs < 0 || n_pairs > 65535) return fail(GSRF_EINVAL, "n_pairs = %d outside [0, 65535]", n_pairs);
+  if (n_el < 1 || n_az < 1 || n_el > 65535 || n_az > 65535)
+    return fail(GSRF_EINVAL, "spectrum %d x %d out of range [1, 65535]", n_el, n_az);
+  return GSRF_OK;
+}
+
+gsrf_status gsrf_loss_workspace_size(int32_t n_pairs, int32_t n_el, int32_t n_az, size_t *bytes) {
+  if (!bytes) return fail(GSRF_EINVAL, "bytes is NULL");
+  const gsrf_status st = check_spectrum(n_pairs, n_el, n_az);
+  if (st != GSRF_OK) return st;
+  *bytes = loss_partials_bytes(n_pairs, n_el, n_az);
+  return GSRF_OK;
+}
+
+gsrf_status gsrf_loss_spectrum(const float *signal, const float *target, int32_t n_pairs, int32_t n_el,
+                               int32_t n_az, float lambda1, float lambda2, float *loss, float *grad_signal,
+                               void *workspace, void *stream) {
+  const gsrf_status st = check_spectrum(n_pairs, n_el, n_az);
+  if (st != GSRF_OK) return st;
+  if (!isfinite(lambda1) || !isfinite(lambda2))
+    return fail(GSRF_EINVAL, "lambda1 = %g, lambda2 = %g: must be finite", (double)lambda1, (double)lambda2);
+  if (n_pairs > 0 && (!signal || !target || !loss || !workspace))
+    return fail(GSRF_EINVAL, "signal, target, loss or workspace is NULL");
+  return dev(launch_loss_spectrum(signal, target, n_pairs, n_el, n_az, lambda1, lambda2, loss, grad_signal,
+                                  workspace, (hipStream_t)stream),
+             "gsrf_loss_spectrum");
+}
+
+gsrf_status gsrf_loss_single(const float *signal_sum, const float *target, int32_t n_pairs, int32_t kind,
+                             float *loss, float *grad_sum, void *stream) {
+  if (n_pairs < 0) return fail(GSRF_EINVAL, "n_pairs = %d is negative", n_pairs);
+  if (kind != GSRF_LOSS_RSSI_DB && kind != GSRF_LOSS_COMPLEX_L2) return fail(GSRF_EINVAL, "loss kind %d", kind);
+  if (n_pairs > 0 && (!signal_sum || !target || !loss)) return fail(GSRF_EINVAL, "signal_sum, target or loss is NULL");
+  return dev(launch_loss_single(signal_sum, target, n_pairs, kind, loss, grad_sum, (hipStream_t)stream),
+             "gsrf_loss_single");
+}
+
+gsrf_status gsrf_sgd_step(int64_t n_gauss, int32_t fle_L, float *means, float *log_scales, float *quats,
+                          float *logits, float *coeffs, const float *d_means, const float *d_log_scales,
+                          const float *d_quats, const float *d_logits, const float *d_coeffs,
+                          const gsrf_sgd_lr *lr, int64_t iteration, void *stream) {
+  if (n_gauss < 0 || n_gauss >= ((int64_t)1 << 31)) return fail(GSRF_EINVAL, "n_gauss = %lld", (long long)n_gauss);
+  if (fle_L < 0 || fle_L > 6) return fail(GSRF_EINVAL, "fle_L = %d outside [0, 6]", fle_L);
+  if (!lr) return fail(GSRF_EINVAL, "lr (host) is NULL");
+  if (!(lr->mean_init > 0.0) || !(lr->mean_final > 0.0) || !isfinite(lr->mean_init) || !isfinite(lr->mean_final))
+    return fail(GSRF_EINVAL, "mean learning rates must be finite and > 0");
+  const double rest[4] = {lr->log_scale, lr->quat, lr->logit, lr->coeff};
+  for (double r : rest)
+    if (!(r >= 0.0) || !isfinite(r)) return fail(GSRF_EINVAL, "learning rates must be finite and >= 0");
+  if (iteration < 0) return fail(GSRF_EINVAL, "iteration = %lld is negative", (long long)iteration);
+  if (n_gauss > 0 && (!means || !log_scales || !quats || !logits || !coeffs || !d_means || !d_log_scales ||
+                      !d_quats || !d_logits || !d_coeffs))
+    return fail(GSRF_EINVAL, "a parameter or gradient pointer is NULL");
+  double t = 1.0;
+  if (lr->mean_steps > 0) t = fmin(fmax((double)iteration / (double)lr->mean_steps, 0.0), 1.0);
+  const double eta_mu = exp((1.0 - t) * log(lr->mean_init) + t * log(lr->mean_final));
+  float *const w[5] = {means, log_scales, quats, logits, coeffs};
+  const float *const g[5] = {d_means, d_log_scales, d_quats, d_logits, d_coeffs};
+  const float eta[5] = {(float)eta_mu, (float)lr->log_scale, (float)lr->quat, (float)lr->logit, (float)lr->coeff};
+  return dev(launch_sgd(n_gauss, fle_K(fle_L), w, g, eta, (hipStream_t)stream), "gsrf_sgd_step");
+}
+
 gsrf_status gsrf_set_kernel_events(void *fwd_start, void *fwd_stop, void *bwd_start, void *bwd_stop) {
   g_kernel_events[0] = (hipEvent_t)fwd_start;
   g_kernel_events[1] = (hipEvent_t)fwd_stop;

@@ -1,0 +1,107 @@
+"""Binding of the training steps either side of the render (argument
+marshalling only; the work runs in libgsrf.so):
+
+* ``SpectrumLoss`` -- antenna-array loss (1 - l1 - l2) L1 + l1 L_SSIM +
+  l2 L_Fourier of each pair's power spectrum |S_uv|^2 and its gradient with
+  respect to the rays (Sec. 3.4, loss function);
+* ``loss_single`` -- single-antenna losses on S_hat (RSSI in dBm, or complex
+  squared error; Sec. 3.4);
+* ``sgd_step`` -- the per-attribute SGD update with the decaying mean
+  learning rate (App. Gaussian primitive optimization; App. training).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import GsrfSgdLr, check
+from .render import FIELDS, _stream_handle
+
+RSSI_DB, COMPLEX_L2 = _lib.GSRF_LOSS_RSSI_DB, _lib.GSRF_LOSS_COMPLEX_L2
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _f32(t, shape, name):
+    assert t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == tuple(shape), \
+        f"{name}: need a contiguous float32 tensor of shape {tuple(shape)}, got {t.dtype} {tuple(t.shape)}"
+
+
+class SpectrumLoss:
+    """Loss of [P, n_el, n_az] spectra; owns the small workspace of partial sums."""
+
+    def __init__(self, n_pairs: int, n_el: int, n_az: int, lambda1: float, lambda2: float, device=None):
+        self.P, self.n_el, self.n_az = int(n_pairs), int(n_el), int(n_az)
+        self.lambda1, self.lambda2 = float(lambda1), float(lambda2)
+        self.device = torch.device(device or "cuda")
+        nb = ctypes.c_size_t(0)
+        check(_lib.lib().gsrf_loss_workspace_size(self.P, self.n_el, self.n_az, ctypes.byref(nb)),
+              "gsrf_loss_workspace_size")
+        self.ws = torch.empty(max(int(nb.value), 8), dtype=torch.uint8, device=self.device)
+
+    def __call__(self, signal, target, loss=None, grad_signal=None, want_grad: bool = True, stream=None):
+        """signal [P, n_el, n_az, 2], target [P, n_el, n_az] -> (loss [P, 4], grad_signal or None).
+        loss[k] = (L, L1, L_SSIM, L_Fourier); grad_signal = dL_k/dRe S + j dL_k/dIm S."""
+        P, ne, na = self.P, self.n_el, self.n_az
+        _f32(signal, (P, ne, na, 2), "signal")
+        _f32(target, (P, ne, na), "target")
+        if loss is None:
+            loss = torch.empty((P, 4), dtype=torch.float32, device=self.device)
+        if want_grad and grad_signal is None:
+            grad_signal = torch.empty_like(signal)
+        check(_lib.lib().gsrf_loss_spectrum(signal.data_ptr(), target.data_ptr(), P, ne, na, self.lambda1,
+                                            self.lambda2, loss.data_ptr(), _ptr(grad_signal) if want_grad else None,
+                                            self.ws.data_ptr(), _stream_handle(stream)), "gsrf_loss_spectrum")
+        return loss, (grad_signal if want_grad else None)
+
+
+def loss_single(signal_sum, target, kind: int, loss=None, grad_sum=None, want_grad: bool = True, stream=None):
+    """signal_sum [P, 2]; target [P] (RSSI_DB, dBm) or [P, 2] (COMPLEX_L2) -> (loss [P], grad_sum [P, 2])."""
+    P = signal_sum.shape[0]
+    _f32(signal_sum, (P, 2), "signal_sum")
+    _f32(target, (P,) if kind == RSSI_DB else (P, 2), "target")
+    if loss is None:
+        loss = torch.empty((P,), dtype=torch.float32, device=signal_sum.device)
+    if want_grad and grad_sum is None:
+        grad_sum = torch.empty_like(signal_sum)
+    check(_lib.lib().gsrf_loss_single(signal_sum.data_ptr(), target.data_ptr(), P, int(kind), loss.data_ptr(),
+                                      _ptr(grad_sum) if want_grad else None, _stream_handle(stream)),
+          "gsrf_loss_single")
+    return loss, (grad_sum if want_grad else None)
+
+
+@dataclass
+class LearningRates:
+    """App. training: mean 1.6e-4 -> 1.6e-6 over 30000 iterations (exponential),
+    scaling 0.01, rotation 0.005, attenuation 0.01, emission 0.0025."""
+    mean_init: float = 1.6e-4
+    mean_final: float = 1.6e-6
+    mean_steps: int = 30_000
+    log_scale: float = 0.01
+    quat: float = 0.005
+    logit: float = 0.01
+    coeff: float = 0.0025
+
+    def c(self) -> GsrfSgdLr:
+        return GsrfSgdLr(self.mean_init, self.mean_final, int(self.mean_steps), self.log_scale, self.quat,
+                         self.logit, self.coeff)
+
+
+def sgd_step(params, grads, iteration: int, fle_L: int, lr: LearningRates | None = None, stream=None):
+    """In-place SGD on (means, log_scales, quats, logits, coeffs) -- dicts keyed
+    by FIELDS or 5-tuples in that order -- with gradients in the same layouts."""
+    p = [params[k] for k in FIELDS] if isinstance(params, dict) else list(params)
+    g = [grads[k] for k in FIELDS] if isinstance(grads, dict) else list(grads)
+    G = p[0].shape[0]
+    K = (fle_L + 1) ** 2
+    for t, shape, name in zip(p + g, [(G, 3), (G, 3), (G, 4), (G,), (G, K, 2)] * 2, [*FIELDS, *FIELDS]):
+        _f32(t, shape, name)
+    lr = lr or LearningRates()
+    c = lr.c()
+    check(_lib.lib().gsrf_sgd_step(G, int(fle_L), *(t.data_ptr() for t in p), *(t.data_ptr() for t in g),
+                                   ctypes.byref(c), int(iteration), _stream_handle(stream)), "gsrf_sgd_step")

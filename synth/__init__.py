@@ -198,3 +198,17 @@ def cotangent(shape, seed: int, stream: int = 0) -> np.ndarray:
     """Seeded upstream gradient, CN(0,1) as real views, FP32."""
     rng = np.random.default_rng([9, seed, stream])
     return rng.normal(0.0, math.sqrt(0.5), size=tuple(shape) + (2,)).astype(np.float32)
+
+
+def spectra(n_pairs: int, n_el: int, n_az: int, seed: int) -> tuple:
+    """Seeded stand-ins for a rendered spectrum and a measured one: rays S_uv
+    CN(0, 0.5) as real views [P, n_el, n_az, 2] FP32, and a target power
+    spectrum [P, n_el, n_az] FP32 that is the power of a second such draw
+    smoothed over 3 x 3 neighbours (measured spectra are smooth images)."""
+    rng = np.random.default_rng([10, seed])
+    sig = rng.normal(0.0, 0.5, size=(n_pairs, n_el, n_az, 2))
+    other = rng.normal(0.0, 0.5, size=(n_pairs, n_el, n_az, 2))
+    p = (other ** 2).sum(-1)
+    pad = np.pad(p, ((0, 0), (1, 1), (1, 1)), mode="edge")
+    t = sum(pad[:, i:i + n_el, j:j + n_az] for i in range(3) for j in range(3)) / 9.0
+    return sig.astype(np.float32), t.astype(np.float32)

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "gsrf.h")
 
 from paper_2502_01826_amd import _lib  # noqa: E402
-from paper_2502_01826_amd._lib import GsrfGrid, GsrfLayout, GsrfPair, GsrfProblem  # noqa: E402
+from paper_2502_01826_amd._lib import GsrfGrid, GsrfLayout, GsrfPair, GsrfProblem, GsrfSgdLr  # noqa: E402
 
 
 def declared_functions():
@@ -47,6 +47,8 @@ int main(void) {
   P(gsrf_pair, freq_hz); P(gsrf_pair, scene);
   P(gsrf_problem, n_gauss); P(gsrf_problem, grid); P(gsrf_problem, splat_capacity); P(gsrf_problem, workspace_bytes);
   P(gsrf_layout, n_records); P(gsrf_layout, n_tiles_az);
+  printf("sizeof_sgd_lr %zu\n", sizeof(gsrf_sgd_lr));
+  P(gsrf_sgd_lr, mean_steps); P(gsrf_sgd_lr, coeff);
   return 0;
 }
 """
@@ -66,6 +68,9 @@ int main(void) {
         assert int(vals[f"gsrf_problem.{f}"]) == getattr(GsrfProblem, f).offset
     for f in ("n_records", "n_tiles_az"):
         assert int(vals[f"gsrf_layout.{f}"]) == getattr(GsrfLayout, f).offset
+    assert int(vals["sizeof_sgd_lr"]) == ctypes.sizeof(GsrfSgdLr)
+    for f in ("mean_steps", "coeff"):
+        assert int(vals[f"gsrf_sgd_lr.{f}"]) == getattr(GsrfSgdLr, f).offset
 
 
 def _host_problem(n_gauss=10, n_pairs=2, grid=None, cap=1000):
@@ -159,3 +164,33 @@ def test_pair_packing_matches_struct():
     raw = a.view(np.uint8).tobytes()
     s = GsrfPair.from_buffer_copy(raw[:40])
     assert list(s.rx) == list(b.pairs[0].rx.astype(np.float32)) and s.freq_hz == 2.4e9 and s.scene == 0
+
+
+def test_training_steps_validate_before_launching():
+    L = _lib.lib()
+    nb = ctypes.c_size_t()
+    assert L.gsrf_loss_workspace_size(3, 90, 360, ctypes.byref(nb)) == _lib.GSRF_OK
+    assert nb.value == 3 * (6 * 12) * 3 * 8          # 16 x 32 pixel tiles, three FP64 sums each
+    assert L.gsrf_loss_workspace_size(0, 90, 360, ctypes.byref(nb)) == _lib.GSRF_OK and nb.value == 0
+    assert L.gsrf_loss_workspace_size(1, 0, 360, ctypes.byref(nb)) == _lib.GSRF_EINVAL
+    # missing device pointers, a NaN weight, bad sizes: refused on the host
+    assert L.gsrf_loss_spectrum(None, None, 1, 9, 36, 0.2, 0.1, None, None, None, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_loss_spectrum(None, None, 1, 9, 36, float("nan"), 0.1, None, None, None, None) == _lib.GSRF_EINVAL
+    assert "lambda" in L.gsrf_last_error().decode()
+    assert L.gsrf_loss_spectrum(None, None, -1, 9, 36, 0.2, 0.1, None, None, None, None) == _lib.GSRF_EINVAL
+    # no pairs: nothing to do, nothing launched
+    assert L.gsrf_loss_spectrum(None, None, 0, 9, 36, 0.2, 0.1, None, None, None, None) == _lib.GSRF_OK
+    assert L.gsrf_loss_single(None, None, 2, 7, None, None, None) == _lib.GSRF_EINVAL
+    assert "kind" in L.gsrf_last_error().decode()
+    assert L.gsrf_loss_single(None, None, 2, _lib.GSRF_LOSS_RSSI_DB, None, None, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_loss_single(None, None, 0, _lib.GSRF_LOSS_COMPLEX_L2, None, None, None) == _lib.GSRF_OK
+    lr = GsrfSgdLr(1.6e-4, 1.6e-6, 30000, 0.01, 0.005, 0.01, 0.0025)
+    assert L.gsrf_sgd_step(10, 2, *([None] * 10), ctypes.byref(lr), 0, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_sgd_step(0, 2, *([None] * 10), ctypes.byref(lr), 0, None) == _lib.GSRF_OK
+    assert L.gsrf_sgd_step(0, 2, *([None] * 10), None, 0, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_sgd_step(0, 2, *([None] * 10), ctypes.byref(lr), -1, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_sgd_step(0, 7, *([None] * 10), ctypes.byref(lr), 0, None) == _lib.GSRF_EINVAL
+    bad = GsrfSgdLr(0.0, 1.6e-6, 30000, 0.01, 0.005, 0.01, 0.0025)
+    assert L.gsrf_sgd_step(0, 2, *([None] * 10), ctypes.byref(bad), 0, None) == _lib.GSRF_EINVAL
+    bad = GsrfSgdLr(1.6e-4, 1.6e-6, 30000, -0.01, 0.005, 0.01, 0.0025)
+    assert L.gsrf_sgd_step(0, 2, *([None] * 10), ctypes.byref(bad), 0, None) == _lib.GSRF_EINVAL
