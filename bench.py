@@ -14,7 +14,8 @@ Prints one JSON line (rank 0).  Extra fields report the forward-only rate,
 the two batched workloads -- 256 pairs over one 500k-Gaussian room (forward)
 and 16 scenes of 20k-1M Gaussians with 8-64 pairs each (forward + adjoint) --
 each as hipGraph replays with an autotuned tile shape, the multi-carrier
-forward (26 carriers of one OFDM block per pass), the roofline of the
+forward (26 carriers of one OFDM block per pass), a whole training iteration
+(render, spectrum loss, adjoint, SGD update), the roofline of the
 dominant kernel of each workload and the FP64 oracle timed on the host's
 cores.  ``--workloads`` restricts the run (profiling).
 """
@@ -112,8 +113,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batched", choices=("full", "small", "none"), default="full",
                     help="batched workloads: full (256 pairs x 500k; 16 uneven scenes), small, or none")
-    ap.add_argument("--workloads", default="plain,fwd_500k,uneven,multi",
-                    help="comma list of plain, fwd_500k, uneven, multi (profiling runs pick one)")
+    ap.add_argument("--workloads", default="plain,fwd_500k,uneven,multi,train",
+                    help="comma list of plain, fwd_500k, uneven, multi, train (profiling runs pick one)")
     ap.add_argument("--carriers", type=int, default=26, help="multi-carrier workload: carriers per pair")
     ap.add_argument("--carrier-step", type=float, default=312.5e3, help="multi-carrier workload: spacing in Hz")
     ap.add_argument("--batched-pairs", type=int, default=256)
@@ -355,6 +356,79 @@ def main() -> int:
                              "timing": "HIP events recorded by the library around the carrier-chunk traversals",
                              "counts": st}}
 
+    def run_train():
+        """One training iteration per step on the plain pair: project, bin_sort,
+        render_fwd, the antenna-array loss against a target spectrum (the power
+        spectrum of a perturbed copy of the room), render_bwd with the loss's
+        gradient, and the SGD update of every attribute.  Eager launches (the
+        mean learning rate changes every iteration)."""
+        from paper_2502_01826_amd import train as tr
+        prob, bufs = make([pair])
+        _, pert = synth.training_step(n=args.gaussians, grid=grid)
+        tprob = Problem(dict(means=pert.means, log_scales=pert.log_scales, quats=pert.quats, logits=pert.logits,
+                             coeffs=pert.coeffs), [pair], grid)
+        tsig, _, _ = tprob.forward()
+        target = (tsig ** 2).sum(-1)
+        pscale = 1.0 / float(target.max())           # spectra compared as images normalised to a peak of 1
+        target = (target * pscale).contiguous()
+        del tprob, tsig
+        lam1, lam2 = 0.2, 0.1
+        loss_fn = tr.SpectrumLoss(1, grid.n_el, grid.n_az, lam1, lam2, power_scale=pscale)
+        lossb = torch.empty((1, 4), dtype=torch.float32, device=dev)
+        gsig = torch.empty_like(bufs["sig"])
+        params = (prob.means, prob.log_scales, prob.quats, prob.logits, prob.coeffs)
+        steps = args.steps
+        ev = {k: [new_event() for _ in range(steps)] for k in ("l0", "l1", "o0", "o1")}
+        first_loss = []
+
+        def iterate(n, it0, with_ev):
+            for i in range(n):
+                prob.project()
+                prob.bin_sort()
+                prob.render_fwd(bufs["sig"], bufs["ssum"], bufs["rssi"])
+                if with_ev:
+                    ev["l0"][i].record(stream)
+                loss_fn(bufs["sig"], target, loss=lossb, grad_signal=gsig)
+                if with_ev:
+                    ev["l1"][i].record(stream)
+                prob.render_bwd(bufs["sig"], gsig, None, out=bufs["grads"])
+                if with_ev:
+                    ev["o0"][i].record(stream)
+                tr.sgd_step(params, bufs["grads"], it0 + i, fle_L=grid.fle_L)
+                if with_ev:
+                    ev["o1"][i].record(stream)
+
+        iterate(1, 0, False)
+        torch.cuda.synchronize()
+        first_loss.append(float(lossb[0, 0]))
+        iterate(args.warmup, 1, False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iterate(steps, 1 + args.warmup, True)
+        torch.cuda.synchronize()
+        t_it = (time.perf_counter() - t0) / steps
+        t_loss = sum(a.elapsed_time(b) for a, b in zip(ev["l0"], ev["l1"])) / steps * 1e-3
+        t_sgd = sum(a.elapsed_time(b) for a, b in zip(ev["o0"], ev["o1"])) / steps * 1e-3
+        n_splats, ok = prob.splat_count()
+        G_, K = prob.n_gauss, grid.K
+        sgd_bytes = G_ * (11 + 2 * K) * 4 * 3          # read w and g, write w
+        out = {"workload": "training iteration on the plain pair (200k Gaussians, 360x90 rays): project+bin_sort+"
+                           "render_fwd+loss_spectrum+render_bwd+sgd_step, loss (1-l1-l2) L1 + l1 SSIM + l2 Fourier "
+                           f"with l1={lam1}, l2={lam2} against the spectrum of a perturbed room",
+               "iterations_per_s": 1.0 / t_it, "ms_per_iteration": t_it * 1e3,
+               "timing": f"{steps} eager iterations after {1 + args.warmup} untimed ones, wall clock between "
+                         "synchronisations",
+               "loss_first_last": [first_loss[0], float(lossb[0, 0])],
+               "kernel_ms": {"loss_spectrum": t_loss * 1e3, "sgd_step": t_sgd * 1e3},
+               "sgd_roofline": {"bound": "hbm", "achieved": sgd_bytes / t_sgd / 1e9, "peak": PEAK_HBM / 1e9,
+                                "unit": "GB/s", "frac": sgd_bytes / t_sgd / PEAK_HBM, "traffic": None,
+                                "bytes_per_launch": sgd_bytes,
+                                "timing": "HIP events around the call on its stream (includes one launch gap)"},
+               "splats_within_capacity": bool(ok)}
+        del prob, bufs, target, gsig
+        torch.cuda.empty_cache()
+        return out
+
     step_stats = {}
     eager = {}
     work = set(args.workloads.split(","))
@@ -384,6 +458,7 @@ def main() -> int:
             del b5
 
     multi = run_multi() if "multi" in work else None
+    train = run_train() if "train" in work else None
 
     cpu = None
     if not args.no_cpu_baseline and "plain" in work:
@@ -413,6 +488,7 @@ def main() -> int:
         "kernels_ms": None if t_fwd_k is None else {"render_fwd": t_fwd_k * 1e3, "render_bwd": t_bwd_k * 1e3},
         "batched": batched,
         "multi_carrier": multi,
+        "train_step": train,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

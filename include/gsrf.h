@@ -270,7 +270,9 @@ gsrf_status gsrf_loss_workspace_size(int32_t n_pairs, int32_t n_el, int32_t n_az
 /*
  * Antenna-array loss (Sec. 3.4, loss function) of each pair's spatial
  * spectrum and its gradient with respect to the rendered rays.  The predicted
- * spectrum is the power x = |S_uv|^2 of every ray, the target y a measured
+ * spectrum is the power x = power_scale * |S_uv|^2 of every ray (power_scale
+ * > 0 a fixed normalisation, e.g. 1 / the largest measured power, since
+ * spectra are compared as normalised images), the target y a measured
  * spectrum of the same shape, N = n_el * n_az:
  *   L = (1 - lambda1 - lambda2) L1 + lambda1 L_SSIM + lambda2 L_Fourier,
  *   L1 = (1/N) sum |x - y|,  L_SSIM = 1 - mean SSIM(x, y),
@@ -285,7 +287,7 @@ gsrf_status gsrf_loss_workspace_size(int32_t n_pairs, int32_t n_el, int32_t n_az
  *   target       [P, n_el, n_az]     target power spectra
  *   loss         [P, 4]              per pair: L, L1, L_SSIM, L_Fourier
  *   grad_signal  [P, n_el, n_az, 2] or NULL: dL_k/dRe S + j dL_k/dIm S for
- *                each pair's own loss L_k (= 2 dL_k/dx * S), the form
+ *                each pair's own loss L_k (= 2 power_scale dL_k/dx * S), the form
  *                gsrf_render_bwd takes; overwritten.  d|x - y|/dx at 0 is 0.
  *   workspace    gsrf_loss_workspace_size bytes (device), may be NULL when
  *                n_pairs = 0.
@@ -293,8 +295,8 @@ gsrf_status gsrf_loss_workspace_size(int32_t n_pairs, int32_t n_el, int32_t n_az
  * Deterministic (fixed-order sums).
  */
 gsrf_status gsrf_loss_spectrum(const float *signal, const float *target, int32_t n_pairs, int32_t n_el,
-                               int32_t n_az, float lambda1, float lambda2, float *loss, float *grad_signal,
-                               void *workspace, void *stream);
+                               int32_t n_az, float power_scale, float lambda1, float lambda2, float *loss,
+                               float *grad_signal, void *workspace, void *stream);
 
 /* Loss kinds of gsrf_loss_single. */
 typedef enum gsrf_loss_kind {

@@ -23,8 +23,10 @@ Paper passages followed:
                                                      updating); App. (training)
 
 Readings taken where the paper is silent:
-  L1  the spatial spectrum of a pair is the power |S_uv|^2 of its rays, an
-      [n_el, n_az] image; the target is a spectrum of the same shape.
+  L1  the spatial spectrum of a pair is the power of its rays, an [n_el, n_az]
+      image c |S_uv|^2 with a fixed normalisation constant c > 0 (measured
+      spectra are compared as normalised images); the target is a spectrum of
+      the same shape.
   L2  SSIM as in the 3D Gaussian splatting method the paper builds on: an
       11 x 11 Gaussian window of sigma 1.5 (normalised), zero padding outside
       the image, C1 = 0.01^2, C2 = 0.03^2, the map averaged over all pixels;
@@ -96,18 +98,20 @@ def fourier_term(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     return (d.real ** 2 + d.imag ** 2).sum() / x.numel()
 
 
-def spectrum_loss_terms(signal: np.ndarray, target: np.ndarray, lam1: float, lam2: float, *, grad: bool = True):
+def spectrum_loss_terms(signal: np.ndarray, target: np.ndarray, lam1: float, lam2: float, *, power_scale: float = 1.0,
+                        grad: bool = True):
     """Antenna-array loss of one pair (Sec. 3.4).
 
     signal  [n_el, n_az] complex (the rendered rays S_uv)
     target  [n_el, n_az] real    (the measured spectrum)
+    power_scale  c of reading L1: the predicted spectrum is c |S_uv|^2
     Returns dict(total, l1, ssim_loss, fourier) and, with grad, G = dL/dRe S +
     j dL/dIm S as complex [n_el, n_az].
     """
     re = torch.tensor(np.real(signal), dtype=F64, requires_grad=grad)
     im = torch.tensor(np.imag(signal), dtype=F64, requires_grad=grad)
     t = torch.tensor(target, dtype=F64)
-    p = re * re + im * im                                  # reading L1: power spectrum
+    p = power_scale * (re * re + im * im)                  # reading L1: power spectrum
     l1 = (p - t).abs().mean()
     ls = 1.0 - ssim_map(p, t).mean()
     lf = fourier_term(p, t)

@@ -87,7 +87,7 @@ def lib() -> ctypes.CDLL:
     L.gsrf_render_fwd_multi.argtypes = [P(GsrfProblem), c_i32, c_f64, c_vp, c_vp, c_vp]
     L.gsrf_set_kernel_events.argtypes = [c_vp, c_vp, c_vp, c_vp]
     L.gsrf_loss_workspace_size.argtypes = [c_i32, c_i32, c_i32, P(c_sz)]
-    L.gsrf_loss_spectrum.argtypes = [c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_vp, c_vp, c_vp, c_vp]
+    L.gsrf_loss_spectrum.argtypes = [c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_f32, c_vp, c_vp, c_vp, c_vp]
     L.gsrf_loss_single.argtypes = [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp]
     L.gsrf_sgd_step.argtypes = [c_i64, c_i32] + [c_vp] * 10 + [P(GsrfSgdLr), c_i64, c_vp]
     for n in EXPORTS[2:]:

@@ -270,15 +270,17 @@ gsrf_status gsrf_loss_workspace_size(int32_t n_pairs, int32_t n_el, int32_t n_az
 }
 
 gsrf_status gsrf_loss_spectrum(const float *signal, const float *target, int32_t n_pairs, int32_t n_el,
-                               int32_t n_az, float lambda1, float lambda2, float *loss, float *grad_signal,
-                               void *workspace, void *stream) {
+                               int32_t n_az, float power_scale, float lambda1, float lambda2, float *loss,
+                               float *grad_signal, void *workspace, void *stream) {
   const gsrf_status st = check_spectrum(n_pairs, n_el, n_az);
   if (st != GSRF_OK) return st;
+  if (!(power_scale > 0.f) || !isfinite(power_scale))
+    return fail(GSRF_EINVAL, "power_scale = %g: must be finite and > 0", (double)power_scale);
   if (!isfinite(lambda1) || !isfinite(lambda2))
     return fail(GSRF_EINVAL, "lambda1 = %g, lambda2 = %g: must be finite", (double)lambda1, (double)lambda2);
   if (n_pairs > 0 && (!signal || !target || !loss || !workspace))
     return fail(GSRF_EINVAL, "signal, target, loss or workspace is NULL");
-  return dev(launch_loss_spectrum(signal, target, n_pairs, n_el, n_az, lambda1, lambda2, loss, grad_signal,
+  return dev(launch_loss_spectrum(signal, target, n_pairs, n_el, n_az, power_scale, lambda1, lambda2, loss, grad_signal,
                                   workspace, (hipStream_t)stream),
              "gsrf_loss_spectrum");
 }

@@ -143,7 +143,8 @@ hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws,
 // Training steps (train.hip).
 size_t loss_partials_bytes(int32_t n_pairs, int32_t n_el, int32_t n_az);
 hipError_t launch_loss_spectrum(const float *signal, const float *target, int32_t n_pairs, int32_t n_el, int32_t n_az,
-                                float lam1, float lam2, float *loss, float *grad_signal, void *ws, hipStream_t s);
+                                float pscale, float lam1, float lam2, float *loss, float *grad_signal, void *ws,
+                                hipStream_t s);
 hipError_t launch_loss_single(const float *signal_sum, const float *target, int32_t n_pairs, int32_t kind,
                               float *loss, float *grad_sum, hipStream_t s);
 hipError_t launch_sgd(int64_t n_gauss, int K, float *const w[5], const float *const g[5], const float eta[5],

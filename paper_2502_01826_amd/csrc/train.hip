@@ -34,7 +34,7 @@ struct LossLds {
 
 // One workgroup per (pair, output tile): the tile's sums of |x - y|, SSIM and
 // (x - y)^2 into partials[(k * tiles + t) * 3 + {0,1,2}] (FP64), and, when
-// grad is non-NULL, dL/dRe S + j dL/dIm S of its pixels.
+// grad is non-NULL, dL/dRe S + j dL/dIm S of its pixels; x = pscale |S|^2.
 //
 // L = (1 - l1 - l2) mean|x - y| + l1 (1 - mean SSIM) + l2 L_F.  With the
 // unnormalised DFT, Parseval's identity makes the Fourier term
@@ -46,7 +46,7 @@ struct LossLds {
 // (w symmetric, zero outside the image).
 __global__ void __launch_bounds__(kLossThreads)
 k_spectrum_loss(const float2 *__restrict__ signal, const float *__restrict__ target, int n_el, int n_az,
-                int tiles_az, int tiles, float lam1, float lam2, double *__restrict__ partials,
+                int tiles_az, int tiles, float pscale, float lam1, float lam2, double *__restrict__ partials,
                 float2 *__restrict__ grad) {
   __shared__ LossLds L;
   const int tid = threadIdx.x;
@@ -71,7 +71,7 @@ k_spectrum_loss(const float2 *__restrict__ signal, const float *__restrict__ tar
     float xv = 0.f, yv = 0.f;
     if (v >= 0 && v < n_el && u >= 0 && u < n_az) {
       const float2 s = signal[img + (size_t)v * n_az + u];
-      xv = fmaf(s.x, s.x, s.y * s.y);
+      xv = pscale * fmaf(s.x, s.x, s.y * s.y);
       yv = target[img + (size_t)v * n_az + u];
     }
     L.x[a][b] = xv;
@@ -166,7 +166,8 @@ k_spectrum_loss(const float2 *__restrict__ signal, const float *__restrict__ tar
       const float sgn = dxy > 0.f ? 1.f : (dxy < 0.f ? -1.f : 0.f);
       const float dldx = c_l1 * sgn + c_ssim * (b1 + 2.f * xv * b2 + yv * b3) + c_f * dxy;
       const float2 s = signal[img + (size_t)v * n_az + u];
-      grad[img + (size_t)v * n_az + u] = make_float2(2.f * dldx * s.x, 2.f * dldx * s.y);
+      const float c = 2.f * pscale * dldx;
+      grad[img + (size_t)v * n_az + u] = make_float2(c * s.x, c * s.y);
     }
   }
   // fixed-order block reduction of the three sums
@@ -217,12 +218,13 @@ size_t loss_partials_bytes(int32_t n_pairs, int32_t n_el, int32_t n_az) {
 }
 
 hipError_t launch_loss_spectrum(const float *signal, const float *target, int32_t n_pairs, int32_t n_el, int32_t n_az,
-                                float lam1, float lam2, float *loss, float *grad_signal, void *ws, hipStream_t s) {
+                                float pscale, float lam1, float lam2, float *loss, float *grad_signal, void *ws,
+                                hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   const int tiles_az = (n_az + kLossTW - 1) / kLossTW, tiles = tiles_az * ((n_el + kLossTH - 1) / kLossTH);
   double *partials = (double *)ws;
   hipLaunchKernelGGL(k_spectrum_loss, dim3((unsigned)tiles, (unsigned)n_pairs), dim3(kLossThreads), 0, s,
-                     (const float2 *)signal, target, n_el, n_az, tiles_az, tiles, lam1, lam2, partials,
+                     (const float2 *)signal, target, n_el, n_az, tiles_az, tiles, pscale, lam1, lam2, partials,
                      (float2 *)grad_signal);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -286,8 +288,24 @@ __global__ void __launch_bounds__(256) k_sgd(SgdSeg seg) {
   const float *__restrict__ g = seg.g[a];
   const int64_t n = seg.n[a];
   const float eta = seg.eta[a];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    w[i] = fmaf(-eta, g[i], w[i]);
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t done = 0;
+  if ((((uintptr_t)w | (uintptr_t)g) & 15) == 0) {   // 16-byte vectors where both arrays allow them
+    float4 *__restrict__ w4 = (float4 *)w;
+    const float4 *__restrict__ g4 = (const float4 *)g;
+    const int64_t n4 = n >> 2;
+    for (int64_t i = first; i < n4; i += stride) {
+      float4 x = w4[i];
+      const float4 d = g4[i];
+      x.x = fmaf(-eta, d.x, x.x);
+      x.y = fmaf(-eta, d.y, x.y);
+      x.z = fmaf(-eta, d.z, x.z);
+      x.w = fmaf(-eta, d.w, x.w);
+      w4[i] = x;
+    }
+    done = n4 << 2;
+  }
+  for (int64_t i = done + first; i < n; i += stride) w[i] = fmaf(-eta, g[i], w[i]);
 }
 
 hipError_t launch_sgd(int64_t n_gauss, int K, float *const w[5], const float *const g[5], const float eta[5],
@@ -303,7 +321,7 @@ hipError_t launch_sgd(int64_t n_gauss, int K, float *const w[5], const float *co
     seg.eta[a] = eta[a];
     if (seg.n[a] > most) most = seg.n[a];
   }
-  const int64_t blocks = (most + 255) / 256;
+  const int64_t blocks = (most / 4 + 255) / 256 + 1;
   hipLaunchKernelGGL(k_sgd, dim3((unsigned)(blocks < 8192 ? blocks : 8192), 5), dim3(256), 0, s, seg);
   return hipGetLastError();
 }

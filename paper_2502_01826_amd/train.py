@@ -2,7 +2,7 @@
 marshalling only; the work runs in libgsrf.so):
 
 * ``SpectrumLoss`` -- antenna-array loss (1 - l1 - l2) L1 + l1 L_SSIM +
-  l2 L_Fourier of each pair's power spectrum |S_uv|^2 and its gradient with
+  l2 L_Fourier of each pair's power spectrum c |S_uv|^2 and its gradient with
   respect to the rays (Sec. 3.4, loss function);
 * ``loss_single`` -- single-antenna losses on S_hat (RSSI in dBm, or complex
   squared error; Sec. 3.4);
@@ -33,11 +33,13 @@ def _f32(t, shape, name):
 
 
 class SpectrumLoss:
-    """Loss of [P, n_el, n_az] spectra; owns the small workspace of partial sums."""
+    """Loss of [P, n_el, n_az] spectra x = power_scale |S|^2; owns the small
+    workspace of partial sums."""
 
-    def __init__(self, n_pairs: int, n_el: int, n_az: int, lambda1: float, lambda2: float, device=None):
+    def __init__(self, n_pairs: int, n_el: int, n_az: int, lambda1: float, lambda2: float, power_scale: float = 1.0,
+                 device=None):
         self.P, self.n_el, self.n_az = int(n_pairs), int(n_el), int(n_az)
-        self.lambda1, self.lambda2 = float(lambda1), float(lambda2)
+        self.lambda1, self.lambda2, self.power_scale = float(lambda1), float(lambda2), float(power_scale)
         self.device = torch.device(device or "cuda")
         nb = ctypes.c_size_t(0)
         check(_lib.lib().gsrf_loss_workspace_size(self.P, self.n_el, self.n_az, ctypes.byref(nb)),
@@ -54,9 +56,10 @@ class SpectrumLoss:
             loss = torch.empty((P, 4), dtype=torch.float32, device=self.device)
         if want_grad and grad_signal is None:
             grad_signal = torch.empty_like(signal)
-        check(_lib.lib().gsrf_loss_spectrum(signal.data_ptr(), target.data_ptr(), P, ne, na, self.lambda1,
-                                            self.lambda2, loss.data_ptr(), _ptr(grad_signal) if want_grad else None,
-                                            self.ws.data_ptr(), _stream_handle(stream)), "gsrf_loss_spectrum")
+        g = _ptr(grad_signal) if want_grad else None
+        check(_lib.lib().gsrf_loss_spectrum(signal.data_ptr(), target.data_ptr(), P, ne, na, self.power_scale,
+                                            self.lambda1, self.lambda2, loss.data_ptr(), g, self.ws.data_ptr(),
+                                            _stream_handle(stream)), "gsrf_loss_spectrum")
         return loss, (grad_signal if want_grad else None)
 
 

@@ -174,12 +174,15 @@ def test_training_steps_validate_before_launching():
     assert L.gsrf_loss_workspace_size(0, 90, 360, ctypes.byref(nb)) == _lib.GSRF_OK and nb.value == 0
     assert L.gsrf_loss_workspace_size(1, 0, 360, ctypes.byref(nb)) == _lib.GSRF_EINVAL
     # missing device pointers, a NaN weight, bad sizes: refused on the host
-    assert L.gsrf_loss_spectrum(None, None, 1, 9, 36, 0.2, 0.1, None, None, None, None) == _lib.GSRF_EINVAL
-    assert L.gsrf_loss_spectrum(None, None, 1, 9, 36, float("nan"), 0.1, None, None, None, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_loss_spectrum(None, None, 1, 9, 36, 1.0, 0.2, 0.1, None, None, None, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_loss_spectrum(None, None, 1, 9, 36, 1.0, float("nan"), 0.1, None, None, None, None) == \
+        _lib.GSRF_EINVAL
     assert "lambda" in L.gsrf_last_error().decode()
-    assert L.gsrf_loss_spectrum(None, None, -1, 9, 36, 0.2, 0.1, None, None, None, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_loss_spectrum(None, None, 1, 9, 36, 0.0, 0.2, 0.1, None, None, None, None) == _lib.GSRF_EINVAL
+    assert "power_scale" in L.gsrf_last_error().decode()
+    assert L.gsrf_loss_spectrum(None, None, -1, 9, 36, 1.0, 0.2, 0.1, None, None, None, None) == _lib.GSRF_EINVAL
     # no pairs: nothing to do, nothing launched
-    assert L.gsrf_loss_spectrum(None, None, 0, 9, 36, 0.2, 0.1, None, None, None, None) == _lib.GSRF_OK
+    assert L.gsrf_loss_spectrum(None, None, 0, 9, 36, 1.0, 0.2, 0.1, None, None, None, None) == _lib.GSRF_OK
     assert L.gsrf_loss_single(None, None, 2, 7, None, None, None) == _lib.GSRF_EINVAL
     assert "kind" in L.gsrf_last_error().decode()
     assert L.gsrf_loss_single(None, None, 2, _lib.GSRF_LOSS_RSSI_DB, None, None, None) == _lib.GSRF_EINVAL

@@ -15,9 +15,9 @@ LOSS_RTOL = 1e-4      # loss values (FP32 sums of FP32 terms vs FP64)
 GRAD_RTOL = 1e-4      # per-pixel gradient, relative to the largest |G| of the pair
 
 
-def _gpu_spectrum_loss(sig, tgt, lam1, lam2):
+def _gpu_spectrum_loss(sig, tgt, lam1, lam2, pscale=1.0):
     P, ne, na = tgt.shape
-    fn = tr.SpectrumLoss(P, ne, na, lam1, lam2)
+    fn = tr.SpectrumLoss(P, ne, na, lam1, lam2, power_scale=pscale)
     s = torch.from_numpy(sig).cuda().contiguous()
     t = torch.from_numpy(tgt).cuda().contiguous()
     loss, g = fn(s, t)
@@ -27,16 +27,19 @@ def _gpu_spectrum_loss(sig, tgt, lam1, lam2):
     return loss.cpu().numpy().astype(np.float64), torch.view_as_complex(g).cpu().numpy().astype(np.complex128)
 
 
-@pytest.mark.parametrize("P,ne,na,lam1,lam2", [(2, 37, 70, 0.2, 0.1), (1, 16, 32, 0.0, 0.0), (1, 9, 36, 1.0, 0.0),
-                                                (3, 5, 7, 0.0, 1.0), (1, 90, 360, 0.2, 0.05)])
-def test_spectrum_loss_matches_oracle(P, ne, na, lam1, lam2):
+@pytest.mark.parametrize("P,ne,na,lam1,lam2,c", [(2, 37, 70, 0.2, 0.1, 1.0), (1, 16, 32, 0.0, 0.0, 1.0),
+                                                  (1, 9, 36, 1.0, 0.0, 1.0), (3, 5, 7, 0.0, 1.0, 1.0),
+                                                  (1, 90, 360, 0.2, 0.05, 1.0), (2, 40, 50, 0.3, 0.02, 1e4)])
+def test_spectrum_loss_matches_oracle(P, ne, na, lam1, lam2, c):
     """Several 16 x 32 tiles with ragged last row and column (37 x 70), one exact
-    tile, spectra smaller than the SSIM window (5 x 7) and the 360 x 90 grid."""
-    say("spectrum loss", P, ne, na, lam1, lam2)
+    tile, spectra smaller than the SSIM window (5 x 7), the 360 x 90 grid, and
+    rays 100x weaker than the target scale (power_scale 1e4)."""
+    say("spectrum loss", P, ne, na, lam1, lam2, c)
     sig, tgt = synth.spectra(P, ne, na, seed=ne * 1000 + na)
-    loss, G = _gpu_spectrum_loss(sig, tgt, lam1, lam2)
+    sig = (sig / np.sqrt(c)).astype(np.float32)
+    loss, G = _gpu_spectrum_loss(sig, tgt, lam1, lam2, c)
     for k in range(P):
-        ref = to.spectrum_loss_terms(sig[k, ..., 0] + 1j * sig[k, ..., 1], tgt[k], lam1, lam2)
+        ref = to.spectrum_loss_terms(sig[k, ..., 0] + 1j * sig[k, ..., 1], tgt[k], lam1, lam2, power_scale=c)
         want = np.array([ref["total"], ref["l1"], ref["ssim_loss"], ref["fourier"]])
         assert np.all(np.abs(loss[k] - want) <= LOSS_RTOL * np.maximum(np.abs(want), 1e-6)), (k, loss[k], want)
         err = np.abs(G[k] - ref["G"]).max()
@@ -98,7 +101,7 @@ def test_sgd_step_is_bit_exact(iteration):
         assert np.array_equal(pd[k].cpu().numpy().view(np.uint32), want[k].view(np.uint32)), k
 
 
-def test_sgd_custom_rates_and_no_decay():
+def test_sgd_custom_rates_no_decay_and_unaligned_arrays():
     rng = np.random.default_rng(23)
     G = 64
     p = {k: rng.normal(0, 1, s).astype(np.float32) for k, s in
@@ -106,7 +109,12 @@ def test_sgd_custom_rates_and_no_decay():
     g = {k: rng.normal(0, 1, v.shape).astype(np.float32) for k, v in p.items()}
     lr = tr.LearningRates(mean_init=0.3, mean_final=0.3, mean_steps=0, log_scale=0.1, quat=0.0, logit=1.0,
                           coeff=0.5)
-    pd = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
+    def offset(v):      # a view starting 4 bytes into its buffer: the kernel's scalar path
+        buf = torch.zeros(v.size + 1, dtype=torch.float32, device="cuda")
+        buf[1:] = torch.from_numpy(v.ravel()).cuda()
+        return buf[1:].view(v.shape)
+
+    pd = {k: offset(v) for k, v in p.items()}
     tr.sgd_step(pd, {k: torch.from_numpy(v).cuda() for k, v in g.items()}, 99, fle_L=0, lr=lr)
     torch.cuda.synchronize()
     want = to.sgd_step(p, g, 99, dict(mean_init=0.3, mean_final=0.3, mean_steps=0, log_scale=0.1, quat=0.0,
@@ -130,16 +138,15 @@ def test_training_iteration_descends():
     tb = synth.Batch([synth.Scene(sc.means, sc.log_scales, sc.quats, sc.logits, tcoef)], b.pairs, g)
     tsig, _, _ = gpu_problem(tb).forward()
     target = (tsig ** 2).sum(-1)
-    scale = float(target.max())
-    target = (target / scale).contiguous()
-    root = float(np.sqrt(scale))
+    c = 1.0 / float(target.max())                         # spectra normalised to a peak of 1
+    target = (target * c).contiguous()
     prob = gpu_problem(b)
-    fn = tr.SpectrumLoss(1, g.n_el, g.n_az, 0.2, 0.1)
+    fn = tr.SpectrumLoss(1, g.n_el, g.n_az, 0.2, 0.1, power_scale=c)
 
     def loss_of():
         s, _, _ = prob.forward()
-        l, Gn = fn((s / root).contiguous(), target)      # spectra normalised to a peak of 1
-        return s, float(l[0, 0]), (Gn / root).contiguous()
+        l, G = fn(s, target)
+        return s, float(l[0, 0]), G
 
     s, l0, G = loss_of()
     grads = prob.render_bwd(s.contiguous(), G)
