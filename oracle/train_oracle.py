@@ -40,11 +40,41 @@ Readings taken where the paper is silent:
       w - eta * g rounded once to FP32.
   L6  the derivative of |x| at x = 0 is 0.
   The weights l1, l2 are not given in the paper; they are arguments.
+  D1  the mean gradient of a Gaussian over a densification window is the
+      FP32 running sum of its dL/dmu, one FP32 add per component and
+      iteration, divided by the number of iterations in which that gradient
+      was not zero (the Gaussian was hit); it is selected when the norm of
+      that average exceeds eps_mu (decided in FP64 from the FP32 sum).
+  D2  the radius is the mean of the diagonal of Sigma = R S S^T R^T; a
+      selected Gaussian is large when the radius exceeds eps_r.
+  D3  clone: the original stays and its copy's mean moves one step of
+      size `clone_step` against the average gradient, mu - step * g_avg
+      ("in the direction of the gradient" read as the descent direction).
+  D4  split: the original is replaced by two Gaussians whose log-scales are
+      reduced by ln(phi) (one FP32 subtraction) and whose means are draws
+      mu + R diag(s) z from the original pdf, z ~ N(0, I) passed in; every
+      other attribute is copied.
+  D5  prune: a Gaussian whose attenuation rho = sigmoid(logit) is below
+      eps_rho is removed; pruning follows densification and applies to the
+      new Gaussians too.
+  D6  output order: the survivors of Gaussian i come before those of i + 1;
+      a clone's original precedes its copy, a split's first child its
+      second; the gradient statistics restart at zero.
+
+  * adaptive density control: every N_mu iterations Gaussians whose mean
+    gradient exceeds eps_mu are cloned (radius <= eps_r) or split in two
+    (scales divided by phi, means drawn from the pdf); every N_rho iterations
+    Gaussians with attenuation below eps_rho are removed; eps_mu = 0.0002,
+    eps_r = 10, eps_rho = 0.004, phi = 1.6      -- App. (number of Gaussian
+                                                   updating), App. (training,
+                                                   parameter table)
 
 Parity pinning: tests/test_oracle_train.py pins SSIM against a pure-Python
 windowed-statistics loop and closed forms, the Fourier term against a literal
-double-sum DFT, every gradient against FP64 central differences, and the
-learning-rate schedule at its end points.
+double-sum DFT, every gradient against FP64 central differences, the
+learning-rate schedule at its end points, and density control against
+hand-built cases (each action, ordering, thresholds from both sides) and the
+sample covariance of split draws.
 """
 from __future__ import annotations
 
@@ -173,3 +203,82 @@ def sgd_step(params: dict, grads: dict, iteration: int, lrs: dict | None = None)
         # from a single rounding only at exact FP32 ties
         out[k] = (np.asarray(w, np.float64) - e32 * np.asarray(grads[k], np.float64)).astype(np.float32)
     return out
+
+
+# --------------------------------------------------------------------------
+# Adaptive density control (App. number of Gaussian updating; parameter table)
+# --------------------------------------------------------------------------
+
+EPS_MU = 0.0002
+EPS_R = 10.0
+EPS_RHO = 0.004
+PHI = 1.6
+
+
+def accumulate_grad_stats(acc: np.ndarray, cnt: np.ndarray, d_means: np.ndarray):
+    """One iteration of the window (reading D1): acc += dL/dmu in FP32, cnt += 1
+    where the gradient is not zero.  Returns new (acc, cnt)."""
+    g = np.asarray(d_means, np.float32)
+    acc = (np.asarray(acc, np.float32) + g).astype(np.float32)      # one IEEE FP32 add per component
+    cnt = np.asarray(cnt, np.int32) + np.any(g != 0, axis=1).astype(np.int32)
+    return acc, cnt
+
+
+def density_control(params: dict, acc: np.ndarray, cnt: np.ndarray, z: np.ndarray, *, clone_step: float,
+                    eps_mu: float = EPS_MU, eps_r: float = EPS_R, eps_rho: float = EPS_RHO, phi: float = PHI,
+                    densify: bool = True, prune: bool = True):
+    """Clone / split / prune (readings D1-D6).
+
+    params: FP32 arrays keyed means [G,3], log_scales [G,3], quats [G,4],
+    logits [G], coeffs [G,K,2]; acc [G,3] FP32 and cnt [G] the window's
+    statistics; z [G,2,3] FP32 standard normal draws for the split children.
+    Returns (new params, dict(clones, splits, pruned)): clones and splits count
+    selected Gaussians that survive pruning, pruned the removed originals.
+    """
+    from .gsrf_oracle import rotation_matrix
+    G = params["means"].shape[0]
+    mu = params["means"].astype(np.float64)
+    ls = params["log_scales"].astype(np.float64)
+    q = torch.tensor(params["quats"], dtype=F64)
+    R = rotation_matrix(q).numpy() if G else np.zeros((0, 3, 3))
+    s = np.exp(ls)
+    Sigma = R @ (s[:, :, None] ** 2 * np.transpose(R, (0, 2, 1)))   # R S S^T R^T
+    radius = np.trace(Sigma, axis1=1, axis2=2) / 3.0
+    a64 = np.asarray(acc, np.float32).astype(np.float64)
+    n = np.asarray(cnt, np.int64)
+    sel = densify & (n > 0) & ((a64 * a64).sum(1) > (eps_mu * n.astype(np.float64)) ** 2)
+    big = radius > eps_r
+    rho = 1.0 / (1.0 + np.exp(-params["logits"].astype(np.float64)))
+    gone = prune & (rho < eps_rho)
+    out = {k: [] for k in params}
+    stats = dict(clones=0, splits=0, pruned=0)
+    ln_phi = np.float32(math.log(phi))
+    for i in range(G):
+        if sel[i] and not big[i]:
+            kids = [("keep", None), ("clone", None)]
+        elif sel[i]:
+            kids = [("split", 0), ("split", 1)]
+        else:
+            kids = [("keep", None)]
+        if gone[i]:
+            stats["pruned"] += 1
+            continue
+        if sel[i]:
+            stats["splits" if big[i] else "clones"] += 1
+        for kind, c in kids:
+            m = params["means"][i]
+            l = params["log_scales"][i]
+            if kind == "clone":
+                m = (mu[i] - clone_step * (a64[i] / n[i])).astype(np.float32)
+            elif kind == "split":
+                m = (mu[i] + R[i] @ (s[i] * z[i, c].astype(np.float64))).astype(np.float32)
+                l = (params["log_scales"][i] - ln_phi).astype(np.float32)     # FP32 subtraction
+            out["means"].append(np.asarray(m, np.float32))
+            out["log_scales"].append(np.asarray(l, np.float32))
+            out["quats"].append(params["quats"][i])
+            out["logits"].append(params["logits"][i])
+            out["coeffs"].append(params["coeffs"][i])
+    K = params["coeffs"].shape[1]
+    shapes = dict(means=(0, 3), log_scales=(0, 3), quats=(0, 4), logits=(0,), coeffs=(0, K, 2))
+    res = {k: (np.stack(v).astype(np.float32) if v else np.zeros(shapes[k], np.float32)) for k, v in out.items()}
+    return res, stats

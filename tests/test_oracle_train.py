@@ -169,3 +169,99 @@ def test_sgd_step_rounds_once():
             lo, hi = np.nextafter(o, np.float32(-np.inf)), np.nextafter(o, np.float32(np.inf))
             d = abs(Fraction(float(o)) - exact)
             assert d <= abs(Fraction(float(lo)) - exact) and d <= abs(Fraction(float(hi)) - exact)
+
+
+def _gauss(n, K=1):
+    return dict(means=np.zeros((n, 3), np.float32), log_scales=np.full((n, 3), -2.0, np.float32),
+                quats=np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)), logits=np.zeros(n, np.float32),
+                coeffs=np.zeros((n, K, 2), np.float32))
+
+
+def test_grad_stats_accumulate_in_fp32_and_count_hits():
+    acc, cnt = np.zeros((3, 3), np.float32), np.zeros(3, np.int32)
+    g1 = np.array([[1e8, 0, 0], [0, 0, 0], [1, 2, 3]], np.float32)
+    g2 = np.array([[1, 0, 0], [0, 0, 0], [0, 0, -1]], np.float32)
+    acc, cnt = to.accumulate_grad_stats(acc, cnt, g1)
+    acc, cnt = to.accumulate_grad_stats(acc, cnt, g2)
+    assert acc[0, 0] == np.float32(1e8)          # 1e8 + 1 rounds back in FP32
+    assert list(cnt) == [2, 0, 2] and np.array_equal(acc[2], np.array([1, 2, 2], np.float32))
+
+
+def test_density_control_actions_by_hand():
+    p = _gauss(6)
+    p["means"][:] = np.arange(18, dtype=np.float32).reshape(6, 3)
+    p["coeffs"][:, 0, 0] = np.arange(6)
+    p["log_scales"][2] = np.log(4.0)              # radius = mean of diag Sigma = 16 > 10: large
+    p["logits"][3] = -8.0                         # rho = 3.4e-4 < 0.004: pruned
+    p["logits"][5] = -8.0
+    eps = 0.0002
+    acc = np.zeros((6, 3), np.float32)
+    cnt = np.array([0, 2, 4, 1, 2, 3], np.int32)
+    acc[1] = [0.004, 0.0, 0.0]                   # average 0.002 > eps: clone
+    acc[2] = [0.0, 0.0, -0.008]                  # average 0.002: split (large)
+    acc[3] = [1.0, 0.0, 0.0]
+    acc[4] = [2 * eps * 0.999, 0.0, 0.0]         # just below the threshold: kept as is
+    acc[5] = [1.0, 1.0, 1.0]                     # selected but pruned: nothing survives
+    z = np.zeros((6, 2, 3), np.float32)
+    z[2, 0] = [1.0, 0.0, 0.0]
+    z[2, 1] = [0.0, -0.5, 2.0]
+    out, st = to.density_control(p, acc, cnt, z, clone_step=0.5)
+    assert st == dict(clones=1, splits=1, pruned=2)
+    # order: 0, 1, copy of 1, children of 2, 4
+    assert np.array_equal(out["coeffs"][:, 0, 0], np.array([0, 1, 1, 2, 2, 4], np.float32))
+    assert np.array_equal(out["means"][0], p["means"][0]) and np.array_equal(out["means"][1], p["means"][1])
+    assert np.allclose(out["means"][2], p["means"][1] - 0.5 * np.array([0.002, 0, 0]), rtol=0, atol=1e-6)
+    # split with R = I: mu + s * z, log-scale reduced by ln 1.6
+    assert np.allclose(out["means"][3], p["means"][2] + 4.0 * np.array([1.0, 0, 0]), atol=1e-6)
+    assert np.allclose(out["means"][4], p["means"][2] + 4.0 * np.array([0.0, -0.5, 2.0]), atol=1e-6)
+    assert np.allclose(out["log_scales"][3:5], np.log(4.0) - np.log(1.6), atol=1e-6)
+    assert np.array_equal(out["log_scales"][2], p["log_scales"][1])
+    assert np.array_equal(out["means"][5], p["means"][4])
+    # switches: no densification keeps every selected one, no pruning keeps the faint ones
+    out2, st2 = to.density_control(p, acc, cnt, z, clone_step=0.5, densify=False)
+    assert st2 == dict(clones=0, splits=0, pruned=2) and out2["means"].shape == (4, 3)
+    out3, st3 = to.density_control(p, acc, cnt, z, clone_step=0.5, prune=False)
+    assert st3 == dict(clones=3, splits=1, pruned=0) and out3["means"].shape == (10, 3)   # 1, 3, 5 cloned
+
+
+def test_split_rotates_the_draw_and_matches_the_pdf():
+    from scipy.spatial.transform import Rotation
+    # 90 degrees about z: the body x axis points along world y
+    p = _gauss(1)
+    p["quats"][0] = [np.cos(np.pi / 4), 0, 0, np.sin(np.pi / 4)]
+    p["log_scales"][0] = np.log([8.0, 1.0, 1.0])
+    acc, cnt = np.array([[1.0, 0, 0]], np.float32), np.array([1], np.int32)
+    z = np.array([[[1.0, 0, 0], [0, 0, 1.0]]], np.float32)
+    out, st = to.density_control(p, acc, cnt, z, clone_step=0.0)
+    assert st["splits"] == 1
+    assert np.allclose(out["means"][0], [0, 8.0, 0], atol=1e-5) and np.allclose(out["means"][1], [0, 0, 1.0], atol=1e-6)
+    # many splits of one random Gaussian: the children's sample covariance is Sigma
+    rng = np.random.default_rng(30)
+    n = 20000
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    s = np.array([3.0, 2.0, 5.0])
+    p = _gauss(n)
+    p["quats"][:] = q.astype(np.float32)
+    p["log_scales"][:] = np.log(s).astype(np.float32)
+    acc = np.ones((n, 3), np.float32)
+    cnt = np.ones(n, np.int32)
+    z = rng.normal(size=(n, 2, 3)).astype(np.float32)
+    out, _ = to.density_control(p, acc, cnt, z, clone_step=0.0)
+    R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    sigma = R @ np.diag(np.exp(2 * np.log(s.astype(np.float32).astype(np.float64)))) @ R.T
+    emp = np.cov(out["means"].astype(np.float64).T)
+    assert np.allclose(emp, sigma, atol=0.05 * np.abs(sigma).max())
+
+
+def test_radius_threshold_is_rotation_invariant():
+    p = _gauss(2)
+    p["log_scales"][:] = np.log([np.sqrt(10.5), np.sqrt(10.5), np.sqrt(10.5)]).astype(np.float32)  # radius 10.5
+    p["quats"][1] = [0.3, -0.5, 0.7, 0.1]
+    acc, cnt = np.ones((2, 3), np.float32), np.ones(2, np.int32)
+    z = np.zeros((2, 2, 3), np.float32)
+    _, st = to.density_control(p, acc, cnt, z, clone_step=0.0)
+    assert st["splits"] == 2
+    p["log_scales"][:] = np.log([np.sqrt(9.5)] * 3).astype(np.float32)
+    _, st = to.density_control(p, acc, cnt, z, clone_step=0.0)
+    assert st["clones"] == 2
