@@ -345,6 +345,68 @@ gsrf_status gsrf_sgd_step(int64_t n_gauss, int32_t fle_L, float *means, float *l
                           const float *d_quats, const float *d_logits, const float *d_coeffs,
                           const gsrf_sgd_lr *lr, int64_t iteration, void *stream);
 
+/*
+ * Adaptive density control (App. number of Gaussian updating).  Over a window
+ * of N_mu iterations the caller accumulates each Gaussian's mean gradient;
+ * then gsrf_density_control clones, splits and prunes in one pass.
+ *
+ * gsrf_grad_stats_accumulate: acc[G,3] += d_means[G,3] (one FP32 add per
+ * component, so the sum is exact to the iteration order) and count[G] += 1
+ * where d_means is not zero (the Gaussian was hit).  Start a window with both
+ * zeroed; gsrf_density_control zeroes its outputs' statistics.
+ */
+gsrf_status gsrf_grad_stats_accumulate(int64_t n_gauss, const float *d_means, float *acc, int32_t *count,
+                                       void *stream);
+
+/* Thresholds of gsrf_density_control (App. parameter table: eps_mu = 0.0002,
+ * eps_r = 10, eps_rho = 0.004, phi = 1.6). */
+typedef struct gsrf_density_params {
+  double eps_mu;      /* mean-gradient threshold: |acc / count| > eps_mu selects */
+  double eps_r;       /* radius threshold: mean of diag Sigma > eps_r splits, else clones */
+  double eps_rho;     /* attenuation threshold: sigmoid(logit) < eps_rho prunes */
+  double phi;         /* split scale divisor (> 1) */
+  double clone_step;  /* a clone's copy moves to mu - clone_step * acc / count */
+  int32_t densify;    /* 0: no clone or split this call */
+  int32_t prune;      /* 0: no pruning this call */
+} gsrf_density_params;
+
+/* Device workspace (bytes) of gsrf_density_control for n_gauss Gaussians. */
+gsrf_status gsrf_density_workspace_size(int64_t n_gauss, size_t *bytes);
+
+/*
+ * Clone, split and prune (App. number of Gaussian updating), every decision
+ * in FP64:
+ *   selected  densify and count > 0 and |acc| > eps_mu * count;
+ *   clone     selected with radius = mean of the diagonal of R S S^T R^T
+ *             <= eps_r: the Gaussian and a copy whose mean is
+ *             mu - clone_step * acc / count (the shift along the averaged
+ *             gradient's descent direction);
+ *   split     selected with radius > eps_r: two Gaussians with log-scales
+ *             reduced by ln(phi) and means mu + R diag(s) z_c drawn from the
+ *             original pdf, z = z_draws[i, c, :] (standard normal, caller's);
+ *   pruned    prune and sigmoid(logit) < eps_rho (also when selected).
+ * Every other attribute is copied.  Output order is stable: the outputs of
+ * Gaussian i precede those of i + 1, an original precedes its copy.
+ *   inputs     means [G,3], log_scales [G,3], quats [G,4], logits [G],
+ *              coeffs [G,K,2] (K = (fle_L + 1)^2), acc [G,3], count [G],
+ *              z_draws [G,2,3] (may be NULL when densify = 0)
+ *   outputs    o_* in the same layouts with room for out_capacity Gaussians:
+ *              out_capacity >= 2 G when densify, >= G otherwise; o_acc and
+ *              o_count are zeroed for the new window.  Outputs must not
+ *              overlap inputs.
+ *   counts     [4] int64 (device): Gaussians out, clones, splits, pruned
+ *   workspace  gsrf_density_workspace_size bytes (device)
+ *   params     HOST
+ * The new count is known on the device only: read counts[0] before using
+ * the outputs.
+ */
+gsrf_status gsrf_density_control(int64_t n_gauss, int32_t fle_L, const float *means, const float *log_scales,
+                                 const float *quats, const float *logits, const float *coeffs, const float *acc,
+                                 const int32_t *count, const float *z_draws, const gsrf_density_params *params,
+                                 int64_t out_capacity, float *o_means, float *o_log_scales, float *o_quats,
+                                 float *o_logits, float *o_coeffs, float *o_acc, int32_t *o_count, int64_t *counts,
+                                 void *workspace, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,11 @@ class GsrfSgdLr(ctypes.Structure):
                 ("quat", c_f64), ("logit", c_f64), ("coeff", c_f64)]
 
 
+class GsrfDensityParams(ctypes.Structure):
+    _fields_ = [("eps_mu", c_f64), ("eps_r", c_f64), ("eps_rho", c_f64), ("phi", c_f64), ("clone_step", c_f64),
+                ("densify", c_i32), ("prune", c_i32)]
+
+
 assert ctypes.sizeof(GsrfPair) == 40
 
 GSRF_LOSS_RSSI_DB, GSRF_LOSS_COMPLEX_L2 = 0, 1
@@ -58,7 +63,7 @@ EXPORTS = ["gsrf_status_str", "gsrf_last_error", "gsrf_workspace_size", "gsrf_la
            "gsrf_splat_count", "gsrf_bin_sort", "gsrf_render_fwd", "gsrf_render_fwd_multi", "gsrf_render_bwd",
            "gsrf_render_stats",
            "gsrf_set_kernel_events", "gsrf_loss_workspace_size", "gsrf_loss_spectrum", "gsrf_loss_single",
-           "gsrf_sgd_step"]
+           "gsrf_sgd_step", "gsrf_grad_stats_accumulate", "gsrf_density_workspace_size", "gsrf_density_control"]
 
 _lib = None
 
@@ -90,6 +95,9 @@ def lib() -> ctypes.CDLL:
     L.gsrf_loss_spectrum.argtypes = [c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_f32, c_vp, c_vp, c_vp, c_vp]
     L.gsrf_loss_single.argtypes = [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp]
     L.gsrf_sgd_step.argtypes = [c_i64, c_i32] + [c_vp] * 10 + [P(GsrfSgdLr), c_i64, c_vp]
+    L.gsrf_grad_stats_accumulate.argtypes = [c_i64, c_vp, c_vp, c_vp, c_vp]
+    L.gsrf_density_workspace_size.argtypes = [c_i64, P(c_sz)]
+    L.gsrf_density_control.argtypes = ([c_i64, c_i32] + [c_vp] * 8 + [P(GsrfDensityParams), c_i64] + [c_vp] * 10)
     for n in EXPORTS[2:]:
         getattr(L, n).restype = c_i32
     _lib = L

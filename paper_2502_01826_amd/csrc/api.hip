@@ -319,6 +319,54 @@ gsrf_status gsrf_sgd_step(int64_t n_gauss, int32_t fle_L, float *means, float *l
   return dev(launch_sgd(n_gauss, fle_K(fle_L), w, g, eta, (hipStream_t)stream), "gsrf_sgd_step");
 }
 
+gsrf_status gsrf_grad_stats_accumulate(int64_t n_gauss, const float *d_means, float *acc, int32_t *count,
+                                       void *stream) {
+  if (n_gauss < 0 || n_gauss >= ((int64_t)1 << 31)) return fail(GSRF_EINVAL, "n_gauss = %lld", (long long)n_gauss);
+  if (n_gauss > 0 && (!d_means || !acc || !count)) return fail(GSRF_EINVAL, "d_means, acc or count is NULL");
+  return dev(launch_grad_accum(n_gauss, d_means, acc, count, (hipStream_t)stream), "gsrf_grad_stats_accumulate");
+}
+
+gsrf_status gsrf_density_workspace_size(int64_t n_gauss, size_t *bytes) {
+  if (!bytes) return fail(GSRF_EINVAL, "bytes is NULL");
+  if (n_gauss < 0 || n_gauss >= ((int64_t)1 << 31)) return fail(GSRF_EINVAL, "n_gauss = %lld", (long long)n_gauss);
+  *bytes = density_workspace_bytes(n_gauss);
+  return GSRF_OK;
+}
+
+gsrf_status gsrf_density_control(int64_t n_gauss, int32_t fle_L, const float *means, const float *log_scales,
+                                 const float *quats, const float *logits, const float *coeffs, const float *acc,
+                                 const int32_t *count, const float *z_draws, const gsrf_density_params *params,
+                                 int64_t out_capacity, float *o_means, float *o_log_scales, float *o_quats,
+                                 float *o_logits, float *o_coeffs, float *o_acc, int32_t *o_count, int64_t *counts,
+                                 void *workspace, void *stream) {
+  if (n_gauss < 0 || n_gauss >= ((int64_t)1 << 30)) return fail(GSRF_EINVAL, "n_gauss = %lld", (long long)n_gauss);
+  if (fle_L < 0 || fle_L > 6) return fail(GSRF_EINVAL, "fle_L = %d outside [0, 6]", fle_L);
+  if (!params) return fail(GSRF_EINVAL, "params (host) is NULL");
+  const gsrf_density_params &d = *params;
+  if (!(d.eps_mu >= 0.0) || !isfinite(d.eps_mu) || !(d.eps_r >= 0.0) || !isfinite(d.eps_r) || !isfinite(d.eps_rho) ||
+      !(d.phi > 1.0) || !isfinite(d.phi) || !isfinite(d.clone_step))
+    return fail(GSRF_EINVAL, "density thresholds: need finite eps_mu, eps_r >= 0, eps_rho, clone_step and phi > 1");
+  const int64_t need = d.densify ? 2 * n_gauss : n_gauss;
+  if (out_capacity < need)
+    return fail(GSRF_EINVAL, "out_capacity = %lld < %lld", (long long)out_capacity, (long long)need);
+  if (!counts || !workspace) return fail(GSRF_EINVAL, "counts or workspace is NULL");
+  if (n_gauss > 0 && (!means || !log_scales || !quats || !logits || !coeffs || !acc || !count ||
+                      (d.densify && !z_draws) || !o_means || !o_log_scales || !o_quats || !o_logits || !o_coeffs ||
+                      !o_acc || !o_count))
+    return fail(GSRF_EINVAL, "an input or output pointer is NULL");
+  DensityIO io{};
+  io.means = means; io.log_scales = log_scales; io.quats = quats; io.logits = logits; io.coeffs = coeffs;
+  io.acc = acc; io.cnt = count; io.z = z_draws;
+  io.n = n_gauss; io.K = fle_K(fle_L);
+  io.eps_mu = d.eps_mu; io.eps_r = d.eps_r; io.eps_rho = d.eps_rho; io.clone_step = d.clone_step;
+  io.ln_phi = (float)log(d.phi); io.densify = d.densify != 0; io.prune = d.prune != 0;
+  io.o_means = o_means; io.o_log_scales = o_log_scales; io.o_quats = o_quats; io.o_logits = o_logits;
+  io.o_coeffs = o_coeffs; io.o_acc = o_acc; io.o_cnt = o_count;
+  io.counts = counts;
+  io.ws = workspace;
+  return dev(launch_density_control(io, (hipStream_t)stream), "gsrf_density_control");
+}
+
 gsrf_status gsrf_set_kernel_events(void *fwd_start, void *fwd_stop, void *bwd_start, void *bwd_stop) {
   g_kernel_events[0] = (hipEvent_t)fwd_start;
   g_kernel_events[1] = (hipEvent_t)fwd_stop;

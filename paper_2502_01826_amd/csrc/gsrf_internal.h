@@ -150,6 +150,24 @@ hipError_t launch_loss_single(const float *signal_sum, const float *target, int3
 hipError_t launch_sgd(int64_t n_gauss, int K, float *const w[5], const float *const g[5], const float eta[5],
                       hipStream_t s);
 
+// Adaptive density control (density.hip).
+struct DensityIO {
+  const float *means, *log_scales, *quats, *logits, *coeffs, *acc, *z;
+  const int32_t *cnt;
+  int64_t n;
+  int K;
+  double eps_mu, eps_r, eps_rho, clone_step;
+  float ln_phi;
+  int densify, prune;
+  float *o_means, *o_log_scales, *o_quats, *o_logits, *o_coeffs, *o_acc;
+  int32_t *o_cnt;
+  int64_t *counts;
+  void *ws;
+};
+size_t density_workspace_bytes(int64_t n);
+hipError_t launch_grad_accum(int64_t n, const float *d_means, float *acc, int32_t *cnt, hipStream_t s);
+hipError_t launch_density_control(const DensityIO &io, hipStream_t s);
+
 // Dynamic LDS available to one workgroup on the current device (bytes).
 size_t max_lds_per_block();
 

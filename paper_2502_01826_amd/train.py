@@ -7,7 +7,10 @@ marshalling only; the work runs in libgsrf.so):
 * ``loss_single`` -- single-antenna losses on S_hat (RSSI in dBm, or complex
   squared error; Sec. 3.4);
 * ``sgd_step`` -- the per-attribute SGD update with the decaying mean
-  learning rate (App. Gaussian primitive optimization; App. training).
+  learning rate (App. Gaussian primitive optimization; App. training);
+* ``GradStats`` / ``density_control`` -- the mean-gradient statistics of a
+  window of iterations and the clone / split / prune pass (App. number of
+  Gaussian updating).
 """
 from __future__ import annotations
 
@@ -17,7 +20,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import GsrfSgdLr, check
+from ._lib import GsrfDensityParams, GsrfSgdLr, check
 from .render import FIELDS, _stream_handle
 
 RSSI_DB, COMPLEX_L2 = _lib.GSRF_LOSS_RSSI_DB, _lib.GSRF_LOSS_COMPLEX_L2
@@ -108,3 +111,69 @@ def sgd_step(params, grads, iteration: int, fle_L: int, lr: LearningRates | None
     c = lr.c()
     check(_lib.lib().gsrf_sgd_step(G, int(fle_L), *(t.data_ptr() for t in p), *(t.data_ptr() for t in g),
                                    ctypes.byref(c), int(iteration), _stream_handle(stream)), "gsrf_sgd_step")
+
+
+class GradStats:
+    """Per-Gaussian running sum of dL/dmu and the number of iterations with a
+    nonzero one, over a densification window."""
+
+    def __init__(self, n_gauss: int, device=None, acc=None, count=None):
+        dev = torch.device(device or "cuda")
+        self.acc = acc if acc is not None else torch.zeros((n_gauss, 3), dtype=torch.float32, device=dev)
+        self.count = count if count is not None else torch.zeros((n_gauss,), dtype=torch.int32, device=dev)
+
+    def accumulate(self, d_means, stream=None):
+        G = self.acc.shape[0]
+        _f32(d_means, (G, 3), "d_means")
+        check(_lib.lib().gsrf_grad_stats_accumulate(G, d_means.data_ptr(), self.acc.data_ptr(), self.count.data_ptr(),
+                                                    _stream_handle(stream)), "gsrf_grad_stats_accumulate")
+
+
+@dataclass
+class DensityParams:
+    """App. parameter table: eps_mu = 0.0002, eps_r = 10, eps_rho = 0.004, phi = 1.6."""
+    eps_mu: float = 0.0002
+    eps_r: float = 10.0
+    eps_rho: float = 0.004
+    phi: float = 1.6
+    clone_step: float = 1.6e-4
+    densify: bool = True
+    prune: bool = True
+
+    def c(self) -> GsrfDensityParams:
+        return GsrfDensityParams(self.eps_mu, self.eps_r, self.eps_rho, self.phi, self.clone_step, int(self.densify),
+                                 int(self.prune))
+
+
+def density_control(params, stats: GradStats, z_draws, fle_L: int, dp: DensityParams | None = None, stream=None):
+    """Clone / split / prune.  params: 5-tuple or dict (FIELDS order);
+    z_draws [G, 2, 3] standard normal (None when not densifying).  Returns
+    (new params tuple, new GradStats, dict(n, clones, splits, pruned)); reads
+    the new count back (one host synchronisation)."""
+    dp = dp or DensityParams()
+    p = [params[k] for k in FIELDS] if isinstance(params, dict) else list(params)
+    G = p[0].shape[0]
+    K = (fle_L + 1) ** 2
+    for t, shape, name in zip(p, [(G, 3), (G, 3), (G, 4), (G,), (G, K, 2)], FIELDS):
+        _f32(t, shape, name)
+    if dp.densify:
+        _f32(z_draws, (G, 2, 3), "z_draws")
+    dev = p[0].device
+    cap = 2 * G if dp.densify else G
+    e = lambda *s_: torch.empty(s_, dtype=torch.float32, device=dev)
+    out = [e(cap, 3), e(cap, 3), e(cap, 4), e(cap), e(cap, K, 2)]
+    o_acc = e(cap, 3)
+    o_cnt = torch.empty((cap,), dtype=torch.int32, device=dev)
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    nb = ctypes.c_size_t(0)
+    check(_lib.lib().gsrf_density_workspace_size(G, ctypes.byref(nb)), "gsrf_density_workspace_size")
+    ws = torch.empty(max(int(nb.value), 8), dtype=torch.uint8, device=dev)
+    c = dp.c()
+    check(_lib.lib().gsrf_density_control(G, int(fle_L), *(t.data_ptr() for t in p), stats.acc.data_ptr(),
+                                          stats.count.data_ptr(), _ptr(z_draws) if dp.densify else None,
+                                          ctypes.byref(c), cap, *(t.data_ptr() for t in out), o_acc.data_ptr(),
+                                          o_cnt.data_ptr(), counts.data_ptr(), ws.data_ptr(), _stream_handle(stream)),
+          "gsrf_density_control")
+    n, clones, splits, pruned = (int(v) for v in counts.cpu())
+    new = tuple(t[:n] for t in out)
+    return new, GradStats(n, dev, o_acc[:n], o_cnt[:n]), dict(n=n, clones=clones, splits=splits, pruned=pruned)

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "gsrf.h")
 
 from paper_2502_01826_amd import _lib  # noqa: E402
-from paper_2502_01826_amd._lib import GsrfGrid, GsrfLayout, GsrfPair, GsrfProblem, GsrfSgdLr  # noqa: E402
+from paper_2502_01826_amd._lib import (GsrfDensityParams, GsrfGrid, GsrfLayout, GsrfPair, GsrfProblem,  # noqa: E402
+                                      GsrfSgdLr)
 
 
 def declared_functions():
@@ -49,6 +50,8 @@ int main(void) {
   P(gsrf_layout, n_records); P(gsrf_layout, n_tiles_az);
   printf("sizeof_sgd_lr %zu\n", sizeof(gsrf_sgd_lr));
   P(gsrf_sgd_lr, mean_steps); P(gsrf_sgd_lr, coeff);
+  printf("sizeof_density %zu\n", sizeof(gsrf_density_params));
+  P(gsrf_density_params, clone_step); P(gsrf_density_params, prune);
   return 0;
 }
 """
@@ -71,6 +74,9 @@ int main(void) {
     assert int(vals["sizeof_sgd_lr"]) == ctypes.sizeof(GsrfSgdLr)
     for f in ("mean_steps", "coeff"):
         assert int(vals[f"gsrf_sgd_lr.{f}"]) == getattr(GsrfSgdLr, f).offset
+    assert int(vals["sizeof_density"]) == ctypes.sizeof(GsrfDensityParams)
+    for f in ("clone_step", "prune"):
+        assert int(vals[f"gsrf_density_params.{f}"]) == getattr(GsrfDensityParams, f).offset
 
 
 def _host_problem(n_gauss=10, n_pairs=2, grid=None, cap=1000):
@@ -197,3 +203,20 @@ def test_training_steps_validate_before_launching():
     assert L.gsrf_sgd_step(0, 2, *([None] * 10), ctypes.byref(bad), 0, None) == _lib.GSRF_EINVAL
     bad = GsrfSgdLr(1.6e-4, 1.6e-6, 30000, -0.01, 0.005, 0.01, 0.0025)
     assert L.gsrf_sgd_step(0, 2, *([None] * 10), ctypes.byref(bad), 0, None) == _lib.GSRF_EINVAL
+
+
+def test_density_control_validates_before_launching():
+    L = _lib.lib()
+    nb = ctypes.c_size_t()
+    assert L.gsrf_density_workspace_size(200_000, ctypes.byref(nb)) == _lib.GSRF_OK
+    assert nb.value == (200_000 // 1024 + 1 + 1) * 8
+    dp = GsrfDensityParams(0.0002, 10.0, 0.004, 1.6, 1.6e-4, 1, 1)
+    args = lambda n, cap, p: (n, 2, *([None] * 8), ctypes.byref(p) if p else None, cap, *([None] * 10))
+    assert L.gsrf_density_control(*args(10, 20, dp)) == _lib.GSRF_EINVAL                 # no device pointers
+    assert L.gsrf_density_control(*args(10, 19, dp)) == _lib.GSRF_EINVAL                 # capacity < 2 G
+    assert "out_capacity" in L.gsrf_last_error().decode()
+    assert L.gsrf_density_control(*args(10, 20, None)) == _lib.GSRF_EINVAL
+    bad = GsrfDensityParams(0.0002, 10.0, 0.004, 1.0, 1.6e-4, 1, 1)                      # phi must exceed 1
+    assert L.gsrf_density_control(*args(10, 20, bad)) == _lib.GSRF_EINVAL
+    assert L.gsrf_grad_stats_accumulate(10, None, None, None, None) == _lib.GSRF_EINVAL
+    assert L.gsrf_grad_stats_accumulate(0, None, None, None, None) == _lib.GSRF_OK

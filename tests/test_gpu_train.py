@@ -159,3 +159,63 @@ def test_training_iteration_descends():
     drop = l0 - l1
     say(f"loss {l0:.6e} -> {l1:.6e}, predicted drop {eta * g2:.3e}, got {drop:.3e}")
     assert 0.5 * eta * g2 < drop < 1.5 * eta * g2
+
+
+def test_grad_stats_accumulate_bit_exact():
+    rng = np.random.default_rng(40)
+    G = 3001
+    acc, cnt = np.zeros((G, 3), np.float32), np.zeros(G, np.int32)
+    st = tr.GradStats(G)
+    for it in range(3):
+        g = rng.normal(0, 1e-3, (G, 3)).astype(np.float32)
+        g[rng.random(G) < 0.3] = 0.0                      # Gaussians no ray hit this iteration
+        acc, cnt = to.accumulate_grad_stats(acc, cnt, g)
+        st.accumulate(torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(st.acc.cpu().numpy().view(np.uint32), acc.view(np.uint32))
+    assert np.array_equal(st.count.cpu().numpy(), cnt)
+
+
+def _population(G, seed):
+    rng = np.random.default_rng(seed)
+    p = dict(means=rng.uniform(-5, 5, (G, 3)).astype(np.float32),
+             log_scales=rng.normal(0.5, 0.9, (G, 3)).astype(np.float32),
+             quats=rng.normal(0, 1, (G, 4)).astype(np.float32),
+             logits=rng.normal(-3, 2, G).astype(np.float32),
+             coeffs=rng.normal(0, 0.3, (G, 9, 2)).astype(np.float32))
+    cnt = rng.integers(0, 6, G).astype(np.int32)
+    acc = (rng.normal(0, 1, (G, 3)) * 3e-4 * np.maximum(cnt, 1)[:, None]).astype(np.float32)
+    acc[cnt == 0] = 0.0
+    z = rng.normal(0, 1, (G, 2, 3)).astype(np.float32)
+    return p, acc, cnt, z
+
+
+@pytest.mark.parametrize("G,densify,prune", [(5000, True, True), (5000, False, True), (5000, True, False),
+                                             (1, True, True), (0, True, True)])
+def test_density_control_matches_oracle(G, densify, prune):
+    """Several 1024-Gaussian blocks with a ragged last one, both switches, one
+    Gaussian and none: every action, the stable order and the counts."""
+    say("density control", G, densify, prune)
+    p, acc, cnt, z = _population(G, 41 + G)
+    if G == 1:
+        acc[0], cnt[0], p["logits"][0] = [1.0, 0.0, 0.0], 1, 0.0
+    step = 1.6e-4
+    want, st = to.density_control(p, acc, cnt, z, clone_step=step, densify=densify, prune=prune)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
+    stats = tr.GradStats(G, acc=torch.from_numpy(acc).cuda(), count=torch.from_numpy(cnt).cuda())
+    dp = tr.DensityParams(clone_step=step, densify=densify, prune=prune)
+    new, nstats, counts = tr.density_control(dev, stats, torch.from_numpy(z).cuda() if densify else None, 2, dp)
+    torch.cuda.synchronize()
+    say("  ", counts, st)
+    assert counts == dict(n=want["means"].shape[0], **st)
+    if G == 5000 and densify:
+        assert st["clones"] > 0 and st["splits"] > 0
+    if G == 5000 and prune:
+        assert st["pruned"] > 0
+    got = dict(zip(("means", "log_scales", "quats", "logits", "coeffs"), (t.cpu().numpy() for t in new)))
+    for k in ("log_scales", "quats", "logits", "coeffs"):
+        assert np.array_equal(got[k].view(np.uint32), want[k].view(np.uint32)), k
+    # means: kept and cloned ones bit for bit; split draws within one FP32 ulp (FP64 sums in another order)
+    ulp = np.spacing(np.abs(want["means"]).astype(np.float32))
+    assert np.all(np.abs(got["means"] - want["means"]) <= ulp), np.abs(got["means"] - want["means"]).max()
+    assert not nstats.acc.any() and not nstats.count.any()
