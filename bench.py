@@ -360,8 +360,9 @@ def main() -> int:
         """One training iteration per step on the plain pair: project, bin_sort,
         render_fwd, the antenna-array loss against a target spectrum (the power
         spectrum of a perturbed copy of the room), render_bwd with the loss's
-        gradient, and the SGD update of every attribute.  Eager launches (the
-        mean learning rate changes every iteration)."""
+        gradient, the mean-gradient statistics and the SGD update of every
+        attribute.  Eager launches (the mean learning rate changes every
+        iteration).  Then one density-control pass on the statistics."""
         from paper_2502_01826_amd import train as tr
         prob, bufs = make([pair])
         _, pert = synth.training_step(n=args.gaussians, grid=grid)
@@ -377,6 +378,7 @@ def main() -> int:
         lossb = torch.empty((1, 4), dtype=torch.float32, device=dev)
         gsig = torch.empty_like(bufs["sig"])
         params = (prob.means, prob.log_scales, prob.quats, prob.logits, prob.coeffs)
+        gstats = tr.GradStats(prob.n_gauss)
         steps = args.steps
         ev = {k: [new_event() for _ in range(steps)] for k in ("l0", "l1", "o0", "o1")}
         first_loss = []
@@ -394,6 +396,7 @@ def main() -> int:
                 prob.render_bwd(bufs["sig"], gsig, None, out=bufs["grads"])
                 if with_ev:
                     ev["o0"][i].record(stream)
+                gstats.accumulate(bufs["grads"][0])
                 tr.sgd_step(params, bufs["grads"], it0 + i, fle_L=grid.fle_L)
                 if with_ev:
                     ev["o1"][i].record(stream)
@@ -412,8 +415,22 @@ def main() -> int:
         n_splats, ok = prob.splat_count()
         G_, K = prob.n_gauss, grid.K
         sgd_bytes = G_ * (11 + 2 * K) * 4 * 3          # read w and g, write w
+        # one density-control pass on the window's statistics (every 100 iterations in the paper)
+        z = torch.from_numpy(np.random.default_rng(5).normal(0, 1, (G_, 2, 3)).astype(np.float32)).to(dev)
+        dp = tr.DensityParams(clone_step=tr.LearningRates().mean_init)
+        d_ev = [(new_event(), new_event()) for _ in range(5)]
+        for a_, b_ in d_ev:
+            a_.record(stream)
+            _, _, dcounts = tr.density_control(params, gstats, z, grid.fle_L, dp, read_counts=False)
+            b_.record(stream)
+        torch.cuda.synchronize()
+        t_dc = sorted(a_.elapsed_time(b_) for a_, b_ in d_ev)[2] * 1e-3
+        n_out, n_clone, n_split, n_pruned = (int(v) for v in dcounts.cpu())
+        row = (11 + 2 * K + 4) * 4                      # attributes + statistics per Gaussian
+        dc_bytes = G_ * (row + 24) + n_out * row         # read every Gaussian and its draws, write the survivors
         out = {"workload": "training iteration on the plain pair (200k Gaussians, 360x90 rays): project+bin_sort+"
-                           "render_fwd+loss_spectrum+render_bwd+sgd_step, loss (1-l1-l2) L1 + l1 SSIM + l2 Fourier "
+                           "render_fwd+loss_spectrum+render_bwd+grad_stats+sgd_step, loss (1-l1-l2) L1 + l1 SSIM + "
+                           "l2 Fourier "
                            f"with l1={lam1}, l2={lam2} against the spectrum of a perturbed room",
                "iterations_per_s": 1.0 / t_it, "ms_per_iteration": t_it * 1e3,
                "timing": f"{steps} eager iterations after {1 + args.warmup} untimed ones, wall clock between "
@@ -424,7 +441,17 @@ def main() -> int:
                                 "unit": "GB/s", "frac": sgd_bytes / t_sgd / PEAK_HBM, "traffic": None,
                                 "bytes_per_launch": sgd_bytes,
                                 "timing": "HIP events around the call on its stream (includes one launch gap)"},
-               "splats_within_capacity": bool(ok)}
+               "splats_within_capacity": bool(ok),
+               "density_control": {"ms": t_dc * 1e3, "gaussians_in": G_, "gaussians_out": n_out, "clones": n_clone,
+                                   "splits": n_split, "pruned": n_pruned,
+                                   "statistics": f"mean gradients accumulated over the {1 + args.warmup + steps} "
+                                                 "iterations above",
+                                   "timing": "median of 5 calls, HIP events around the call (count, scan and apply "
+                                             "kernels plus the binding's allocations)",
+                                   "roofline": {"bound": "hbm", "achieved": dc_bytes / t_dc / 1e9,
+                                                "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                                "frac": dc_bytes / t_dc / PEAK_HBM, "traffic": None,
+                                                "bytes_per_launch": dc_bytes}}}
         del prob, bufs, target, gsig
         torch.cuda.empty_cache()
         return out

@@ -145,11 +145,14 @@ class DensityParams:
                                  int(self.prune))
 
 
-def density_control(params, stats: GradStats, z_draws, fle_L: int, dp: DensityParams | None = None, stream=None):
+def density_control(params, stats: GradStats, z_draws, fle_L: int, dp: DensityParams | None = None, stream=None,
+                    read_counts: bool = True):
     """Clone / split / prune.  params: 5-tuple or dict (FIELDS order);
     z_draws [G, 2, 3] standard normal (None when not densifying).  Returns
     (new params tuple, new GradStats, dict(n, clones, splits, pruned)); reads
-    the new count back (one host synchronisation)."""
+    the new count back (one host synchronisation).  With read_counts=False it
+    returns the capacity-sized outputs and the device counts tensor instead,
+    without synchronising."""
     dp = dp or DensityParams()
     p = [params[k] for k in FIELDS] if isinstance(params, dict) else list(params)
     G = p[0].shape[0]
@@ -174,6 +177,8 @@ def density_control(params, stats: GradStats, z_draws, fle_L: int, dp: DensityPa
                                           ctypes.byref(c), cap, *(t.data_ptr() for t in out), o_acc.data_ptr(),
                                           o_cnt.data_ptr(), counts.data_ptr(), ws.data_ptr(), _stream_handle(stream)),
           "gsrf_density_control")
+    if not read_counts:
+        return tuple(out), (o_acc, o_cnt), counts
     n, clones, splits, pruned = (int(v) for v in counts.cpu())
     new = tuple(t[:n] for t in out)
     return new, GradStats(n, dev, o_acc[:n], o_cnt[:n]), dict(n=n, clones=clones, splits=splits, pruned=pruned)
