@@ -105,10 +105,10 @@ __device__ __forceinline__ void ray_load(int u, int v, const RenderArgs &a, floa
 // Stage Gaussian g into an LDS slot (FP64 geometry relative to RX and TX).
 // ---------------------------------------------------------------------------
 // txg (adjoint only, else null) receives the TX leg of dL/dt, the unit vector
-// (mu - tx)/|mu - tx|, and g's bits in w.  step_rev = (carrier step)/c for the
-// multi-carrier forward, else 0: g4.zw = ((|mu - tx| + D), D) * step_rev, so
+// (mu - tx)/|mu - tx|, and g's bits in w.  STEP (the multi-carrier forward):
+// g4.zw = ((|mu - tx| + D), D) * step_rev with step_rev = (carrier step)/c, so
 // that a hit at t adds (|mu - tx| + t) * step / c turns per carrier step.
-template <int K>
+template <int K, bool STEP = false>
 __device__ void stage_entry(const RenderArgs &a, uint32_t g, double rx, double ry, double rz, double tx,
                             double ty, double tz, double inv_lam, float4 *geo, float *cf, float4 *txg = nullptr,
                             double step_rev = 0.0) {
@@ -131,7 +131,10 @@ __device__ void stage_entry(const RenderArgs &a, uint32_t g, double rx, double r
                        (float)(D * inv_lam));
   geo[2] = q1;
   geo[3] = make_float4(q2.x, q2.y, q0.w, q2.z);
-  geo[4] = make_float4((float)(ph - floor(ph)), (float)D2, (float)((dtx + D) * step_rev), (float)(D * step_rev));
+  if constexpr (STEP)
+    geo[4] = make_float4((float)(ph - floor(ph)), (float)D2, (float)((dtx + D) * step_rev), (float)(D * step_rev));
+  else
+    geo[4] = make_float4((float)(ph - floor(ph)), (float)D2, 0.f, 0.f);
   if (txg) {
     const double it = dtx > 0.0 ? 1.0 / dtx : 0.0;
     *txg = make_float4((float)(qx * it), (float)(qy * it), (float)(qz * it), __uint_as_float(g));

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     const int nb = (int)min((uint32_t)B, s1 - base);
     __syncthreads();
     if (tid < nb)
-      stage_entry<K>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
+      stage_entry<K, MULTI>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                      sgeo + kGeo * tid, scf + 2 * K * tid, BWD ? stx + tid : nullptr, step_rev);
     if constexpr (BWD)
       for (int i = tid; i < nb; i += NT) {   // what the previous batch's flush left
