@@ -239,12 +239,17 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     const int tu_w = min(a.tw, a.n_az - tu * a.tw), tv_h = max(0, min(th_, a.n_el - v0));
     n_valid_rays = tu_w * tv_h;
   }
+  // each staging thread's list entry for the next batch is loaded one batch
+  // ahead, so staging waits for one global round trip (the entry's records), not two
+  uint32_t g_next = (tid < B && s0 + tid < s1) ? a.val[s0 + tid] : 0u;
   for (uint32_t base = s0; base < s1; base += B) {
     const int nb = (int)min((uint32_t)B, s1 - base);
     __syncthreads();
+    const uint32_t g_cur = g_next;
     if (tid < nb)
-      stage_entry<K, MULTI>(a, a.val[base + tid], pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
+      stage_entry<K, MULTI>(a, g_cur, pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                      sgeo + kGeo * tid, scf + 2 * K * tid, BWD ? stx + tid : nullptr, step_rev);
+    if (tid < B && base + B + tid < s1) g_next = a.val[base + B + tid];
     if constexpr (BWD)
       for (int i = tid; i < nb; i += NT) {   // what the previous batch's flush left
         sflag[i] = 0u;
