@@ -239,32 +239,51 @@ hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws,
   return hipGetLastError();
 }
 
-// S_hat of every (pair, carrier) of a multi-carrier render: one workgroup sums
-// the carrier's spectrum in FP64 in a fixed order.
-__global__ __launch_bounds__(256) void k_sum_multi(const float2 *__restrict__ multi, int64_t n_rays, int n_freq,
-                                                   float *__restrict__ signal_sum) {
-  __shared__ double sr[256], si[256];
-  const int f = blockIdx.x, k = blockIdx.y;
+// S_hat of every (pair, carrier) of a multi-carrier render: one workgroup of
+// 1024 threads sums the carrier's spectrum in FP64 in a fixed order (thread t
+// takes rays t, t + 1024, ... with four loads in flight, then the threads'
+// sums are reduced by wave butterflies and the 16 wave sums in wave order).
+constexpr int kSumThreads = 1024;
+__global__ __launch_bounds__(kSumThreads) void k_sum_multi(const float2 *__restrict__ multi, int64_t n_rays,
+                                                           int n_freq, float *__restrict__ signal_sum) {
+  __shared__ double wr[kSumThreads / 64], wi[kSumThreads / 64];
+  const int f = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
   const float2 *src = multi + ((size_t)k * n_freq + f) * n_rays;
   double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < n_rays; i += 256) {
+  int64_t i = tid;
+  for (; i + 3 * kSumThreads < n_rays; i += 4 * kSumThreads) {
+    const float2 x0 = src[i], x1 = src[i + kSumThreads], x2 = src[i + 2 * kSumThreads], x3 = src[i + 3 * kSumThreads];
+    a += (double)x0.x;
+    b += (double)x0.y;
+    a += (double)x1.x;
+    b += (double)x1.y;
+    a += (double)x2.x;
+    b += (double)x2.y;
+    a += (double)x3.x;
+    b += (double)x3.y;
+  }
+  for (; i < n_rays; i += kSumThreads) {
     const float2 x = src[i];
-    a += x.x;
-    b += x.y;
+    a += (double)x.x;
+    b += (double)x.y;
   }
-  sr[threadIdx.x] = a;
-  si[threadIdx.x] = b;
+  for (int d = 32; d >= 1; d >>= 1) {
+    a += __shfl_xor(a, d, 64);
+    b += __shfl_xor(b, d, 64);
+  }
+  if ((tid & 63) == 0) {
+    wr[tid >> 6] = a;
+    wi[tid >> 6] = b;
+  }
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      sr[threadIdx.x] += sr[threadIdx.x + off];
-      si[threadIdx.x] += si[threadIdx.x + off];
+  if (tid == 0) {
+    double x = 0.0, y = 0.0;
+    for (int w = 0; w < kSumThreads / 64; ++w) {
+      x += wr[w];
+      y += wi[w];
     }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    signal_sum[2 * ((size_t)k * n_freq + f)] = (float)sr[0];
-    signal_sum[2 * ((size_t)k * n_freq + f) + 1] = (float)si[0];
+    signal_sum[2 * ((size_t)k * n_freq + f)] = (float)x;
+    signal_sum[2 * ((size_t)k * n_freq + f) + 1] = (float)y;
   }
 }
 
@@ -303,7 +322,7 @@ hipError_t launch_render_fwd_multi(const gsrf_problem *p, const Layout &lay, cha
   }
   if (e != hipSuccess) return e;
   mark_kernel_event(1, s);
-  hipLaunchKernelGGL(k_sum_multi, dim3((unsigned)n_freq, (unsigned)p->n_pairs), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_sum_multi, dim3((unsigned)n_freq, (unsigned)p->n_pairs), dim3(kSumThreads), 0, s,
                      (const float2 *)signal, (int64_t)p->grid.n_el * p->grid.n_az, n_freq, signal_sum);
   return hipGetLastError();
 }
