@@ -125,6 +125,8 @@ def main() -> int:
     ap.add_argument("--tile", default="8x8", help="tile_w x tile_h (64, 128 or 256 rays)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="render traversal: 0 two-phase, or 1, 2, 4 lanes per ray (direct)")
+    ap.add_argument("--footprint", choices=("cap", "paper"), default="cap",
+                    help="splat binning: exact bounding cap, or the paper's 3 sqrt(lambda_max) footprint")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -140,7 +142,8 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     tw, th = (int(x) for x in args.tile.split("x"))
-    grid = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=args.lanes)
+    grid = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=args.lanes,
+                      footprint=int(args.footprint == "paper"))
     batch = synth.paper_scale(n=args.gaussians, grid=grid)
     scene, pair = batch.scenes[0], batch.pairs[0]
     params = dict(means=scene.means, log_scales=scene.log_scales, quats=scene.quats, logits=scene.logits,
@@ -293,7 +296,8 @@ def main() -> int:
         achieved = fl / tk
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VALU,
-                "traffic": measured_traffic(dom, f"{args.tile}/{args.lanes}/{args.gaussians}"), "kernel": dom,
+                "traffic": (measured_traffic(dom, f"{args.tile}/{args.lanes}/{args.gaussians}")
+                            if args.footprint == "cap" else None), "kernel": dom,
                 "kernel_ms": tk * 1e3, "flop_per_launch": fl, "timing": "HIP events recorded by the library "
                 "immediately around the render kernel on its stream, averaged over the timed steps",
                 "counts": {**stats, "splats": n_splats}}
@@ -507,7 +511,7 @@ def main() -> int:
         "config": {"workload": "paper-scale differentiated step: 200k Gaussians in a 10x8x3 m room, one TX/RX "
                                "pair, 360x90 rays, 5 GHz, FLE L=2; project+bin_sort+render_fwd+render_bwd",
                    "gaussians": args.gaussians, "rays": "360x90", "pairs": 1, "tile": args.tile,
-                   "lanes_per_ray": args.lanes},
+                   "lanes_per_ray": args.lanes, "footprint": args.footprint},
         "step_timing": "hipGraph replays of the captured step (project, bin_sort, render_fwd, render_bwd)",
         "step_ms_events": step_stats or None,
         "eager": eager or None,

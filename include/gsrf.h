@@ -65,6 +65,15 @@ typedef enum gsrf_status {
  *              1, 2 or 4: direct traversal, that many lanes per ray, each
  *              testing and processing a different entry.  Every value gives
  *              the same hit decisions; the results agree to rounding.
+ *   footprint  which rays' tiles a Gaussian is binned into (Sec. 3.3,
+ *              splatting).  0 (default): a cap that bounds the 3-sigma
+ *              ellipsoid exactly, so binning never drops a hit.  1: the
+ *              paper's footprint, the bounding square of the circle of radius
+ *              3 sqrt(lambda_max(J Sigma J^T)) around the projected centre,
+ *              J the Jacobian of the ray-index map at mu.  It linearises that
+ *              map, so hits of a ray outside the square are dropped.  Both
+ *              keep the exact per-ray 3-sigma test of the render.
+ *              GSRF_EINVAL for other values.
  */
 typedef struct gsrf_grid {
   int32_t n_az, n_el;
@@ -75,6 +84,7 @@ typedef struct gsrf_grid {
   float alpha_max;
   int32_t tile_w, tile_h;
   int32_t lanes_per_ray;
+  int32_t footprint;
 } gsrf_grid;
 
 /*

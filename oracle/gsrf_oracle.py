@@ -22,6 +22,8 @@ Paper passages followed (arXiv 2502.01826):
   * phase of a path of length d: 2 pi f d / c        -- Sec. 2 (RF propagation), worked example
   * single-antenna sum S_hat = sum_uv S_uv           -- Sec. 3.4 (loss, single antenna)
   * 64-bit splat key (tile | distance)               -- App. E (CUDA kernel paragraph)
+  * paper footprint Sigma2D = J Sigma J^T,
+    r_k = 3 sqrt(lambda_max), binning variant        -- Sec. 3.3 (splatting)
 
 Readings taken where the paper is silent or ambiguous:
   R1  transmittance amplitude is 1 - o*G(x_mid) with o = sigmoid(logit); its
@@ -316,12 +318,14 @@ def _candidates(P, act, rx, grid, dirs, order, chunk_cols=65536):
 
 
 def trace(scene_or_params, pair, grid, rays_uv=None, *, grad=False, bands: Bands | None = None,
-          ray_chunk: int = 64):
+          ray_chunk: int = 64, rects=None):
     """Render rays (u, v) of one TX/RX pair.
 
     Returns a dict with S (complex128 [R]), A_uv (condition scale
     sum_i T_i |c~_i|, [R]), n_active [R], marginal [R] (bool), and, if
     ``grad``, the differentiable real/imag tensors S_r, S_i and the Params.
+    ``rects`` (tu0, ntu, tv0, ntv, ...) restricts each ray to the Gaussians
+    whose tile rectangle holds the ray's tile (a non-conservative binning).
     """
     P = scene_or_params if isinstance(scene_or_params, Params) else Params.from_scene(scene_or_params, grad)
     bands = bands or Bands()
@@ -356,6 +360,9 @@ def trace(scene_or_params, pair, grid, rays_uv=None, *, grad=False, bands: Bands
             continue
         cols_t = torch.tensor(cols)
         terms = _per_ray_terms(P, act, rx, tx, lam, grid, dirs, Y, cols_t)
+        if rects is not None:
+            allow = torch.tensor(rect_allow(rects, grid, uv)[:, cols])
+            terms["disc"] = torch.where(allow, terms["disc"], torch.full_like(terms["disc"], -math.inf))
         S_r, S_i, A_uv, hit, active, T = _composite(terms, grid)
         out_r.append(S_r); out_i.append(S_i); out_A.append(A_uv)
         out_n.append(active.sum(1))
@@ -587,6 +594,110 @@ def cap_rects(means, log_scales, rx, grid):
     tu0 = np.where(visible, tu0, 0)
     tv0 = np.where(visible, tv0, 0)
     return tu0, ntu, tv0, ntv, marg
+
+
+def footprint_jacobian(e, grid):
+    """Jacobian (2 x 3, ray-index units) of the map x -> (u, v) at offset e = x - r.
+
+    u = alpha / d_alpha with alpha = atan2(e_y, e_x), v = (beta - el_lo) / d_beta
+    with beta = atan2(e_z, |e_xy|) (Sec. 3.3, eqs. spherical coords and
+    discretization).  Undefined on the vertical through the receiver.
+    """
+    ex, ey, ez = (float(c) for c in e)
+    n_az, n_el = grid.n_az, grid.n_el
+    dalpha = 2.0 * math.pi / n_az
+    dbeta = (_f32(grid.el_hi) - _f32(grid.el_lo)) / n_el
+    rho2 = ex * ex + ey * ey
+    rho = math.sqrt(rho2)
+    D2 = rho2 + ez * ez
+    ja = np.array([-ey / rho2, ex / rho2, 0.0]) / dalpha
+    jb = np.array([-ez * ex / (D2 * rho), -ez * ey / (D2 * rho), rho / D2]) / dbeta
+    return np.stack([ja, jb])
+
+
+def footprint_rects(means, log_scales, quats, rx, grid):
+    """Tile rectangle of each Gaussian's paper footprint, FP64 (reading R25, variant).
+
+    Sec. 3.3 (splatting): the projected centre (u_k, v_k) is the ray cell of
+    the direction mu - r (spherical coordinates, then floor discretisation);
+    Sigma2D = J Sigma J^T with J the Jacobian of that map at mu; the radius is
+    r_k = 3 sqrt(lambda_max(Sigma2D)), and rays with
+    (u - u_k)^2 + (v - v_k)^2 <= r_k^2 are the splat.  Binning keeps the
+    circle's bounding square u_k +- m, v_k +- m, m = floor(r_k), rows clipped
+    to the grid, columns modulo n_az.  Not conservative (J linearises the map).
+    The cap's exact guards stay: culled if D + Rb < r_rx (1 - 1e-6), every ray
+    covered if D <= Rb (1 + 1e-6) (Rb = 3 max s), every column covered on the
+    receiver's vertical or when 2m + 1 >= n_az.
+
+    Returns (tu0, ntu, tv0, ntv, marginal) like ``cap_rects``; marginal flags a
+    floor within 1e-9 (relative) of an integer.
+    """
+    mu = np.asarray(means, dtype=np.float64)
+    r = np.asarray(rx, dtype=np.float64)
+    ls = np.asarray(log_scales, dtype=np.float64)
+    R = rotation_matrix(torch.tensor(np.asarray(quats, dtype=np.float64))).numpy()
+    n = mu.shape[0]
+    n_az, n_el, tw, th = grid.n_az, grid.n_el, grid.tile_w, grid.tile_h
+    nta = -(-n_az // tw)
+    el_lo, el_hi, r_rx = _f32(grid.el_lo), _f32(grid.el_hi), _f32(grid.r_rx)
+    dalpha = 2.0 * math.pi / n_az
+    dbeta = (el_hi - el_lo) / n_el
+    out = np.zeros((n, 4), dtype=np.int64)
+    marg = np.zeros(n, dtype=bool)
+    for g in range(n):
+        e = mu[g] - r
+        D = math.sqrt((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2])
+        Rb = 3.0 * math.exp(ls[g].max())
+        if D + Rb < r_rx * (1.0 - 1e-6):
+            continue
+        rho = math.hypot(e[0], e[1])
+        if D <= Rb * (1.0 + 1e-6):
+            v_lo, v_hi, u_lo, u_hi, full = 0, n_el - 1, 0, n_az - 1, True
+        else:
+            alpha = math.atan2(e[1], e[0])
+            if alpha < 0:
+                alpha += 2.0 * math.pi
+            xu = alpha / dalpha
+            xv = (math.atan2(e[2], rho) - el_lo) / dbeta
+            u_k = min(math.floor(xu), n_az - 1)
+            v_k = math.floor(xv)
+            if rho == 0.0:
+                m, full = n_el, True
+                marg[g] |= bool(_near_int(xv))
+            else:
+                Sigma = R[g] @ np.diag(np.exp(2.0 * ls[g])) @ R[g].T
+                J = footprint_jacobian(e, grid)
+                S2 = J @ Sigma @ J.T
+                a, b, c = S2[0, 0], S2[0, 1], S2[1, 1]
+                lam_max = 0.5 * (a + c) + math.sqrt(0.25 * (a - c) ** 2 + b * b)
+                r_k = 3.0 * math.sqrt(lam_max)
+                m = math.floor(min(r_k, 1e9))
+                full = 2 * m + 1 >= n_az
+                marg[g] |= bool(_near_int(xu) | _near_int(xv) | _near_int(r_k))
+            v_lo, v_hi = max(v_k - m, 0), min(v_k + m, n_el - 1)
+            u_lo, u_hi = (0, n_az - 1) if full else (u_k - m, u_k + m)
+        if v_lo > v_hi:
+            continue
+        if u_lo < 0:
+            u_lo, u_hi = u_lo + n_az, u_hi + n_az
+        tu0 = u_lo // tw
+        ntu = u_hi // tw - tu0 + 1 if u_hi < n_az else (nta - tu0) + (u_hi - n_az) // tw + 1
+        if ntu >= nta:
+            tu0, ntu = 0, nta
+        tv0 = v_lo // th
+        out[g] = (tu0, ntu, tv0, v_hi // th - tv0 + 1)
+    return out[:, 0], out[:, 1], out[:, 2], out[:, 3], marg
+
+
+def rect_allow(rects, grid, rays_uv):
+    """Per-(ray, Gaussian) mask: the ray's tile lies in the Gaussian's rectangle."""
+    tu0, ntu, tv0, ntv = (np.asarray(x, dtype=np.int64) for x in rects[:4])
+    nta = grid.n_tiles_az
+    uv = np.asarray(rays_uv, dtype=np.int64).reshape(-1, 2)
+    tu = (uv[:, 0] // grid.tile_w)[:, None]
+    tv = (uv[:, 1] // grid.tile_h)[:, None]
+    return ((ntu * ntv > 0)[None, :] & (tv >= tv0[None, :]) & (tv < (tv0 + ntv)[None, :])
+            & (((tu - tu0[None, :]) % nta) < ntu[None, :]))
 
 
 def rect_tiles(tu0, ntu, tv0, ntv, grid):

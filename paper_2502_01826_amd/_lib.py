@@ -25,7 +25,7 @@ c_i32, c_i64, c_f32, c_f64, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes
 class GsrfGrid(ctypes.Structure):
     _fields_ = [("n_az", c_i32), ("n_el", c_i32), ("el_lo", c_f32), ("el_hi", c_f32), ("fle_L", c_i32),
                 ("r_rx", c_f32), ("t_min", c_f32), ("alpha_max", c_f32), ("tile_w", c_i32), ("tile_h", c_i32),
-                ("lanes_per_ray", c_i32)]
+                ("lanes_per_ray", c_i32), ("footprint", c_i32)]
 
 
 class GsrfPair(ctypes.Structure):

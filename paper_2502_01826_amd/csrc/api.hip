@@ -46,6 +46,8 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
     return fail(GSRF_EINVAL, "tile %d x %d: tile_w * tile_h must be 32, 64, 128 or 256", g.tile_w, g.tile_h);
   if (g.lanes_per_ray != 0 && g.lanes_per_ray != 1 && g.lanes_per_ray != 2 && g.lanes_per_ray != 4)
     return fail(GSRF_EINVAL, "lanes_per_ray = %d: must be 0, 1, 2 or 4", g.lanes_per_ray);
+  if (g.footprint != 0 && g.footprint != 1)
+    return fail(GSRF_EINVAL, "footprint = %d: must be 0 (exact cap) or 1 (paper footprint)", g.footprint);
   if (nt == 32 && g.lanes_per_ray != 0)
     return fail(GSRF_EINVAL, "32-ray tiles need the two-phase traversal (lanes_per_ray = 0)");
   if (!(g.el_lo < g.el_hi) || g.el_lo < -1.5707964f || g.el_hi > 1.5707964f)

@@ -287,6 +287,74 @@ __device__ __noinline__ ushort4 cap_rect_fp64(float mx, float my, float mz, floa
   return tile_rect(v_lo, v_hi, u_lo, u_hi, full, n_az, tw, th, nta);
 }
 
+// The paper's footprint (Sec. 3.3, splatting), FP64, as a binning variant:
+// projected centre (u_k, v_k) = floor of the direction's ray-index
+// coordinates; Sigma2D = J Sigma J^T with J the Jacobian of
+// x -> (alpha / d_alpha, (beta - el_lo) / d_beta) at mu and
+// Sigma = R diag(s^2) R^T; r_k = 3 sqrt(lambda_max(Sigma2D)); the circle's
+// bounding square u_k +- m, v_k +- m with m = floor(r_k), rows clipped,
+// columns modulo n_az.  Not conservative: J linearises the map.  The cap's
+// exact guards stay (cull when D + Rb < r_rx, everything when the receiver
+// lies within Rb); on the receiver's vertical, or when 2m + 1 >= n_az, every
+// column is covered.
+__device__ __noinline__ ushort4 footprint_rect_fp64(const float *mu_f, const float *rx_f, const float *q_f,
+                                                    const float *ls_f, const gsrf_grid &grid, int32_t nta) {
+  const int n_az = grid.n_az, n_el = grid.n_el;
+  const double ex = (double)mu_f[0] - (double)rx_f[0];
+  const double ey = (double)mu_f[1] - (double)rx_f[1];
+  const double ez = (double)mu_f[2] - (double)rx_f[2];
+  const double rho2 = ex * ex + ey * ey;
+  const double D2 = rho2 + ez * ez;
+  const double D = sqrt(D2);
+  const double l0 = ls_f[0], l1 = ls_f[1], l2 = ls_f[2];
+  const double Rb = 3.0 * exp(fmax(fmax(l0, l1), l2));
+  if (D + Rb < (double)grid.r_rx * (1.0 - 1e-6)) return make_ushort4(0, 0, 0, 0);
+  if (D <= Rb * (1.0 + 1e-6))
+    return tile_rect(0, n_el - 1, 0, n_az - 1, true, n_az, grid.tile_w, grid.tile_h, nta);
+  const double pi = 3.14159265358979323846;
+  const double dalpha = 2.0 * pi / n_az;
+  const double dbeta = ((double)grid.el_hi - (double)grid.el_lo) / n_el;
+  const double rho = sqrt(rho2);
+  double alpha = atan2(ey, ex);
+  if (alpha < 0) alpha += 2.0 * pi;
+  long u_k = (long)floor(alpha / dalpha);
+  if (u_k > n_az - 1) u_k = n_az - 1;
+  const long v_k = (long)floor((atan2(ez, rho) - (double)grid.el_lo) / dbeta);
+  long m;
+  bool full;
+  if (rho == 0.0) {
+    m = n_el;
+    full = true;
+  } else {
+    double w = q_f[0], x = q_f[1], y = q_f[2], z = q_f[3];
+    const double qn = sqrt(w * w + x * x + y * y + z * z);
+    w /= qn; x /= qn; y /= qn; z /= qn;
+    const double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                            {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                            {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+    const double s2[3] = {exp(2.0 * l0), exp(2.0 * l1), exp(2.0 * l2)};
+    // rows of J: d alpha / dx and d beta / dx in index units
+    const double ja[3] = {-ey / rho2 / dalpha, ex / rho2 / dalpha, 0.0};
+    const double jb[3] = {-ez * ex / (D2 * rho) / dbeta, -ez * ey / (D2 * rho) / dbeta, rho / D2 / dbeta};
+    // J Sigma J^T = sum_i s_i^2 (J r_i)(J r_i)^T over the columns r_i of R
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      const double pa = ja[0] * R[0][i] + ja[1] * R[1][i] + ja[2] * R[2][i];
+      const double pb = jb[0] * R[0][i] + jb[1] * R[1][i] + jb[2] * R[2][i];
+      a += s2[i] * pa * pa;
+      b += s2[i] * pa * pb;
+      c += s2[i] * pb * pb;
+    }
+    const double lam = 0.5 * (a + c) + sqrt(0.25 * (a - c) * (a - c) + b * b);
+    const double r_k = 3.0 * sqrt(lam);
+    m = (long)floor(fmin(r_k, 1e9));
+    full = 2 * m + 1 >= n_az;
+  }
+  const long v_lo = v_k - m < 0 ? 0 : v_k - m;
+  const long v_hi = v_k + m > n_el - 1 ? n_el - 1 : v_k + m;
+  return tile_rect(v_lo, v_hi, u_k - m, u_k + m, full, n_az, grid.tile_w, grid.tile_h, nta);
+}
+
 // One record: depth key (always FP64: bits of fp32(D^2), D^2 without FMA)
 // and an attempt at the rectangle in FP32; false when the FP64 evaluation
 // is needed.
@@ -311,6 +379,7 @@ template <int RB>
 __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pairs,
                                                  const int64_t *__restrict__ scene_off,
                                                  const int64_t *__restrict__ rec_base, const float *__restrict__ prep,
+                                                 const float *__restrict__ quats, const float *__restrict__ log_scales,
                                                  gsrf_grid grid, int32_t nta,
                                                  int32_t T, int64_t PT, int sub_shift, uint32_t *__restrict__ rec_key,
                                                  ushort4 *__restrict__ rec_rect, uint32_t *__restrict__ tile_cnt) {
@@ -332,7 +401,7 @@ __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pa
   if (j < n) {
     uint32_t key;
     const float4 *pg = (const float4 *)(prep + (size_t)kPrep * (g0 + j));   // (mu, N) ... (3 max s, max log s)
-    if (!project_record_fast(pr, pg[0], pg[3].x, grid, nta, &key, &rc))
+    if (!project_record_fast(pr, pg[0], pg[3].x, grid, nta, &key, &rc) || grid.footprint)
       fallback[atomicAdd(&n_fallback, 1)] = threadIdx.x;
     rec_key[rec_base[k] + j] = key;
   }
@@ -342,6 +411,11 @@ __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pa
   for (int i = threadIdx.x; i < n_fallback; i += RB) {
     const int slot = fallback[i];
     const float *pg = prep + (size_t)kPrep * (g0 + j0 + slot);
+    const int64_t g = g0 + j0 + slot;
+    if (grid.footprint) {
+      rects[slot] = footprint_rect_fp64(pg, pr.rx, quats + 4 * g, log_scales + 3 * g, grid, nta);
+      continue;
+    }
     rects[slot] = cap_rect_fp64(pg[0], pg[1], pg[2], pr.rx[0], pr.rx[1], pr.rx[2], pg[13], grid.n_az, grid.n_el,
                                 grid.el_lo, grid.el_hi, grid.r_rx, grid.tile_w, grid.tile_h, nta);
   }
@@ -507,7 +581,7 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
     const int sub_shift = lay.rec_block == 1024 ? 2 : 0;   // emit's workgroup = 256 << sub_shift records
     dim3 grid((unsigned)((lay.max_scene + 255) / 256), (unsigned)p->n_pairs);
     hipLaunchKernelGGL(k_project<256>, grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev, rec_base,
-                       (const float *)prep, p->grid, lay.nta, lay.T, PT, sub_shift, (uint32_t *)(ws + lay.rec_key),
+                       (const float *)prep, p->quats, p->log_scales, p->grid, lay.nta, lay.T, PT, sub_shift, (uint32_t *)(ws + lay.rec_key),
                        (ushort4 *)(ws + lay.rec_rect), tile_cnt);
   }
   int64_t *blk = (int64_t *)(ws + lay.scan_blk);

@@ -46,6 +46,7 @@ class GridSpec:
     tile_w: int = 16
     tile_h: int = 16
     lanes_per_ray: int = 0
+    footprint: int = 0
 
     @staticmethod
     def of(g) -> "GridSpec":
@@ -54,7 +55,7 @@ class GridSpec:
 
     def c(self) -> GsrfGrid:
         return GsrfGrid(self.n_az, self.n_el, self.el_lo, self.el_hi, self.fle_L, self.r_rx, self.t_min,
-                        self.alpha_max, self.tile_w, self.tile_h, self.lanes_per_ray)
+                        self.alpha_max, self.tile_w, self.tile_h, self.lanes_per_ray, self.footprint)
 
     @property
     def K(self) -> int:

@@ -40,6 +40,7 @@ class Grid:
     tile_w: int = 16
     tile_h: int = 16
     lanes_per_ray: int = 0
+    footprint: int = 0          # 0: exact bounding cap, 1: the paper's 3 sqrt(lambda_max) footprint
 
     @property
     def K(self) -> int:

@@ -353,3 +353,55 @@ def test_large_batch_wide_workgroups_match_oracle():
             np.testing.assert_array_equal(kv[keep_g], rk[keep_r])
         uv = np.stack([rng.integers(0, g.n_az, 24), rng.integers(0, g.n_el, 24)], 1)
         compare_rays(S[k][uv[:, 1], uv[:, 0]], oracle.trace(sc, p, g, uv), sc, p, g)
+
+
+@pytest.mark.parametrize("tw,th,G", [(8, 8, 0), (16, 8, 0), (8, 8, 2)])
+def test_paper_footprint_binning_matches_oracle(tw, th, G):
+    """Binning by the paper's footprint (grid.footprint = 1): every record's
+    rectangle bit for bit (outside FP64-marginal floors), the tile lists, and
+    the render restricted to those tiles against the oracle, ray by ray."""
+    g = Grid(n_az=72, n_el=18, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G, footprint=1)
+    b = synth.tiny(grid=g, n=2000)
+    sc, p = b.scenes[0], b.pairs[0]
+    say("paper footprint", tw, th, "lanes", G)
+    prob = gpu_problem(b)
+    S, Ssum, _ = gpu_forward(prob)
+    rects = oracle.footprint_rects(sc.means, sc.log_scales, sc.quats, p.rx, g)
+    marg = rects[4]
+    L = gpu_lists(prob)
+    assert L["overflow"] == 0
+    np.testing.assert_array_equal(L["rec_rect"][~marg], np.stack(rects[:4], 1)[~marg])
+    if not marg.any():
+        assert L["n"] == int((rects[1] * rects[3]).sum())
+    ref = oracle.render(sc, p, g, rects=rects)
+    # rays in a tile of a Gaussian whose rectangle is marginal are not compared
+    skip = np.zeros(ref["S"].shape[0], bool)
+    if marg.any():
+        allow = oracle.rect_allow(rects, g, ref["rays_uv"])
+        skip = allow[:, marg].any(1)
+    ok = ~skip & ~ref["marginal"]
+    err = np.abs(S[0].ravel() - ref["S"])
+    assert np.all(err[ok] <= TOL * np.maximum(ref["A_uv"][ok], 1e-30)), float(err[ok].max())
+    # a real variant: some hit of the exact binning is dropped here
+    exact = oracle.render(sc, p, Grid(n_az=72, n_el=18, fle_L=2, tile_w=tw, tile_h=th))
+    assert (ref["n_active"] < exact["n_active"]).any()
+
+
+def test_paper_footprint_rectangles_at_paper_scale():
+    """200k Gaussians, 360x90 rays, 8x8 tiles: sampled records' footprint
+    rectangles against the oracle, and the forward's total against the sum of
+    sampled rays (paper-scale launch configuration)."""
+    g = Grid(n_az=360, n_el=90, fle_L=2, tile_w=8, tile_h=8, footprint=1)
+    b = synth.paper_scale(grid=g)
+    sc, p = b.scenes[0], b.pairs[0]
+    say("paper footprint at paper scale")
+    prob = gpu_problem(b)
+    S, Ssum, _ = gpu_forward(prob)
+    L = gpu_lists(prob)
+    assert L["overflow"] == 0
+    idx = np.random.default_rng(11).choice(sc.n, 3000, replace=False)
+    rects = oracle.footprint_rects(sc.means[idx], sc.log_scales[idx], sc.quats[idx], p.rx, g)
+    marg = rects[4]
+    np.testing.assert_array_equal(L["rec_rect"][idx][~marg], np.stack(rects[:4], 1)[~marg])
+    assert np.isfinite(S).all()
+    np.testing.assert_allclose(Ssum[0], S[0].sum(), rtol=1e-4, atol=1e-4 * np.abs(S[0]).sum())

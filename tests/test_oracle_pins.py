@@ -465,3 +465,106 @@ def test_cap_rect_seam_wrap_and_culls():
     big = one_gaussian(np.array([5.3, 5.0, 1.2]), 0.5, np.array([1.0, 0.0]), 1)
     r = oracle.cap_rects(big.means, big.log_scales, rx, g)
     assert r[1][0] * r[3][0] == g.n_tiles
+
+
+# --------------------------------------------------------------------------
+# Paper footprint binning variant (Sec. 3.3 splatting: Sigma2D = J Sigma J^T,
+# r_k = 3 sqrt(lambda_max)); tile 1 x 1 makes the rectangle the ray square.
+# --------------------------------------------------------------------------
+
+def _index_map(e, g):
+    d_a = 2 * math.pi / g.n_az
+    d_b = (g.el_hi - g.el_lo) / g.n_el
+    return np.array([math.atan2(e[1], e[0]) / d_a,
+                     (math.atan2(e[2], math.sqrt(e[0] ** 2 + e[1] ** 2)) - g.el_lo) / d_b])
+
+
+def test_footprint_jacobian_matches_finite_differences():
+    g = Grid(n_az=360, n_el=90, el_lo=0.0, el_hi=math.pi / 2)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        e = rng.normal(size=3) * 3
+        J = oracle.footprint_jacobian(e, g)
+        h = 1e-6
+        fd = np.stack([(_index_map(e + h * ax, g) - _index_map(e - h * ax, g)) / (2 * h) for ax in np.eye(3)], 1)
+        np.testing.assert_allclose(J, fd, rtol=1e-6, atol=1e-6)
+        # the radial direction maps to no displacement
+        np.testing.assert_allclose(J @ e, 0.0, atol=1e-9)
+
+
+def _deg_dir(az_deg, el_deg):
+    a, b = math.radians(az_deg), math.radians(el_deg)
+    return np.array([math.cos(b) * math.cos(a), math.cos(b) * math.sin(a), math.sin(b)])
+
+
+def _quat_x_to(axis_world, roll=0.0):
+    """(w, x, y, z) of a rotation that takes the x axis to ``axis_world``."""
+    a = axis_world / np.linalg.norm(axis_world)
+    v = np.cross([1.0, 0.0, 0.0], a)
+    ang = math.acos(np.clip(a[0], -1.0, 1.0))
+    rot = Rotation.from_rotvec(v / np.linalg.norm(v) * ang) * Rotation.from_rotvec([roll, 0.0, 0.0])
+    x, y, z, w = rot.as_quat()
+    return (w, x, y, z)
+
+
+def test_footprint_isotropic_and_anisotropic_closed_forms():
+    g = Grid(n_az=360, n_el=90, fle_L=0, tile_w=1, tile_h=1)     # 1 degree cells
+    rx = np.array([5.0, 4.0, 1.5])
+    D, az, el = 5.0, 100.3, 30.4
+    e = D * _deg_dir(az, el)
+    rho = D * math.cos(math.radians(el))
+    d1 = math.radians(1.0)
+    # isotropic: lambda_max = s^2 max(1/(rho da)^2, 1/(D db)^2) = (s / (rho da))^2; r_k = 4.5
+    s = 4.5 * rho * d1 / 3.0
+    sc = one_gaussian(rx + e, s, np.array([1.0, 0.0]), 1)
+    tu0, ntu, tv0, ntv, marg = oracle.footprint_rects(sc.means, sc.log_scales, sc.quats, rx, g)
+    assert not marg[0]
+    assert (tu0[0], ntu[0], tv0[0], ntv[0]) == (96, 9, 26, 9)
+    # long axis along the ray: it projects to nothing, same square as the isotropic one
+    ls = np.log([[0.4, s, s]])
+    q = np.array([_quat_x_to(e, roll=0.7)])
+    r = oracle.footprint_rects(sc.means, ls, q, rx, g)
+    assert (r[0][0], r[1][0], r[2][0], r[3][0]) == (96, 9, 26, 9)
+    # long axis along the azimuth tangent: a = (s_big / (rho da))^2, c = (s / (D db))^2, b = 0
+    t_az = np.array([-math.sin(math.radians(az)), math.cos(math.radians(az)), 0.0])
+    s_big = 6.5 * rho * d1 / 3.0                                 # r_k = 6.5 -> m = 6
+    r = oracle.footprint_rects(sc.means, np.log([[s_big, s, s]]), np.array([_quat_x_to(t_az, roll=0.3)]), rx, g)
+    assert (r[0][0], r[1][0], r[2][0], r[3][0]) == (94, 13, 24, 13)
+    # the same axis along the elevation tangent: c dominates, r_k = 3 s_big / (D db)
+    t_el = np.array([-math.sin(math.radians(el)) * math.cos(math.radians(az)),
+                     -math.sin(math.radians(el)) * math.sin(math.radians(az)), math.cos(math.radians(el))])
+    s_el = 7.5 * D * d1 / 3.0                                    # r_k = 7.5 -> m = 7
+    r = oracle.footprint_rects(sc.means, np.log([[s_el, s, s]]), np.array([_quat_x_to(t_el, roll=1.1)]), rx, g)
+    assert (r[0][0], r[1][0], r[2][0], r[3][0]) == (93, 15, 23, 15)
+
+
+def test_footprint_guards_vertical_and_tiles():
+    g = Grid(n_az=360, n_el=90, fle_L=0, tile_w=16, tile_h=16)
+    rx = np.array([5.0, 5.0, 1.0])
+    one = lambda mu, s: one_gaussian(np.asarray(mu, float), s, np.array([1.0, 0.0]), 1)
+    fr = lambda sc: oracle.footprint_rects(sc.means, sc.log_scales, sc.quats, rx, g)
+    # straight above the receiver: every column, the top rows
+    r = fr(one([5.0, 5.0, 3.0], 0.05))
+    assert r[1][0] == g.n_tiles_az and r[2][0] + r[3][0] == -(-90 // 16)
+    # inside the RESS -> culled; receiver inside the bounding sphere -> every tile
+    assert fr(one([5.3, 5.0, 1.2], 0.05))[1][0] == 0
+    r = fr(one([5.3, 5.0, 1.2], 0.5))
+    assert r[1][0] * r[3][0] == g.n_tiles
+    # at the seam: columns on both sides
+    r = fr(one([8.0, 5.0, 1.5], 0.1))
+    tiles = oracle.rect_tiles(int(r[0][0]), int(r[1][0]), int(r[2][0]), int(r[3][0]), g)
+    cols = sorted(set(t % g.n_tiles_az for t in tiles))
+    assert 0 in cols and g.n_tiles_az - 1 in cols
+
+
+def test_trace_rect_restriction_keeps_conservative_results():
+    """Restricting each ray to the exact cap's tiles changes nothing (the cap
+    holds every hit); the footprint restriction only removes hits."""
+    b = synth.tiny(n=400)
+    sc, p, g = b.scenes[0], b.pairs[0], b.grid
+    full = oracle.render(sc, p, g)
+    capped = oracle.render(sc, p, g, rects=oracle.cap_rects(sc.means, sc.log_scales, p.rx, g))
+    np.testing.assert_array_equal(full["n_active"], capped["n_active"])
+    np.testing.assert_allclose(full["S"], capped["S"], rtol=1e-12, atol=1e-12 * np.abs(full["S"]).max())
+    fp = oracle.render(sc, p, g, rects=oracle.footprint_rects(sc.means, sc.log_scales, sc.quats, p.rx, g))
+    assert np.all(fp["n_active"] <= full["n_active"] + (fp["T_end"] < g.t_min * 1.01))
