@@ -483,11 +483,12 @@ def rssi_dbm(S_sum) -> float:
 # a7/a8: gradients = autograd of the plain definition (App. D; R21, R22)
 # --------------------------------------------------------------------------
 
-def vjp(scene, pair, grid, G, g_sum=None, rays_uv=None, ray_chunk: int = 64):
+def vjp(scene, pair, grid, G, g_sum=None, rays_uv=None, ray_chunk: int = 64, rects=None):
     """Gradient of L = sum_r Re(conj(G_r + g_sum) S_r) w.r.t. the scene parameters.
 
     ``G`` is [R,2] (re, im) aligned with ``rays_uv`` (all rays when None);
     ``g_sum`` is the [2] cotangent of S_hat = sum over the listed rays.
+    ``rects`` restricts the rays as in ``trace``.
     Returns FP64 numpy gradients keyed means/log_scales/quats/logits/coeffs.
     """
     P = Params.from_scene(scene, requires_grad=True)
@@ -495,7 +496,7 @@ def vjp(scene, pair, grid, G, g_sum=None, rays_uv=None, ray_chunk: int = 64):
     if g_sum is not None:
         G = G + np.asarray(g_sum, dtype=np.float64).reshape(1, 2)
     Gt = torch.tensor(G, dtype=F64)
-    res = trace(P, pair, grid, rays_uv, grad=True, ray_chunk=ray_chunk)
+    res = trace(P, pair, grid, rays_uv, grad=True, ray_chunk=ray_chunk, rects=rects)
     L = (Gt[:, 0] * res["S_r"] + Gt[:, 1] * res["S_i"]).sum()
     grads = torch.autograd.grad(L, P.tensors(), allow_unused=True)
     names = ["means", "log_scales", "quats", "logits", "coeffs"]

@@ -189,3 +189,25 @@ def test_many_tile_launch_gradients_match_oracle():
     out = prob.render_bwd(sig, gt)
     torch.cuda.synchronize()
     _compare({n: o.cpu().numpy().astype(np.float64) for n, o in zip(NAMES, out)}, ref)
+
+
+@pytest.mark.parametrize("tw,th,G", [(8, 8, 0), (16, 8, 0), (8, 8, 4)])
+def test_paper_footprint_gradients_match_oracle(tw, th, G):
+    """The adjoint over the paper-footprint binning (grid.footprint = 1) against
+    the oracle's gradients of the render restricted to the same tiles."""
+    g = Grid(n_az=36, n_el=9, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G, footprint=1)
+    b = synth.tiny(grid=g)
+    sc, p = b.scenes[0], b.pairs[0]
+    say("footprint gradients", tw, th, "lanes", G)
+    rects = oracle.footprint_rects(sc.means, sc.log_scales, sc.quats, p.rx, g)
+    assert not rects[4].any()
+    prob = gpu_problem(b)
+    sig, _, _ = prob.forward()
+    torch.cuda.synchronize()
+    ref = oracle.render(sc, p, g, rects=rects)
+    R = g.n_az * g.n_el
+    G = synth.cotangent((R,), seed=2).astype(np.float64)
+    G[ref["marginal"]] = 0.0
+    gr = oracle.vjp(sc, p, g, G, rects=rects)
+    gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), G.reshape(1, g.n_el, g.n_az, 2))
+    _compare(gg, gr)
