@@ -672,7 +672,7 @@ def footprint_rects(means, log_scales, quats, rx, grid):
                 a, b, c = S2[0, 0], S2[0, 1], S2[1, 1]
                 lam_max = 0.5 * (a + c) + math.sqrt(0.25 * (a - c) ** 2 + b * b)
                 r_k = 3.0 * math.sqrt(lam_max)
-                m = math.floor(min(r_k, 1e9))
+                m = math.floor(r_k) if r_k < 1e9 else 10 ** 9      # NaN or huge: every column
                 full = 2 * m + 1 >= n_az
                 marg[g] |= bool(_near_int(xu) | _near_int(xv) | _near_int(r_k))
             v_lo, v_hi = max(v_k - m, 0), min(v_k + m, n_el - 1)
