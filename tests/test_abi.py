@@ -119,6 +119,7 @@ def test_workspace_size_and_layout():
      "32-ray tiles"),
     (lambda p: setattr(p.grid, "fle_L", 7), "fle_L"),
     (lambda p: setattr(p.grid, "lanes_per_ray", 3), "lanes_per_ray"),
+    (lambda p: setattr(p.grid, "footprint", 2), "footprint"),
     (lambda p: setattr(p.grid, "n_az", 0), "grid size"),
     (lambda p: setattr(p.grid, "alpha_max", 1.0), "alpha_max"),
     (lambda p: setattr(p.grid, "el_hi", -0.5), "elevation"),
