@@ -234,7 +234,8 @@ def main() -> int:
 
         tune = autotune(build, grid, grad=grad, make_grad=make_grad, iters=2)
         tw, th, lanes = tune.best
-        g = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=lanes)
+        g = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=lanes,
+                       footprint=grid.footprint)
         prob = build(g)
         gs, gsum = make_grad(prob) if grad else (None, None)
         step = GraphStep(prob, grad, gs, gsum)
