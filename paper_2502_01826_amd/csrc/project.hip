@@ -297,29 +297,29 @@ __device__ __noinline__ ushort4 cap_rect_fp64(float mx, float my, float mz, floa
 // exact guards stay (cull when D + Rb < r_rx, everything when the receiver
 // lies within Rb); on the receiver's vertical, or when 2m + 1 >= n_az, every
 // column is covered.
-__device__ __noinline__ ushort4 footprint_rect_fp64(const float *mu_f, const float *rx_f, const float *q_f,
-                                                    const float *ls_f, const gsrf_grid &grid, int32_t nta) {
-  const int n_az = grid.n_az, n_el = grid.n_el;
-  const double ex = (double)mu_f[0] - (double)rx_f[0];
-  const double ey = (double)mu_f[1] - (double)rx_f[1];
-  const double ez = (double)mu_f[2] - (double)rx_f[2];
+__device__ __noinline__ ushort4 footprint_rect_fp64(float mx, float my, float mz, float rx, float ry, float rz,
+                                                    const float *q_f, const float *ls_f, int n_az, int n_el,
+                                                    float el_lo_f, float el_hi_f, float r_rx, int tw, int th,
+                                                    int32_t nta) {
+  const double ex = (double)mx - (double)rx;
+  const double ey = (double)my - (double)ry;
+  const double ez = (double)mz - (double)rz;
   const double rho2 = ex * ex + ey * ey;
   const double D2 = rho2 + ez * ez;
   const double D = sqrt(D2);
   const double l0 = ls_f[0], l1 = ls_f[1], l2 = ls_f[2];
   const double Rb = 3.0 * exp(fmax(fmax(l0, l1), l2));
-  if (D + Rb < (double)grid.r_rx * (1.0 - 1e-6)) return make_ushort4(0, 0, 0, 0);
-  if (D <= Rb * (1.0 + 1e-6))
-    return tile_rect(0, n_el - 1, 0, n_az - 1, true, n_az, grid.tile_w, grid.tile_h, nta);
+  if (D + Rb < (double)r_rx * (1.0 - 1e-6)) return make_ushort4(0, 0, 0, 0);
+  if (D <= Rb * (1.0 + 1e-6)) return tile_rect(0, n_el - 1, 0, n_az - 1, true, n_az, tw, th, nta);
   const double pi = 3.14159265358979323846;
   const double dalpha = 2.0 * pi / n_az;
-  const double dbeta = ((double)grid.el_hi - (double)grid.el_lo) / n_el;
+  const double dbeta = ((double)el_hi_f - (double)el_lo_f) / n_el;
   const double rho = sqrt(rho2);
   double alpha = atan2(ey, ex);
   if (alpha < 0) alpha += 2.0 * pi;
   long u_k = (long)floor(alpha / dalpha);
   if (u_k > n_az - 1) u_k = n_az - 1;
-  const long v_k = (long)floor((atan2(ez, rho) - (double)grid.el_lo) / dbeta);
+  const long v_k = (long)floor((atan2(ez, rho) - (double)el_lo_f) / dbeta);
   long m;
   bool full;
   if (rho == 0.0) {
@@ -352,7 +352,7 @@ __device__ __noinline__ ushort4 footprint_rect_fp64(const float *mu_f, const flo
   }
   const long v_lo = v_k - m < 0 ? 0 : v_k - m;
   const long v_hi = v_k + m > n_el - 1 ? n_el - 1 : v_k + m;
-  return tile_rect(v_lo, v_hi, u_k - m, u_k + m, full, n_az, grid.tile_w, grid.tile_h, nta);
+  return tile_rect(v_lo, v_hi, u_k - m, u_k + m, full, n_az, tw, th, nta);
 }
 
 // One record: depth key (always FP64: bits of fp32(D^2), D^2 without FMA)
@@ -375,7 +375,8 @@ __device__ __forceinline__ bool project_record_fast(const gsrf_pair &pr, float4 
 // so this kernel's workgroups (RB records) count into the sub-bucket from
 // which emit's workgroup of the same records later reserves: sub_shift =
 // log2(emit workgroup / RB).
-template <int RB>
+// FOOT: bin by the paper's footprint (grid.footprint = 1) instead of the cap.
+template <int RB, bool FOOT>
 __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pairs,
                                                  const int64_t *__restrict__ scene_off,
                                                  const int64_t *__restrict__ rec_base, const float *__restrict__ prep,
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pa
   if (j < n) {
     uint32_t key;
     const float4 *pg = (const float4 *)(prep + (size_t)kPrep * (g0 + j));   // (mu, N) ... (3 max s, max log s)
-    if (!project_record_fast(pr, pg[0], pg[3].x, grid, nta, &key, &rc) || grid.footprint)
+    if (!project_record_fast(pr, pg[0], pg[3].x, grid, nta, &key, &rc) || FOOT)
       fallback[atomicAdd(&n_fallback, 1)] = threadIdx.x;
     rec_key[rec_base[k] + j] = key;
   }
@@ -412,8 +413,10 @@ __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pa
     const int slot = fallback[i];
     const float *pg = prep + (size_t)kPrep * (g0 + j0 + slot);
     const int64_t g = g0 + j0 + slot;
-    if (grid.footprint) {
-      rects[slot] = footprint_rect_fp64(pg, pr.rx, quats + 4 * g, log_scales + 3 * g, grid, nta);
+    if constexpr (FOOT) {
+      rects[slot] = footprint_rect_fp64(pg[0], pg[1], pg[2], pr.rx[0], pr.rx[1], pr.rx[2], quats + 4 * g,
+                                        log_scales + 3 * g, grid.n_az, grid.n_el, grid.el_lo, grid.el_hi,
+                                        grid.r_rx, grid.tile_w, grid.tile_h, nta);
       continue;
     }
     rects[slot] = cap_rect_fp64(pg[0], pg[1], pg[2], pr.rx[0], pr.rx[1], pr.rx[2], pg[13], grid.n_az, grid.n_el,
@@ -580,9 +583,14 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
   if (lay.n_records > 0) {
     const int sub_shift = lay.rec_block == 1024 ? 2 : 0;   // emit's workgroup = 256 << sub_shift records
     dim3 grid((unsigned)((lay.max_scene + 255) / 256), (unsigned)p->n_pairs);
-    hipLaunchKernelGGL(k_project<256>, grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev, rec_base,
-                       (const float *)prep, p->quats, p->log_scales, p->grid, lay.nta, lay.T, PT, sub_shift, (uint32_t *)(ws + lay.rec_key),
-                       (ushort4 *)(ws + lay.rec_rect), tile_cnt);
+    if (p->grid.footprint)
+      hipLaunchKernelGGL((k_project<256, true>), grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev,
+                         rec_base, (const float *)prep, p->quats, p->log_scales, p->grid, lay.nta, lay.T, PT, sub_shift,
+                         (uint32_t *)(ws + lay.rec_key), (ushort4 *)(ws + lay.rec_rect), tile_cnt);
+    else
+      hipLaunchKernelGGL((k_project<256, false>), grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev,
+                         rec_base, (const float *)prep, p->quats, p->log_scales, p->grid, lay.nta, lay.T, PT, sub_shift,
+                         (uint32_t *)(ws + lay.rec_key), (ushort4 *)(ws + lay.rec_rect), tile_cnt);
   }
   int64_t *blk = (int64_t *)(ws + lay.scan_blk);
   int64_t *counters = (int64_t *)(ws + lay.counters);
