@@ -119,3 +119,33 @@ def test_autotune_returns_a_timed_candidate():
     g2 = Grid(n_az=72, n_el=18, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=lanes)
     S = torch.view_as_complex(Problem(prm, [pr], g2).forward()[0]).cpu().numpy().astype(np.complex128)
     compare_rays(S[0].ravel(), oracle.render(sc, pr, g2), sc, pr, g2)
+
+
+def test_uneven_batch_footprint_binning_matches_oracle():
+    """Paper-footprint binning (grid.footprint = 1) over three scenes of uneven
+    size and nine pairs: every record's rectangle per pair, and sampled rays of
+    every pair against the oracle render restricted to the same tiles."""
+    from gpu_common import TOL, gpu_lists
+    g = Grid(n_az=72, n_el=18, fle_L=2, tile_w=8, tile_h=8, footprint=1)
+    b = _uneven(g, seed=3)
+    say("uneven batch, paper footprint:", len(b.scenes), "scenes,", len(b.pairs), "pairs")
+    prob = gpu_problem(b)
+    sig, _, _ = prob.forward()
+    torch.cuda.synchronize()
+    S = torch.view_as_complex(sig).cpu().numpy().astype(np.complex128)
+    L = gpu_lists(prob)
+    assert L["overflow"] == 0
+    rng = np.random.default_rng(9)
+    for k, p in enumerate(b.pairs):
+        sc = b.scenes[p.scene]
+        rects = oracle.footprint_rects(sc.means, sc.log_scales, sc.quats, p.rx, g)
+        marg = rects[4]
+        got = L["rec_rect"][L["base"][k]:L["base"][k] + sc.n]
+        np.testing.assert_array_equal(got[~marg], np.stack(rects[:4], 1)[~marg])
+        uv = np.stack([rng.integers(0, g.n_az, 24), rng.integers(0, g.n_el, 24)], 1)
+        ref = oracle.trace(sc, p, g, uv, rects=rects)
+        ok = ~ref["marginal"]
+        if marg.any():
+            ok &= ~oracle.rect_allow(rects, g, uv)[:, marg].any(1)
+        err = np.abs(S[k][uv[:, 1], uv[:, 0]] - ref["S"])
+        assert np.all(err[ok] <= TOL * np.maximum(ref["A_uv"][ok], 1e-30)), (k, float(err[ok].max()))
