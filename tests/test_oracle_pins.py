@@ -568,3 +568,23 @@ def test_trace_rect_restriction_keeps_conservative_results():
     np.testing.assert_allclose(full["S"], capped["S"], rtol=1e-12, atol=1e-12 * np.abs(full["S"]).max())
     fp = oracle.render(sc, p, g, rects=oracle.footprint_rects(sc.means, sc.log_scales, sc.quats, p.rx, g))
     assert np.all(fp["n_active"] <= full["n_active"] + (fp["T_end"] < g.t_min * 1.01))
+
+
+def test_rect_allow_matches_rect_tile_enumeration():
+    """The per-(ray, Gaussian) restriction mask equals membership of the ray's
+    tile in the rectangle's explicit tile list (seam-wrapping ones included)."""
+    g = Grid(n_az=72, n_el=18, fle_L=0, tile_w=8, tile_h=4)
+    b = synth.tiny(grid=g, n=300)
+    sc, p = b.scenes[0], b.pairs[0]
+    vv, uu = np.meshgrid(np.arange(g.n_el), np.arange(g.n_az), indexing="ij")
+    uv = np.stack([uu.ravel(), vv.ravel()], 1)
+    tile_of = (uv[:, 1] // g.tile_h) * g.n_tiles_az + uv[:, 0] // g.tile_w
+    for rects in (oracle.cap_rects(sc.means, sc.log_scales, p.rx, g),
+                  oracle.footprint_rects(sc.means, sc.log_scales, sc.quats, p.rx, g)):
+        allow = oracle.rect_allow(rects, g, uv)
+        wraps = 0
+        for i in range(sc.n):
+            tiles = set(oracle.rect_tiles(int(rects[0][i]), int(rects[1][i]), int(rects[2][i]), int(rects[3][i]), g))
+            wraps += int(rects[0][i] + rects[1][i] > g.n_tiles_az)
+            np.testing.assert_array_equal(allow[:, i], np.isin(tile_of, list(tiles)))
+        assert wraps > 0
