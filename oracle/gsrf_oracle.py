@@ -429,7 +429,7 @@ def ray_sequence(scene, pair, grid, u: int, v: int, *, direction=None, basis=Non
                 T=T[0].detach().numpy(), S=complex(S_r[0]) + 1j * float(S_i[0]), A_uv=float(A_uv[0]))
 
 
-def ray_variants(scene, pair, grid, u: int, v: int, bands: Bands | None = None, max_flip: int = 4):
+def ray_variants(scene, pair, grid, u: int, v: int, bands: Bands | None = None, max_flip: int = 8):
     """All FP32-admissible results for one ray (R28).
 
     Decisions inside the marginal bands (hit test edges, termination edge) are
