@@ -47,6 +47,19 @@ Readings taken where the paper is silent or ambiguous:
       conservative), widened by 1e-5 rad.
   R28 at FP32-marginal discrete decisions both outcomes are correct.
 
+Paper-literal variants, selected by grid attributes (0 = the readings above):
+  depth_order = 1   each ray takes its hits in increasing chord-midpoint
+                    parameter t_mid (App. A.3), ties by depth key then index;
+  fle_eval = 1      the radiance psi_k is the FLE evaluated once per Gaussian
+                    at the direction of mu_k from the receiver (the R13
+                    alternative) instead of at the ray's direction;
+  transmittance = 1 the transmittance of a hit is the chord form
+                    rho = exp(-alpha_k dt) of App. A.2, dt = t_out - t_in the
+                    3-sigma chord, with the amplitude attenuation coefficient
+                    alpha_k = exp(logit) (per metre, >= 0), no excess phase
+                    (the propagation phase of the path is kept, R1, R14) and no
+                    opacity clamp.
+
 Parity pinning: every function here is pinned by a CPU test in
 tests/test_oracle_*.py against closed forms, library routines, the paper's
 worked example or brute force.  The FLE conventions (R10-R13), the phase
@@ -192,6 +205,48 @@ def fle_basis(L: int, alpha, x) -> np.ndarray:
     return out
 
 
+def fle_basis_dir(L: int, e: torch.Tensor):
+    """FLE basis Y_i at unit directions e [n,3] (torch, differentiable): (Yr, Yi) [n, K].
+
+    With w = e_x + j e_y = rho e^{j alpha} and x = e_z (rho^2 = 1 - x^2),
+    e^{j m alpha} P_l^m(x) = w^m Q_l^m(x) where Q_l^m = P_l^m / (1 - x^2)^{m/2}
+    follows the same textbook recurrences with Q_m^m = (-1)^m (2m-1)!!;
+    m < 0 by P_l^{-m} = (-1)^m (l-m)!/(l+m)! P_l^m, so Y_{l,-m} =
+    (-1)^m (l-m)!/(l+m)! conj(w)^m Q_l^m.  Smooth at the poles (no angle).
+    """
+    ex, ey, x = e[:, 0], e[:, 1], e[:, 2]
+    K = (L + 1) ** 2
+    wr = [torch.ones_like(x)]
+    wi = [torch.zeros_like(x)]
+    for m in range(1, L + 1):                                   # w^m by repeated products
+        wr.append(wr[-1] * ex - wi[-1] * ey)
+        wi.append(wr[-2] * ey + wi[-1] * ex)
+    Yr = [None] * K
+    Yi = [None] * K
+    for m in range(0, L + 1):
+        dfact = 1.0
+        for k in range(1, 2 * m, 2):
+            dfact *= k
+        q_prev2 = None
+        q_prev1 = ((-1) ** m) * dfact * torch.ones_like(x)      # Q_m^m
+        for l in range(m, L + 1):
+            if l == m:
+                q = q_prev1
+            elif l == m + 1:
+                q = x * (2 * m + 1) * q_prev1
+                q_prev2, q_prev1 = q_prev1, q
+            else:
+                q = ((2 * l - 1) * x * q_prev1 - (l + m - 1) * q_prev2) / (l - m)
+                q_prev2, q_prev1 = q_prev1, q
+            Yr[l * l + l + m] = wr[m] * q
+            Yi[l * l + l + m] = wi[m] * q
+            if m > 0:
+                f = ((-1) ** m) * math.factorial(l - m) / math.factorial(l + m)
+                Yr[l * l + l - m] = f * wr[m] * q
+                Yi[l * l + l - m] = -f * wi[m] * q
+    return torch.stack(Yr, dim=-1), torch.stack(Yi, dim=-1)
+
+
 def ray_basis(grid) -> np.ndarray:
     """[n_el, n_az, K] FLE basis at every ray: alpha_u and x = sin(beta_v) (R11)."""
     alpha, beta = ray_angles(grid)
@@ -229,6 +284,7 @@ class Bands:
     q: float = 3e-4        # |Q - 9| (absolute, Mahalanobis^2 units)
     t: float = 1e-5        # |t - r_rx| relative to max(1, t)
     T: float = 3e-4        # |T - t_min| relative to t_min
+    tie: float = 1e-6      # depth_order = 1: |t_i - t_j| of neighbouring hits relative to max(1, t)
 
 
 def _per_ray_terms(P: Params, act, rx, tx, lam, grid, dirs, Y, cols):
@@ -241,6 +297,8 @@ def _per_ray_terms(P: Params, act, rx, tx, lam, grid, dirs, Y, cols):
     M, Nn, o = act
     M, Nn, o = M[cols], Nn[cols], o[cols]
     mu = P.mu[cols]
+    chord = getattr(grid, "transmittance", 0) == 1
+    fle_g = getattr(grid, "fle_eval", 0) == 1
     R = dirs.shape[0]
     delta = rx[None, :] - mu                                   # [n,3]
     Md = (M @ delta.unsqueeze(-1)).squeeze(-1)                 # [n,3]
@@ -253,19 +311,55 @@ def _per_ray_terms(P: Params, act, rx, tx, lam, grid, dirs, Y, cols):
     Q = C[None, :] - B * B / A
     G = torch.exp(-0.5 * Q)
     p = Nn[None, :] * G
-    alpha = torch.clamp(o[None, :] * G, max=_f32(grid.alpha_max))
+    if chord:
+        # App. A.2: rho = exp(-alpha_k dt), dt = t_out - t_in = 2 sqrt(disc) / A
+        with torch.no_grad():
+            inside = disc > 0
+        dt = torch.where(inside, 2.0 * torch.sqrt(torch.where(inside, disc, torch.ones_like(disc))) / A,
+                         torch.zeros_like(disc))
+        keep = torch.exp(-torch.exp(P.a[cols])[None, :] * dt)
+        alpha = 1.0 - keep
+    else:
+        alpha = torch.clamp(o[None, :] * G, max=_f32(grid.alpha_max))
+        keep = None
     dtx = torch.linalg.norm(mu - tx[None, :], dim=-1)          # ||mu - tx||
     d = dtx[None, :] + t                                       # path length (R14)
     phase = 2.0 * math.pi * d / lam
     c = P.c[cols]                                              # [n,K,2]
-    Yr, Yi = Y.real, Y.imag                                    # [R,K]
-    psi_r = Yr @ c[:, :, 0].T - Yi @ c[:, :, 1].T              # [R,n]
-    psi_i = Yi @ c[:, :, 0].T + Yr @ c[:, :, 1].T
+    if fle_g:
+        # psi_k at the direction of mu_k from the receiver, one value per Gaussian
+        e = mu - rx[None, :]
+        e = e / torch.linalg.norm(e, dim=-1, keepdim=True)
+        gYr, gYi = fle_basis_dir(grid.fle_L, e)                # [n,K]
+        psi_r = ((gYr * c[:, :, 0]) - (gYi * c[:, :, 1])).sum(-1)[None, :].expand(R, -1)
+        psi_i = ((gYi * c[:, :, 0]) + (gYr * c[:, :, 1])).sum(-1)[None, :].expand(R, -1)
+    else:
+        Yr, Yi = Y.real, Y.imag                                # [R,K]
+        psi_r = Yr @ c[:, :, 0].T - Yi @ c[:, :, 1].T          # [R,n]
+        psi_i = Yi @ c[:, :, 0].T + Yr @ c[:, :, 1].T
     cs, sn = torch.cos(phase), torch.sin(phase)
     # c~ = p * psi * e^{-j phase}
     ct_r = p * (psi_r * cs + psi_i * sn)
     ct_i = p * (psi_i * cs - psi_r * sn)
-    return dict(disc=disc, t=t, Q=Q, G=G, p=p, alpha=alpha, ct_r=ct_r, ct_i=ct_i)
+    out = dict(disc=disc, t=t, Q=Q, G=G, p=p, alpha=alpha, ct_r=ct_r, ct_i=ct_i)
+    if keep is not None:
+        out["keep"] = keep
+    return out
+
+
+def _order_by_tmid(terms, cols_t, grid):
+    """depth_order = 1 (App. A.3): each ray's hits in increasing t_mid.
+
+    Rows are permuted independently: hits first by t (stable, so equal t keep
+    the depth-key order), then every non-hit in key order.  Returns the
+    permuted terms and the [R, n] Gaussian ids per position."""
+    r_rx = _f32(grid.r_rx)
+    with torch.no_grad():
+        hit = (terms["disc"] >= 0) & (terms["t"] >= r_rx)
+        skey = torch.where(hit, terms["t"].detach(), torch.full_like(terms["t"], math.inf))
+        perm = torch.sort(skey, dim=1, stable=True).indices
+    out = {k: torch.gather(v, 1, perm) for k, v in terms.items()}
+    return out, torch.gather(cols_t[None, :].expand(perm.shape[0], -1), 1, perm)
 
 
 def _composite(terms, grid):
@@ -273,8 +367,10 @@ def _composite(terms, grid):
     r_rx, t_min = _f32(grid.r_rx), _f32(grid.t_min)
     with torch.no_grad():
         hit = (terms["disc"] >= 0) & (terms["t"] >= r_rx)
-    a_eff = torch.where(hit, terms["alpha"], torch.zeros_like(terms["alpha"]))
-    keep = 1.0 - a_eff
+    if "keep" in terms:
+        keep = torch.where(hit, terms["keep"], torch.ones_like(terms["keep"]))
+    else:
+        keep = 1.0 - torch.where(hit, terms["alpha"], torch.zeros_like(terms["alpha"]))
     incl = torch.cumprod(keep, dim=1)
     T = torch.cat([torch.ones_like(incl[:, :1]), incl[:, :-1]], dim=1)   # T before each Gaussian
     with torch.no_grad():
@@ -363,6 +459,10 @@ def trace(scene_or_params, pair, grid, rays_uv=None, *, grad=False, bands: Bands
         if rects is not None:
             allow = torch.tensor(rect_allow(rects, grid, uv)[:, cols])
             terms["disc"] = torch.where(allow, terms["disc"], torch.full_like(terms["disc"], -math.inf))
+        if getattr(grid, "depth_order", 0) == 1:
+            terms, colmat = _order_by_tmid(terms, cols_t, grid)
+        else:
+            colmat = cols_t[None, :].expand(uv.shape[0], -1)
         S_r, S_i, A_uv, hit, active, T = _composite(terms, grid)
         out_r.append(S_r); out_i.append(S_i); out_A.append(A_uv)
         out_n.append(active.sum(1))
@@ -370,7 +470,7 @@ def trace(scene_or_params, pair, grid, rays_uv=None, *, grad=False, bands: Bands
         with torch.no_grad():
             a_act = torch.where(active, terms["alpha"], torch.zeros_like(T))
             out_T.append(torch.prod(1.0 - a_act, dim=1))
-            sig = (active.to(F64) * (cols_t.to(F64) + 1.0)[None, :]).sum(1)
+            sig = (active.to(F64) * (colmat.to(F64) + 1.0)).sum(1)
             out_sig.append(sig)
     S_r = torch.cat(out_r); S_i = torch.cat(out_i)
     res = dict(
@@ -402,11 +502,19 @@ def _marginal(terms, hit, active, T, grid, bands: Bands):
         t_edge = ((t - r_rx).abs() <= tb) & (Q <= LEVEL + bands.q)
         near_hit = hit | q_edge | t_edge
         T_edge = near_hit & ((T - t_min).abs() <= bands.T * t_min)
-        return ((q_edge | t_edge) & reached | T_edge).any(1)
+        flag = ((q_edge | t_edge) & reached | T_edge).any(1)
+        if getattr(grid, "depth_order", 0) == 1:
+            # neighbouring hits (rows already in t order) whose t_mid nearly tie:
+            # FP32 may order them either way
+            both = hit[:, 1:] & hit[:, :-1] & reached[:, :-1]
+            tie = (t[:, 1:] - t[:, :-1]).abs() <= bands.tie * torch.clamp(t[:, :-1].abs(), min=1.0)
+            flag = flag | (both & tie).any(1)
+        return flag
 
 
 def ray_sequence(scene, pair, grid, u: int, v: int, *, direction=None, basis=None):
-    """Per-ray detail in depth order: every Gaussian's Q, t, alpha and c~.
+    """Per-ray detail in depth order: every Gaussian's Q, t, alpha and c~
+    (with depth_order = 1: the ray's hits in t_mid order, then the rest).
 
     ``direction`` / ``basis`` override the grid's ray (used by the worked
     example, which needs an exactly unit direction).  Returns numpy arrays
@@ -422,6 +530,9 @@ def ray_sequence(scene, pair, grid, u: int, v: int, *, direction=None, basis=Non
     act = activate(P)
     with torch.no_grad():
         terms = _per_ray_terms(P, act, rx, tx, lam, grid, dirs, Y, torch.tensor(order))
+        if getattr(grid, "depth_order", 0) == 1:
+            terms, colmat = _order_by_tmid(terms, torch.tensor(order), grid)
+            order = colmat[0].numpy()
         S_r, S_i, A_uv, hit, active, T = _composite(terms, grid)
     g = lambda k: terms[k][0].detach().numpy()
     return dict(order=order, Q=g("Q"), t=g("t"), alpha=g("alpha"), p=g("p"),
@@ -445,15 +556,29 @@ def ray_variants(scene, pair, grid, u: int, v: int, bands: Bands | None = None, 
     maybe = (~sure) & (Q <= LEVEL + bands.q) & (t >= r_rx - tb)
     idx = np.nonzero(sure | maybe)[0]
     flips = [i for i in idx if maybe[i]]
-    if len(flips) > max_flip:
+    tmid = getattr(grid, "depth_order", 0) == 1
+    ties = []
+    if tmid:
+        # neighbours in t order whose t_mid nearly tie: either order is admissible
+        by_t = sorted(idx, key=lambda i: (t[i], i))
+        for a_, b_ in zip(by_t[:-1], by_t[1:]):
+            if abs(t[b_] - t[a_]) <= bands.tie * max(1.0, abs(t[a_])):
+                ties.append((a_, b_))
+    if len(flips) + len(ties) > max_flip:
         return None
     out = []
-    for mask in range(1 << len(flips)):
+    for mask in range(1 << (len(flips) + len(ties))):
         chosen = set(i for i in idx if sure[i])
         for b, i in enumerate(flips):
             if mask >> b & 1:
                 chosen.add(i)
         seq = [i for i in idx if i in chosen]
+        if tmid:
+            seq = sorted(seq, key=lambda i: (t[i], i))
+            for b, (a_, b_) in enumerate(ties):
+                if mask >> (len(flips) + b) & 1 and a_ in chosen and b_ in chosen:
+                    ia, ib = seq.index(a_), seq.index(b_)
+                    seq[ia], seq[ib] = seq[ib], seq[ia]
         for thr in (t_min * (1 - bands.T), t_min, t_min * (1 + bands.T)):
             T, S = 1.0, 0.0 + 0.0j
             for i in seq:

@@ -41,6 +41,9 @@ class Grid:
     tile_h: int = 16
     lanes_per_ray: int = 0
     footprint: int = 0          # 0: exact bounding cap, 1: the paper's 3 sqrt(lambda_max) footprint
+    depth_order: int = 0        # 0: per-Gaussian distance key, 1: per-ray chord-midpoint order
+    fle_eval: int = 0           # 0: radiance at the ray's direction, 1: at the Gaussian's direction
+    transmittance: int = 0      # 0: 1 - o G(x_mid), 1: chord form exp(-alpha dt)
 
     @property
     def K(self) -> int:
