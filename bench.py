@@ -36,28 +36,104 @@ PEAK_FP32_VALU = 157.3e12   # FLOP/s: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 
 PEAK_HBM = 8.0e12           # B/s
 
 
-def flops_per(K: int) -> dict:
-    """Algorithmic FP32 FLOPs (FMA = 2) per hit test and per processed hit.
+# Algorithmic work per unit of the tiled method (the scope table's measurement
+# model): a tile test (a ray of a tile against a list entry up to the tile's
+# termination) costs 20 FP32 operations (6 FMA for A, 3 FMA for B, rcp, Q, t,
+# two compares), a processed hit 70 (exp, p, alpha, local phase, sincos, psi
+# as 9 complex MACs, complex scale and accumulate, T), and the adjoint three
+# times the forward.  These are the counts `frac` is taken against.
+ALG_TEST, ALG_HIT, ALG_BWD_FACTOR = 20.0, 70.0, 3.0
+
+
+def alg_flops(st: dict) -> dict:
+    fwd = st["tile_tests"] * ALG_TEST + st["hits"] * ALG_HIT
+    return {"render_fwd": fwd, "render_bwd": ALG_BWD_FACTOR * fwd}
+
+
+def flops_impl(K: int) -> dict:
+    """FP32 operations (FMA = 2) the kernels execute per hit test and per
+    processed hit, for comparison with the algorithmic counts.
 
     test: eps (6) + M v (15) + A (5) + b (5) + M eps (15) + c (5) + 1/A, b/A (2)
-          + Q (3) + t (2) + two compares (2) = 60
+          + Q (3) + t (2) + two compares (2) = 60 (forward only: the adjoint
+          reuses the forward's hit masks and makes no tests)
     hit, forward: exp(-Q/2) (2) + alpha, p (3) + phase (2) + sincos (30)
           + psi (8K) + psi e^{-j phase} (6) + c~ (2) + S, T update (7) = 52 + 8K
-    hit, adjoint extra: prefix and remainder (6) + dL/dp, dL/dphase, dL/dalpha (13)
-          + dL/dG, dL/dQ, dL/dt (7) + p_perp, M p_perp (18) + dL/dM (30)
-          + dL/dmu (9) + dL/dN, dL/do (2) + dL/dpsi (8) + dL/dc (6K) + T (2)
-          + one add per accumulator for the reduction over rays (12 + 2K)
-          = 107 + 8K
+    hit, adjoint: the forward's hit terms (52 + 8K) + prefix and remainder (6)
+          + dL/dp, dL/dphase, dL/dalpha (13) + dL/dG, dL/dQ, dL/dt (7)
+          + p_perp, M p_perp (18) + dL/dM (30) + dL/dmu (9) + dL/dN, dL/do (2)
+          + dL/dpsi (8) + dL/dc (6K) + T (2) + one add per accumulator for the
+          reduction over rays (12 + 2K) = 159 + 16K
     """
     return dict(test=60.0, hit_fwd=52.0 + 8 * K, hit_bwd=52.0 + 8 * K + 107.0 + 8 * K)
 
 
-def flops_multi(K: int, n_freq: int, chunks: int, tile_tests: int, hits: int) -> float:
-    """Algorithmic FP32 FLOPs of the multi-carrier forward: per traversal (one
-    per chunk of carriers) the tile tests and the single-carrier hit work plus
-    the step phasor (fma 2 + sincos 30 + weight 1 = 33); per hit and carrier
-    the two accumulating FMAs (4) and the phasor rotation (6) = 10."""
-    return chunks * tile_tests * 60.0 + hits * (chunks * (52.0 + 8 * K + 33.0) + 10.0 * n_freq)
+def impl_flops(st: dict, K: int) -> dict:
+    f = flops_impl(K)
+    return {"render_fwd": st["tests"] * f["test"] + st["hits"] * f["hit_fwd"],
+            "render_bwd": st["hits"] * f["hit_bwd"]}
+
+
+def flops_multi(n_freq: int, tile_tests: int, hits: int) -> float:
+    """Algorithmic FP32 FLOPs of the multi-carrier forward: the single-carrier
+    forward's (tile tests x 20 + processed hits x 70) once, plus per hit and
+    extra carrier the phase term and the complex accumulate (10)."""
+    return tile_tests * ALG_TEST + hits * (ALG_HIT + 10.0 * (n_freq - 1))
+
+
+def kernel_roofline(kernel: str, st: dict, K: int, t_kernel: float) -> dict:
+    """Roofline object of one render kernel: algorithmic FLOPs per launch over
+    its measured duration, against the FP32 VALU peak."""
+    fl = alg_flops(st)[kernel]
+    ach = fl / t_kernel
+    return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP32_VALU, "traffic": None, "kernel": kernel, "kernel_ms": t_kernel * 1e3,
+            "flop_per_launch": fl,
+            "flop_model": f"tile tests x {ALG_TEST:g} + processed hits x {ALG_HIT:g}"
+                          + (f", x {ALG_BWD_FACTOR:g} for the adjoint" if kernel == "render_bwd" else ""),
+            "flop_model_impl": impl_flops(st, K)[kernel]}
+
+
+def pipeline_roofline(st: dict, n_gauss: int, visible: int, splats: int, rays: int, t_step: float,
+                      bwd: bool) -> dict:
+    """Whole-path roofline time t_roof = max(F / VALU peak, B / HBM peak) over
+    the measured step time, with F the algorithmic FLOPs of the render
+    kernel(s) and B the algorithmic bytes: the scene read once (116 B per
+    Gaussian), 16 B per visible (pair, Gaussian) record, two passes of 12 B per
+    splat, 8 B per output ray, and for the adjoint 29 floats per staged
+    (tile, Gaussian) entry."""
+    af = alg_flops(st)
+    F = af["render_fwd"] + (af["render_bwd"] if bwd else 0.0)
+    B = 116.0 * n_gauss + 16.0 * visible + 24.0 * splats + 8.0 * rays + (116.0 * st["staged"] if bwd else 0.0)
+    t_roof = max(F / PEAK_FP32_VALU, B / PEAK_HBM)
+    return {"flop": F, "bytes": B, "t_roof_ms": t_roof * 1e3, "t_measured_ms": t_step * 1e3,
+            "frac": t_roof / t_step, "bound": "alu" if F / PEAK_FP32_VALU >= B / PEAK_HBM else "hbm"}
+
+
+def visible_records(prob) -> int:
+    """(pair, Gaussian) records whose tile rectangle is not empty."""
+    import torch
+    lay = prob.layout()
+    r = prob.view(lay.rec_rect, torch.int16, int(lay.n_records) * 4).view(-1, 4).to(torch.int32) & 0xFFFF
+    return int(((r[:, 1] * r[:, 3]) > 0).sum())
+
+
+def host_cpu() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        import psutil
+        phys = psutil.cpu_count(logical=False)
+    except Exception:
+        phys = None
+    return {"cpu_model": model, "physical_cores": phys, "logical_cpus": os.cpu_count()}
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "render_traffic.json")
@@ -103,7 +179,8 @@ def cpu_baseline(scene, pair, grid, min_seconds: float = 8.0) -> dict:
     per_spectrum = dt * n_rays / sample
     return {"value": 1.0 / per_spectrum, "unit": "spectra/s", "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"FP64 forward + autograd gradient of {sample} of {n_rays} rays of one pair "
-                      f"({dt:.1f} s), scaled by {n_rays / sample:.1f}"}
+                      f"({dt:.1f} s), scaled by {n_rays / sample:.1f}",
+            "threads_used": torch.get_num_threads(), **host_cpu()}
 
 
 def main() -> int:
@@ -209,14 +286,12 @@ def main() -> int:
         t_f = ev1["f0"][0].elapsed_time(ev1["f1"][0]) * 1e-3
         t_b = ev1["b0"][0].elapsed_time(ev1["b1"][0]) * 1e-3 if bwd else 0.0
         st = prob.render_stats()
-        fp = flops_per(grid.K)
-        fl_f = st["tile_tests"] * fp["test"] + st["hits"] * fp["hit_fwd"]
-        fl_b = st["tile_tests"] * fp["test"] + st["hits"] * fp["hit_bwd"]
-        dom, fl, tk = ("render_bwd", fl_b, t_b) if (bwd and t_b >= t_f) else ("render_fwd", fl_f, t_f)
-        ach = fl / tk
-        return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP32_VALU, "traffic": None, "kernel": dom, "kernel_ms": tk * 1e3,
-                "flop_per_launch": fl, "counts": st}
+        dom, tk = ("render_bwd", t_b) if (bwd and t_b >= t_f) else ("render_fwd", t_f)
+        roof = kernel_roofline(dom, st, grid.K, tk)
+        roof["counts"] = st
+        roof["other_kernel"] = (kernel_roofline("render_fwd" if dom == "render_bwd" else "render_bwd", st, grid.K,
+                                                t_f if dom == "render_bwd" else t_b) if bwd else None)
+        return roof
 
     def run_batched(b, grad, label):
         from paper_2502_01826_amd.batch import GraphStep, autotune
@@ -243,8 +318,13 @@ def main() -> int:
         t = st["median"]
         bufs = dict(sig=step.signal, ssum=step.signal_sum, rssi=step.rssi, G=gs, gsum=gsum, grads=step.grads)
         roof = roofline(prob, bufs, grad)
-        n_splats, _ = prob.splat_count()
+        n_splats, ok = prob.splat_count()
+        if not ok:
+            raise RuntimeError(f"{label}: {n_splats} splats exceed the capacity fixed before capture")
         roof["counts"]["splats"] = n_splats
+        vis = visible_records(prob)
+        pipe = pipeline_roofline(roof["counts"], int(cat.means.shape[0]), vis, n_splats,
+                                 P * grid.n_az * grid.n_el, t, grad)
         del step, prob
         torch.cuda.empty_cache()
         return {"workload": label, "pairs": P, "gaussians": int(cat.means.shape[0]),
@@ -255,7 +335,8 @@ def main() -> int:
                 " for all pairs)",
                 "tile": f"{tw}x{th}", "lanes_per_ray": lanes,
                 "autotune_ms": {f"{a}x{b_}/{c}": v * 1e3 for (a, b_, c), v in tune.seconds.items()},
-                "roofline": roof}
+                "splats_within_capacity": True, "visible_records": vis,
+                "roofline": roof, "pipeline_roofline": pipe}
 
     def run_plain():
         prob, bufs = make([pair])
@@ -285,23 +366,24 @@ def main() -> int:
         del gstep
         t_fwd_only = timed(prob, bufs, args.steps, 1, False)
         stats = prob.render_stats()
-        n_splats, _ = prob.splat_count()
+        n_splats, ok = prob.splat_count()
+        if not ok:
+            raise RuntimeError(f"plain step: {n_splats} splats exceed the capacity fixed before timing")
         K = grid.K
-        f = flops_per(K)
-        fl_fwd = stats["tile_tests"] * f["test"] + stats["hits"] * f["hit_fwd"]
-        fl_bwd = stats["tile_tests"] * f["test"] + stats["hits"] * f["hit_bwd"]
-        if t_bwd_k >= t_fwd_k:
-            dom, fl, tk = "render_bwd", fl_bwd, t_bwd_k
-        else:
-            dom, fl, tk = "render_fwd", fl_fwd, t_fwd_k
-        achieved = fl / tk
-        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VALU,
-                "traffic": (measured_traffic(dom, f"{args.tile}/{args.lanes}/{args.gaussians}")
-                            if args.footprint == "cap" else None), "kernel": dom,
-                "kernel_ms": tk * 1e3, "flop_per_launch": fl, "timing": "HIP events recorded by the library "
-                "immediately around the render kernel on its stream, averaged over the timed steps",
-                "counts": {**stats, "splats": n_splats}}
+        dom, tk = ("render_bwd", t_bwd_k) if t_bwd_k >= t_fwd_k else ("render_fwd", t_fwd_k)
+        roof = kernel_roofline(dom, stats, K, tk)
+        roof["traffic"] = (measured_traffic(dom, f"{args.tile}/{args.lanes}/{args.gaussians}")
+                           if args.footprint == "cap" else None)
+        roof["timing"] = ("HIP events recorded by the library immediately around the render kernel on its "
+                          "stream, averaged over the timed steps")
+        roof["counts"] = {**stats, "splats": n_splats}
+        roof["other_kernel"] = kernel_roofline("render_fwd" if dom == "render_bwd" else "render_bwd", stats, K,
+                                               t_fwd_k if dom == "render_bwd" else t_bwd_k)
+        vis = visible_records(prob)
+        roof["pipeline"] = {
+            "graph_replay": pipeline_roofline(stats, prob.n_gauss, vis, n_splats, grid.n_az * grid.n_el, t_step, True),
+            "plain_eager": pipeline_roofline(stats, prob.n_gauss, vis, n_splats, grid.n_az * grid.n_el, t_eager,
+                                             True)}
         del prob, bufs
         torch.cuda.empty_cache()
         return t_step, t_fwd_only, t_fwd_k, t_bwd_k, roof
@@ -342,7 +424,10 @@ def main() -> int:
         torch.cuda.synchronize()
         t_1k = sum(a.elapsed_time(b) for a, b in zip(ev1["f0"], ev1["f1"])) / steps * 1e-3
         st = prob.render_stats()
-        fl = flops_multi(grid.K, nf, len(multi_chunks(nf)), st["tile_tests"], st["hits"])
+        n_splats, ok = prob.splat_count()
+        if not ok:
+            raise RuntimeError(f"multi-carrier: {n_splats} splats exceed the capacity fixed before timing")
+        fl = flops_multi(nf, st["tile_tests"], st["hits"])
         ach = fl / t_mk
         del prob, bufs, msig, msum
         torch.cuda.empty_cache()
@@ -516,6 +601,10 @@ def main() -> int:
         "step_timing": "hipGraph replays of the captured step (project, bin_sort, render_fwd, render_bwd)",
         "step_ms_events": step_stats or None,
         "eager": eager or None,
+        "plain": None if not eager else {"spectra_per_s": eager["spectra_per_s"], "ms_per_step": eager["ms_per_step"],
+                                         "timing": "eager launches of project, bin_sort, render_fwd, render_bwd "
+                                                   "for one pair on one stream, wall clock between "
+                                                   "synchronisations (the plain per-pair launch)"},
         "fwd_only": None if t_fwd_only is None else {"spectra_per_s": 1.0 / t_fwd_only, "ms": t_fwd_only * 1e3},
         "kernels_ms": None if t_fwd_k is None else {"render_fwd": t_fwd_k * 1e3, "render_bwd": t_bwd_k * 1e3},
         "batched": batched,

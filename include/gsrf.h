@@ -74,6 +74,21 @@ typedef enum gsrf_status {
  *              map, so hits of a ray outside the square are dropped.  Both
  *              keep the exact per-ray 3-sigma test of the render.
  *              GSRF_EINVAL for other values.
+ * The paper-literal variants of the render (each 0 = the default reading;
+ * GSRF_EINVAL for values other than 0 and 1; they need lanes_per_ray = 0;
+ * gsrf_render_fwd supports them, while gsrf_render_bwd, gsrf_render_fwd_multi
+ * and gsrf_render_stats return GSRF_ENOTSUP when any is set):
+ *   depth_order    1: every ray takes its hits in increasing chord-midpoint
+ *              parameter t_mid = -B/A (App. A.3: Gaussians sorted by their
+ *              midpoint times), ties in depth-key order, instead of the
+ *              per-tile distance-key order.  Needs hit_capacity (gsrf_problem).
+ *   fle_eval       1: the radiance psi_k is the FLE evaluated once per
+ *              (pair, Gaussian) at the direction of mu_k from the receiver,
+ *              instead of at each ray's direction (Sec. 3.2 eq. FLE).
+ *   transmittance  1: a hit's transmittance is the chord form of App. A.2,
+ *              rho = exp(-alpha_k dt) with dt = t_out - t_in the 3-sigma
+ *              chord and alpha_k = exp(opacity_logit) per metre, instead of
+ *              1 - min(o G, alpha_max); the propagation phase is unchanged.
  */
 typedef struct gsrf_grid {
   int32_t n_az, n_el;
@@ -85,6 +100,9 @@ typedef struct gsrf_grid {
   int32_t tile_w, tile_h;
   int32_t lanes_per_ray;
   int32_t footprint;
+  int32_t depth_order;
+  int32_t fle_eval;
+  int32_t transmittance;
 } gsrf_grid;
 
 /*
@@ -128,6 +146,8 @@ typedef struct gsrf_problem {
   int64_t splat_capacity;            /* max (tile, Gaussian) splats, < 2^32 */
   void *workspace;
   size_t workspace_bytes;
+  int64_t hit_capacity;              /* depth_order = 1: max (ray, Gaussian) hit records, < 2^40;
+                                        ignored (may be 0) otherwise */
 } gsrf_problem;
 
 /* Byte offsets of the workspace arrays that tests and tools may read.  Tile
@@ -179,6 +199,14 @@ gsrf_status gsrf_project(const gsrf_problem *p, void *stream);
  * splat_capacity (the caller then re-sizes and re-runs from gsrf_project).
  */
 gsrf_status gsrf_splat_count(const gsrf_problem *p, int64_t *n_splats, void *stream);
+
+/*
+ * depth_order = 1 only: synchronises `stream` and returns (HOST) the number of
+ * (ray, Gaussian) hit records the last gsrf_render_fwd needed (every hit of
+ * every ray, before termination).  GSRF_ECAPACITY if it exceeds
+ * hit_capacity: that render wrote zeros; re-size and render again.
+ */
+gsrf_status gsrf_ray_hit_count(const gsrf_problem *p, int64_t *n_hits, void *stream);
 
 /*
  * Steps a3 + a4 (Alg. 1 sphericalSplatting, the 64-bit key sort of App. E,

@@ -284,7 +284,7 @@ class Bands:
     q: float = 3e-4        # |Q - 9| (absolute, Mahalanobis^2 units)
     t: float = 1e-5        # |t - r_rx| relative to max(1, t)
     T: float = 3e-4        # |T - t_min| relative to t_min
-    tie: float = 1e-6      # depth_order = 1: |t_i - t_j| of neighbouring hits relative to max(1, t)
+    tie: float = 1e-6      # depth_order = 1: |t_i - t_j| of neighbouring hits (absolute, metres)
 
 
 def _per_ray_terms(P: Params, act, rx, tx, lam, grid, dirs, Y, cols):
@@ -507,7 +507,7 @@ def _marginal(terms, hit, active, T, grid, bands: Bands):
             # neighbouring hits (rows already in t order) whose t_mid nearly tie:
             # FP32 may order them either way
             both = hit[:, 1:] & hit[:, :-1] & reached[:, :-1]
-            tie = (t[:, 1:] - t[:, :-1]).abs() <= bands.tie * torch.clamp(t[:, :-1].abs(), min=1.0)
+            tie = (t[:, 1:] - t[:, :-1]).abs() <= bands.tie
             flag = flag | (both & tie).any(1)
         return flag
 
@@ -562,7 +562,7 @@ def ray_variants(scene, pair, grid, u: int, v: int, bands: Bands | None = None, 
         # neighbours in t order whose t_mid nearly tie: either order is admissible
         by_t = sorted(idx, key=lambda i: (t[i], i))
         for a_, b_ in zip(by_t[:-1], by_t[1:]):
-            if abs(t[b_] - t[a_]) <= bands.tie * max(1.0, abs(t[a_])):
+            if abs(t[b_] - t[a_]) <= bands.tie:
                 ties.append((a_, b_))
     if len(flips) + len(ties) > max_flip:
         return None

@@ -25,7 +25,8 @@ c_i32, c_i64, c_f32, c_f64, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes
 class GsrfGrid(ctypes.Structure):
     _fields_ = [("n_az", c_i32), ("n_el", c_i32), ("el_lo", c_f32), ("el_hi", c_f32), ("fle_L", c_i32),
                 ("r_rx", c_f32), ("t_min", c_f32), ("alpha_max", c_f32), ("tile_w", c_i32), ("tile_h", c_i32),
-                ("lanes_per_ray", c_i32), ("footprint", c_i32)]
+                ("lanes_per_ray", c_i32), ("footprint", c_i32), ("depth_order", c_i32), ("fle_eval", c_i32),
+                ("transmittance", c_i32)]
 
 
 class GsrfPair(ctypes.Structure):
@@ -36,7 +37,7 @@ class GsrfProblem(ctypes.Structure):
     _fields_ = [("means", c_vp), ("log_scales", c_vp), ("quats", c_vp), ("opacity_logits", c_vp), ("coeffs", c_vp),
                 ("n_gauss", c_i64), ("n_scenes", c_i32), ("scene_offsets", c_vp), ("scene_offsets_dev", c_vp),
                 ("pairs", c_vp), ("pair_scene", c_vp), ("n_pairs", c_i32), ("grid", GsrfGrid),
-                ("splat_capacity", c_i64), ("workspace", c_vp), ("workspace_bytes", c_sz)]
+                ("splat_capacity", c_i64), ("workspace", c_vp), ("workspace_bytes", c_sz), ("hit_capacity", c_i64)]
 
 
 class GsrfLayout(ctypes.Structure):
@@ -60,7 +61,7 @@ assert ctypes.sizeof(GsrfPair) == 40
 GSRF_LOSS_RSSI_DB, GSRF_LOSS_COMPLEX_L2 = 0, 1
 
 EXPORTS = ["gsrf_status_str", "gsrf_last_error", "gsrf_workspace_size", "gsrf_layout_of", "gsrf_project",
-           "gsrf_splat_count", "gsrf_bin_sort", "gsrf_render_fwd", "gsrf_render_fwd_multi", "gsrf_render_bwd",
+           "gsrf_splat_count", "gsrf_ray_hit_count", "gsrf_bin_sort", "gsrf_render_fwd", "gsrf_render_fwd_multi", "gsrf_render_bwd",
            "gsrf_render_stats",
            "gsrf_set_kernel_events", "gsrf_loss_workspace_size", "gsrf_loss_spectrum", "gsrf_loss_single",
            "gsrf_sgd_step", "gsrf_grad_stats_accumulate", "gsrf_density_workspace_size", "gsrf_density_control"]
@@ -85,6 +86,7 @@ def lib() -> ctypes.CDLL:
     L.gsrf_layout_of.argtypes = [P(GsrfProblem), P(GsrfLayout)]
     L.gsrf_project.argtypes = [P(GsrfProblem), c_vp]
     L.gsrf_splat_count.argtypes = [P(GsrfProblem), P(c_i64), c_vp]
+    L.gsrf_ray_hit_count.argtypes = [P(GsrfProblem), P(c_i64), c_vp]
     L.gsrf_bin_sort.argtypes = [P(GsrfProblem), c_vp]
     L.gsrf_render_fwd.argtypes = [P(GsrfProblem), c_vp, c_vp, c_vp, c_vp]
     L.gsrf_render_bwd.argtypes = [P(GsrfProblem), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]

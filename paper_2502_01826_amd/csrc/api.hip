@@ -50,6 +50,14 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
     return fail(GSRF_EINVAL, "footprint = %d: must be 0 (exact cap) or 1 (paper footprint)", g.footprint);
   if (nt == 32 && g.lanes_per_ray != 0)
     return fail(GSRF_EINVAL, "32-ray tiles need the two-phase traversal (lanes_per_ray = 0)");
+  if ((g.depth_order != 0 && g.depth_order != 1) || (g.fle_eval != 0 && g.fle_eval != 1) ||
+      (g.transmittance != 0 && g.transmittance != 1))
+    return fail(GSRF_EINVAL, "depth_order = %d, fle_eval = %d, transmittance = %d: each must be 0 or 1",
+                g.depth_order, g.fle_eval, g.transmittance);
+  if (has_variant(g) && g.lanes_per_ray != 0)
+    return fail(GSRF_EINVAL, "the paper-literal variants need the two-phase traversal (lanes_per_ray = 0)");
+  if (g.depth_order && (p->hit_capacity < 0 || p->hit_capacity >= ((int64_t)1 << 40)))
+    return fail(GSRF_EINVAL, "hit_capacity = %lld outside [0, 2^40)", (long long)p->hit_capacity);
   if (!(g.el_lo < g.el_hi) || g.el_lo < -1.5707964f || g.el_hi > 1.5707964f)
     return fail(GSRF_EINVAL, "elevation span [%g, %g] invalid", (double)g.el_lo, (double)g.el_hi);
   if (!(g.r_rx >= 0.f) || !(g.t_min >= 0.f) || !(g.alpha_max > 0.f && g.alpha_max < 1.f))
@@ -126,6 +134,15 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.grad_acc = take((size_t)G * L.acc_stride * 4);
   L.hitmask = take(g.lanes_per_ray == 0 ? (size_t)L.cap * (size_t)(g.tile_w * g.tile_h / 32) * 4 : 0);
   L.rays = take((size_t)g.n_az * g.n_el * ray_stride(L.K) * 4);
+  {
+    const int64_t n_all = g.depth_order ? (int64_t)p->n_pairs * g.n_az * g.n_el : 0;
+    L.hit_cap = g.depth_order ? p->hit_capacity : 0;
+    L.ray_cnt = take((size_t)n_all * 4);
+    L.ray_off = take((size_t)n_all * 8);
+    L.tmid_blk = take((size_t)((n_all + kTmidScan - 1) / kTmidScan + 1) * 8);
+    L.hit_key = take((size_t)L.hit_cap * 8);
+    L.hit_val = take((size_t)L.hit_cap * 16);
+  }
   L.total = o;
   if (need_device && p->workspace_bytes < L.total)
     return fail(GSRF_EINVAL, "workspace_bytes %zu < required %zu", p->workspace_bytes, L.total);
@@ -202,6 +219,23 @@ gsrf_status gsrf_splat_count(const gsrf_problem *p, int64_t *n_splats, void *str
   return GSRF_OK;
 }
 
+gsrf_status gsrf_ray_hit_count(const gsrf_problem *p, int64_t *n_hits, void *stream) {
+  if (!n_hits) return fail(GSRF_EINVAL, "n_hits is NULL");
+  Layout L;
+  gsrf_status st = plan(p, &L, true);
+  if (st != GSRF_OK) return st;
+  if (!p->grid.depth_order) return fail(GSRF_EINVAL, "gsrf_ray_hit_count needs depth_order = 1");
+  int64_t c[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(c, (char *)p->workspace + L.counters, sizeof(c), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return dev(e, "gsrf_ray_hit_count");
+  *n_hits = c[2];
+  if (c[2] > L.hit_cap)
+    return fail(GSRF_ECAPACITY, "%lld hit records exceed capacity %lld", (long long)c[2], (long long)L.hit_cap);
+  return GSRF_OK;
+}
+
 gsrf_status gsrf_bin_sort(const gsrf_problem *p, void *stream) {
   Layout L;
   gsrf_status st = plan(p, &L, true);
@@ -225,6 +259,7 @@ gsrf_status gsrf_render_fwd_multi(const gsrf_problem *p, int32_t n_freq, double 
   if (!(freq_step_hz >= 0.0) || !(freq_step_hz < 1e12)) return fail(GSRF_EINVAL, "freq_step_hz = %g", freq_step_hz);
   if (p->grid.lanes_per_ray != 0)
     return fail(GSRF_ENOTSUP, "the multi-carrier forward uses the two-phase traversal (lanes_per_ray = 0)");
+  if (has_variant(p->grid)) return fail(GSRF_ENOTSUP, "the multi-carrier forward has no paper-literal variants");
   Layout L;
   gsrf_status st = plan(p, &L, true);
   if (st != GSRF_OK) return st;
@@ -243,6 +278,7 @@ gsrf_status gsrf_render_bwd(const gsrf_problem *p, const float *signal, const fl
   if (p->n_pairs > 0 && (!signal || !grad_signal)) return fail(GSRF_EINVAL, "signal or grad_signal is NULL");
   if (p->n_gauss > 0 && (!d_means || !d_log_scales || !d_quats || !d_logits || !d_coeffs))
     return fail(GSRF_EINVAL, "a gradient output pointer is NULL");
+  if (has_variant(p->grid)) return fail(GSRF_ENOTSUP, "no adjoint for the paper-literal render variants");
   return dev(launch_render_bwd(p, L, (char *)p->workspace, signal, grad_signal, grad_sum, d_means, d_log_scales,
                                d_quats, d_logits, d_coeffs, (hipStream_t)stream),
              "gsrf_render_bwd");
@@ -253,6 +289,7 @@ gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stre
   gsrf_status st = plan(p, &L, true);
   if (st != GSRF_OK) return st;
   if (!counts) return fail(GSRF_EINVAL, "counts is NULL");
+  if (has_variant(p->grid)) return fail(GSRF_ENOTSUP, "no traversal counters for the paper-literal render variants");
   return dev(launch_render_stats(p, L, (char *)p->workspace, counts, (hipStream_t)stream), "gsrf_render_stats");
 }
 

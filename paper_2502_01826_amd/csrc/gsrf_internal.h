@@ -106,6 +106,10 @@ struct Layout {
   size_t tile_sum, grad_acc;
   size_t hitmask;         // two-phase traversal: per splat, tile-area / 32 words of forward hit bits
   size_t rays;            // [n_el * n_az][ray_stride(K)] ray directions and FLE basis (FP32)
+  // per-ray midpoint order (depth_order = 1): hits per ray, first record per
+  // ray, block sums of their scan, and the records (sort key, terms)
+  size_t ray_cnt, ray_off, tmid_blk, hit_key, hit_val;
+  int64_t hit_cap;
   size_t total;
   int64_t n_records;
   int32_t rec_block;      // records per workgroup in emit (256 or 1024)
@@ -126,6 +130,12 @@ void mark_kernel_event(int i, hipStream_t s);
 struct RenderArgs;
 RenderArgs make_render_args(const gsrf_problem *p, const Layout &lay, char *ws);
 
+// A paper-literal variant of the render is selected (per-ray midpoint order,
+// per-Gaussian FLE or chord transmittance).
+inline bool has_variant(const gsrf_grid &g) { return g.depth_order != 0 || g.fle_eval != 0 || g.transmittance != 0; }
+// Rays per midpoint-order scan block.
+constexpr int kTmidScan = 1024;
+
 // Launch helpers implemented in the .hip files; each returns hipSuccess or the
 // launch error.
 hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hipStream_t s);
@@ -133,6 +143,8 @@ hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, h
 hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws, float *signal,
                              float *signal_sum, float *rssi_dbm, hipStream_t s);
 hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *ws, int64_t *counts, hipStream_t s);
+hipError_t launch_render_fwd_variant(const gsrf_problem *p, const Layout &lay, char *ws, float *signal,
+                                     float *signal_sum, float *rssi_dbm, hipStream_t s);
 hipError_t launch_render_fwd_multi(const gsrf_problem *p, const Layout &lay, char *ws, int32_t n_freq, double f_step,
                                    float *signal, float *signal_sum, hipStream_t s);
 hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws, const float *signal,

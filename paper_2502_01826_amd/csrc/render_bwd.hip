@@ -82,7 +82,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
           hit = test_hit(vx, vy, vz, geo, a.r_rx, h);
           if (hit) {
             hit_terms<K>(geo, scf + 2 * K * j, Yr, Yi, a.amax, h);
-            f = 1.0f - h.alpha;
+            f = h.keep;
             ctr = h.p * h.pzr;
             cti = h.p * h.pzi;
           }

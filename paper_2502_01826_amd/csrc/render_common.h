@@ -34,8 +34,11 @@ struct RenderArgs {
   uint32_t *hitmask;        // [splats][R / 32]: per list entry, its hits over the tile's rays (two-phase
                             // traversal: written by the forward, read by the adjoint)
   const float *rays;        // [n_el * n_az][ray_stride(K)] ray table made by gsrf_project
+  const float *logits;      // [G] opacity logits (the chord transmittance's attenuation coefficient)
   int32_t T, nta, n_az, n_el, tw;
   float el_lo, el_hi, r_rx, t_min, amax;
+  int32_t fle_g;            // 1: radiance at the Gaussian's direction (variant kernels only)
+  int32_t chord;            // 1: chord transmittance exp(-alpha dt) (variant kernels only)
 };
 
 // Geometry record per staged Gaussian: five float4
@@ -108,7 +111,63 @@ __device__ __forceinline__ void ray_load(int u, int v, const RenderArgs &a, floa
 // (mu - tx)/|mu - tx|, and g's bits in w.  STEP (the multi-carrier forward):
 // g4.zw = ((|mu - tx| + D), D) * step_rev with step_rev = (carrier step)/c, so
 // that a hit at t adds (|mu - tx| + t) * step / c turns per carrier step.
-template <int K, bool STEP = false>
+// VAR (the paper-literal variant kernels): with a.fle_g the entry's radiance
+// psi_k = sum_i c_i Y_i(e) at the direction e of mu from the receiver is
+// formed here, once per entry, and stored as cf[0..1] in place of the
+// coefficients; with a.chord g3.w holds the attenuation coefficient
+// exp(logit) in place of the opacity.
+template <int L>
+__device__ __forceinline__ void psi_at_direction(double ex, double ey, double ez, const float *c, double &pr,
+                                                 double &pi) {
+  // Y_lm = w^m Q_l^m(x), w = ex + j ey, x = ez, Q_l^m = P_l^m / (1 - x^2)^(m/2);
+  // Y_{l,-m} = (-1)^m (l-m)!/(l+m)! conj(w)^m Q_l^m (Sec. 3.2 eq. FLE)
+  double wr = 1.0, wi = 0.0;      // w^m
+  double qmm = 1.0;               // Q_m^m = (-1)^m (2m-1)!!
+  pr = 0.0;
+  pi = 0.0;
+#pragma unroll
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) {
+      const double nr = wr * ex - wi * ey, ni = wr * ey + wi * ex;
+      wr = nr;
+      wi = ni;
+      qmm = -qmm * (2 * m - 1);
+    }
+    double q2 = 0.0, q1 = qmm;
+#pragma unroll
+    for (int l = m; l <= L; ++l) {
+      double q;
+      if (l == m) {
+        q = qmm;
+      } else if (l == m + 1) {
+        q = ez * (2 * m + 1) * qmm;
+        q2 = q1;
+        q1 = q;
+      } else {
+        q = ((2 * l - 1) * ez * q1 - (l + m - 1) * q2) / (l - m);
+        q2 = q1;
+        q1 = q;
+      }
+      const double yr = wr * q, yi = wi * q;
+      const int ip = l * l + l + m;
+      const double cr = c[2 * ip], ci = c[2 * ip + 1];
+      pr += cr * yr - ci * yi;
+      pi += cr * yi + ci * yr;
+      if (m > 0) {
+        double f = 1.0;   // (l+m)! / (l-m)!
+        for (int t = l - m + 1; t <= l + m; ++t) f *= t;
+        const double s = ((m & 1) ? -1.0 : 1.0) / f;
+        const int in = l * l + l - m;
+        const double nr = s * yr, ni = -s * yi;       // (-1)^m (l-m)!/(l+m)! conj(w^m) Q
+        const double dr = c[2 * in], di = c[2 * in + 1];
+        pr += dr * nr - di * ni;
+        pi += dr * ni + di * nr;
+      }
+    }
+  }
+}
+
+template <int K, bool STEP = false, bool VAR = false>
 __device__ void stage_entry(const RenderArgs &a, uint32_t g, double rx, double ry, double rz, double tx,
                             double ty, double tz, double inv_lam, float4 *geo, float *cf, float4 *txg = nullptr,
                             double step_rev = 0.0) {
@@ -138,6 +197,18 @@ __device__ void stage_entry(const RenderArgs &a, uint32_t g, double rx, double r
   if (txg) {
     const double it = dtx > 0.0 ? 1.0 / dtx : 0.0;
     *txg = make_float4((float)(qx * it), (float)(qy * it), (float)(qz * it), __uint_as_float(g));
+  }
+  if constexpr (VAR) {
+    geo[4].w = (float)(D - (double)(float)D);   // D's low part: the midpoint order's key
+    if (a.chord) geo[3].w = expf(a.logits[g]);
+    if (a.fle_g) {
+      constexpr int LL = K == 1 ? 0 : K == 4 ? 1 : K == 9 ? 2 : K == 16 ? 3 : K == 25 ? 4 : K == 36 ? 5 : 6;
+      double pr, pi;
+      psi_at_direction<LL>(e0, e1, e2, a.coeffs + (size_t)2 * K * g, pr, pi);
+      cf[0] = (float)pr;
+      cf[1] = (float)pi;
+      return;
+    }
   }
   const float4 *c4 = (const float4 *)(a.coeffs + (size_t)2 * K * g);
   if ((K & 1) == 0) {   // 2K floats per Gaussian: 16-byte aligned rows when K is even
@@ -184,6 +255,7 @@ struct Terms {
   float sn, cs;         // sin/cos of the phase
   float pr, pi;         // psi
   float pzr, pzi;       // psi e^{-j phase}
+  float keep;           // transmittance factor of the hit (1 - alpha, or exp(-alpha_k dt))
   bool clamped;
 };
 
@@ -209,22 +281,36 @@ __device__ __forceinline__ bool test_hit(float vx, float vy, float vz, const flo
   return (h.Q <= kLevel) && (t >= r_rx);
 }
 
-template <int K>
+template <int K, bool VAR = false>
 __device__ __forceinline__ void hit_terms(const float4 *geo, const float *cf, const float *Yr, const float *Yi,
-                                          float amax, Terms &h) {
+                                          float amax, Terms &h, int fle_g = 0, int chord = 0) {
   const float4 g1 = geo[1], g3 = geo[3], g4 = geo[4];
   h.G = __builtin_amdgcn_exp2f(-0.72134752044448170f * h.Q);   // exp(-Q/2)
-  const float oG = g3.w * h.G;
-  h.clamped = oG > amax;
-  h.alpha = fminf(oG, amax);
+  if (VAR && chord) {
+    // App. A.2: rho = exp(-alpha_k dt), dt = t_out - t_in = 2 sqrt((9 - Q) / A)
+    const float dt = 2.0f * sqrtf(fmaxf(kLevel - h.Q, 0.f) * h.rA);
+    h.keep = __builtin_amdgcn_exp2f(-1.44269504088896341f * g3.w * dt);
+    h.alpha = 1.0f - h.keep;
+    h.clamped = false;
+  } else {
+    const float oG = g3.w * h.G;
+    h.clamped = oG > amax;
+    h.alpha = fminf(oG, amax);
+    h.keep = 1.0f - h.alpha;
+  }
   h.p = g3.z * h.G;
   sincos_rev(fmaf(-g1.w, h.bA, g4.x), h.sn, h.cs);
   float pr = 0.f, pi = 0.f;
+  if (VAR && fle_g) {
+    pr = cf[0];
+    pi = cf[1];
+  } else {
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const float cr = cf[2 * i], ci = cf[2 * i + 1];
-    pr = fmaf(cr, Yr[i], fmaf(-ci, Yi[i], pr));
-    pi = fmaf(cr, Yi[i], fmaf(ci, Yr[i], pi));
+    for (int i = 0; i < K; ++i) {
+      const float cr = cf[2 * i], ci = cf[2 * i + 1];
+      pr = fmaf(cr, Yr[i], fmaf(-ci, Yi[i], pr));
+      pi = fmaf(cr, Yi[i], fmaf(ci, Yr[i], pi));
+    }
   }
   h.pr = pr;
   h.pi = pi;

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
           hit = test_hit(vx, vy, vz, sgeo + kGeo * j, a.r_rx, h);
           if (hit) {
             hit_terms<K>(sgeo + kGeo * j, scf + 2 * K * j, Yr, Yi, a.amax, h);
-            f = 1.0f - h.alpha;
+            f = h.keep;
             ctr = h.p * h.pzr;
             cti = h.p * h.pzi;
           }
@@ -210,6 +210,9 @@ RenderArgs make_render_args(const gsrf_problem *p, const Layout &lay, char *ws) 
   a.tend = (const uint32_t *)(ws + lay.tile_end);
   a.hitmask = (uint32_t *)(ws + lay.hitmask);
   a.rays = (const float *)(ws + lay.rays);
+  a.logits = p->opacity_logits;
+  a.fle_g = p->grid.fle_eval;
+  a.chord = p->grid.transmittance;
   a.T = lay.T;
   a.nta = lay.nta;
   a.n_az = p->grid.n_az;
@@ -226,6 +229,7 @@ RenderArgs make_render_args(const gsrf_problem *p, const Layout &lay, char *ws) 
 hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws, float *signal, float *signal_sum,
                              float *rssi_dbm, hipStream_t s) {
   if (p->n_pairs == 0) return hipSuccess;
+  if (has_variant(p->grid)) return launch_render_fwd_variant(p, lay, ws, signal, signal_sum, rssi_dbm, s);
   const RenderArgs a = make_render_args(p, lay, ws);
   const int64_t nblocks = (int64_t)p->n_pairs * lay.T;
   float2 *tsum = (float2 *)(ws + lay.tile_sum);
@@ -234,7 +238,7 @@ hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws,
   mark_kernel_event(1, s);
   if (e != hipSuccess) return e;
   // partials per pair: one per render workgroup of the pair's tiles
-  const int split = p->grid.lanes_per_ray == 0 ? tp_split(p->grid.tile_w * p->grid.tile_h, nblocks) : 1;
+  const int split = p->grid.lanes_per_ray == 0 ? tp_split(p->grid.tile_w * p->grid.tile_h, nblocks, p->grid.tile_h) : 1;
   hipLaunchKernelGGL(k_rssi, dim3(p->n_pairs), dim3(256), 0, s, tsum, lay.T * split, signal_sum, rssi_dbm);
   return hipGetLastError();
 }

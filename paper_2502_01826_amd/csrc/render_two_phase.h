@@ -37,7 +37,19 @@ namespace gsrf {
 // phase factor of carrier c + 1 is that of carrier c times the step's).  The
 // wide form holds twice the accumulators at half the occupancy; it pays when
 // more than 16 carriers remain.
-enum TpMode { kTpFwd = 0, kTpFwdStats = 1, kTpBwd = 2, kTpFwdMulti = 3, kTpFwdMultiWide = 4 };
+// kTpCount / kTpCollect: the two passes of the per-ray midpoint order
+// (App. A.3): phase-1 tests over the whole list without termination, writing
+// the entry masks and counting each ray's hits; then, from those masks, one
+// record per hit (t_mid, transmittance factor, T-free contribution) at the
+// ray's offset, for a per-ray sort and composite.
+// Midpoint-order sort key: t_mid in units of 2^-24 m (t clamped to
+// [0, 2^16) m) above a 24-bit rank of the hit in list order.
+constexpr int kTmidRankBits = 24;
+constexpr uint64_t kTmidRankMask = ((uint64_t)1 << kTmidRankBits) - 1;
+constexpr double kTmidKeyScale = 16777216.0;                 // 2^24 per metre
+constexpr double kTmidMaxT = 65536.0 - 1.0 / 16777216.0;
+enum TpMode { kTpFwd = 0, kTpFwdStats = 1, kTpBwd = 2, kTpFwdMulti = 3, kTpFwdMultiWide = 4, kTpCount = 5,
+              kTpCollect = 6 };
 constexpr int kMultiChunk = 16, kMultiChunkWide = 32;
 constexpr int multi_chunk(int mode) {
   return mode == kTpFwdMulti ? kMultiChunk : mode == kTpFwdMultiWide ? kMultiChunkWide : 1;
@@ -62,6 +74,11 @@ struct TpIO {
   const float2 *grad_sum;         // adjoint: dL/dS_hat per pair, or null
   float *acc;                     // adjoint accumulators [n_gauss][acc_stride]
   int acc_stride;
+  uint32_t *ray_cnt;              // midpoint order: hits per ray [P, n_el, n_az]
+  const uint64_t *ray_off;        // midpoint order: first record of each ray
+  uint64_t *hit_key;              // midpoint order: (t_mid key << 24 | hit rank) per record
+  float4 *hit_val;                // midpoint order: (keep, Re, Im of p psi e^{-j phi}, -) per record
+  const int64_t *counters;        // [3] = records over capacity (collect writes nothing then)
 };
 
 // BCAP: largest staged batch (128).  Smaller batches waste fewer tests past
@@ -162,12 +179,15 @@ __device__ __forceinline__ unsigned phase1_tests(const RayMono &v, const float4 
 // forward launches with few tiles use it to double the waves in flight.  The
 // hit masks have the same layout either way (ray r of the tile is bit r % 32
 // of word r / 32), so the adjoint need not split as the forward did.
-template <int L, int R, int MODE, int BCAP, int SPLIT>
+template <int L, int R, int MODE, int BCAP, int SPLIT, bool VAR = false>
 __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   using TP = TwoPhase<R>;
   using SH = TpShape<L, R, MODE, BCAP>;
   constexpr int FC = multi_chunk(MODE);
   constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats, MULTI = FC > 1;
+  constexpr bool COUNT = MODE == kTpCount, COLLECT = MODE == kTpCollect;
+  if constexpr (COLLECT)
+    if (io.counters[3] != 0) return;           // records over capacity: the whole launch writes nothing
   constexpr int NT = TP::NT, G = TP::G, EP = TP::EP, RPW = TP::RPW;
   constexpr int K = SH::K, B = SH::B, NACC = SH::NACC, MW = SH::MW, MWS = SH::MWS;
   constexpr int NV = pow2_at_least(NACC);
@@ -234,6 +254,10 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   bool done = !valid || (1.0f < a.t_min);
   if (q == 0) sdone[r] = done ? 1 : 0;
   unsigned long long n_test = 0, n_hit = 0, n_staged = 0, n_tile_tests = 0, n_steps = 0;
+  uint32_t n_ray_hits = 0;   // midpoint order: the ray's hits so far (count: phase-1 thread e = 0; collect: its G lanes)
+  uint64_t ray_base = 0;
+  if constexpr (COLLECT)
+    if (valid) ray_base = io.ray_off[((size_t)k * a.n_el + v) * a.n_az + u];
   int n_valid_rays = 0;
   if constexpr (STATS) {
     const int tu_w = min(a.tw, a.n_az - tu * a.tw), tv_h = max(0, min(th_, a.n_el - v0));
@@ -247,15 +271,15 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     __syncthreads();
     const uint32_t g_cur = g_next;
     if (tid < nb)
-      stage_entry<K, MULTI>(a, g_cur, pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
-                     sgeo + kGeo * tid, scf + 2 * K * tid, BWD ? stx + tid : nullptr, step_rev);
+      stage_entry<K, MULTI, VAR>(a, g_cur, pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
+                                 sgeo + kGeo * tid, scf + 2 * K * tid, BWD ? stx + tid : nullptr, step_rev);
     if (tid < B && base + B + tid < s1) g_next = a.val[base + B + tid];
     if constexpr (BWD)
       for (int i = tid; i < nb; i += NT) {   // what the previous batch's flush left
         sflag[i] = 0u;
         sacc[NACC * i + NACC - 1] = 0.f;
       }
-    if constexpr (!BWD)
+    if constexpr (!BWD && !COLLECT)
       for (int i = tid; i < R * MWS + 4 * MW; i += NT) smask[i] = 0u;   // ray rows and union rows
 
     if (STATS && tid == 0) {
@@ -264,13 +288,17 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     }
     __syncthreads();
     // ---- phase 1: the forward tests; the adjoint takes the forward's hit masks ----
-    if constexpr (!BWD) {
+    if constexpr (!BWD && !COLLECT) {
       if (valid1 && !sdone[r1]) {
         const unsigned nt = phase1_tests<EP, MW>(w1, sgeo, nb, e, a.r_rx, smask + r1 * MWS, suni + (r1 / RPW) * MW);
         if (STATS) n_test += nt;
       }
       __syncthreads();
-      if constexpr (MODE == kTpFwd) {
+      if constexpr (COUNT) {
+        if (e == 0 && valid1)
+          for (int w = 0; w < MW; ++w) n_ray_hits += __builtin_popcount(smask[r1 * MWS + w]);
+      }
+      if constexpr (MODE == kTpFwd || COUNT) {
         // entry masks = transpose of the ray rows, one 32 x 32 bit block per
         // half-wave: block (ray block rb, entry word w); lane l of the half
         // reads ray 32 rb + l's row word and ends with entry 32 w + l's bits
@@ -284,8 +312,9 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
         }
       }
     } else {
-      // the forward's entry masks, transposed back into the rows of the rays
-      // still active; then the union rows of the phase-2 waves
+      // (the adjoint, and the midpoint order's collect pass) the forward's
+      // entry masks, transposed back into the rows of the rays still active;
+      // then the union rows of the phase-2 waves
       constexpr int NBLK = (R / 32) * MW;
       const int hl = lane & 31;
       for (int blk = (tid >> 5); blk < NBLK; blk += NT / 32) {
@@ -305,8 +334,35 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       }
       __syncthreads();
     }
+    // ---- midpoint order, collect: one record per hit of the ray, in list order ----
+    if constexpr (COLLECT) {
+      if (valid) {
+        const uint32_t *mine = smask + r * MWS;
+        for (int w = 0; w < MW; ++w) {
+          uint32_t bits = mine[w];
+          while (bits) {
+            const int j = w * 32 + __builtin_ctz(bits);
+            bits &= bits - 1;
+            if ((int)(n_ray_hits & (G - 1)) == q) {
+              const float4 *geo = sgeo + kGeo * j;
+              Terms h;
+              test_hit(vx, vy, vz, geo, a.r_rx, h);            // the terms of the phase-1 hit
+              hit_terms<K, true>(geo, scf + 2 * K * j, Yr, Yi, a.amax, h, a.fle_g, a.chord);
+              // t_mid = D (1 - b/A) with D = hi + lo, in FP64 from the FP32 terms (error
+              // ~1e-7 m), as a fixed-point key of 2^-24 m over [0, 2^16) m above the rank
+              const double dh = geo[0].w;
+              const double tm = fmin(fmax(dh - dh * (double)h.bA + (double)geo[4].w, 0.0), kTmidMaxT);
+              io.hit_key[ray_base + n_ray_hits] =
+                  ((uint64_t)(tm * kTmidKeyScale) << kTmidRankBits) | (n_ray_hits & kTmidRankMask);
+              io.hit_val[ray_base + n_ray_hits] = make_float4(h.keep, h.p * h.pzr, h.p * h.pzi, 0.f);
+            }
+            ++n_ray_hits;
+          }
+        }
+      }
+    }
     // ---- phase 2: walk the wave's union, G entries per step ----
-    if (__ballot(!done) != 0) {                              // wave-uniform
+    if (!COUNT && !COLLECT && __ballot(!done) != 0) {        // wave-uniform
       const uint32_t *uw = suni + wave * MW;
       const uint32_t *mine = smask + r * MWS;
       int wi = 0;
@@ -332,8 +388,8 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
         float f = 1.f, ctr = 0.f, cti = 0.f;
         if (hit) {
           test_hit(vx, vy, vz, geo, a.r_rx, h);               // the terms of the phase-1 hit
-          hit_terms<K>(geo, scf + 2 * K * j, Yr, Yi, a.amax, h);
-          f = 1.0f - h.alpha;
+          hit_terms<K, VAR>(geo, scf + 2 * K * j, Yr, Yi, a.amax, h, a.fle_g, a.chord);
+          f = h.keep;
           ctr = h.p * h.pzr;
           cti = h.p * h.pzi;
         }
@@ -410,6 +466,11 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     }
     if (__syncthreads_and(done ? 1 : 0)) break;
   }
+  if constexpr (COUNT) {
+    if (e == 0 && valid1) io.ray_cnt[((size_t)k * a.n_el + v1) * a.n_az + u1] = n_ray_hits;
+    return;
+  }
+  if constexpr (COLLECT) return;
   if constexpr (!BWD) {
     if constexpr (G > 1) {   // the ray's total over its G lanes
 #pragma unroll
@@ -464,16 +525,16 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   }
 }
 
-template <int L, int R, int MODE, int BCAP, int SPLIT>
+template <int L, int R, int MODE, int BCAP, int SPLIT, bool VAR = false>
 hipError_t tp_launch(const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
   constexpr size_t lds = TpShape<L, R, MODE, BCAP>::lds();
   if constexpr (lds > 65536) {   // high FLE degrees: opt in to more than 64 KB of LDS
-    const hipError_t e = hipFuncSetAttribute((const void *)k_render_tp<L, R, MODE, BCAP, SPLIT>,
+    const hipError_t e = hipFuncSetAttribute((const void *)k_render_tp<L, R, MODE, BCAP, SPLIT, VAR>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_render_tp<L, R, MODE, BCAP, SPLIT>), dim3((unsigned)(nblocks * SPLIT)), dim3(256), lds, s, a,
-                     io);
+  hipLaunchKernelGGL((k_render_tp<L, R, MODE, BCAP, SPLIT, VAR>), dim3((unsigned)(nblocks * SPLIT)), dim3(256), lds,
+                     s, a, io);
   return hipGetLastError();
 }
 
@@ -483,13 +544,16 @@ hipError_t tp_launch(const RenderArgs &a, const TpIO &io, int64_t nblocks, hipSt
 constexpr int64_t kFewBlocks = 2048;
 
 // Workgroups per tile of the two-phase forward (1 or 2) for a launch over
-// `tiles` (pair, tile) units.
-inline int tp_split(int area, int64_t tiles) { return (area >= 64 && tiles <= kFewBlocks) ? 2 : 1; }
+// `tiles` (pair, tile) units: the split halves the tile's rows, so a tile of
+// one row is never split.
+inline int tp_split(int area, int64_t tiles, int tile_h) {
+  return (area >= 64 && tile_h >= 2 && tiles <= kFewBlocks) ? 2 : 1;
+}
 
 template <int L, int MODE>
 hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
   if constexpr (MODE == kTpFwd || multi_chunk(MODE) > 1) {   // (the counters follow whole tiles, as the adjoint does)
-    if (tp_split(area, nblocks) == 2) {
+    if (tp_split(area, nblocks, area / a.tw) == 2) {
       switch (area) {
         case 64: return tp_launch<L, 32, MODE, 128, 2>(a, io, nblocks, s);
         case 128: return tp_launch<L, 64, MODE, 128, 2>(a, io, nblocks, s);
@@ -502,6 +566,19 @@ hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nb
     case 64: return tp_launch<L, 64, MODE, 128, 1>(a, io, nblocks, s);
     case 128: return tp_launch<L, 128, MODE, 128, 1>(a, io, nblocks, s);
     default: return tp_launch<L, 256, MODE, 128, 1>(a, io, nblocks, s);
+  }
+}
+
+// The paper-literal variant kernels (per-Gaussian FLE, chord transmittance,
+// and the two passes of the per-ray midpoint order): whole tiles, runtime
+// switches read from RenderArgs.
+template <int L, int MODE>
+hipError_t tp_dispatch_var(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
+  switch (area) {
+    case 32: return tp_launch<L, 32, MODE, 128, 1, true>(a, io, nblocks, s);
+    case 64: return tp_launch<L, 64, MODE, 128, 1, true>(a, io, nblocks, s);
+    case 128: return tp_launch<L, 128, MODE, 128, 1, true>(a, io, nblocks, s);
+    default: return tp_launch<L, 256, MODE, 128, 1, true>(a, io, nblocks, s);
   }
 }
 

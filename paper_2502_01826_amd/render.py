@@ -47,6 +47,9 @@ class GridSpec:
     tile_h: int = 16
     lanes_per_ray: int = 0
     footprint: int = 0
+    depth_order: int = 0        # 1: per-ray chord-midpoint order (App. A.3)
+    fle_eval: int = 0           # 1: radiance at each Gaussian's direction
+    transmittance: int = 0      # 1: chord transmittance exp(-alpha dt) (App. A.2)
 
     @staticmethod
     def of(g) -> "GridSpec":
@@ -55,7 +58,8 @@ class GridSpec:
 
     def c(self) -> GsrfGrid:
         return GsrfGrid(self.n_az, self.n_el, self.el_lo, self.el_hi, self.fle_L, self.r_rx, self.t_min,
-                        self.alpha_max, self.tile_w, self.tile_h, self.lanes_per_ray, self.footprint)
+                        self.alpha_max, self.tile_w, self.tile_h, self.lanes_per_ray, self.footprint,
+                        self.depth_order, self.fle_eval, self.transmittance)
 
     @property
     def K(self) -> int:
@@ -90,7 +94,8 @@ class Problem:
     count ever exceeds the capacity.
     """
 
-    def __init__(self, params: dict, pairs, grid, scene_offsets=None, splat_capacity=None, device="cuda"):
+    def __init__(self, params: dict, pairs, grid, scene_offsets=None, splat_capacity=None, device="cuda",
+                 hit_capacity=None):
         self.device = torch.device(device)
         self.grid = GridSpec.of(grid)
         self.set_params(**params)
@@ -105,6 +110,9 @@ class Problem:
         self.pairs = list(pairs)
         self.auto_capacity = splat_capacity is None
         self.cap = int(splat_capacity or 0)
+        # per-ray midpoint order: (ray, Gaussian) hit records, sized by the first render
+        self.auto_hit_capacity = hit_capacity is None
+        self.hit_cap = int(hit_capacity or 0)
         self.ws = None
         self._alloc()
 
@@ -132,6 +140,7 @@ class Problem:
         p.splat_capacity = self.cap
         p.workspace = self.ws.data_ptr() if self.ws is not None else None
         p.workspace_bytes = self.ws.numel() if self.ws is not None else 0
+        p.hit_capacity = self.hit_cap
         return p
 
     def workspace_bytes(self, cap=None) -> int:
@@ -230,9 +239,25 @@ class Problem:
                 self.project(stream)
         self.bin_sort(stream)
 
+    def ray_hit_count(self, stream=None) -> tuple[int, bool]:
+        """depth_order = 1: hit records the last render needed, and whether they fit."""
+        n = ctypes.c_int64()
+        st = _lib.lib().gsrf_ray_hit_count(ctypes.byref(self._problem()), ctypes.byref(n), _stream_handle(stream))
+        if st not in (_lib.GSRF_OK, _lib.GSRF_ECAPACITY):
+            check(st, "gsrf_ray_hit_count")
+        return int(n.value), st == _lib.GSRF_OK
+
     def forward(self, stream=None):
         self.prepare(stream)
-        return self.render_fwd(stream=stream)
+        out = self.render_fwd(stream=stream)
+        if self.grid.depth_order and self.auto_hit_capacity:
+            n, ok = self.ray_hit_count(stream)
+            if not ok:                      # the render wrote zeros: grow the records and render again
+                self.hit_cap = max(int(n * 1.25) + 4096, 65536)
+                self._alloc()               # a new workspace: project and bin_sort again
+                self.prepare(stream)
+                out = self.render_fwd(stream=stream)
+        return out
 
 
 class GSRFRender(torch.autograd.Function):

@@ -120,6 +120,12 @@ def test_workspace_size_and_layout():
     (lambda p: setattr(p.grid, "fle_L", 7), "fle_L"),
     (lambda p: setattr(p.grid, "lanes_per_ray", 3), "lanes_per_ray"),
     (lambda p: setattr(p.grid, "footprint", 2), "footprint"),
+    (lambda p: setattr(p.grid, "depth_order", 2), "depth_order"),
+    (lambda p: setattr(p.grid, "fle_eval", -1), "fle_eval"),
+    (lambda p: setattr(p.grid, "transmittance", 3), "transmittance"),
+    (lambda p: (setattr(p.grid, "transmittance", 1), setattr(p.grid, "lanes_per_ray", 1)), "two-phase"),
+    (lambda p: (setattr(p.grid, "depth_order", 1), setattr(p.grid, "lanes_per_ray", 0),
+                setattr(p, "hit_capacity", -5)), "hit_capacity"),
     (lambda p: setattr(p.grid, "n_az", 0), "grid size"),
     (lambda p: setattr(p.grid, "alpha_max", 1.0), "alpha_max"),
     (lambda p: setattr(p.grid, "el_hi", -0.5), "elevation"),

@@ -57,6 +57,22 @@ def test_tiny_gradients_match_oracle(tw, th, G):
     _compare(gg, gr)
 
 
+@pytest.mark.parametrize("tw,th", [(64, 1), (128, 1)])
+def test_single_row_tile_gradients(tw, th):
+    """Adjoint after a forward that took the few-tile path with one-row tiles."""
+    g = Grid(n_az=290, n_el=5, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=0)
+    b = synth.tiny(grid=g, n=1200)
+    sc, p = b.scenes[0], b.pairs[0]
+    prob = gpu_problem(b)
+    sig, _, _ = prob.forward()
+    ref = oracle.render(sc, p, g)
+    Gc = synth.cotangent((g.n_az * g.n_el,), seed=9).astype(np.float64)
+    Gc[ref["marginal"]] = 0.0
+    say("single-row tile gradients", tw, th)
+    gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), Gc.reshape(1, g.n_el, g.n_az, 2))
+    _compare(gg, oracle.vjp(sc, p, g, Gc))
+
+
 @pytest.mark.parametrize("L,G,th", [(0, 0, 8), (1, 4, 8), (3, 0, 8), (6, 0, 8), (6, 1, 8), (0, 0, 4), (6, 0, 4)])
 def test_gradients_across_fle_degrees(L, G, th):
     """Adjoint at every FLE degree the kernels instantiate (K = 1 .. 49)."""

@@ -179,6 +179,27 @@ def test_ragged_tiles_and_seam(tw, th, G):
     compare_rays(S[0].ravel(), ref, sc, p, g)
 
 
+@pytest.mark.parametrize("tw,th", [(64, 1), (128, 1), (32, 2), (256, 1)])
+def test_single_row_tiles_in_a_few_tile_launch(tw, th):
+    """Tiles of one or two rows in a launch with few tiles (the forward's
+    two-workgroups-per-tile path): every ray rendered, no row left unwritten."""
+    g = Grid(n_az=290, n_el=5, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=0)
+    b = synth.tiny(grid=g, n=1200)
+    sc, p = b.scenes[0], b.pairs[0]
+    say("single-row tiles", tw, th)
+    prob = gpu_problem(b)
+    sig = torch.full((1, g.n_el, g.n_az, 2), float("nan"), device="cuda")
+    ssum = torch.empty((1, 2), device="cuda")
+    prob.prepare()
+    prob.render_fwd(sig, ssum, None)
+    torch.cuda.synchronize()
+    S = torch.view_as_complex(sig).cpu().numpy().astype(np.complex128)
+    assert np.isfinite(S).all()
+    ref = oracle.render(sc, p, g)
+    compare_rays(S[0].ravel(), ref, sc, p, g)
+    assert abs(complex(*ssum[0].cpu().numpy()) - ref["S_sum"]) <= 1e-4 * ref["A_uv"].sum()
+
+
 @pytest.mark.parametrize("L,G,th", [(0, 1, 8), (1, 2, 8), (3, 4, 8), (4, 1, 8), (6, 4, 8), (5, 2, 8), (0, 0, 8),
                                     (1, 0, 8), (3, 0, 8), (6, 0, 8), (2, 0, 4), (6, 0, 4)])
 def test_fle_degrees(L, G, th):
