@@ -198,6 +198,8 @@ def main() -> int:
     ap.add_argument("--batched-iters", type=int, default=50)
     ap.add_argument("--batched-warmup", type=int, default=10)
     ap.add_argument("--gaussians", type=int, default=200_000)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched workloads: use --tile instead of autotuning (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="8x8", help="tile_w x tile_h (64, 128 or 256 rays)")
     ap.add_argument("--lanes", type=int, default=0,
@@ -294,7 +296,7 @@ def main() -> int:
         return roof
 
     def run_batched(b, grad, label):
-        from paper_2502_01826_amd.batch import GraphStep, autotune
+        from paper_2502_01826_amd.batch import GraphStep, TuneResult, autotune
         cat, offs = b.concat()
         prm = dict(means=cat.means, log_scales=cat.log_scales, quats=cat.quats, logits=cat.logits,
                    coeffs=cat.coeffs)
@@ -307,7 +309,10 @@ def main() -> int:
             return (torch.from_numpy(synth.cotangent((P, grid.n_el, grid.n_az), seed=13)).to(dev),
                     torch.from_numpy(synth.cotangent((P,), seed=14)).to(dev))
 
-        tune = autotune(build, grid, grad=grad, make_grad=make_grad, iters=2)
+        if args.no_autotune:
+            tune = TuneResult(best=(grid.tile_w, grid.tile_h, grid.lanes_per_ray))
+        else:
+            tune = autotune(build, grid, grad=grad, make_grad=make_grad, iters=2)
         tw, th, lanes = tune.best
         g = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=lanes,
                        footprint=grid.footprint)

@@ -4,6 +4,15 @@
         per-kernel dispatch count, total and average duration from a
         ``rocprofv3 --kernel-trace --output-format csv`` directory (markdown).
 
+    python -m paper_2502_01826_amd.profiling counters DIR [DIR ...] --kernel NAME=SUBSTR \
+        [--ms NAME=MS ...]
+        per-dispatch means of every counter of ``rocprofv3 --pmc`` runs for
+        the named kernels, and the utilisation figures derived from them
+        (markdown): VALU busy and lane utilisation, FMA share of the VALU
+        instructions, FP32 operations executed (64 lanes per counted wave
+        instruction) and, given the kernel's duration, their rate against
+        the FP32 VALU peak; LDS bank-conflict cycles per LDS instruction.
+
     python -m paper_2502_01826_amd.profiling traffic --fetch DIR --write DIR \
         --cal-fetch DIR --cal-write DIR --cal-bytes N --kernel NAME=SUBSTR \
         --config CFG --out FILE
@@ -66,6 +75,43 @@ def trace_table(d: str) -> str:
     return "\n".join(out)
 
 
+PEAK_FP32 = 157.3e12     # FP32 VALU peak of MI355X, FLOP/s (packed FMA)
+
+
+def counter_table(dirs, kernels, ms) -> str:
+    """Per-dispatch counter means for each NAME=SUBSTR kernel over the runs in dirs."""
+    per = {name: defaultdict(lambda: defaultdict(float)) for name, _ in kernels}
+    for d in dirs:
+        for r in _csv(d, "counter_collection.csv"):
+            for name, sub in kernels:
+                if sub in r["Kernel_Name"]:
+                    per[name][r["Counter_Name"]][(d, r["Dispatch_Id"])] += float(r["Counter_Value"])
+    mean = {name: {c: sum(v.values()) / len(v) for c, v in cs.items()} for name, cs in per.items()}
+    out = ["| kernel | VALU busy | VALU lane util | VALU instr (wave) | FMA share | FP32 op executed | "
+           "executed TFLOP/s (frac of 157.3) | LDS instr | LDS conflict cycles / LDS instr | waves | SALU instr |",
+           "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for name, _ in kernels:
+        m = mean[name]
+        g = lambda c: m.get(c)
+        f = lambda x, fmt: "—" if x is None else format(x, fmt)
+        flops = None
+        if g("SQ_INSTS_VALU_FLOPS_FP32") is not None:
+            flops = 64.0 * (g("SQ_INSTS_VALU_FLOPS_FP32") + (g("SQ_INSTS_VALU_FLOPS_FP32_TRANS") or 0.0))
+        rate = None
+        if flops is not None and name in ms:
+            rate = flops / (ms[name] * 1e-3)
+        fma = (g("SQ_INSTS_VALU_FMA_F32") / g("SQ_INSTS_VALU")) if g("SQ_INSTS_VALU") else None
+        conf = (g("SQ_LDS_BANK_CONFLICT") / g("SQ_INSTS_LDS")) if g("SQ_INSTS_LDS") else None
+        busy = g("VALUBusy")
+        util = g("VALUUtilization")
+        out.append(f"| {name} | {f(busy, '.1f')}% | {f(util, '.1f')}% | {f(g('SQ_INSTS_VALU'), '.3e')} | "
+                   f"{f(fma, '.3f')} | {f(flops, '.3e')} | "
+                   + ("—" if rate is None else f"{rate / 1e12:.1f} ({rate / PEAK_FP32:.3f})")
+                   + f" | {f(g('SQ_INSTS_LDS'), '.3e')} | {f(conf, '.2f')} | {f(g('SQ_WAVES'), '.0f')} | "
+                   f"{f(g('SQ_INSTS_SALU'), '.3e')} |")
+    return "\n".join(out)
+
+
 def counter_per_dispatch(d: str, counter: str, substr: str) -> float:
     """Mean over dispatches of kernels whose name contains substr (KiB)."""
     vals = defaultdict(float)
@@ -103,6 +149,10 @@ def main(argv=None) -> int:
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("dir")
+    k = sub.add_parser("counters")
+    k.add_argument("dirs", nargs="+")
+    k.add_argument("--kernel", action="append", required=True, help="NAME=SUBSTR")
+    k.add_argument("--ms", action="append", default=[], help="NAME=MS (kernel duration)")
     c = sub.add_parser("traffic")
     c.add_argument("--fetch", required=True)
     c.add_argument("--write", required=True)
@@ -116,6 +166,10 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace_table(a.dir))
+    elif a.cmd == "counters":
+        ks = [tuple(x.split("=", 1)) for x in a.kernel]
+        ms = {n: float(v) for n, v in (x.split("=", 1) for x in a.ms)}
+        print(counter_table(a.dirs, ks, ms))
     else:
         rec = traffic(a)
         with open(a.out, "w") as fh:
