@@ -336,6 +336,26 @@ gsrf_status gsrf_loss_spectrum(const float *signal, const float *target, int32_t
                                int32_t n_az, float power_scale, float lambda1, float lambda2, float *loss,
                                float *grad_signal, void *workspace, void *stream);
 
+/*
+ * gsrf_loss_spectrum without a workspace argument and without any device
+ * allocation, for callers that cannot allocate: code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Arguments, outputs,
+ * validation and results are those of gsrf_loss_spectrum (the same kernels);
+ * the per-tile FP64 partial sums live in a fixed 1 MiB device array of the
+ * library instead (one copy per GPU, held until the process ends), so
+ *   n_pairs * ceil(n_el / 16) * ceil(n_az / 32) * 24 bytes <= 1 MiB
+ * (606 spectra of 360 x 90 rays) and larger calls fail with GSRF_ECAPACITY
+ * before anything is enqueued.  The first call on a device looks the array's
+ * address up (hipGetSymbolAddress, no allocation); call it with the stream's
+ * device current (GSRF_EINVAL otherwise).  Every call on a GPU shares that
+ * GPU's array: calls that may overlap on one GPU (different streams without
+ * ordering between them) race and must not be issued.  Nothing in the array
+ * has to start at zero; it keeps the last call's partial sums.
+ */
+gsrf_status gsrf_loss_spectrum_noalloc(const float *signal, const float *target, int32_t n_pairs, int32_t n_el,
+                                       int32_t n_az, float power_scale, float lambda1, float lambda2, float *loss,
+                                       float *grad_signal, void *stream);
+
 /* Loss kinds of gsrf_loss_single. */
 typedef enum gsrf_loss_kind {
   GSRF_LOSS_RSSI_DB = 0,      /* |10 log10 |S_hat|^2 - t|, t an RSSI in dBm (target [P]) */

@@ -63,7 +63,8 @@ GSRF_LOSS_RSSI_DB, GSRF_LOSS_COMPLEX_L2 = 0, 1
 EXPORTS = ["gsrf_status_str", "gsrf_last_error", "gsrf_workspace_size", "gsrf_layout_of", "gsrf_project",
            "gsrf_splat_count", "gsrf_ray_hit_count", "gsrf_bin_sort", "gsrf_render_fwd", "gsrf_render_fwd_multi", "gsrf_render_bwd",
            "gsrf_render_stats",
-           "gsrf_set_kernel_events", "gsrf_loss_workspace_size", "gsrf_loss_spectrum", "gsrf_loss_single",
+           "gsrf_set_kernel_events", "gsrf_loss_workspace_size", "gsrf_loss_spectrum", "gsrf_loss_spectrum_noalloc",
+           "gsrf_loss_single",
            "gsrf_sgd_step", "gsrf_grad_stats_accumulate", "gsrf_density_workspace_size", "gsrf_density_control"]
 
 _lib = None
@@ -95,6 +96,7 @@ def lib() -> ctypes.CDLL:
     L.gsrf_set_kernel_events.argtypes = [c_vp, c_vp, c_vp, c_vp]
     L.gsrf_loss_workspace_size.argtypes = [c_i32, c_i32, c_i32, P(c_sz)]
     L.gsrf_loss_spectrum.argtypes = [c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_f32, c_vp, c_vp, c_vp, c_vp]
+    L.gsrf_loss_spectrum_noalloc.argtypes = [c_vp, c_vp, c_i32, c_i32, c_i32, c_f32, c_f32, c_f32, c_vp, c_vp, c_vp]
     L.gsrf_loss_single.argtypes = [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp]
     L.gsrf_sgd_step.argtypes = [c_i64, c_i32] + [c_vp] * 10 + [P(GsrfSgdLr), c_i64, c_vp]
     L.gsrf_grad_stats_accumulate.argtypes = [c_i64, c_vp, c_vp, c_vp, c_vp]

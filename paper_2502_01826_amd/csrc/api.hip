@@ -324,6 +324,33 @@ gsrf_status gsrf_loss_spectrum(const float *signal, const float *target, int32_t
              "gsrf_loss_spectrum");
 }
 
+gsrf_status gsrf_loss_spectrum_noalloc(const float *signal, const float *target, int32_t n_pairs, int32_t n_el,
+                                       int32_t n_az, float power_scale, float lambda1, float lambda2, float *loss,
+                                       float *grad_signal, void *stream) {
+  const gsrf_status st = check_spectrum(n_pairs, n_el, n_az);
+  if (st != GSRF_OK) return st;
+  if (!(power_scale > 0.f) || !isfinite(power_scale))
+    return fail(GSRF_EINVAL, "power_scale = %g: must be finite and > 0", (double)power_scale);
+  if (!isfinite(lambda1) || !isfinite(lambda2))
+    return fail(GSRF_EINVAL, "lambda1 = %g, lambda2 = %g: must be finite", (double)lambda1, (double)lambda2);
+  const size_t need = loss_partials_bytes(n_pairs, n_el, n_az);
+  if (need > loss_scratch_bytes())
+    return fail(GSRF_ECAPACITY,
+                "%d spectra of %d x %d rays need %zu bytes of partial sums; the fixed scratch holds %zu "
+                "(use gsrf_loss_spectrum with a workspace)",
+                n_pairs, n_el, n_az, need, loss_scratch_bytes());
+  if (n_pairs > 0 && (!signal || !target || !loss)) return fail(GSRF_EINVAL, "signal, target or loss is NULL");
+  if (n_pairs == 0) return GSRF_OK;
+  void *ws = nullptr;
+  const hipError_t e = loss_scratch_address((hipStream_t)stream, &ws);
+  if (e == hipErrorInvalidDevice)
+    return fail(GSRF_EINVAL, "the stream's device is not the current device (or the device index is above 63)");
+  if (e != hipSuccess) return dev(e, "gsrf_loss_spectrum_noalloc: scratch address");
+  return dev(launch_loss_spectrum(signal, target, n_pairs, n_el, n_az, power_scale, lambda1, lambda2, loss, grad_signal,
+                                  ws, (hipStream_t)stream),
+             "gsrf_loss_spectrum_noalloc");
+}
+
 gsrf_status gsrf_loss_single(const float *signal_sum, const float *target, int32_t n_pairs, int32_t kind,
                              float *loss, float *grad_sum, void *stream) {
   if (n_pairs < 0) return fail(GSRF_EINVAL, "n_pairs = %d is negative", n_pairs);

@@ -154,6 +154,11 @@ hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws,
 
 // Training steps (train.hip).
 size_t loss_partials_bytes(int32_t n_pairs, int32_t n_el, int32_t n_az);
+// Bytes of the fixed device scratch behind gsrf_loss_spectrum_noalloc, and
+// its address on the current device (hipErrorInvalidDevice when a non-null
+// stream belongs to another device).
+size_t loss_scratch_bytes();
+hipError_t loss_scratch_address(hipStream_t s, void **out);
 hipError_t launch_loss_spectrum(const float *signal, const float *target, int32_t n_pairs, int32_t n_el, int32_t n_az,
                                 float pscale, float lam1, float lam2, float *loss, float *grad_signal, void *ws,
                                 hipStream_t s);

@@ -4,6 +4,8 @@
 // primitive optimization, eq. updating).
 #include <math.h>
 
+#include <mutex>
+
 #include "gsrf_internal.h"
 
 namespace gsrf {
@@ -210,6 +212,44 @@ k_loss_final(const double *__restrict__ partials, int tiles, double n_pix, float
     loss[4 * k + 2] = (float)ls;
     loss[4 * k + 3] = (float)lf;
   }
+}
+
+// Scratch of gsrf_loss_spectrum_noalloc: the per-tile FP64 partial sums that
+// gsrf_loss_spectrum keeps in its caller's workspace, here in a fixed device
+// array (one copy per GPU, held until the process ends).  In host code the
+// array's name is a host-side stand-in, so kernels receive the address that
+// hipGetSymbolAddress reports for the current device, looked up once per
+// device.  k_spectrum_loss writes every partial it covers before
+// k_loss_final reads it, so nothing has to start at zero.
+constexpr size_t kLossScratchBytes = (size_t)1 << 20;
+static __device__ __align__(256) double scratch[kLossScratchBytes / sizeof(double)];
+
+size_t loss_scratch_bytes() { return kLossScratchBytes; }
+
+hipError_t loss_scratch_address(hipStream_t s, void **out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (s) {
+    int sdev = -1;
+    e = hipStreamGetDevice(s, &sdev);
+    if (e != hipSuccess) return e;
+    if (sdev != dev) return hipErrorInvalidDevice;   // the scratch looked up must be the stream's GPU's
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 size_t loss_partials_bytes(int32_t n_pairs, int32_t n_el, int32_t n_az) {

@@ -4,6 +4,8 @@ marshalling only; the work runs in libgsrf.so):
 * ``SpectrumLoss`` -- antenna-array loss (1 - l1 - l2) L1 + l1 L_SSIM +
   l2 L_Fourier of each pair's power spectrum c |S_uv|^2 and its gradient with
   respect to the rays (Sec. 3.4, loss function);
+* ``loss_spectrum_noalloc`` -- the same loss without a workspace (fixed
+  per-GPU scratch in the library, for callers that cannot allocate);
 * ``loss_single`` -- single-antenna losses on S_hat (RSSI in dBm, or complex
   squared error; Sec. 3.4);
 * ``sgd_step`` -- the per-attribute SGD update with the decaying mean
@@ -64,6 +66,27 @@ class SpectrumLoss:
                                             self.lambda1, self.lambda2, loss.data_ptr(), g, self.ws.data_ptr(),
                                             _stream_handle(stream)), "gsrf_loss_spectrum")
         return loss, (grad_signal if want_grad else None)
+
+
+def loss_spectrum_noalloc(signal, target, lambda1: float, lambda2: float, power_scale: float = 1.0, loss=None,
+                          grad_signal=None, want_grad: bool = True, stream=None):
+    """The loss of ``SpectrumLoss`` through gsrf_loss_spectrum_noalloc: no
+    workspace, the partial sums in the library's fixed per-GPU scratch (calls
+    on one GPU must not overlap).  signal [P, n_el, n_az, 2], target
+    [P, n_el, n_az] -> (loss [P, 4], grad_signal or None); pass loss and
+    grad_signal to allocate nothing here either."""
+    P, ne, na = signal.shape[0], signal.shape[1], signal.shape[2]
+    _f32(signal, (P, ne, na, 2), "signal")
+    _f32(target, (P, ne, na), "target")
+    if loss is None:
+        loss = torch.empty((P, 4), dtype=torch.float32, device=signal.device)
+    if want_grad and grad_signal is None:
+        grad_signal = torch.empty_like(signal)
+    check(_lib.lib().gsrf_loss_spectrum_noalloc(signal.data_ptr(), target.data_ptr(), P, ne, na, float(power_scale),
+                                                float(lambda1), float(lambda2), loss.data_ptr(),
+                                                _ptr(grad_signal) if want_grad else None, _stream_handle(stream)),
+          "gsrf_loss_spectrum_noalloc")
+    return loss, (grad_signal if want_grad else None)
 
 
 def loss_single(signal_sum, target, kind: int, loss=None, grad_sum=None, want_grad: bool = True, stream=None):
