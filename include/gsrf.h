@@ -254,12 +254,18 @@ gsrf_status gsrf_render_fwd_multi(const gsrf_problem *p, int32_t n_freq, double 
 /*
  * Steps a7 + a8 (App. C backward kernel; App. D gradients, including the
  * covariance chain the paper omits): recomputes each ray's transmittance
- * front to back (no per-ray state is stored by render_fwd beyond `signal`)
- * and forms the gradient of L with respect to every parameter, where the
- * caller supplies dL/dS per ray and per pair.  Must follow gsrf_render_fwd
- * of the same prepared problem on the same workspace: with lanes_per_ray = 0
- * it reuses the per-list-entry hit masks that call records there.
+ * front to back and forms the gradient of L with respect to every
+ * parameter, where the caller supplies dL/dS per ray and per pair.  Must
+ * follow gsrf_render_fwd of the same prepared problem on the same workspace:
+ * the remainder sum_{i>j} T_i c~_i of each hit is that forward's S minus the
+ * running prefix, with S taken from the FP64 copy the forward leaves in the
+ * workspace (so the remainder stays accurate to its own size, zero after a
+ * ray's last hit, rather than to |S|); with lanes_per_ray = 0 it also reuses
+ * the per-list-entry hit masks recorded there.  No other per-ray state is
+ * kept between the passes.
  *   signal       [P, n_el, n_az, 2]  the render_fwd output for this problem
+ *                (checked for NULL; the values used are the workspace's FP64
+ *                copy of it)
  *   grad_signal  [P, n_el, n_az, 2]  dL/dRe S + j dL/dIm S
  *   grad_sum     [P, 2] or NULL      dL/dS_hat (added to every ray of the pair)
  * Outputs are OVERWRITTEN (not accumulated), summed over all pairs:

@@ -623,12 +623,49 @@ def vjp(scene, pair, grid, G, g_sum=None, rays_uv=None, ray_chunk: int = 64, rec
     Gt = torch.tensor(G, dtype=F64)
     res = trace(P, pair, grid, rays_uv, grad=True, ray_chunk=ray_chunk, rects=rects)
     L = (Gt[:, 0] * res["S_r"] + Gt[:, 1] * res["S_i"]).sum()
-    grads = torch.autograd.grad(L, P.tensors(), allow_unused=True)
+    if L.requires_grad:
+        grads = torch.autograd.grad(L, P.tensors(), allow_unused=True)
+    else:                                   # no ray hits anything: every gradient is zero
+        grads = [None] * len(P.tensors())
     names = ["means", "log_scales", "quats", "logits", "coeffs"]
     out = {}
     for nm, g, t in zip(names, grads, P.tensors()):
         out[nm] = (torch.zeros_like(t) if g is None else g).detach().numpy()
     return out
+
+
+def vjp_abs(scene, pair, grid, G, g_sum=None, rays_uv=None, ray_chunk: int = 4, rects=None):
+    """``vjp`` together with an absolute scale of each gradient entry.
+
+    Each gradient entry is dL/dtheta = Re(conj(G) dS/dtheta) summed over rays
+    (R21).  Its scale is the sum over groups of ``ray_chunk`` rays of the
+    group's complex magnitude |sum_r conj(G_r) dS_r/dtheta|, formed from the
+    gradients for the cotangents G and j G (the second gives the imaginary
+    part), so it does not vanish when the real projection happens to be small
+    and it bounds |dL/dtheta|.  With one ray per group it is
+    sum_r |G_r| |dS_r/dtheta|: what an FP32 evaluation of those terms, each with
+    a small relative error, can be compared against, the way A_uv is for a ray.
+    Returns (grads, scales), both keyed as vjp.
+    """
+    G = np.asarray(G, dtype=np.float64).reshape(-1, 2)
+    if g_sum is not None:
+        G = G + np.asarray(g_sum, dtype=np.float64).reshape(1, 2)
+    jG = np.stack([-G[:, 1], G[:, 0]], axis=1)          # j (Gr + j Gi) = -Gi + j Gr
+    if rays_uv is None:
+        vv, uu = np.meshgrid(np.arange(grid.n_el), np.arange(grid.n_az), indexing="ij")
+        rays_uv = np.stack([uu.ravel(), vv.ravel()], axis=1)
+    rays_uv = np.asarray(rays_uv, dtype=np.int64).reshape(-1, 2)
+    names = ["means", "log_scales", "quats", "logits", "coeffs"]
+    tot = {nm: np.zeros(np.shape(getattr(scene, nm)), np.float64) for nm in names}
+    scl = {nm: np.zeros(np.shape(getattr(scene, nm)), np.float64) for nm in names}
+    for s in range(0, rays_uv.shape[0], ray_chunk):
+        uv = rays_uv[s:s + ray_chunk]
+        re = vjp(scene, pair, grid, G[s:s + ray_chunk], rays_uv=uv, ray_chunk=ray_chunk, rects=rects)
+        im = vjp(scene, pair, grid, jG[s:s + ray_chunk], rays_uv=uv, ray_chunk=ray_chunk, rects=rects)
+        for nm in names:
+            tot[nm] += re[nm]
+            scl[nm] += np.hypot(re[nm], im[nm])
+    return tot, scl
 
 
 # --------------------------------------------------------------------------

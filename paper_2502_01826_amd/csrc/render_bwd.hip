@@ -4,8 +4,9 @@
 //
 // Same traversal as the forward (render_common.h), recomputing each ray's
 // transmittance front to back; the remainder R_j = sum_{i>j} T_i c~_i comes
-// from the forward output S minus the running prefix, so no per-ray state is
-// stored between the passes.  Per processed hit a lane forms its contribution
+// from the forward's S minus the running prefix, both FP64 sums of the same
+// exact products T_i c~_i, so it is accurate to the size of the remainder
+// itself (zero after a ray's last hit) and only S is kept between the passes.  Per processed hit a lane forms its contribution
 // to the Gaussian's accumulators; the rays of a wave are summed by a
 // reduce-scatter (recursive halving over lanes), the waves meet in LDS, and
 // one burst of global atomics per (tile, Gaussian) flushes them.
@@ -14,7 +15,7 @@
 namespace gsrf {
 
 template <int L, int NT, int G>
-__global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *__restrict__ signal,
+__global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const double2 *__restrict__ sig64,
                                                    const float2 *__restrict__ grad_signal,
                                                    const float2 *__restrict__ grad_sum, float *__restrict__ acc,
                                                    int acc_stride) {
@@ -44,10 +45,12 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
   const float twopi_lam = (float)(2.0 * 3.14159265358979323846 / lam);
   float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
   ray_load<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
-  float Sfr = 0.f, Sfi = 0.f, Gr = 0.f, Gi = 0.f;
+  float Gr = 0.f, Gi = 0.f;
+  double Sfr = 0.0, Sfi = 0.0;   // the forward's FP64 S
   if (valid) {
     const size_t ri = ((size_t)k * a.n_el + v) * a.n_az + u;
-    const float2 sf = signal[ri], gg = grad_signal[ri];
+    const double2 sf = sig64[ri];
+    const float2 gg = grad_signal[ri];
     Sfr = sf.x; Sfi = sf.y; Gr = gg.x; Gi = gg.y;
     if (grad_sum) {
       const float2 gs = grad_sum[k];
@@ -58,7 +61,8 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
   for (int i = threadIdx.x; i < NACC * B; i += NT) sacc[i] = 0.f;
   for (int i = threadIdx.x; i < B; i += NT) sflag[i] = 0u;
   const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
-  float T = 1.f, Pr = 0.f, Pi = 0.f;
+  float T = 1.f;
+  double Pr = 0.0, Pi = 0.0;     // FP64 prefix of the exact products T_j c~_j, as the forward summed them
   bool done = !valid || (1.0f < a.t_min);
   for (uint32_t base = s0; base < s1; base += B) {
     const int nb = (int)min((uint32_t)B, s1 - base);
@@ -91,10 +95,10 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
         group_prod<G>(f, q, excl, total);
         const float Tj = T * excl;
         const bool proc = hit && (Tj >= a.t_min);
-        const float wr = proc ? Tj * ctr : 0.f, wi = proc ? Tj * cti : 0.f;
-        float wr_in, wi_in, wr_tot, wi_tot;
-        group_sum<G>(wr, q, wr_in, wr_tot);
-        group_sum<G>(wi, q, wi_in, wi_tot);
+        const double wr = proc ? (double)Tj * (double)ctr : 0.0, wi = proc ? (double)Tj * (double)cti : 0.0;
+        double wr_in, wi_in, wr_tot, wi_tot;
+        group_sum64<G>(wr, q, wr_in, wr_tot);
+        group_sum64<G>(wi, q, wi_in, wi_tot);
         T = T * total;
         done = done || (T < a.t_min);
         if (__ballot(proc) != 0) {
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(RenderArgs a, const float2 *_
 #pragma unroll
           for (int i = 0; i < NV; ++i) c[i] = 0.f;
           if (proc) {
-            const float Rr = Sfr - (Pr + wr_in), Ri = Sfi - (Pi + wi_in);
+            const float Rr = (float)(Sfr - (Pr + wr_in)), Ri = (float)(Sfi - (Pi + wi_in));
             hit_adjoint<K, NV>(h, geo, Tj, ctr, cti, Rr, Ri, Gr, Gi, vx, vy, vz, Yr, Yi, twopi_lam, c);
             sflag[j] = 1;
           }
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(256) void k_chain(const float *__restrict__ log_sca
 }
 
 template <int L, int NT, int G>
-static hipError_t bwd_launch(const RenderArgs &a, int64_t nblocks, const float2 *sig, const float2 *gsig,
+static hipError_t bwd_launch(const RenderArgs &a, int64_t nblocks, const double2 *sig, const float2 *gsig,
                              const float2 *gsum, float *acc, int S, hipStream_t s) {
   constexpr int K = (L + 1) * (L + 1);
   constexpr int B = lds_batch(L, NT, true);
@@ -222,11 +226,11 @@ static hipError_t bwd_launch(const RenderArgs &a, int64_t nblocks, const float2 
 
 
 template <int L>
-static hipError_t bwd_dispatch(int area, int G, const RenderArgs &a, int64_t nblocks, const float2 *sig,
+static hipError_t bwd_dispatch(int area, int G, const RenderArgs &a, int64_t nblocks, const double2 *sig,
                                const float2 *gsig, const float2 *gsum, float *acc, int S, hipStream_t s) {
   if (G == 0) {
     TpIO io{};
-    io.signal = const_cast<float2 *>(sig);
+    io.sig64 = const_cast<double2 *>(sig);
     io.grad_signal = gsig;
     io.grad_sum = gsum;
     io.acc = acc;
@@ -257,7 +261,10 @@ hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws,
     const int area = p->grid.tile_w * p->grid.tile_h;
     const int G = p->grid.lanes_per_ray;   // 0: two-phase traversal
     const int64_t nb = (int64_t)p->n_pairs * lay.T;
-    const float2 *sg = (const float2 *)signal, *gs = (const float2 *)grad_signal, *gm = (const float2 *)grad_sum;
+    // S of the preceding gsrf_render_fwd in FP64 (its workspace copy; `signal` is that
+    // forward's FP32 output and is not read here)
+    const double2 *sg = (const double2 *)(ws + lay.sig64);
+    const float2 *gs = (const float2 *)grad_signal, *gm = (const float2 *)grad_sum;
     mark_kernel_event(2, s);
     switch (p->grid.fle_L) {
       case 0: e = bwd_dispatch<0>(area, G, a, nb, sg, gs, gm, acc, lay.acc_stride, s); break;

@@ -437,6 +437,49 @@ __device__ __forceinline__ void group_sum(float x, int q, float &incl, float &to
   }
 }
 
+// FP64 forms of the above for the running complex sums of a ray: a 64-bit
+// value moves as its two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double swizzle_last8_64(double v) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), kSwizzleLast8);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), kSwizzleLast8);
+  return __hiloint2double(hi, lo);
+}
+
+// Inclusive prefix and total of x over the G lanes of a ray, in FP64.
+template <int G>
+__device__ __forceinline__ void group_sum64(double x, int q, double &incl, double &total) {
+  if constexpr (G == 1) {
+    incl = x;
+    total = x;
+  } else if constexpr (G == 2) {
+    const double lo = dpp64<quad_perm(0, 0, 2, 2)>(x);
+    incl = (q >= 1) ? x + lo : x;
+    total = dpp64<quad_perm(1, 1, 3, 3)>(incl);
+  } else if constexpr (G == 4) {
+    const double s1 = dpp64<quad_perm(0, 0, 1, 2)>(x);
+    const double y = (q >= 1) ? x + s1 : x;
+    const double s2 = dpp64<quad_perm(0, 1, 0, 1)>(y);
+    incl = (q >= 2) ? y + s2 : y;
+    total = dpp64<quad_perm(3, 3, 3, 3)>(incl);
+  } else {
+    static_assert(G == 8, "lanes per ray: 1, 2, 4 or 8");
+    const double s1 = dpp64<kDppRowShr1>(x);
+    const double y = (q >= 1) ? x + s1 : x;
+    const double s2 = dpp64<kDppRowShr2>(y);
+    const double z = (q >= 2) ? y + s2 : y;
+    const double s4 = dpp64<kDppRowShr4>(z);
+    incl = (q >= 4) ? z + s4 : z;
+    total = swizzle_last8_64(incl);
+  }
+}
+
 // Reduce-scatter across the lanes of a wave that share q = lane % G (the rays
 // of the wave), by recursive halving: at lane distance D the lane keeps half of
 // its live slots and adds the partner's copy of them.  On return the lane holds

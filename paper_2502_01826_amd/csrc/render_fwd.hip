@@ -14,7 +14,7 @@ namespace gsrf {
 
 template <int L, int NT, int G, bool STATS>
 __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restrict__ signal,
-                                                   float2 *__restrict__ tile_sum,
+                                                   double2 *__restrict__ sig64, float2 *__restrict__ tile_sum,
                                                    unsigned long long *__restrict__ stats) {
   constexpr int K = (L + 1) * (L + 1);
   constexpr int B = lds_batch(L, NT, false);
@@ -36,7 +36,8 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
   float vx = 0.f, vy = 0.f, vz = 1.f, Yr[K], Yi[K];
   ray_load<L>(valid ? u : 0, valid ? v : 0, a, vx, vy, vz, Yr, Yi);
   const uint32_t s0 = a.tstart[gt], s1 = a.tend[gt];
-  float T = 1.f, Sr = 0.f, Si = 0.f;
+  float T = 1.f;
+  double Sr = 0.0, Si = 0.0;   // FP64 sums of the exact products T_j c~_j (the adjoint's remainders need them)
   bool done = !valid || (1.0f < a.t_min);
   unsigned long long n_test = 0, n_hit = 0, n_staged = 0, n_tile_tests = 0;
   for (uint32_t base = s0; base < s1; base += B) {
@@ -70,8 +71,8 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
         group_prod<G>(f, q, excl, total);
         const float Tj = T * excl;
         if (hit && Tj >= a.t_min) {
-          Sr = fmaf(Tj, ctr, Sr);
-          Si = fmaf(Tj, cti, Si);
+          Sr = fma((double)Tj, (double)ctr, Sr);
+          Si = fma((double)Tj, (double)cti, Si);
           if (STATS) ++n_hit;
         }
         T = T * total;
@@ -97,12 +98,16 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
     if (n_tile_tests) atomicAdd(stats + 4, n_tile_tests);
     return;
   }
-  if (valid && q == 0) signal[((size_t)k * a.n_el + v) * a.n_az + u] = make_float2(Sr, Si);
+  if (valid && q == 0) {
+    const size_t ri = ((size_t)k * a.n_el + v) * a.n_az + u;
+    signal[ri] = make_float2((float)Sr, (float)Si);
+    sig64[ri] = make_double2(Sr, Si);
+  }
   // deterministic tile partial of S_hat (fixed tree order)
   __syncthreads();
   float *red = (float *)smem;
-  red[threadIdx.x] = (q == 0) ? Sr : 0.f;
-  red[NT + threadIdx.x] = (q == 0) ? Si : 0.f;
+  red[threadIdx.x] = (q == 0) ? (float)Sr : 0.f;
+  red[NT + threadIdx.x] = (q == 0) ? (float)Si : 0.f;
   __syncthreads();
   for (int off = NT / 2; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) {
@@ -147,56 +152,58 @@ __global__ void k_rssi(const float2 *__restrict__ tile_sum, int32_t T, float *__
 }
 
 template <int L, int NT, int G>
-static hipError_t fwd_launch(const RenderArgs &a, int64_t nblocks, float2 *sig, float2 *tsum,
+static hipError_t fwd_launch(const RenderArgs &a, int64_t nblocks, float2 *sig, double2 *sig64, float2 *tsum,
                              unsigned long long *stats, hipStream_t s) {
   constexpr int K = (L + 1) * (L + 1);
   constexpr int B = lds_batch(L, NT, false);
   size_t lds = (size_t)B * (kGeo * 16 + 2 * K * 4);
   if (lds < (size_t)NT * 8) lds = (size_t)NT * 8;
   if (stats)
-    hipLaunchKernelGGL((k_render_fwd<L, NT, G, true>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, tsum, stats);
-  else
-    hipLaunchKernelGGL((k_render_fwd<L, NT, G, false>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, tsum,
+    hipLaunchKernelGGL((k_render_fwd<L, NT, G, true>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, sig64, tsum,
                        stats);
+  else
+    hipLaunchKernelGGL((k_render_fwd<L, NT, G, false>), dim3((unsigned)nblocks), dim3(NT), lds, s, a, sig, sig64,
+                       tsum, stats);
   return hipGetLastError();
 }
 
 
 template <int L>
-static hipError_t fwd_dispatch(int area, int G, const RenderArgs &a, int64_t nblocks, float2 *sig, float2 *tsum,
-                               unsigned long long *stats, hipStream_t s) {
+static hipError_t fwd_dispatch(int area, int G, const RenderArgs &a, int64_t nblocks, float2 *sig, double2 *sig64,
+                               float2 *tsum, unsigned long long *stats, hipStream_t s) {
   if (G == 0) {
     TpIO io{};
     io.signal = sig;
+    io.sig64 = sig64;
     io.tile_sum = tsum;
     io.stats = stats;
     return stats ? tp_dispatch<L, kTpFwdStats>(area, a, io, nblocks, s) : tp_dispatch<L, kTpFwd>(area, a, io, nblocks, s);
   }
   switch (area * 8 + G) {
-    case 64 * 8 + 1: return fwd_launch<L, 64, 1>(a, nblocks, sig, tsum, stats, s);
-    case 64 * 8 + 2: return fwd_launch<L, 128, 2>(a, nblocks, sig, tsum, stats, s);
-    case 64 * 8 + 4: return fwd_launch<L, 256, 4>(a, nblocks, sig, tsum, stats, s);
-    case 128 * 8 + 1: return fwd_launch<L, 128, 1>(a, nblocks, sig, tsum, stats, s);
-    case 128 * 8 + 2: return fwd_launch<L, 256, 2>(a, nblocks, sig, tsum, stats, s);
-    case 128 * 8 + 4: return fwd_launch<L, 512, 4>(a, nblocks, sig, tsum, stats, s);
-    case 256 * 8 + 1: return fwd_launch<L, 256, 1>(a, nblocks, sig, tsum, stats, s);
-    case 256 * 8 + 2: return fwd_launch<L, 512, 2>(a, nblocks, sig, tsum, stats, s);
-    default: return fwd_launch<L, 1024, 4>(a, nblocks, sig, tsum, stats, s);
+    case 64 * 8 + 1: return fwd_launch<L, 64, 1>(a, nblocks, sig, sig64, tsum, stats, s);
+    case 64 * 8 + 2: return fwd_launch<L, 128, 2>(a, nblocks, sig, sig64, tsum, stats, s);
+    case 64 * 8 + 4: return fwd_launch<L, 256, 4>(a, nblocks, sig, sig64, tsum, stats, s);
+    case 128 * 8 + 1: return fwd_launch<L, 128, 1>(a, nblocks, sig, sig64, tsum, stats, s);
+    case 128 * 8 + 2: return fwd_launch<L, 256, 2>(a, nblocks, sig, sig64, tsum, stats, s);
+    case 128 * 8 + 4: return fwd_launch<L, 512, 4>(a, nblocks, sig, sig64, tsum, stats, s);
+    case 256 * 8 + 1: return fwd_launch<L, 256, 1>(a, nblocks, sig, sig64, tsum, stats, s);
+    case 256 * 8 + 2: return fwd_launch<L, 512, 2>(a, nblocks, sig, sig64, tsum, stats, s);
+    default: return fwd_launch<L, 1024, 4>(a, nblocks, sig, sig64, tsum, stats, s);
   }
 }
 
-static hipError_t fwd_any(const gsrf_problem *p, const RenderArgs &a, int64_t nblocks, float2 *sig, float2 *tsum,
-                          unsigned long long *stats, hipStream_t s) {
+static hipError_t fwd_any(const gsrf_problem *p, const RenderArgs &a, int64_t nblocks, float2 *sig, double2 *sig64,
+                          float2 *tsum, unsigned long long *stats, hipStream_t s) {
   const int area = p->grid.tile_w * p->grid.tile_h;
   const int G = p->grid.lanes_per_ray;   // 0: two-phase traversal
   switch (p->grid.fle_L) {
-    case 0: return fwd_dispatch<0>(area, G, a, nblocks, sig, tsum, stats, s);
-    case 1: return fwd_dispatch<1>(area, G, a, nblocks, sig, tsum, stats, s);
-    case 2: return fwd_dispatch<2>(area, G, a, nblocks, sig, tsum, stats, s);
-    case 3: return fwd_dispatch<3>(area, G, a, nblocks, sig, tsum, stats, s);
-    case 4: return fwd_dispatch<4>(area, G, a, nblocks, sig, tsum, stats, s);
-    case 5: return fwd_dispatch<5>(area, G, a, nblocks, sig, tsum, stats, s);
-    default: return fwd_dispatch<6>(area, G, a, nblocks, sig, tsum, stats, s);
+    case 0: return fwd_dispatch<0>(area, G, a, nblocks, sig, sig64, tsum, stats, s);
+    case 1: return fwd_dispatch<1>(area, G, a, nblocks, sig, sig64, tsum, stats, s);
+    case 2: return fwd_dispatch<2>(area, G, a, nblocks, sig, sig64, tsum, stats, s);
+    case 3: return fwd_dispatch<3>(area, G, a, nblocks, sig, sig64, tsum, stats, s);
+    case 4: return fwd_dispatch<4>(area, G, a, nblocks, sig, sig64, tsum, stats, s);
+    case 5: return fwd_dispatch<5>(area, G, a, nblocks, sig, sig64, tsum, stats, s);
+    default: return fwd_dispatch<6>(area, G, a, nblocks, sig, sig64, tsum, stats, s);
   }
 }
 
@@ -234,7 +241,7 @@ hipError_t launch_render_fwd(const gsrf_problem *p, const Layout &lay, char *ws,
   const int64_t nblocks = (int64_t)p->n_pairs * lay.T;
   float2 *tsum = (float2 *)(ws + lay.tile_sum);
   mark_kernel_event(0, s);
-  hipError_t e = fwd_any(p, a, nblocks, (float2 *)signal, tsum, nullptr, s);
+  hipError_t e = fwd_any(p, a, nblocks, (float2 *)signal, (double2 *)(ws + lay.sig64), tsum, nullptr, s);
   mark_kernel_event(1, s);
   if (e != hipSuccess) return e;
   // partials per pair: one per render workgroup of the pair's tiles
@@ -336,7 +343,7 @@ hipError_t launch_render_stats(const gsrf_problem *p, const Layout &lay, char *w
   if (e != hipSuccess || p->n_pairs == 0) return e;
   const RenderArgs a = make_render_args(p, lay, ws);
   const int64_t nblocks = (int64_t)p->n_pairs * lay.T;
-  return fwd_any(p, a, nblocks, nullptr, nullptr, (unsigned long long *)counts, s);
+  return fwd_any(p, a, nblocks, nullptr, nullptr, nullptr, (unsigned long long *)counts, s);
 }
 
 }  // namespace gsrf

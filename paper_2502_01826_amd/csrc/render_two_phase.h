@@ -64,7 +64,9 @@ struct TwoPhase {
 };
 
 struct TpIO {
-  float2 *signal;                 // forward output S [P, n_el, n_az]; read by the adjoint
+  float2 *signal;                 // forward output S [P, n_el, n_az]
+  double2 *sig64;                 // S in FP64 (forward writes, adjoint reads): the remainders
+                                  // S - prefix stay accurate to the size of the remainder
   float2 *tile_sum;               // forward: per-(pair, tile) partial of S_hat
   unsigned long long *stats;      // forward with counters: tests, hits, staged, rays, tile tests, walk slots
   float2 *multi;                  // multi-carrier: S [P, n_freq, n_el, n_az]
@@ -233,12 +235,14 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     ray_load_dir(valid1 ? u1 : 0, valid1 ? v1 : 0, a, K, wx, wy, wz);
     w1 = ray_mono(wx, wy, wz);
   }
-  float twopi_lam = 0.f, Sfr = 0.f, Sfi = 0.f, Gr = 0.f, Gi = 0.f;
+  float twopi_lam = 0.f, Gr = 0.f, Gi = 0.f;
+  double Sfr = 0.0, Sfi = 0.0;
   if constexpr (BWD) {
     twopi_lam = (float)(2.0 * 3.14159265358979323846 / lam);
     if (valid) {
       const size_t ri = ((size_t)k * a.n_el + v) * a.n_az + u;
-      const float2 sf = io.signal[ri], gg = io.grad_signal[ri];
+      const double2 sf = io.sig64[ri];
+      const float2 gg = io.grad_signal[ri];
       Sfr = sf.x; Sfi = sf.y; Gr = gg.x; Gi = gg.y;
       if (io.grad_sum) {
         const float2 gs = io.grad_sum[k];
@@ -250,7 +254,12 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     for (int i = tid; i < B; i += NT) sflag[i] = 0u;
   }
   const uint32_t s0 = a.tstart[gtile], s1 = v0 < a.n_el ? a.tend[gtile] : s0;   // a half below the grid: no rays
-  float T = 1.f, Sr = 0.f, Si = 0.f, Pr = 0.f, Pi = 0.f;
+  // S (forward) and the prefix sum_{j<=i} T_j c~_j (adjoint) in FP64: each
+  // term T_j c~_j is an exact FP64 product of two FP32 values, formed
+  // identically by both passes, so R_i = S - prefix_i is accurate to ~1e-16 |S|
+  // and vanishes with the remainder (the last hit of a ray)
+  float T = 1.f;
+  double Sr = 0.0, Si = 0.0, Pr = 0.0, Pi = 0.0;
   bool done = !valid || (1.0f < a.t_min);
   if (q == 0) sdone[r] = done ? 1 : 0;
   unsigned long long n_test = 0, n_hit = 0, n_staged = 0, n_tile_tests = 0, n_steps = 0;
@@ -399,8 +408,8 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
         const bool proc = hit && (Tj >= a.t_min);
         if constexpr (!BWD) {
           if (proc) {
-            Sr = fmaf(Tj, ctr, Sr);
-            Si = fmaf(Tj, cti, Si);
+            Sr = fma((double)Tj, (double)ctr, Sr);
+            Si = fma((double)Tj, (double)cti, Si);
             if (STATS) ++n_hit;
             if constexpr (MULTI) {
               // carrier c: p psi e^{-j phi_c}, phi_{c+1} = phi_c + 2 pi (|mu - tx| + t) step / c0
@@ -422,16 +431,16 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
           T = T * total;
           done = done || (T < a.t_min);
         } else {
-          const float wr = proc ? Tj * ctr : 0.f, wi_ = proc ? Tj * cti : 0.f;
-          float wr_in, wi_in, wr_tot, wi_tot;
-          group_sum<G>(wr, q, wr_in, wr_tot);
-          group_sum<G>(wi_, q, wi_in, wi_tot);
+          const double wr = proc ? (double)Tj * (double)ctr : 0.0, wi_ = proc ? (double)Tj * (double)cti : 0.0;
+          double wr_in, wi_in, wr_tot, wi_tot;
+          group_sum64<G>(wr, q, wr_in, wr_tot);
+          group_sum64<G>(wi_, q, wi_in, wi_tot);
           T = T * total;
           done = done || (T < a.t_min);
           if (__ballot(proc) != 0) {
             AdjHit ah{};
             if (proc) {
-              const float Rr = Sfr - (Pr + wr_in), Ri = Sfi - (Pi + wi_in);
+              const float Rr = (float)(Sfr - (Pr + wr_in)), Ri = (float)(Sfi - (Pi + wi_in));
               ah = adj_hit(h, geo, Tj, ctr, cti, Rr, Ri, Gr, Gi, vx, vy, vz, twopi_lam);
               sflag[j] = 1u;
             }
@@ -505,10 +514,14 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       }
       return;
     }
-    if (valid && q == 0) io.signal[((size_t)k * a.n_el + v) * a.n_az + u] = make_float2(Sr, Si);
+    if (valid && q == 0) {
+      const size_t ri = ((size_t)k * a.n_el + v) * a.n_az + u;
+      io.signal[ri] = make_float2((float)Sr, (float)Si);
+      if (io.sig64) io.sig64[ri] = make_double2(Sr, Si);
+    }
     // tile partial of S_hat in a fixed order: each wave's rays by a butterfly,
     // then the four wave totals in wave order
-    float xr = (q == 0) ? Sr : 0.f, xi = (q == 0) ? Si : 0.f;
+    float xr = (q == 0) ? (float)Sr : 0.f, xi = (q == 0) ? (float)Si : 0.f;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
       xr += __shfl_xor(xr, d, 64);

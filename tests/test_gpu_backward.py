@@ -1,4 +1,7 @@
 """GPU parity of the adjoint (a7-a8) against the oracle's FP64 gradients, through the C ABI."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -23,11 +26,24 @@ def _gpu_grads(prob, S_sig, G, gsum=None):
     return {n: o.cpu().numpy().astype(np.float64) for n, o in zip(NAMES, out)}
 
 
-def _compare(gg, gr, tol=GTOL):
+def _compare(gg, gr, tol=GTOL, scale=None):
+    """Per tensor: ||g_gpu - g_ref|| <= tol ||g_ref||.  With ``scale`` (the
+    oracle's vjp_abs magnitudes) also every entry:
+    |g_gpu - g_ref| <= tol * scale + 1e-7 max|g_ref| -- scale is the sum of the
+    per-group magnitudes the entry sums, the gradient's analogue of A_uv."""
     for n in NAMES:
         num = np.linalg.norm(gg[n] - gr[n])
         den = np.linalg.norm(gr[n])
-        say(f"  grad {n}: rel {num / max(den, 1e-30):.2e}  |ref| {den:.3e}")
+        msg = f"  grad {n}: rel {num / max(den, 1e-30):.2e}  |ref| {den:.3e}"
+        if scale is not None:
+            err = np.abs(gg[n] - gr[n])
+            lim = tol * scale[n] + 1e-7 * np.abs(gr[n]).max(initial=0.0)
+            worst = float((err / np.maximum(scale[n], 1e-300))[scale[n] > 0].max(initial=0.0))
+            bad = np.argwhere(err > lim)
+            msg += f"  entrywise max err/scale {worst:.2e} over {int((scale[n] > 0).sum())} entries"
+            assert len(bad) == 0, (n, len(bad), [(tuple(i), gg[n][tuple(i)], gr[n][tuple(i)], scale[n][tuple(i)])
+                                                 for i in bad[:5]])
+        say(msg)
         assert num <= tol * den, n
 
 
@@ -50,11 +66,11 @@ def test_tiny_gradients_match_oracle(tw, th, G):
     # marginal rays get -gsum so that their total cotangent is zero as well
     Gg = G.copy()
     Gg[ref["marginal"]] = -gsum[None, :]
-    gr = oracle.vjp(sc, p, g, Gr)
+    gr, scale = oracle.vjp_abs(sc, p, g, Gr)
     gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), Gg.reshape(1, g.n_el, g.n_az, 2),
                     gsum.reshape(1, 2))
     say("tiny gradients", int(ref["marginal"].sum()), "marginal rays")
-    _compare(gg, gr)
+    _compare(gg, gr, scale=scale)
 
 
 @pytest.mark.parametrize("tw,th", [(64, 1), (128, 1)])
@@ -70,7 +86,8 @@ def test_single_row_tile_gradients(tw, th):
     Gc[ref["marginal"]] = 0.0
     say("single-row tile gradients", tw, th)
     gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), Gc.reshape(1, g.n_el, g.n_az, 2))
-    _compare(gg, oracle.vjp(sc, p, g, Gc))
+    gr, scale = oracle.vjp_abs(sc, p, g, Gc)
+    _compare(gg, gr, scale=scale)
 
 
 @pytest.mark.parametrize("L,G,th", [(0, 0, 8), (1, 4, 8), (3, 0, 8), (6, 0, 8), (6, 1, 8), (0, 0, 4), (6, 0, 4)])
@@ -87,7 +104,8 @@ def test_gradients_across_fle_degrees(L, G, th):
     Gc[ref["marginal"]] = 0.0
     say("fle degree gradients", L, "lanes", G)
     gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), Gc.reshape(1, g.n_el, g.n_az, 2))
-    _compare(gg, oracle.vjp(sc, p, g, Gc))
+    gr, scale = oracle.vjp_abs(sc, p, g, Gc)
+    _compare(gg, gr, scale=scale)
 
 
 def test_gradients_against_central_differences():
@@ -150,8 +168,8 @@ def test_autograd_function_l2_step():
     loss.backward()
     S = torch.view_as_complex(sig.detach()).cpu().numpy()[0].ravel().astype(np.complex128)
     Gr = 2 * np.stack([S.real - target["S"].real, S.imag - target["S"].imag], -1) * ok[:, None]
-    gr = oracle.vjp(sc, p, g, Gr)
-    _compare({n: t.grad.cpu().numpy().astype(np.float64) for n, t in zip(NAMES, ps)}, gr, tol=2e-3)
+    gr, scale = oracle.vjp_abs(sc, p, g, Gr)
+    _compare({n: t.grad.cpu().numpy().astype(np.float64) for n, t in zip(NAMES, ps)}, gr, tol=2e-3, scale=scale)
 
 
 @pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (8, 8, 0), (16, 16, 0), (8, 4, 0)])
@@ -173,8 +191,8 @@ def test_paper_scale_gradients_on_sampled_rays(tw, th, G):
     G[0, uv[:, 1], uv[:, 0]] = Gs
     say("paper-scale gradients on", len(uv), "rays")
     gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), G)
-    gr = oracle.vjp(sc, p, g, Gs, rays_uv=uv)
-    _compare(gg, gr)
+    gr, scale = oracle.vjp_abs(sc, p, g, Gs, rays_uv=uv)
+    _compare(gg, gr, scale=scale)
 
 
 def test_many_tile_launch_gradients_match_oracle():
@@ -190,7 +208,7 @@ def test_many_tile_launch_gradients_match_oracle():
     S = torch.view_as_complex(sig).cpu().numpy().astype(np.complex128)
     rng = np.random.default_rng(21)
     G = np.zeros((len(b.pairs), g.n_el, g.n_az, 2))
-    ref = None
+    ref = scale = None
     for k, p in enumerate(b.pairs):
         uv = np.unique(np.stack([rng.integers(0, g.n_az, 16), rng.integers(0, g.n_el, 16)], 1), axis=0)
         tr = oracle.trace(sc, p, g, uv)
@@ -198,13 +216,14 @@ def test_many_tile_launch_gradients_match_oracle():
         uv = uv[~tr["marginal"]]
         Gs = synth.cotangent((len(uv),), seed=40 + k).astype(np.float64)
         G[k, uv[:, 1], uv[:, 0]] = Gs
-        r = oracle.vjp(sc, p, g, Gs, rays_uv=uv)
+        r, rs = oracle.vjp_abs(sc, p, g, Gs, rays_uv=uv)
         ref = r if ref is None else {n: ref[n] + r[n] for n in NAMES}
+        scale = rs if scale is None else {n: scale[n] + rs[n] for n in NAMES}
     say("many-tile launch: 10 pairs x 540 tiles")
     gt = torch.from_numpy(G.astype(np.float32)).cuda()
     out = prob.render_bwd(sig, gt)
     torch.cuda.synchronize()
-    _compare({n: o.cpu().numpy().astype(np.float64) for n, o in zip(NAMES, out)}, ref)
+    _compare({n: o.cpu().numpy().astype(np.float64) for n, o in zip(NAMES, out)}, ref, scale=scale)
 
 
 @pytest.mark.parametrize("tw,th,G", [(8, 8, 0), (16, 8, 0), (8, 8, 4)])
@@ -224,6 +243,58 @@ def test_paper_footprint_gradients_match_oracle(tw, th, G):
     R = g.n_az * g.n_el
     G = synth.cotangent((R,), seed=2).astype(np.float64)
     G[ref["marginal"]] = 0.0
-    gr = oracle.vjp(sc, p, g, G, rects=rects)
+    gr, scale = oracle.vjp_abs(sc, p, g, G, rects=rects)
     gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), G.reshape(1, g.n_el, g.n_az, 2))
-    _compare(gg, gr)
+    _compare(gg, gr, scale=scale)
+
+
+GOLD_FD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_scale_fd.json")
+
+
+def test_paper_scale_gradients_full_cotangent_and_central_differences():
+    """The differentiated step at full size (200k Gaussians, 360x90 rays, 5 GHz,
+    8x8 tiles, two-phase traversal: the launch the benchmark times) with a
+    cotangent on every ray the oracle does not flag as marginal.  For 500
+    seeded Gaussians that contribute: every attribute's gradient entry by entry
+    against the oracle's (within 1e-3 of its vjp_abs scale), and its
+    directional derivative along a seeded direction against the oracle's FP64
+    central difference; per attribute, the full gradient's norm against the
+    oracle's.  Reference values: tests/golden/make_paper_scale_fd.py (oracle
+    only)."""
+    with open(GOLD_FD) as fh:
+        d = json.load(fh)
+    gd = d["grid"]
+    g = Grid(n_az=gd["n_az"], n_el=gd["n_el"], fle_L=gd["fle_L"], tile_w=gd["tile_w"], tile_h=gd["tile_h"],
+             lanes_per_ray=0)
+    b = synth.paper_scale(grid=g)
+    say("paper scale, full cotangent:", len(d["gaussians"]), "Gaussians with stored differences")
+    prob = gpu_problem(b)
+    sig, _, _ = prob.forward()
+    G = synth.cotangent((g.n_az * g.n_el,), seed=d["cotangent_seed"]).astype(np.float64)
+    G[np.asarray(d["marginal_rays"], dtype=np.int64)] = 0.0
+    gg = _gpu_grads(prob, torch.view_as_complex(sig).cpu().numpy()[0].ravel(), G.reshape(1, g.n_el, g.n_az, 2))
+    for n in NAMES:
+        ref = d["grad_norm"][n]
+        got = float(np.linalg.norm(gg[n]))
+        say(f"  |grad {n}|: gpu {got:.6e} oracle {ref:.6e}")
+        assert abs(got - ref) <= GTOL * ref, n
+    n_fd = n_ent = 0
+    worst = {n: 0.0 for n in NAMES}
+    for rec in d["gaussians"]:
+        i = rec["index"]
+        for n in NAMES:
+            e = rec[n]
+            gi = gg[n][i].reshape(-1)
+            gr, sc = np.asarray(e["grad"]), np.asarray(e["scale"])
+            floor = 1e-7 * d["grad_norm"][n]
+            err = np.abs(gi - gr)
+            assert np.all(err <= GTOL * sc + floor), (i, n, gi, gr, sc)
+            worst[n] = max(worst[n], float((err / np.maximum(sc, 1e-300)).max()))
+            n_ent += gi.size
+            if e["fd"] is not None:
+                v = np.asarray(e["v"])
+                lim = GTOL * float(np.abs(v) @ sc) + floor
+                assert abs(float(gi @ v) - e["fd"]) <= lim, (i, n, float(gi @ v), e["fd"], lim)
+                n_fd += 1
+    say("  entries", n_ent, "worst err/scale", {n: f"{w:.1e}" for n, w in worst.items()}, "differences", n_fd)
+    assert n_fd >= 0.9 * len(NAMES) * len(d["gaussians"])

@@ -63,18 +63,22 @@ def test_uneven_batch_forward_and_gradients_match_oracle():
     gg = {n: o.cpu().numpy().astype(np.float64) for n, o in zip(NAMES, out)}
     for s, sc in enumerate(b.scenes):
         lo, hi = offs[s], offs[s + 1]
-        ref = None
+        ref = scale = None
         for k, pr in enumerate(b.pairs):
             if pr.scene != s:
                 continue
             uv, Gs = per_pair[k]
-            r = oracle.vjp(sc, pr, g, Gs, rays_uv=uv)
+            r, rs = oracle.vjp_abs(sc, pr, g, Gs, rays_uv=uv)
             ref = r if ref is None else {n: ref[n] + r[n] for n in NAMES}
+            scale = rs if scale is None else {n: scale[n] + rs[n] for n in NAMES}
         for n in NAMES:
             num = np.linalg.norm(gg[n][lo:hi] - ref[n])
             den = np.linalg.norm(ref[n])
             say(f"  scene {s} grad {n}: rel {num / max(den, 1e-30):.2e}")
             assert num <= GTOL * den, (s, n)
+            # every entry against its summed per-group magnitude (vjp_abs)
+            err = np.abs(gg[n][lo:hi] - ref[n])
+            assert np.all(err <= GTOL * scale[n] + 1e-7 * np.abs(ref[n]).max(initial=0.0)), (s, n)
 
 
 def test_graph_replays_match_eager():

@@ -273,8 +273,8 @@ def test_multi_scene_multi_pair_batch():
 @pytest.mark.parametrize("tw,th,G", [(16, 16, 1), (8, 8, 4), (16, 8, 2), (8, 8, 0), (16, 16, 0), (8, 4, 0)])
 def test_paper_scale_sampled_rays_and_tiles(tw, th, G):
     """200k Gaussians, 360x90 rays, 5 GHz, at the launch configurations the
-    benchmark times: sampled rays against the oracle, sampled tile lists bit
-    exact, and S_hat equal to the sum of the spectrum."""
+    benchmark times: sampled rays against the oracle, every record's rectangle
+    and every tile list bit exact, and S_hat equal to the sum of the spectrum."""
     b = synth.paper_scale(grid=Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=G))
     sc, p, g = b.scenes[0], b.pairs[0], b.grid
     say("paper scale: 200k gaussians, 360x90, tile", tw, th, "lanes", G)
@@ -289,7 +289,12 @@ def test_paper_scale_sampled_rays_and_tiles(tw, th, G):
     L = gpu_lists(prob)
     assert L["overflow"] == 0
     np.testing.assert_array_equal(L["rec_key"], oracle.depth_key32(sc.means, p.rx).astype(np.uint32))
-    tiles = rng.choice(L["T"], 12, replace=False)
+    # every record's cap rectangle (the FP32 screen or its FP64 fallback) and
+    # every tile list, bit for bit, except Gaussians at a marginal decision
+    tu0, ntu, tv0, ntv, cm = oracle.cap_rects(sc.means, sc.log_scales, p.rx, g)
+    np.testing.assert_array_equal(L["rec_rect"][~cm], np.stack([tu0, ntu, tv0, ntv], 1)[~cm])
+    say("paper scale: records", sc.n, "marginal rectangles", int(cm.sum()))
+    tiles = np.arange(L["T"])
     ref_l, marg = oracle_tile_members(sc, p, g, tiles)
     bad = set(np.nonzero(marg)[0].tolist())
     for t in tiles:
@@ -335,8 +340,8 @@ def test_long_tile_lists_are_merged_exactly():
 
 def test_large_batch_wide_workgroups_match_oracle():
     """500k Gaussians x 9 pairs = 4.5 M records: project and emit run with
-    1024-record workgroups; sampled tile lists of three pairs stay bit exact
-    and sampled rays match the oracle."""
+    1024-record workgroups; every record's key and rectangle and sampled tile
+    lists of three pairs stay bit exact and sampled rays match the oracle."""
     g = Grid(n_az=360, n_el=90, fle_L=2, tile_w=16, tile_h=8, lanes_per_ray=0)
     b = synth.batched(n=500_000, n_pairs=9, grid=g)
     sc = b.scenes[0]
@@ -355,10 +360,15 @@ def test_large_batch_wide_workgroups_match_oracle():
     first[L["ts"][L["te"] > L["ts"]]] = True
     assert np.all(step_ok | first[1:])
     say("longest list", int((L["te"] - L["ts"]).max()))
-    for k in (0, 4, 8):
+    for k in range(9):     # every record's key and cap rectangle, bit for bit
         p = b.pairs[k]
         np.testing.assert_array_equal(L["rec_key"][k * sc.n:(k + 1) * sc.n],
                                       oracle.depth_key32(sc.means, p.rx).astype(np.uint32))
+        tu0, ntu, tv0, ntv, cm = oracle.cap_rects(sc.means, sc.log_scales, p.rx, g)
+        np.testing.assert_array_equal(L["rec_rect"][k * sc.n:(k + 1) * sc.n][~cm],
+                                      np.stack([tu0, ntu, tv0, ntv], 1)[~cm])
+    for k in (0, 4, 8):
+        p = b.pairs[k]
         lens = L["te"][k * T:(k + 1) * T] - L["ts"][k * T:(k + 1) * T]
         # six random tiles and the two longest (sorted by the long-bucket kernel)
         tiles = np.unique(np.concatenate([rng.choice(T, 6, replace=False), np.argsort(lens)[-2:]]))
