@@ -296,7 +296,7 @@ def main() -> int:
         return roof
 
     def run_batched(b, grad, label):
-        from paper_2502_01826_amd.batch import GraphStep, TuneResult, autotune
+        from paper_2502_01826_amd.batch import GraphStep, TuneCache, TuneResult, autotune
         cat, offs = b.concat()
         prm = dict(means=cat.means, log_scales=cat.log_scales, quats=cat.quats, logits=cat.logits,
                    coeffs=cat.coeffs)
@@ -312,7 +312,8 @@ def main() -> int:
         if args.no_autotune:
             tune = TuneResult(best=(grid.tile_w, grid.tile_h, grid.lanes_per_ray))
         else:
-            tune = autotune(build, grid, grad=grad, make_grad=make_grad, iters=2)
+            tune = autotune(build, grid, grad=grad, make_grad=make_grad, iters=2,
+                            cache=TuneCache(TuneCache.default_path()), size=(int(cat.means.shape[0]), P))
         tw, th, lanes = tune.best
         g = synth.Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=lanes,
                        footprint=grid.footprint)
@@ -340,6 +341,7 @@ def main() -> int:
                 " for all pairs)",
                 "tile": f"{tw}x{th}", "lanes_per_ray": lanes,
                 "autotune_ms": {f"{a}x{b_}/{c}": v * 1e3 for (a, b_, c), v in tune.seconds.items()},
+                "autotune_cached": tune.cached,
                 "splats_within_capacity": True, "visible_records": vis,
                 "roofline": roof, "pipeline_roofline": pipe}
 

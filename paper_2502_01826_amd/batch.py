@@ -11,6 +11,9 @@ inputs change between replays checks ``Problem.splat_count()`` afterwards.
 """
 from __future__ import annotations
 
+import json
+import math
+import os
 import time
 from dataclasses import dataclass, field
 
@@ -19,7 +22,7 @@ import torch
 from .render import GridSpec, Problem
 
 # Launch configurations the tuner tries: (tile_w, tile_h, lanes_per_ray).
-DEFAULT_CANDIDATES = ((8, 4, 0), (8, 8, 0), (16, 8, 0))
+DEFAULT_CANDIDATES = ((8, 4, 0), (8, 8, 0), (16, 8, 0), (16, 16, 0), (32, 8, 0))
 
 
 class GraphStep:
@@ -92,16 +95,77 @@ class GraphStep:
 class TuneResult:
     best: tuple
     seconds: dict = field(default_factory=dict)     # candidate -> median seconds per replay
+    cached: bool = False                            # taken from a TuneCache without timing
+
+
+def tune_key(grid, n_gauss: int, n_pairs: int, grad: bool, candidates, arch: str | None = None) -> str:
+    """Cache key of a tuning result: the device's architecture, the batch's
+    size class (powers of two of the Gaussian and pair counts), the ray grid,
+    the FLE degree, the binning and paper-literal switches, whether the
+    adjoint is included, and the candidate set."""
+    g = GridSpec.of(grid)
+    if arch is None:
+        props = torch.cuda.get_device_properties(torch.cuda.current_device())
+        arch = getattr(props, "gcnArchName", props.name)
+    bucket = lambda x: int(round(math.log2(max(1, x))))
+    cand = ";".join(f"{a}x{b}/{c}" for a, b, c in candidates)
+    return (f"{arch}|G2^{bucket(n_gauss)}|P2^{bucket(n_pairs)}|{g.n_az}x{g.n_el}|L{g.fle_L}|"
+            f"fp{g.footprint}|v{g.depth_order}{g.fle_eval}{g.transmittance}|{'bwd' if grad else 'fwd'}|{cand}")
+
+
+class TuneCache:
+    """Tuning results by ``tune_key``, kept in memory and, when a path is
+    given, in a JSON file (read at construction, rewritten on every put)."""
+
+    def __init__(self, path: str | None = None):
+        self.path = path
+        self.entries = {}
+        if path and os.path.exists(path):
+            try:
+                with open(path) as fh:
+                    self.entries = json.load(fh)
+            except (OSError, ValueError):
+                self.entries = {}
+
+    @staticmethod
+    def default_path() -> str:
+        return os.environ.get("GSRF_TUNE_CACHE",
+                              os.path.join(os.path.expanduser("~"), ".cache", "gsrf", "tune.json"))
+
+    def get(self, key: str):
+        e = self.entries.get(key)
+        if e is None:
+            return None
+        return TuneResult(best=tuple(e["best"]),
+                          seconds={tuple(int(x) for x in k.split(",")): v for k, v in e["seconds"].items()},
+                          cached=True)
+
+    def put(self, key: str, res: TuneResult):
+        self.entries[key] = {"best": list(res.best),
+                             "seconds": {",".join(str(x) for x in k): v for k, v in res.seconds.items()}}
+        if self.path:
+            os.makedirs(os.path.dirname(self.path) or ".", exist_ok=True)
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(self.entries, fh, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
 
 
 def autotune(build, grid, candidates=DEFAULT_CANDIDATES, grad: bool = False, iters: int = 3,
-             make_grad=None) -> TuneResult:
+             make_grad=None, cache: TuneCache | None = None, size: tuple | None = None) -> TuneResult:
     """Time one graph replay per launch configuration and return the fastest.
 
     ``build(grid)`` returns a fresh Problem for a grid; ``make_grad(prob)``
     returns (grad_signal, grad_sum) when ``grad``.  Each candidate's problem is
-    released before the next is built, so peak memory is one batch.
+    released before the next is built, so peak memory is one batch.  With a
+    ``cache`` and ``size`` = (Gaussians, pairs), a result stored under the
+    batch's ``tune_key`` is returned without timing, and a new one is stored.
     """
+    key = tune_key(grid, size[0], size[1], grad, candidates) if (cache is not None and size) else None
+    if key is not None:
+        hit = cache.get(key)
+        if hit is not None:
+            return hit
     res = TuneResult(best=None)
     base = GridSpec.of(grid)
     for tw, th, lanes in candidates:
@@ -113,4 +177,6 @@ def autotune(build, grid, candidates=DEFAULT_CANDIDATES, grad: bool = False, ite
         del step, prob
         torch.cuda.empty_cache()
     res.best = min(res.seconds, key=res.seconds.get)
+    if key is not None:
+        cache.put(key, res)
     return res

@@ -227,3 +227,25 @@ def test_density_control_validates_before_launching():
     assert L.gsrf_density_control(*args(10, 20, bad)) == _lib.GSRF_EINVAL
     assert L.gsrf_grad_stats_accumulate(10, None, None, None, None) == _lib.GSRF_EINVAL
     assert L.gsrf_grad_stats_accumulate(0, None, None, None, None) == _lib.GSRF_OK
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """The autotuner's cache: keys separate architecture, size class, grid,
+    FLE degree, switches, direction and candidates; results survive a reload."""
+    from paper_2502_01826_amd.batch import TuneCache, TuneResult, tune_key
+    from synth import Grid
+    g = Grid(n_az=360, n_el=90, fle_L=2)
+    cand = ((8, 4, 0), (8, 8, 0))
+    k = tune_key(g, 500_000, 256, False, cand, arch="gfx950")
+    assert k == tune_key(g, 480_000, 250, False, cand, arch="gfx950")           # same size class
+    assert k != tune_key(g, 500_000, 256, True, cand, arch="gfx950")           # adjoint included
+    assert k != tune_key(g, 2_000_000, 256, False, cand, arch="gfx950")        # 4x the Gaussians
+    assert k != tune_key(g, 500_000, 256, False, cand, arch="gfx942")          # another device
+    assert k != tune_key(Grid(n_az=360, n_el=90, fle_L=3), 500_000, 256, False, cand, arch="gfx950")
+    assert k != tune_key(g, 500_000, 256, False, cand[:1], arch="gfx950")
+    path = str(tmp_path / "tune.json")
+    c = TuneCache(path)
+    assert c.get(k) is None
+    c.put(k, TuneResult(best=(8, 8, 0), seconds={(8, 4, 0): 0.024, (8, 8, 0): 0.019}))
+    r = TuneCache(path).get(k)
+    assert r.cached and r.best == (8, 8, 0) and r.seconds == {(8, 4, 0): 0.024, (8, 8, 0): 0.019}
