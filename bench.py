@@ -430,14 +430,41 @@ def main() -> int:
         run(prob, bufs, steps, False, ev1)
         torch.cuda.synchronize()
         t_1k = sum(a.elapsed_time(b) for a, b in zip(ev1["f0"], ev1["f1"])) / steps * 1e-3
+        # the several-carrier adjoint (after the one-carrier forward that records the hit
+        # masks), against the one-carrier adjoint kernel of the same pair
+        Gm = torch.from_numpy(synth.cotangent((1, nf, grid.n_el, grid.n_az), seed=15)).to(dev)
+        Gms = torch.from_numpy(synth.cotangent((1, nf), seed=16)).to(dev)
+        ev2 = {k: [new_event() for _ in range(steps)] for k in ("b0", "b1")}
+        prob.render_bwd_multi(nf, df, Gm, Gms, out=bufs["grads"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            _lib.lib().gsrf_set_kernel_events(None, None, ev2["b0"][i].cuda_event, ev2["b1"][i].cuda_event)
+            prob.render_bwd_multi(nf, df, Gm, Gms, out=bufs["grads"])
+        _lib.lib().gsrf_set_kernel_events(None, None, None, None)
+        torch.cuda.synchronize()
+        t_bwd_call = (time.perf_counter() - t0) / steps
+        t_mb = sum(a.elapsed_time(b) for a, b in zip(ev2["b0"], ev2["b1"])) / steps * 1e-3
+        run(prob, bufs, 1, True)
+        torch.cuda.synchronize()
+        run(prob, bufs, steps, True, ev1)
+        torch.cuda.synchronize()
+        t_1b = sum(a.elapsed_time(b) for a, b in zip(ev1["b0"], ev1["b1"])) / steps * 1e-3
         st = prob.render_stats()
         n_splats, ok = prob.splat_count()
         if not ok:
             raise RuntimeError(f"multi-carrier: {n_splats} splats exceed the capacity fixed before timing")
         fl = flops_multi(nf, st["tile_tests"], st["hits"])
         ach = fl / t_mk
-        del prob, bufs, msig, msum
+        del prob, bufs, msig, msum, Gm, Gms
         torch.cuda.empty_cache()
+        adjoint = {"kernel_ms": t_mb * 1e3, "call_ms": t_bwd_call * 1e3,
+                   "carrier_gradients_per_s": nf / t_bwd_call,
+                   "single_carrier_adjoint_kernel_ms": t_1b * 1e3,
+                   "speedup_vs_per_carrier_adjoints": nf * t_1b / t_mb,
+                   "timing": f"{steps} eager gsrf_render_bwd_multi calls (total and adjoint passes per 16 carriers, "
+                             "chain rule) after one warm-up call; kernel_ms: HIP events recorded by the library "
+                             "around the traversals"}
         return {"workload": f"multi-carrier forward: {nf} carriers {df / 1e3:g} kHz apart (one OFDM block) on the "
                             "plain pair, 200k Gaussians, 360x90 rays",
                 "carriers": nf, "carrier_step_hz": df,
@@ -447,6 +474,7 @@ def main() -> int:
                 "carriers_per_traversal": multi_chunks(nf),
                 "kernel_ms": t_mk * 1e3, "single_carrier_kernel_ms": t_1k * 1e3,
                 "speedup_vs_per_carrier_kernels": nf * t_1k / t_mk,
+                "adjoint": adjoint,
                 "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                              "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None,
                              "kernel": "render_fwd_multi traversals", "flop_per_launch": fl,

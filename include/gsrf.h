@@ -278,6 +278,34 @@ gsrf_status gsrf_render_bwd(const gsrf_problem *p, const float *signal, const fl
                             float *d_logits, float *d_coeffs, void *stream);
 
 /*
+ * Adjoint of the multi-carrier forward (the CSI vectors of Sec. 4 train one
+ * set of Gaussians on every subcarrier; each path's phase is 2 pi f tau,
+ * Sec. 2): the gradient of L = sum_c L_c with respect to every parameter,
+ * where carrier c of pair k is at pairs[k].freq_hz + c * freq_step_hz and the
+ * caller supplies each carrier's dL/dS per ray and per pair.  Equals the sum
+ * over carriers of gsrf_render_bwd at each carrier's frequency, in one
+ * traversal per 16 carriers instead of one per carrier: the carriers share
+ * the hit decisions and transmittance, and the adjoint of every carrier's
+ * phase is folded into two complex weights per hit.  Must follow
+ * gsrf_render_fwd of the same prepared problem on the same workspace (it
+ * reuses the hit masks recorded there; the hit decisions do not depend on the
+ * carrier); the forward's multi-carrier output is not needed -- each chunk of
+ * carriers first sums sum_c Re(conj(G_c) S_c) per ray in FP64 over the same
+ * hits, so the remainders are accurate to their own size.
+ *   n_freq        1 .. 4096 carriers per pair
+ *   freq_step_hz  carrier spacing, >= 0 (Hz)
+ *   grad_signal   [P, n_freq, n_el, n_az, 2]  dL/dRe S + j dL/dIm S per carrier
+ *   grad_sum      [P, n_freq, 2] or NULL      dL/dS_hat per pair and carrier
+ * Outputs OVERWRITTEN, summed over pairs and carriers, as gsrf_render_bwd.
+ * Needs lanes_per_ray = 0 (GSRF_ENOTSUP otherwise, and for the paper-literal
+ * variants).
+ */
+gsrf_status gsrf_render_bwd_multi(const gsrf_problem *p, int32_t n_freq, double freq_step_hz,
+                                  const float *grad_signal, const float *grad_sum, float *d_means,
+                                  float *d_log_scales, float *d_quats, float *d_logits, float *d_coeffs,
+                                  void *stream);
+
+/*
  * Instrumentation for the roofline: replays the render_fwd traversal of a
  * problem prepared by gsrf_project + gsrf_bin_sort without writing any
  * output, and stores (DEVICE, int64 [6], overwritten) the number of

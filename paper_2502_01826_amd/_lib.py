@@ -62,7 +62,7 @@ GSRF_LOSS_RSSI_DB, GSRF_LOSS_COMPLEX_L2 = 0, 1
 
 EXPORTS = ["gsrf_status_str", "gsrf_last_error", "gsrf_workspace_size", "gsrf_layout_of", "gsrf_project",
            "gsrf_splat_count", "gsrf_ray_hit_count", "gsrf_bin_sort", "gsrf_render_fwd", "gsrf_render_fwd_multi", "gsrf_render_bwd",
-           "gsrf_render_stats",
+           "gsrf_render_bwd_multi", "gsrf_render_stats",
            "gsrf_set_kernel_events", "gsrf_loss_workspace_size", "gsrf_loss_spectrum", "gsrf_loss_spectrum_noalloc",
            "gsrf_loss_single",
            "gsrf_sgd_step", "gsrf_grad_stats_accumulate", "gsrf_density_workspace_size", "gsrf_density_control"]
@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
     L.gsrf_bin_sort.argtypes = [P(GsrfProblem), c_vp]
     L.gsrf_render_fwd.argtypes = [P(GsrfProblem), c_vp, c_vp, c_vp, c_vp]
     L.gsrf_render_bwd.argtypes = [P(GsrfProblem), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]
+    L.gsrf_render_bwd_multi.argtypes = [P(GsrfProblem), c_i32, c_f64] + [c_vp] * 8
     L.gsrf_render_stats.argtypes = [P(GsrfProblem), c_vp, c_vp]
     L.gsrf_render_fwd_multi.argtypes = [P(GsrfProblem), c_i32, c_f64, c_vp, c_vp, c_vp]
     L.gsrf_set_kernel_events.argtypes = [c_vp, c_vp, c_vp, c_vp]

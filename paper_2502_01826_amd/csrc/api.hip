@@ -134,6 +134,7 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.grad_acc = take((size_t)G * L.acc_stride * 4);
   L.hitmask = take(g.lanes_per_ray == 0 ? (size_t)L.cap * (size_t)(g.tile_w * g.tile_h / 32) * 4 : 0);
   L.sig64 = take((size_t)p->n_pairs * g.n_az * g.n_el * 16);
+  L.wtot = take(g.lanes_per_ray == 0 ? (size_t)p->n_pairs * g.n_az * g.n_el * 8 : 0);
   L.rays = take((size_t)g.n_az * g.n_el * ray_stride(L.K) * 4);
   {
     const int64_t n_all = g.depth_order ? (int64_t)p->n_pairs * g.n_az * g.n_el : 0;
@@ -283,6 +284,27 @@ gsrf_status gsrf_render_bwd(const gsrf_problem *p, const float *signal, const fl
   return dev(launch_render_bwd(p, L, (char *)p->workspace, signal, grad_signal, grad_sum, d_means, d_log_scales,
                                d_quats, d_logits, d_coeffs, (hipStream_t)stream),
              "gsrf_render_bwd");
+}
+
+gsrf_status gsrf_render_bwd_multi(const gsrf_problem *p, int32_t n_freq, double freq_step_hz,
+                                  const float *grad_signal, const float *grad_sum, float *d_means,
+                                  float *d_log_scales, float *d_quats, float *d_logits, float *d_coeffs,
+                                  void *stream) {
+  if (!p) return fail(GSRF_EINVAL, "problem is NULL");
+  if (n_freq < 1 || n_freq > kMaxCarriers) return fail(GSRF_EINVAL, "n_freq = %d outside [1, %d]", n_freq, kMaxCarriers);
+  if (!(freq_step_hz >= 0.0) || !(freq_step_hz < 1e12)) return fail(GSRF_EINVAL, "freq_step_hz = %g", freq_step_hz);
+  if (p->grid.lanes_per_ray != 0)
+    return fail(GSRF_ENOTSUP, "the multi-carrier adjoint uses the two-phase traversal (lanes_per_ray = 0)");
+  if (has_variant(p->grid)) return fail(GSRF_ENOTSUP, "no adjoint for the paper-literal render variants");
+  Layout L;
+  gsrf_status st = plan(p, &L, true);
+  if (st != GSRF_OK) return st;
+  if (p->n_pairs > 0 && !grad_signal) return fail(GSRF_EINVAL, "grad_signal is NULL");
+  if (p->n_gauss > 0 && (!d_means || !d_log_scales || !d_quats || !d_logits || !d_coeffs))
+    return fail(GSRF_EINVAL, "a gradient output pointer is NULL");
+  return dev(launch_render_bwd_multi(p, L, (char *)p->workspace, n_freq, freq_step_hz, grad_signal, grad_sum, d_means,
+                                     d_log_scales, d_quats, d_logits, d_coeffs, (hipStream_t)stream),
+             "gsrf_render_bwd_multi");
 }
 
 gsrf_status gsrf_render_stats(const gsrf_problem *p, int64_t *counts, void *stream) {

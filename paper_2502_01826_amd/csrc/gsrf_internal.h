@@ -106,6 +106,7 @@ struct Layout {
   size_t tile_sum, grad_acc;
   size_t hitmask;         // two-phase traversal: per splat, tile-area / 32 words of forward hit bits
   size_t sig64;           // [P][n_el * n_az] double2: the forward's S in FP64, read by the adjoint
+  size_t wtot;            // [P][n_el * n_az] double: the several-carrier adjoint's per-ray totals
   size_t rays;            // [n_el * n_az][ray_stride(K)] ray directions and FLE basis (FP32)
   // per-ray midpoint order (depth_order = 1): hits per ray, first record per
   // ray, block sums of their scan, and the records (sort key, terms)
@@ -148,6 +149,10 @@ hipError_t launch_render_fwd_variant(const gsrf_problem *p, const Layout &lay, c
                                      float *signal_sum, float *rssi_dbm, hipStream_t s);
 hipError_t launch_render_fwd_multi(const gsrf_problem *p, const Layout &lay, char *ws, int32_t n_freq, double f_step,
                                    float *signal, float *signal_sum, hipStream_t s);
+hipError_t launch_render_bwd_multi(const gsrf_problem *p, const Layout &lay, char *ws, int32_t n_freq, double f_step,
+                                   const float *grad_signal, const float *grad_sum, float *d_means,
+                                   float *d_log_scales, float *d_quats, float *d_logits, float *d_coeffs,
+                                   hipStream_t s);
 hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws, const float *signal,
                              const float *grad_signal, const float *grad_sum, float *d_means,
                              float *d_log_scales, float *d_quats, float *d_logits, float *d_coeffs,

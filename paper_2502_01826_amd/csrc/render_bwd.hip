@@ -287,3 +287,67 @@ hipError_t launch_render_bwd(const gsrf_problem *p, const Layout &lay, char *ws,
 }
 
 }  // namespace gsrf
+
+namespace gsrf {
+
+// Several carriers (OFDM subcarriers, Sec. 4): per chunk of kGcChunk carriers a
+// total pass and an adjoint pass over the forward's hit masks (the carriers
+// share every hit decision); every chunk adds into the same accumulators and
+// the chain rule runs once.
+template <int L>
+static hipError_t bwd_multi_chunks(int area, const RenderArgs &a, int64_t nblocks, int32_t n_freq, double f_step,
+                                   const float2 *gsig, const float2 *gsum, double *wtot, float *acc, int S,
+                                   hipStream_t s) {
+  for (int32_t f0 = 0; f0 < n_freq; f0 += kGcChunk) {
+    TpIO io{};
+    io.n_freq = n_freq;
+    io.f_first = f0;
+    io.f_step = f_step;
+    io.grad_multi = gsig;
+    io.grad_sum_multi = gsum;
+    io.wtot = wtot;
+    io.acc = acc;
+    io.acc_stride = S;
+    hipError_t e = tp_dispatch<L, kTpMultiTotal>(area, a, io, nblocks, s);
+    if (e != hipSuccess) return e;
+    e = tp_dispatch<L, kTpBwdMulti>(area, a, io, nblocks, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_render_bwd_multi(const gsrf_problem *p, const Layout &lay, char *ws, int32_t n_freq, double f_step,
+                                   const float *grad_signal, const float *grad_sum, float *d_means,
+                                   float *d_log_scales, float *d_quats, float *d_logits, float *d_coeffs,
+                                   hipStream_t s) {
+  float *acc = (float *)(ws + lay.grad_acc);
+  hipError_t e = fill<float>(acc, 0.f, p->n_gauss * lay.acc_stride, s);
+  if (e != hipSuccess) return e;
+  if (p->n_pairs > 0) {
+    const RenderArgs a = make_render_args(p, lay, ws);
+    const int area = p->grid.tile_w * p->grid.tile_h;
+    const int64_t nb = (int64_t)p->n_pairs * lay.T;
+    const float2 *gs = (const float2 *)grad_signal, *gm = (const float2 *)grad_sum;
+    double *wt = (double *)(ws + lay.wtot);    // the per-ray totals of a chunk
+    mark_kernel_event(2, s);
+    switch (p->grid.fle_L) {
+      case 0: e = bwd_multi_chunks<0>(area, a, nb, n_freq, f_step, gs, gm, wt, acc, lay.acc_stride, s); break;
+      case 1: e = bwd_multi_chunks<1>(area, a, nb, n_freq, f_step, gs, gm, wt, acc, lay.acc_stride, s); break;
+      case 2: e = bwd_multi_chunks<2>(area, a, nb, n_freq, f_step, gs, gm, wt, acc, lay.acc_stride, s); break;
+      case 3: e = bwd_multi_chunks<3>(area, a, nb, n_freq, f_step, gs, gm, wt, acc, lay.acc_stride, s); break;
+      case 4: e = bwd_multi_chunks<4>(area, a, nb, n_freq, f_step, gs, gm, wt, acc, lay.acc_stride, s); break;
+      case 5: e = bwd_multi_chunks<5>(area, a, nb, n_freq, f_step, gs, gm, wt, acc, lay.acc_stride, s); break;
+      default: e = bwd_multi_chunks<6>(area, a, nb, n_freq, f_step, gs, gm, wt, acc, lay.acc_stride, s); break;
+    }
+    mark_kernel_event(3, s);
+    if (e != hipSuccess) return e;
+  }
+  if (p->n_gauss > 0) {
+    hipLaunchKernelGGL(k_chain, dim3((unsigned)((p->n_gauss + 255) / 256)), dim3(256), 0, s, p->log_scales, p->quats,
+                       p->opacity_logits, (const float *)acc, lay.acc_stride, lay.K, p->n_gauss, d_means, d_log_scales,
+                       d_quats, d_logits, d_coeffs);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsrf

@@ -596,6 +596,66 @@ __device__ __forceinline__ AdjHit adj_hit(const Terms &h, const float4 *geo, flo
   return a;
 }
 
+// The per-hit scalars for several carriers f_c = f_b + c df (c = 0 .. C-1) at
+// once.  Carrier c's term is p psi e^{-j phi_c} with phi_c = phi_b + c delta, so
+// every sum over carriers of conj(G_c) times a carrier-c term is conj(Ge)
+// times the base-carrier term, with Ge = sum_c G_c e^{j c delta}; the path
+// length enters carrier c's phase as 2 pi f_c / c0, which adds
+// Ge2 = sum_c c G_c e^{j c delta} at 2 pi df / c0.  num is
+// sum_c Re(conj(G_c) R_c), the carriers' remainders after the hit.
+__device__ __forceinline__ AdjHit adj_hit_multi(const Terms &h, const float4 *geo, float Tj, float ctr, float cti,
+                                                float num, float Ger, float Gei, float Ge2r, float Ge2i, float vx,
+                                                float vy, float vz, float twopi_lam, float twopi_dlam) {
+  AdjHit a;
+  const float dLdp = Tj * fmaf(Ger, h.pzr, Gei * h.pzi);
+  const float dLdphi = Tj * fmaf(Ger, cti, -(Gei * ctr));
+  const float dLdphi2 = Tj * fmaf(Ge2r, cti, -(Ge2i * ctr));
+  const float dLda = h.clamped ? 0.f : -num / (1.0f - h.alpha);
+  const float4 g0 = geo[0], g3 = geo[3];
+  const float D = g0.w;
+  const float dLdG = fmaf(dLdp, g3.z, dLda * g3.w);
+  a.gQ = -0.5f * h.G * dLdG;
+  a.gt = fmaf(dLdphi, twopi_lam, dLdphi2 * twopi_dlam);
+  a.gtA = a.gt * h.rA;
+  a.px = D * fmaf(-h.bA, vx, h.ex);
+  a.py = D * fmaf(-h.bA, vy, h.ey);
+  a.pz = D * fmaf(-h.bA, vz, h.ez);
+  a.qx = D * fmaf(-h.bA, h.w0, h.m0);
+  a.qy = D * fmaf(-h.bA, h.w1, h.m1);
+  a.qz = D * fmaf(-h.bA, h.w2, h.m2);
+  a.w0 = h.w0;
+  a.w1 = h.w1;
+  a.w2 = h.w2;
+  a.dN = dLdp * h.G;
+  a.dO = dLda * h.G;
+  const float Tp = Tj * h.p;
+  a.dpr = Tp * fmaf(Ger, h.cs, -(Gei * h.sn));
+  a.dpi = Tp * fmaf(Gei, h.cs, Ger * h.sn);
+  return a;
+}
+
+// Ge = sum_c G_c e^{j c delta} and Ge2 = sum_c c G_c e^{j c delta} over the
+// chunk's carriers (g: its kGcChunk values of dL/dS of the ray), with
+// (sd, cd) = (sin delta, cos delta): the phase step between carriers.
+template <int NC>
+__device__ __forceinline__ void carrier_sums_n(const float2 *g, float sd, float cd, float &Ger, float &Gei, float &Ge2r,
+                                               float &Ge2i) {
+  float zr = 1.f, zi = 0.f;
+  Ger = Gei = Ge2r = Ge2i = 0.f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const float2 gc = g[c];
+    const float tr = fmaf(gc.x, zr, -(gc.y * zi)), ti = fmaf(gc.x, zi, gc.y * zr);
+    Ger += tr;
+    Gei += ti;
+    Ge2r = fmaf((float)c, tr, Ge2r);
+    Ge2i = fmaf((float)c, ti, Ge2i);
+    const float nr = fmaf(zr, cd, -(zi * sd)), ni = fmaf(zi, cd, zr * sd);
+    zr = nr;
+    zi = ni;
+  }
+}
+
 template <int K>
 __device__ __forceinline__ float adj_slot(int s, const AdjHit &a, float vx, float vy, float vz, const float *Yr,
                                           const float *Yi) {

@@ -49,8 +49,16 @@ constexpr uint64_t kTmidRankMask = ((uint64_t)1 << kTmidRankBits) - 1;
 constexpr double kTmidKeyScale = 16777216.0;                 // 2^24 per metre
 constexpr double kTmidMaxT = 65536.0 - 1.0 / 16777216.0;
 enum TpMode { kTpFwd = 0, kTpFwdStats = 1, kTpBwd = 2, kTpFwdMulti = 3, kTpFwdMultiWide = 4, kTpCount = 5,
-              kTpCollect = 6 };
+              kTpCollect = 6, kTpMultiTotal = 7, kTpBwdMulti = 8 };
 constexpr int kMultiChunk = 16, kMultiChunkWide = 32;
+// kTpMultiTotal / kTpBwdMulti: the adjoint for kGcChunk carriers at once
+// (OFDM subcarriers, Sec. 4) over the forward's hit masks.  The total pass
+// walks each ray's processed hits and sums w_i = T_i Re(conj(Ge_i) c~_i) in
+// FP64 -- sum_c Re(conj(G_c) S_c) of the ray, Ge_i = sum_c G_c e^{j c delta_i}
+// (adj_hit_multi) -- which the adjoint pass then uses for the remainders
+// sum_{i>j} w_i = total - prefix_j, as the one-carrier adjoint uses S.  The
+// carriers' dL/dS of the tile's rays are held in LDS.
+constexpr int kGcChunk = 16;
 constexpr int multi_chunk(int mode) {
   return mode == kTpFwdMulti ? kMultiChunk : mode == kTpFwdMultiWide ? kMultiChunkWide : 1;
 }
@@ -81,6 +89,10 @@ struct TpIO {
   uint64_t *hit_key;              // midpoint order: (t_mid key << 24 | hit rank) per record
   float4 *hit_val;                // midpoint order: (keep, Re, Im of p psi e^{-j phi}, -) per record
   const int64_t *counters;        // [3] = records over capacity (collect writes nothing then)
+  // several-carrier adjoint (io.n_freq carriers, io.f_first the chunk's first)
+  const float2 *grad_multi;       // dL/dS [P, n_freq, n_el, n_az]
+  const float2 *grad_sum_multi;   // dL/dS_hat [P, n_freq], or null
+  double *wtot;                   // per ray: sum_c Re(conj(G_c) S_c) of the chunk (total pass writes)
 };
 
 // BCAP: largest staged batch (128).  Smaller batches waste fewer tests past
@@ -88,7 +100,8 @@ struct TpIO {
 // fewer barriers.
 template <int L, int R, int MODE, int BCAP>
 struct TpShape {
-  static constexpr bool BWD = MODE == kTpBwd;
+  static constexpr bool BWD = MODE == kTpBwd || MODE == kTpBwdMulti;     // adjoint (accumulators)
+  static constexpr bool GC = MODE == kTpBwdMulti || MODE == kTpMultiTotal;   // carriers' dL/dS in LDS
   static constexpr int K = (L + 1) * (L + 1);
   static constexpr int B = lds_batch(L, 256, BWD, BCAP);
   static constexpr int NACC = n_acc(L);
@@ -97,7 +110,8 @@ struct TpShape {
   static constexpr int MWR = R / 32;             // hit-mask words per entry (one bit per ray)
   // LDS: geometry, [TX legs], coefficients, [accumulators, flags], ray rows, union rows, done flags
   static constexpr size_t kLds = (size_t)B * (kGeo * 16 + 2 * K * 4) + (BWD ? (size_t)B * (16 + NACC * 4 + 4) : 0) +
-                                 (size_t)R * MWS * 4 + (size_t)4 * MW * 4 + (size_t)R * 4;
+                                 (size_t)R * MWS * 4 + (size_t)4 * MW * 4 + (size_t)R * 4 +
+                                 (GC ? (size_t)R * kGcChunk * 8 : 0);
   static constexpr size_t lds() { return kLds < 256 * 8 ? 256 * 8 : kLds; }
 };
 
@@ -188,6 +202,8 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   constexpr int FC = multi_chunk(MODE);
   constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats, MULTI = FC > 1;
   constexpr bool COUNT = MODE == kTpCount, COLLECT = MODE == kTpCollect;
+  constexpr bool GC = SH::GC, MTOT = MODE == kTpMultiTotal, BMULTI = MODE == kTpBwdMulti;
+  constexpr bool MASKED = BWD || COLLECT || MTOT;   // hit decisions from the forward's masks
   if constexpr (COLLECT)
     if (io.counters[3] != 0) return;           // records over capacity: the whole launch writes nothing
   constexpr int NT = TP::NT, G = TP::G, EP = TP::EP, RPW = TP::RPW;
@@ -202,6 +218,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   uint32_t *smask = (uint32_t *)(sflag + (BWD ? B : 0));    // [R][MWS]
   uint32_t *suni = smask + R * MWS;                         // [4][MW]
   int *sdone = (int *)(suni + 4 * MW);                      // [R]
+  float2 *sgc = (float2 *)(sdone + R);                      // [R][kGcChunk] (several-carrier adjoint)
   constexpr int MWR = SH::MWR;
   const int gt = blockIdx.x;                 // (pair, tile, half)
   const int gtile = gt / SPLIT, half = gt - gtile * SPLIT;
@@ -221,9 +238,9 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   const bool valid1 = (u1 < a.n_az) && (v1 < a.n_el);
   const gsrf_pair pr = a.pairs[k];
   // (multi-carrier: the launch's first carrier)
-  const double freq = MULTI ? pr.freq_hz + io.f_first * io.f_step : pr.freq_hz;
+  const double freq = (MULTI || GC) ? pr.freq_hz + io.f_first * io.f_step : pr.freq_hz;
   const double lam = kC0 / freq, inv_lam = freq / kC0;
-  const double step_rev = MULTI ? io.f_step / kC0 : 0.0;
+  const double step_rev = (MULTI || GC) ? io.f_step / kC0 : 0.0;
   float mr[FC], mi[FC];   // multi-carrier accumulators
 #pragma unroll
   for (int c = 0; c < FC; ++c) mr[c] = mi[c] = 0.f;
@@ -235,9 +252,34 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     ray_load_dir(valid1 ? u1 : 0, valid1 ? v1 : 0, a, K, wx, wy, wz);
     w1 = ray_mono(wx, wy, wz);
   }
-  float twopi_lam = 0.f, Gr = 0.f, Gi = 0.f;
+  float twopi_lam = 0.f, twopi_dlam = 0.f, Gr = 0.f, Gi = 0.f;
   double Sfr = 0.0, Sfi = 0.0;
-  if constexpr (BWD) {
+  if constexpr (GC) {
+    // the chunk's carriers' dL/dS (+ dL/dS_hat) of the tile's rays; zero past the last carrier
+    const int nc = min(kGcChunk, io.n_freq - io.f_first);
+    for (int i = tid; i < R * kGcChunk; i += NT) {
+      const int rr = i / kGcChunk, c = i - rr * kGcChunk;
+      const int uu = tu * a.tw + rr % a.tw, vv = v0 + rr / a.tw;
+      float2 gv = make_float2(0.f, 0.f);
+      if (c < nc && uu < a.n_az && vv < a.n_el) {
+        const size_t kc = (size_t)k * io.n_freq + io.f_first + c;
+        gv = io.grad_multi[(kc * a.n_el + vv) * a.n_az + uu];
+        if (io.grad_sum_multi) {
+          const float2 gs = io.grad_sum_multi[kc];
+          gv.x += gs.x;
+          gv.y += gs.y;
+        }
+      }
+      sgc[i] = gv;
+    }
+    twopi_dlam = (float)(2.0 * 3.14159265358979323846 * io.f_step / kC0);
+  }
+  if constexpr (BMULTI) {
+    twopi_lam = (float)(2.0 * 3.14159265358979323846 / lam);
+    if (valid) Sfr = io.wtot[((size_t)k * a.n_el + v) * a.n_az + u];
+    for (int i = tid; i < NACC * B; i += NT) sacc[i] = 0.f;
+    for (int i = tid; i < B; i += NT) sflag[i] = 0u;
+  } else if constexpr (BWD) {
     twopi_lam = (float)(2.0 * 3.14159265358979323846 / lam);
     if (valid) {
       const size_t ri = ((size_t)k * a.n_el + v) * a.n_az + u;
@@ -280,7 +322,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     __syncthreads();
     const uint32_t g_cur = g_next;
     if (tid < nb)
-      stage_entry<K, MULTI, VAR>(a, g_cur, pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
+      stage_entry<K, MULTI || GC, VAR>(a, g_cur, pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                                  sgeo + kGeo * tid, scf + 2 * K * tid, BWD ? stx + tid : nullptr, step_rev);
     if (tid < B && base + B + tid < s1) g_next = a.val[base + B + tid];
     if constexpr (BWD)
@@ -288,7 +330,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
         sflag[i] = 0u;
         sacc[NACC * i + NACC - 1] = 0.f;
       }
-    if constexpr (!BWD && !COLLECT)
+    if constexpr (!MASKED)
       for (int i = tid; i < R * MWS + 4 * MW; i += NT) smask[i] = 0u;   // ray rows and union rows
 
     if (STATS && tid == 0) {
@@ -297,7 +339,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     }
     __syncthreads();
     // ---- phase 1: the forward tests; the adjoint takes the forward's hit masks ----
-    if constexpr (!BWD && !COLLECT) {
+    if constexpr (!MASKED) {
       if (valid1 && !sdone[r1]) {
         const unsigned nt = phase1_tests<EP, MW>(w1, sgeo, nb, e, a.r_rx, smask + r1 * MWS, suni + (r1 / RPW) * MW);
         if (STATS) n_test += nt;
@@ -406,7 +448,18 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
         group_prod<G>(f, q, excl, total);
         const float Tj = T * excl;
         const bool proc = hit && (Tj >= a.t_min);
-        if constexpr (!BWD) {
+        if constexpr (MTOT) {
+          // the ray's sum over hits of T_j Re(conj(Ge_j) c~_j), FP64
+          if (proc) {
+            float sd, cd, Ger, Gei, Ge2r, Ge2i;
+            const float4 g4 = geo[4];
+            sincos_rev(fmaf(-h.bA, g4.w, g4.z), sd, cd);
+            carrier_sums_n<kGcChunk>(sgc + r * kGcChunk, sd, cd, Ger, Gei, Ge2r, Ge2i);
+            Sr = fma((double)Tj, (double)fmaf(Ger, ctr, Gei * cti), Sr);
+          }
+          T = T * total;
+          done = done || (T < a.t_min);
+        } else if constexpr (!BWD) {
           if (proc) {
             Sr = fma((double)Tj, (double)ctr, Sr);
             Si = fma((double)Tj, (double)cti, Si);
@@ -431,17 +484,38 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
           T = T * total;
           done = done || (T < a.t_min);
         } else {
-          const double wr = proc ? (double)Tj * (double)ctr : 0.0, wi_ = proc ? (double)Tj * (double)cti : 0.0;
-          double wr_in, wi_in, wr_tot, wi_tot;
+          // FP64 prefix of the hits' terms: T_j c~_j (one carrier), or the scalar
+          // T_j Re(conj(Ge_j) c~_j) (several), whose total the total pass left in Sfr
+          double wr = 0.0, wi_ = 0.0;
+          float Ger = 0.f, Gei = 0.f, Ge2r = 0.f, Ge2i = 0.f;
+          if constexpr (BMULTI) {
+            if (proc) {
+              float sd, cd;
+              const float4 g4 = geo[4];
+              sincos_rev(fmaf(-h.bA, g4.w, g4.z), sd, cd);
+              carrier_sums_n<kGcChunk>(sgc + r * kGcChunk, sd, cd, Ger, Gei, Ge2r, Ge2i);
+              wr = (double)Tj * (double)fmaf(Ger, ctr, Gei * cti);
+            }
+          } else if (proc) {
+            wr = (double)Tj * (double)ctr;
+            wi_ = (double)Tj * (double)cti;
+          }
+          double wr_in, wi_in = 0.0, wr_tot, wi_tot = 0.0;
           group_sum64<G>(wr, q, wr_in, wr_tot);
-          group_sum64<G>(wi_, q, wi_in, wi_tot);
+          if constexpr (!BMULTI) group_sum64<G>(wi_, q, wi_in, wi_tot);
           T = T * total;
           done = done || (T < a.t_min);
           if (__ballot(proc) != 0) {
             AdjHit ah{};
             if (proc) {
-              const float Rr = (float)(Sfr - (Pr + wr_in)), Ri = (float)(Sfi - (Pi + wi_in));
-              ah = adj_hit(h, geo, Tj, ctr, cti, Rr, Ri, Gr, Gi, vx, vy, vz, twopi_lam);
+              if constexpr (BMULTI) {
+                const float num = (float)(Sfr - (Pr + wr_in));
+                ah = adj_hit_multi(h, geo, Tj, ctr, cti, num, Ger, Gei, Ge2r, Ge2i, vx, vy, vz, twopi_lam,
+                                   twopi_dlam);
+              } else {
+                const float Rr = (float)(Sfr - (Pr + wr_in)), Ri = (float)(Sfi - (Pi + wi_in));
+                ah = adj_hit(h, geo, Tj, ctr, cti, Rr, Ri, Gr, Gi, vx, vy, vz, twopi_lam);
+              }
               sflag[j] = 1u;
             }
             // the slots in parts of 16, each reduced over the wave's rays before the next is formed
@@ -480,6 +554,13 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
     return;
   }
   if constexpr (COLLECT) return;
+  if constexpr (MTOT) {
+    double xr = Sr;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) xr += __shfl_xor(xr, d, G);
+    if (valid && q == 0) io.wtot[((size_t)k * a.n_el + v) * a.n_az + u] = xr;
+    return;
+  }
   if constexpr (!BWD) {
     if constexpr (G > 1) {   // the ray's total over its G lanes
 #pragma unroll

@@ -220,6 +220,22 @@ class Problem:
                                          *(o.data_ptr() for o in out), _stream_handle(stream)), "gsrf_render_bwd")
         return out
 
+    def render_bwd_multi(self, n_freq: int, freq_step_hz: float, grad_signal, grad_sum=None, out=None, stream=None):
+        """Adjoint of render_fwd_multi after render_fwd: grad_signal [P, n_freq, n_el, n_az, 2],
+        grad_sum [P, n_freq, 2] or None -> gradients summed over pairs and carriers."""
+        G, K = self.n_gauss, self.grid.K
+        if out is None:
+            e = lambda *s: torch.empty(s, dtype=torch.float32, device=self.device)
+            out = (e(G, 3), e(G, 3), e(G, 4), e(G), e(G, K, 2))
+        assert grad_signal.is_contiguous() and tuple(grad_signal.shape) == (
+            self.n_pairs, int(n_freq), self.grid.n_el, self.grid.n_az, 2)
+        gs = grad_sum.contiguous() if grad_sum is not None else None
+        check(_lib.lib().gsrf_render_bwd_multi(ctypes.byref(self._problem()), int(n_freq), float(freq_step_hz),
+                                               grad_signal.data_ptr(), gs.data_ptr() if gs is not None else None,
+                                               *(o.data_ptr() for o in out), _stream_handle(stream)),
+              "gsrf_render_bwd_multi")
+        return out
+
     def render_stats(self, stream=None) -> dict:
         """Counts of the forward traversal (instrumentation; run after prepare())."""
         c = torch.zeros(6, dtype=torch.int64, device=self.device)

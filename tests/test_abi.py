@@ -249,3 +249,20 @@ def test_tune_cache_round_trip(tmp_path):
     c.put(k, TuneResult(best=(8, 8, 0), seconds={(8, 4, 0): 0.024, (8, 8, 0): 0.019}))
     r = TuneCache(path).get(k)
     assert r.cached and r.best == (8, 8, 0) and r.seconds == {(8, 4, 0): 0.024, (8, 8, 0): 0.019}
+
+
+def test_multi_carrier_adjoint_validates_before_launching():
+    L = _lib.lib()
+    p, keep = _host_problem()
+    none8 = [None] * 8
+    assert L.gsrf_render_bwd_multi(ctypes.byref(p), 0, 1e6, *none8) == _lib.GSRF_EINVAL
+    assert "n_freq" in L.gsrf_last_error().decode()
+    assert L.gsrf_render_bwd_multi(ctypes.byref(p), 4097, 1e6, *none8) == _lib.GSRF_EINVAL
+    assert L.gsrf_render_bwd_multi(ctypes.byref(p), 4, float("nan"), *none8) == _lib.GSRF_EINVAL
+    p.grid.lanes_per_ray = 1
+    assert L.gsrf_render_bwd_multi(ctypes.byref(p), 4, 1e6, *none8) == _lib.GSRF_ENOTSUP
+    p.grid.lanes_per_ray = 0
+    p.grid.transmittance = 1
+    assert L.gsrf_render_bwd_multi(ctypes.byref(p), 4, 1e6, *none8) == _lib.GSRF_ENOTSUP
+    p.grid.transmittance = 0
+    assert L.gsrf_render_bwd_multi(ctypes.byref(p), 4, 1e6, *none8) == _lib.GSRF_EINVAL   # no workspace

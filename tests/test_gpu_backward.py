@@ -298,3 +298,100 @@ def test_paper_scale_gradients_full_cotangent_and_central_differences():
                 n_fd += 1
     say("  entries", n_ent, "worst err/scale", {n: f"{w:.1e}" for n, w in worst.items()}, "differences", n_fd)
     assert n_fd >= 0.9 * len(NAMES) * len(d["gaussians"])
+
+
+def _multi_reference(sc, pairs_scene, g, n_freq, step, Gm, gsum_m, ray_chunk=8):
+    """sum over carriers of the oracle's gradient at each carrier's frequency,
+    with the summed vjp_abs scale."""
+    ref = scale = None
+    for k, p in pairs_scene:
+        for c in range(n_freq):
+            pc = Pair(p.rx, p.tx, p.freq_hz + c * step)
+            gs = None if gsum_m is None else gsum_m[k, c]
+            r, s = oracle.vjp_abs(sc, pc, g, Gm[k, c].reshape(-1, 2), g_sum=gs, ray_chunk=ray_chunk)
+            ref = r if ref is None else {n: ref[n] + r[n] for n in NAMES}
+            scale = s if scale is None else {n: scale[n] + s[n] for n in NAMES}
+    return ref, scale
+
+
+@pytest.mark.parametrize("n_freq,step,tw,th", [(20, 10e6, 8, 8), (5, 312.5e3, 16, 8), (1, 0.0, 8, 4)])
+def test_multi_carrier_gradients_match_oracle_sum(n_freq, step, tw, th):
+    """gsrf_render_bwd_multi against the sum over carriers of the oracle's
+    gradient at each carrier frequency (20 carriers: two chunks of 16 and 4,
+    10 MHz apart so that the phases differ by whole turns across the room; an
+    OFDM block's 312.5 kHz spacing; one carrier), per tensor and per entry,
+    with dL/dS_hat per carrier."""
+    g = Grid(n_az=24, n_el=8, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=0)
+    rng = np.random.default_rng([103, n_freq])
+    sc = synth.draw_scene(rng, 800, (4.0, 4.0, 3.0), g.K)
+    p = Pair(np.array([2.0, 2.1, 1.0], np.float32), np.array([0.5, 3.0, 2.0], np.float32), 2.4e9)
+    prob = gpu_problem(Batch([sc], [p], g))
+    prob.forward()
+    torch.cuda.synchronize()
+    marg = oracle.render(sc, p, g)["marginal"]        # hit decisions do not depend on the carrier
+    R = g.n_az * g.n_el
+    Gm = synth.cotangent((1, n_freq, R), seed=31).astype(np.float64)
+    Gm[:, :, marg] = 0.0
+    gsum = synth.cotangent((1, n_freq), seed=32).astype(np.float64) * 0.1
+    Gdev = Gm.copy()
+    Gdev[:, :, marg] = -gsum[:, :, None, :]           # marginal rays: total cotangent zero as well
+    Gref = Gm.copy()
+    Gref[:, :, ~marg] += gsum[:, :, None, :]
+    say("multi-carrier gradients:", n_freq, "carriers", step, "Hz apart, tile", tw, th, int(marg.sum()), "marginal")
+    out = prob.render_bwd_multi(n_freq, step, torch.from_numpy(Gdev.reshape(1, n_freq, g.n_el, g.n_az, 2)
+                                                               .astype(np.float32)).cuda().contiguous(),
+                                torch.from_numpy(gsum.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    gg = {n: o.cpu().numpy().astype(np.float64) for n, o in zip(NAMES, out)}
+    ref, scale = _multi_reference(sc, [(0, p)], g, n_freq, step, Gref, None)
+    _compare(gg, ref, scale=scale)
+
+
+def test_multi_carrier_adjoint_of_one_carrier_equals_the_adjoint():
+    """One carrier through gsrf_render_bwd_multi and gsrf_render_bwd on the
+    same forward: the same gradient to rounding (entry by entry)."""
+    b = synth.tiny(n=1200)
+    sc, p, g = b.scenes[0], b.pairs[0], b.grid
+    prob = gpu_problem(b)
+    sig, _, _ = prob.forward()
+    G = torch.from_numpy(synth.cotangent((1, g.n_el, g.n_az), seed=41)).cuda()
+    one = prob.render_bwd(sig, G, None)
+    multi = prob.render_bwd_multi(1, 0.0, G.reshape(1, 1, g.n_el, g.n_az, 2).contiguous())
+    torch.cuda.synchronize()
+    for n, a, m in zip(NAMES, one, multi):
+        a, m = a.cpu().numpy().astype(np.float64), m.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(a - m) <= 1e-5 * np.abs(a).max() + 1e-6 * np.abs(a)), n
+
+
+def test_multi_carrier_gradients_in_a_multi_scene_batch():
+    """Three scenes, two pairs each at 2.4 / 5 / 5.8 GHz, 4 carriers 1 MHz
+    apart; cotangent on 12 sampled rays per pair and carrier."""
+    g = Grid(n_az=36, n_el=9, fle_L=2, tile_w=8, tile_h=8, lanes_per_ray=0)
+    rng = np.random.default_rng(77)
+    scenes = [synth.draw_scene(rng, n, (4.0, 4.0, 3.0), g.K) for n in (900, 1500, 400)]
+    pairs = []
+    for s, f in zip(range(3), (2.4e9, 5.0e9, 5.8e9)):
+        for _ in range(2):
+            pairs.append(Pair(rng.uniform([0.5, 0.5, 0.3], [3.5, 3.5, 2.7]).astype(np.float32),
+                              rng.uniform([0.5, 0.5, 0.3], [3.5, 3.5, 2.7]).astype(np.float32), f, scene=s))
+    b = Batch(scenes, pairs, g)
+    prob = gpu_problem(b)
+    prob.forward()
+    torch.cuda.synchronize()
+    n_freq, step, P, R = 4, 1e6, len(pairs), g.n_az * g.n_el
+    Gm = np.zeros((P, n_freq, R, 2))
+    for k, pr in enumerate(pairs):
+        marg = oracle.render(scenes[pr.scene], pr, g)["marginal"]
+        pick = rng.choice(np.nonzero(~marg)[0], size=12, replace=False)
+        Gm[k][:, pick] = synth.cotangent((n_freq, 12), seed=50 + k)
+    say("multi-carrier gradients, 3 scenes x 2 pairs, 4 carriers")
+    out = prob.render_bwd_multi(n_freq, step, torch.from_numpy(Gm.reshape(P, n_freq, g.n_el, g.n_az, 2)
+                                                               .astype(np.float32)).cuda().contiguous())
+    torch.cuda.synchronize()
+    gg = {n: o.cpu().numpy().astype(np.float64) for n, o in zip(NAMES, out)}
+    cat, offs = b.concat()
+    for s, sc in enumerate(scenes):
+        lo, hi = offs[s], offs[s + 1]
+        ref, scale = _multi_reference(sc, [(k, pr) for k, pr in enumerate(pairs) if pr.scene == s], g, n_freq, step,
+                                      Gm, None)
+        _compare({n: gg[n][lo:hi] for n in NAMES}, ref, scale=scale)
