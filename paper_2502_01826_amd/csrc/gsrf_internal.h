@@ -42,9 +42,10 @@ constexpr int kScanTiles = 1024;
 constexpr int ray_stride(int K) { return (4 + 2 * K + 3) / 4 * 4; }
 
 // Balanced expansion of the tile rectangles of a workgroup's RB records
-// (RB = 256 or 1024, one per thread): the rectangles' splat counts are scanned
-// and every thread takes splats s = tid, tid + RB, ..., locating the owning
-// record by binary search.
+// (RB = 256 or 1024, one per thread): the rectangles' splat counts are scanned;
+// then either every thread takes splats s = tid, tid + RB, ..., locating the
+// owning record by binary search (rect_splat), or each thread takes an equal run
+// of consecutive splats (rect_for_each).
 template <int RB>
 struct RectScan {
   ushort4 rect[RB];
@@ -75,10 +76,11 @@ __device__ __forceinline__ void rect_scan(RectScan<RB> &rs, ushort4 rc) {
   __syncthreads();
 }
 
-// splat s of the workgroup: owning record (thread slot) and its tile id
+// splat s of the workgroup: owning record (thread slot; the last record whose
+// offset is <= s) and its tile id
 template <int RB>
 __device__ __forceinline__ int rect_splat(const RectScan<RB> &rs, uint32_t s, int nta, int *tile) {
-  int pos = 0;                      // last record whose offset is <= s (off[0] = 0)
+  int pos = 0;
 #pragma unroll
   for (int step = RB / 2; step >= 1; step >>= 1)
     if (rs.off[pos + step] <= s) pos += step;
@@ -93,6 +95,43 @@ __device__ __forceinline__ int rect_splat(const RectScan<RB> &rs, uint32_t s, in
   if (tu >= nta) tu -= nta;
   *tile = tv * nta + tu;
   return pos;
+}
+
+// Every splat of the workgroup, f(s, record slot, tile id): thread tid takes the
+// contiguous splats [tid E, tid E + E), E = ceil(total / RB), finds the record
+// of its first splat by binary search (the last record whose offset is <= s)
+// and walks forward from there, stepping through the rectangle's columns and
+// rows and on to the next record with splats.
+template <int RB, typename F>
+__device__ __forceinline__ void rect_for_each(const RectScan<RB> &rs, uint32_t total, int nta, F f) {
+  const uint32_t E = (total + RB - 1) / RB;
+  uint32_t s = (uint32_t)threadIdx.x * E;
+  const uint32_t send = min(total, s + E);
+  if (s >= send) return;
+  int pos = 0;
+#pragma unroll
+  for (int step = RB / 2; step >= 1; step >>= 1)
+    if (rs.off[pos + step] <= s) pos += step;
+  uint32_t nxt = rs.off[pos + 1];
+  ushort4 rc = rs.rect[pos];
+  const uint32_t local = s - rs.off[pos];
+  const uint32_t q = (uint32_t)(((float)local + 0.5f) * rs.inv_ntu[pos]);   // (as in rect_splat)
+  int tv = rc.z + (int)q;
+  int cu = (int)(local - q * rc.y);
+  for (;;) {
+    int tu = rc.x + cu;
+    if (tu >= nta) tu -= nta;
+    f(s, pos, tv * nta + tu);
+    if (++s >= send) break;
+    if (s < nxt) {
+      if (++cu == (int)rc.y) { cu = 0; ++tv; }
+    } else {   // off[RB] = total > s ends the walk
+      do { ++pos; nxt = rs.off[pos + 1]; } while (nxt <= s);
+      rc = rs.rect[pos];
+      tv = rc.z;
+      cu = 0;
+    }
+  }
 }
 
 // Byte offsets of every workspace array plus derived sizes.

@@ -167,16 +167,21 @@ __global__ __launch_bounds__(256) void k_activate(const float *__restrict__ mean
 // ---------------------------------------------------------------------------
 #pragma clang fp contract(off)
 // Ray index ranges -> tile rectangle (integer tail shared by both evaluations).
-__device__ __forceinline__ ushort4 tile_rect(long v_lo, long v_hi, long u_lo, long u_hi, bool full, int n_az, int tw,
+// Tile sides are powers of two (the area is 32, 64, 128 or 256) and every
+// dividend below is non-negative (rows are clipped to the grid, and one turn
+// added to a negative first column makes it non-negative because the columns
+// span less than one and a half turns), so the tile indices are shifts.
+__device__ __forceinline__ ushort4 tile_rect(int v_lo, int v_hi, int u_lo, int u_hi, bool full, int n_az, int tw,
                                              int th, int32_t nta) {
   if (full) { u_lo = 0; u_hi = n_az - 1; }
   if (!((v_lo <= v_hi) && (full || u_hi >= u_lo))) return make_ushort4(0, 0, 0, 0);
   if (u_lo < 0) { u_lo += n_az; u_hi += n_az; }
-  long tu0 = u_lo / tw;
-  long ntu = (u_hi < n_az) ? (u_hi / tw - tu0 + 1) : ((nta - tu0) + (u_hi - n_az) / tw + 1);
+  const int sw = __builtin_ctz((unsigned)tw), sh = __builtin_ctz((unsigned)th);
+  int tu0 = u_lo >> sw;
+  int ntu = (u_hi < n_az) ? ((u_hi >> sw) - tu0 + 1) : ((nta - tu0) + ((u_hi - n_az) >> sw) + 1);
   if (ntu >= nta) { tu0 = 0; ntu = nta; }
-  const long tv0 = v_lo / th;
-  const long ntv = v_hi / th - tv0 + 1;
+  const int tv0 = v_lo >> sh;
+  const int ntv = (v_hi >> sh) - tv0 + 1;
   return make_ushort4((unsigned short)tu0, (unsigned short)ntu, (unsigned short)tv0, (unsigned short)ntv);
 }
 
@@ -220,11 +225,11 @@ __device__ __forceinline__ bool cap_rect_fp32(float ex, float ey, float ez, floa
   const float tolv = kFastAngTol / dbeta;
   if (near_int(xl, tolv + kFastRelTol * (fabsf(xl) + 1.f)) || near_int(xh, tolv + kFastRelTol * (fabsf(xh) + 1.f)))
     return false;
-  long v_lo = (long)ceilf(xl), v_hi = (long)floorf(xh);
+  int v_lo = (int)ceilf(xl), v_hi = (int)floorf(xh);
   if (v_lo < 0) v_lo = 0;
   if (v_hi > grid.n_el - 1) v_hi = grid.n_el - 1;
   bool full = (hi >= halfpi) || (lo <= -halfpi);
-  long u_lo = 0, u_hi = grid.n_az - 1;
+  int u_lo = 0, u_hi = grid.n_az - 1;
   if (!full) {
     const float cb = rho / D;                                    // cos(beta_c)
     if (cb < 0.2f) return false;
@@ -238,8 +243,8 @@ __device__ __forceinline__ bool cap_rect_fp32(float ex, float ey, float ez, floa
     const float tolu = kFastAngTol / dalpha;
     if (near_int(ul, tolu + kFastRelTol * (fabsf(ul) + 1.f)) || near_int(uh, tolu + kFastRelTol * (fabsf(uh) + 1.f)))
       return false;
-    u_lo = (long)ceilf(ul);
-    u_hi = (long)floorf(uh);
+    u_lo = (int)ceilf(ul);
+    u_hi = (int)floorf(uh);
     if (u_hi - u_lo + 1 >= grid.n_az) full = true;
   }
   *out = tile_rect(v_lo, v_hi, u_lo, u_hi, full, grid.n_az, grid.tile_w, grid.tile_h, nta);
@@ -284,7 +289,7 @@ __device__ __noinline__ ushort4 cap_rect_fp64(float mx, float my, float mz, floa
       if (u_hi - u_lo + 1 >= n_az) full = true;
     }
   }
-  return tile_rect(v_lo, v_hi, u_lo, u_hi, full, n_az, tw, th, nta);
+  return tile_rect((int)v_lo, (int)v_hi, (int)u_lo, (int)u_hi, full, n_az, tw, th, nta);
 }
 
 // The paper's footprint (Sec. 3.3, splatting), FP64, as a binning variant:
@@ -352,7 +357,8 @@ __device__ __noinline__ ushort4 footprint_rect_fp64(float mx, float my, float mz
   }
   const long v_lo = v_k - m < 0 ? 0 : v_k - m;
   const long v_hi = v_k + m > n_el - 1 ? n_el - 1 : v_k + m;
-  return tile_rect(v_lo, v_hi, u_k - m, u_k + m, full, n_az, tw, th, nta);
+  if (full) return tile_rect((int)v_lo, (int)v_hi, 0, n_az - 1, true, n_az, tw, th, nta);
+  return tile_rect((int)v_lo, (int)v_hi, (int)(u_k - m), (int)(u_k + m), false, n_az, tw, th, nta);
 }
 
 // One record: depth key (always FP64: bits of fp32(D^2), D^2 without FMA)
@@ -427,11 +433,7 @@ __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pa
   if (j < n) rec_rect[rec_base[k] + j] = rc;
   rect_scan(rs, rc);
   const uint32_t total = rs.off[RB];
-  for (uint32_t sp = threadIdx.x; sp < total; sp += RB) {
-    int t;
-    rect_splat(rs, sp, nta, &t);
-    atomicAdd(&hist[t], 1u);
-  }
+  rect_for_each(rs, total, nta, [&](uint32_t, int, int t) { atomicAdd(&hist[t], 1u); });
   __syncthreads();
   uint32_t *dst = tile_cnt + (size_t)((blockIdx.x >> sub_shift) % kSub) * PT + (size_t)k * T;
   for (int t = threadIdx.x; t < T; t += blockDim.x)

@@ -11,6 +11,8 @@
 // sub-buckets it makes (below), in LDS for buckets of up to `chunk` entries
 // and through global scratch for longer ones.  No workgroup ever waits on
 // another, so every wave finishes.
+#include <climits>
+
 #include "gsrf_internal.h"
 
 namespace gsrf {
@@ -104,12 +106,13 @@ __global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs
 // ---------------------------------------------------------------------------
 constexpr int kSortRegs = 8;              // entries per thread held in registers (LDS path)
 
-// Workgroup shapes: 1024 threads (any bucket; up to 2^11 sub-buckets) and 256
-// threads (buckets of at most 8 x 256 entries, held in registers; 2^9).
+// Workgroup shapes: 1024 threads (any bucket; up to 2^11 sub-buckets), 512
+// threads (buckets of at most 8 x 512 entries, held in registers; 2^10) and 256
+// threads (at most 8 x 256 entries; 2^9).
 template <int NT>
 struct SortShape {
   static constexpr int kWaves = NT / 64;
-  static constexpr int kBitsMax = NT >= 1024 ? 11 : 9;
+  static constexpr int kBitsMax = NT >= 1024 ? 11 : NT >= 512 ? 10 : 9;
   static constexpr int kBins = 1 << kBitsMax;
   static constexpr int kRedWords = 4 * kWaves;    // u64: wave min/max, totals, wave sums
 };
@@ -118,6 +121,10 @@ constexpr int kSortBitsMax = SortShape<kTileSortThreads>::kBitsMax;
 constexpr int kSortBins = SortShape<kTileSortThreads>::kBins;
 constexpr int kSmallSortThreads = 256;
 constexpr int kSmallSortMax = kSortRegs * kSmallSortThreads;   // 2048 entries
+constexpr int kMidSortThreads = 512;
+// 3840 of the 4096 entries the registers hold: with 2^10 sub-buckets the
+// workgroup's LDS stays under 40 KB, so four workgroups share a CU
+constexpr int kMidSortMax = 3840;
 
 __device__ __forceinline__ uint64_t composite(uint32_t k, uint32_t v) { return ((uint64_t)k << 32) | v; }
 
@@ -192,7 +199,7 @@ __device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint3
 // buffer bkv; SH: the buffer is in LDS, else in global memory and ranked
 // through the LDS window skv.
 template <int NT, bool SH, int REGS = kSortRegs>
-__device__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint2 *bkv, uint32_t *__restrict__ ok,
+__device__ __forceinline__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint2 *bkv, uint32_t *__restrict__ ok,
                               uint32_t *__restrict__ ov, uint32_t *hist, uint32_t *start, uint64_t *red, uint2 *skv,
                               int chunk) {
   constexpr int kSortWaves = SortShape<NT>::kWaves, kSortBitsMax = SortShape<NT>::kBitsMax;
@@ -397,11 +404,14 @@ __global__ __launch_bounds__(kTileSortThreads, 8) void k_tile_sort(const uint32_
   sort_bucket(ekv, s0, n, chunk, klo, val, tkv, hist, start, red, skv);
 }
 
-// a4 for launches with many tiles, in two kernels: one 256-thread workgroup
-// per tile sorts the buckets of at most 2048 entries (four times as many
-// workgroups per CU as the 1024-thread kernel, for the same waves), then a
-// fixed grid of 1024-thread workgroups sorts the longer ones: workgroup b
-// takes tiles b, b + grid, ..., finding the long ones 1024 tiles at a time.
+// a4 for launches with many tiles, in three kernels by bucket length: one
+// 256-thread workgroup per tile sorts the buckets of at most 2048 entries
+// (four times as many workgroups per CU as the 1024-thread kernel, for the same
+// waves); a fixed grid of 512-thread workgroups, four per CU, sorts those of
+// 2049-4096 entries, and a fixed grid of 1024-thread workgroups, two per CU,
+// the longer ones.  A bucket's sort is a chain of dependent steps (load,
+// extremes, histogram, scan, scatter, rank, store) that one workgroup cannot
+// overlap, so the shortest buckets get the most workgroups in flight.
 __global__ __launch_bounds__(kSmallSortThreads) void k_tile_sort_small(const uint32_t *__restrict__ tstart,
                                                                       const uint32_t *__restrict__ tend,
                                                                       const uint2 *__restrict__ ekv,
@@ -418,52 +428,91 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_tile_sort_small(const uin
   msd_rank_sort<NT, true>(ekv + s0, n, skv, klo + s0, val + s0, hist, start, red, skv, kSmallSortMax);
 }
 
-// Buckets longer than `lo` entries in a fixed grid: workgroup b takes tiles
-// b, b + grid, ..., finding its long ones 1024 tiles at a time.
-__global__ __launch_bounds__(kTileSortThreads, 8) void k_tile_sort_long(
-    const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend, int64_t PT, int lo, int chunk,
+// The tiles whose buckets hold lo < n <= hi entries, for a fixed grid:
+// workgroup b takes tiles b, b + grid, ..., finding them NT tiles at a time
+// (kept in tile order), and calls sort(start, n) for each.  `list` (NT words)
+// may share the sort's LDS: each thread keeps one list entry in a register
+// and hands it over through `bcast` when its turn comes.
+template <int NT, typename F>
+__device__ __forceinline__ void for_each_band_tile(const uint32_t *__restrict__ tstart,
+                                                   const uint32_t *__restrict__ tend, int64_t PT, int lo, int hi,
+                                                   uint32_t *list, uint32_t *n_list, uint32_t *bcast, F sort) {
+  constexpr int W = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t stride = gridDim.x;
+  for (int64_t k0 = 0; blockIdx.x + k0 * stride < PT; k0 += NT) {
+    const int64_t t = blockIdx.x + (k0 + tid) * stride;
+    const int n = t < PT ? (int)(tend[t] - tstart[t]) : 0;
+    const bool in = n > lo && n <= hi;
+    const uint64_t m = __ballot(in);
+    if (lane == 0) n_list[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t run = 0;
+      for (int w = 0; w < W; ++w) {
+        const uint32_t c = n_list[w];
+        n_list[w] = run;
+        run += c;
+      }
+      n_list[W] = run;
+    }
+    __syncthreads();
+    if (in) list[n_list[wave] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
+    __syncthreads();
+    const int cnt = (int)n_list[W];
+    const uint32_t mine = tid < cnt ? list[tid] : 0u;
+    __syncthreads();
+    for (int i = 0; i < cnt; ++i) {
+      if (tid == i) *bcast = mine;
+      __syncthreads();
+      const uint32_t tt = *bcast;
+      const uint32_t s0 = tstart[tt];
+      sort(s0, (int)(tend[tt] - s0));
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(kMidSortThreads) void k_tile_sort_mid(const uint32_t *__restrict__ tstart,
+                                                                  const uint32_t *__restrict__ tend,
+                                                                  const uint2 *__restrict__ ekv,
+                                                                  uint32_t *__restrict__ klo,
+                                                                  uint32_t *__restrict__ val) {
+  constexpr int NT = kMidSortThreads, NB = SortShape<NT>::kBins;
+  __shared__ uint64_t red[SortShape<NT>::kRedWords];
+  __shared__ uint32_t hist[NB], start[NB];
+  __shared__ uint2 skv[kMidSortMax];
+  const int gt = blockIdx.x;
+  const uint32_t s0 = tstart[gt];
+  const int n = (int)(tend[gt] - s0);
+  if (n <= kSmallSortMax || n > kMidSortMax) return;
+  msd_rank_sort<NT, true>(ekv + s0, n, skv, klo + s0, val + s0, hist, start, red, skv, kMidSortMax);
+}
+
+// The long buckets by 1024-thread workgroups: REGS = 8 (two workgroups per CU,
+// 64 VGPRs) for buckets up to that kernel's LDS chunk, REGS = 16 (one per CU,
+// a chunk of 16384 entries in 128 KB of LDS) for the longer ones, which beyond
+// the chunk go through global memory.
+template <int REGS>
+__global__ __launch_bounds__(kTileSortThreads, REGS == kSortRegs ? 8 : 4) void k_tile_sort_long(
+    const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend, int64_t PT, int lo, int hi, int chunk,
     const uint2 *__restrict__ ekv, uint32_t *__restrict__ klo, uint32_t *__restrict__ val, uint2 *__restrict__ tkv) {
   extern __shared__ uint64_t sm64[];
   uint64_t *red = sm64;
   uint32_t *hist = (uint32_t *)(sm64 + 4 * kSortWaves);
   uint32_t *start = hist + kSortBins;
   uint2 *skv = (uint2 *)(start + kSortBins);
-  __shared__ uint32_t list[kTileSortThreads];
-  __shared__ uint32_t n_list[kSortWaves + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t stride = gridDim.x;
-  for (int64_t k0 = 0; blockIdx.x + k0 * stride < PT; k0 += kTileSortThreads) {
-    // this block's next 1024 tiles: keep the long buckets, in tile order
-    const int64_t t = blockIdx.x + (k0 + tid) * stride;
-    const int n = t < PT ? (int)(tend[t] - tstart[t]) : 0;
-    const bool longb = n > lo;
-    const uint64_t m = __ballot(longb);
-    if (lane == 0) n_list[wave] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t run = 0;
-      for (int w = 0; w < kSortWaves; ++w) {
-        const uint32_t c = n_list[w];
-        n_list[w] = run;
-        run += c;
-      }
-      n_list[kSortWaves] = run;
-    }
-    __syncthreads();
-    if (longb) list[n_list[wave] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
-    __syncthreads();
-    const int cnt = (int)n_list[kSortWaves];
-    for (int i = 0; i < cnt; ++i) {
-      const uint32_t tt = list[i];
-      const uint32_t s0 = tstart[tt];
-      sort_bucket(ekv, s0, (int)(tend[tt] - s0), chunk, klo, val, tkv, hist, start, red, skv);
-      __syncthreads();
-    }
-  }
+  __shared__ uint32_t n_list[kSortWaves + 1], bcast;
+  // (the tile list shares the scatter buffer: chunk >= 1024 entries)
+  for_each_band_tile<kTileSortThreads>(tstart, tend, PT, lo, hi, (uint32_t *)skv, n_list, &bcast,
+                                       [&](uint32_t s0, int n) {
+    sort_bucket<REGS>(ekv, s0, n, chunk, klo, val, tkv, hist, start, red, skv);
+  });
 }
 
-static int g_sort_chunk = 0, g_long_chunk = 0, g_n_cu = 0;
-static size_t g_sort_lds = 0, g_long_lds = 0;
+static int g_sort_chunk = 0, g_long_chunk = 0, g_xl_chunk = 0, g_n_cu = 0;
+static size_t g_sort_lds = 0, g_long_lds = 0, g_xl_lds = 0;
+constexpr int kXlRegs = 16;
 
 size_t max_lds_per_block() {
   int dev = 0, v = 0;
@@ -493,11 +542,13 @@ static void set_lds(const void *f, size_t bytes) {
 
 static void choose_sort_chunk() {
   if (g_sort_chunk) return;
-  const size_t list_bytes = (size_t)4 * (kTileSortThreads + kSortWaves + 1);
+  const size_t list_bytes = (size_t)4 * (kSortWaves + 2);   // n_list, bcast
   g_sort_chunk = sort_chunk_for(0, 2, kSortRegs, &g_sort_lds);
   set_lds((const void *)k_tile_sort, g_sort_lds);
   g_long_chunk = sort_chunk_for(list_bytes, 2, kSortRegs, &g_long_lds);
-  set_lds((const void *)k_tile_sort_long, g_long_lds);
+  set_lds((const void *)k_tile_sort_long<kSortRegs>, g_long_lds);
+  g_xl_chunk = sort_chunk_for(list_bytes, 1, kXlRegs, &g_xl_lds);
+  set_lds((const void *)k_tile_sort_long<kXlRegs>, g_xl_lds);
   int dev = 0, n = 0;
   if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
       n > 0)
@@ -539,9 +590,13 @@ hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, h
   } else {
     hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)PT), dim3(kSmallSortThreads), 0, s, tstart, tend, ekv, klo,
                        val);
+    hipLaunchKernelGGL(k_tile_sort_mid, dim3((unsigned)PT), dim3(kMidSortThreads), 0, s, tstart, tend, ekv, klo, val);
     const int64_t grid = 2 * (int64_t)g_n_cu < PT ? 2 * (int64_t)g_n_cu : PT;   // two workgroups per CU
-    hipLaunchKernelGGL(k_tile_sort_long, dim3((unsigned)grid), dim3(kTileSortThreads), g_long_lds, s, tstart, tend,
-                       PT, kSmallSortMax, g_long_chunk, ekv, klo, val, tkv);
+    hipLaunchKernelGGL(k_tile_sort_long<kSortRegs>, dim3((unsigned)grid), dim3(kTileSortThreads), g_long_lds, s,
+                       tstart, tend, PT, kMidSortMax, g_long_chunk, g_long_chunk, ekv, klo, val, tkv);
+    const int64_t xgrid = (int64_t)g_n_cu < PT ? (int64_t)g_n_cu : PT;         // one workgroup per CU
+    hipLaunchKernelGGL(k_tile_sort_long<kXlRegs>, dim3((unsigned)xgrid), dim3(kTileSortThreads), g_xl_lds, s,
+                       tstart, tend, PT, g_long_chunk, INT_MAX, g_xl_chunk, ekv, klo, val, tkv);
   }
   return hipGetLastError();
 }

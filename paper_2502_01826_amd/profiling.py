@@ -100,7 +100,8 @@ def counter_table(dirs, kernels, ms) -> str:
         rate = None
         if flops is not None and name in ms:
             rate = flops / (ms[name] * 1e-3)
-        fma = (g("SQ_INSTS_VALU_FMA_F32") / g("SQ_INSTS_VALU")) if g("SQ_INSTS_VALU") else None
+        fma = (g("SQ_INSTS_VALU_FMA_F32") / g("SQ_INSTS_VALU")) \
+            if g("SQ_INSTS_VALU") and g("SQ_INSTS_VALU_FMA_F32") is not None else None
         conf = (g("SQ_LDS_BANK_CONFLICT") / g("SQ_INSTS_LDS")) if g("SQ_INSTS_LDS") else None
         busy = g("VALUBusy")
         util = g("VALUUtilization")

@@ -61,6 +61,43 @@ def gpu_lists(prob: Problem):
                 rec_key=rkey, rec_rect=rrect.reshape(-1, 4).astype(np.int64))
 
 
+def lists_from_rects(L: dict, nta: int, gauss_base):
+    """Every tile's expected sorted list, built on the host from the records'
+    rectangles and keys: each record (pair k, Gaussian j) lands in the tiles of
+    its rectangle (columns modulo nta); within a tile the entries are ordered by
+    (key, Gaussian index).  Returns (tile of each entry, key, Gaussian index),
+    tile-major.  gauss_base[k] is pair k's first Gaussian index."""
+    base, T = L["base"], L["T"]
+    R = int(base[-1])
+    rect = L["rec_rect"][:R]
+    cnt = rect[:, 1] * rect[:, 3]
+    rec = np.repeat(np.arange(R, dtype=np.int64), cnt)
+    first = np.repeat(np.cumsum(cnt) - cnt, cnt)
+    local = np.arange(rec.size, dtype=np.int64) - first
+    ntu = rect[rec, 1]
+    row, col = local // ntu, local % ntu
+    pair = np.searchsorted(base, rec, side="right") - 1
+    tile = pair * T + (rect[rec, 2] + row) * nta + (rect[rec, 0] + col) % nta
+    key = L["rec_key"][rec].astype(np.int64)
+    gid = np.asarray(gauss_base, np.int64)[pair] + (rec - base[pair])
+    order = np.lexsort((gid, key, tile))
+    return tile[order], key[order], gid[order]
+
+
+def assert_lists_complete(L: dict, nta: int, gauss_base):
+    """Every tile list (all tiles of all pairs) equals the host expansion of
+    the records' rectangles, entry for entry and in (key, Gaussian) order."""
+    tile, key, gid = lists_from_rects(L, nta, gauss_base)
+    PT = L["ts"].size
+    lens = L["te"] - L["ts"]
+    np.testing.assert_array_equal(lens, np.bincount(tile, minlength=PT))
+    idx = np.repeat(L["ts"], lens) + (np.arange(int(lens.sum()), dtype=np.int64) -
+                                      np.repeat(np.cumsum(lens) - lens, lens))
+    np.testing.assert_array_equal(L["klo"][idx].astype(np.int64), key)
+    np.testing.assert_array_equal(L["val"][idx].astype(np.int64), gid)
+    return lens
+
+
 def compare_rays(S_gpu, res, scene, pair, grid, tol=TOL, max_marginal_frac=0.03):
     """Per-ray check of GPU values against an oracle ``trace`` result.
 

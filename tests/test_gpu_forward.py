@@ -8,8 +8,8 @@ import torch
 import oracle
 import synth
 from synth import Batch, Grid, Pair, Scene
-from gpu_common import (TOL, compare_rays, gpu_forward, gpu_lists, gpu_problem, oracle_tile_members, params_of,
-                        say)
+from gpu_common import (TOL, assert_lists_complete, compare_rays, gpu_forward, gpu_lists, gpu_problem,
+                        oracle_tile_members, params_of, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -360,6 +360,13 @@ def test_large_batch_wide_workgroups_match_oracle():
     first[L["ts"][L["te"] > L["ts"]]] = True
     assert np.all(step_ok | first[1:])
     say("longest list", int((L["te"] - L["ts"]).max()))
+    # every list of every pair against the host expansion of the records'
+    # rectangles (all bucket-length tiers of the sort: up to 2048, 3840, the
+    # 2-per-CU chunk, 16384 entries and beyond)
+    lens = assert_lists_complete(L, g.n_az // g.tile_w + (g.n_az % g.tile_w > 0), [0] * 9)
+    say("list lengths per tier", [int(((lens > a) & (lens <= b_)).sum()) for a, b_ in
+                                  [(0, 2048), (2048, 3840), (3840, 7936), (7936, 16384), (16384, 1 << 30)]])
+    assert (lens > 16384).any() and ((lens > 2048) & (lens <= 3840)).any()
     for k in range(9):     # every record's key and cap rectangle, bit for bit
         p = b.pairs[k]
         np.testing.assert_array_equal(L["rec_key"][k * sc.n:(k + 1) * sc.n],
@@ -468,3 +475,45 @@ def test_paper_footprint_multi_carrier_forward():
         ok = ~ref["marginal"]
         err = np.abs(S[0, c].ravel() - ref["S"])
         assert np.all(err[ok] <= TOL * np.maximum(ref["A_uv"][ok], 1e-30)), (c, float(err[ok].max()))
+
+
+@pytest.mark.gpu
+def test_every_record_on_the_fp64_rectangle_matches_oracle():
+    """100k Gaussians 80-87 degrees above the receiver: cos(beta_c) < 0.2 and
+    the cap below the pole, so the FP32 screen decides none of them and every
+    record takes the FP64 evaluation (all 256 lanes of each projection
+    workgroup).  Every rectangle bit for bit against the oracle, every tile
+    list complete, and sampled rays near the zenith against the oracle."""
+    g = Grid(n_az=360, n_el=90, fle_L=2, tile_w=8, tile_h=8, lanes_per_ray=0)
+    rng = np.random.default_rng(23)
+    n = 100_000
+    rx = np.array([5.0, 4.0, 0.5], np.float32)
+    el = np.radians(rng.uniform(80.0, 87.0, n))
+    az = rng.uniform(0.0, 2 * np.pi, n)
+    d = rng.uniform(1.5, 2.5, n)
+    means = rx.astype(np.float64) + np.stack([d * np.cos(el) * np.cos(az), d * np.cos(el) * np.sin(az),
+                                              d * np.sin(el)], 1)
+    base = synth.draw_scene(rng, n, (1.0, 1.0, 1.0), g.K)
+    sc = Scene(means.astype(np.float32), np.log(rng.uniform(0.004, 0.008, (n, 3))).astype(np.float32),
+                     base.quats, base.logits, base.coeffs)
+    p = Pair(rx, np.array([2.0, 2.0, 1.5], np.float32), 5e9)
+    b = Batch([sc], [p], g)
+    # premise: not full (beta_c + theta below the pole) and cos(beta_c) < 0.2 for every record
+    e = sc.means.astype(np.float64) - rx
+    D = np.linalg.norm(e, axis=1)
+    Rb = 3.0 * np.exp(sc.log_scales.astype(np.float64).max(1))
+    bc = np.arctan2(e[:, 2], np.hypot(e[:, 0], e[:, 1]))
+    assert np.all(bc + np.arcsin(Rb / D) + 1e-4 < np.pi / 2) and np.all(np.cos(bc) < 0.2) and np.all(D > 1.2)
+    say("FP64 rectangles: 100k records near the pole")
+    prob = gpu_problem(b)
+    S, _, _ = gpu_forward(prob)
+    L = gpu_lists(prob)
+    assert L["overflow"] == 0
+    tu0, ntu, tv0, ntv, cm = oracle.cap_rects(sc.means, sc.log_scales, p.rx, g)
+    assert (ntu * ntv > 0).sum() > 90_000
+    np.testing.assert_array_equal(L["rec_rect"][~cm], np.stack([tu0, ntu, tv0, ntv], 1)[~cm])
+    say("records", n, "marginal", int(cm.sum()))
+    lens = assert_lists_complete(L, g.n_tiles_az, [0])
+    say("splats", int(lens.sum()))
+    uv = np.stack([rng.integers(0, g.n_az, 40), rng.integers(80, g.n_el, 40)], 1)
+    compare_rays(S[0][uv[:, 1], uv[:, 0]], oracle.trace(sc, p, g, uv), sc, p, g)
