@@ -95,6 +95,10 @@ struct TpIO {
   double *wtot;                   // per ray: sum_c Re(conj(G_c) S_c) of the chunk (total pass writes)
 };
 
+// LDS words of a masked pass's batch fill: entry count, first position left
+// over, per-wave counts (up to 4 waves), active-ray words (up to 8).
+constexpr int kFillWords = 16;
+
 // BCAP: largest staged batch (128).  Smaller batches waste fewer tests past
 // the rays' termination (the last batch is tested whole), larger ones need
 // fewer barriers.
@@ -102,6 +106,8 @@ template <int L, int R, int MODE, int BCAP>
 struct TpShape {
   static constexpr bool BWD = MODE == kTpBwd || MODE == kTpBwdMulti;     // adjoint (accumulators)
   static constexpr bool GC = MODE == kTpBwdMulti || MODE == kTpMultiTotal;   // carriers' dL/dS in LDS
+  // hit decisions taken from the forward's masks (adjoint, total pass, midpoint collect)
+  static constexpr bool MASKED = BWD || MODE == kTpCollect || MODE == kTpMultiTotal;
   static constexpr int K = (L + 1) * (L + 1);
   static constexpr int B = lds_batch(L, 256, BWD, BCAP);
   static constexpr int NACC = n_acc(L);
@@ -111,7 +117,8 @@ struct TpShape {
   // LDS: geometry, [TX legs], coefficients, [accumulators, flags], ray rows, union rows, done flags
   static constexpr size_t kLds = (size_t)B * (kGeo * 16 + 2 * K * 4) + (BWD ? (size_t)B * (16 + NACC * 4 + 4) : 0) +
                                  (size_t)R * MWS * 4 + (size_t)4 * MW * 4 + (size_t)R * 4 +
-                                 (GC ? (size_t)R * kGcChunk * 8 : 0);
+                                 (GC ? (size_t)R * kGcChunk * 8 : 0) +
+                                 (MASKED ? (size_t)(B * (MWR + 1) + kFillWords) * 4 : 0);
   static constexpr size_t lds() { return kLds < 256 * 8 ? 256 * 8 : kLds; }
 };
 
@@ -190,6 +197,91 @@ __device__ __forceinline__ unsigned phase1_tests(const RayMono &v, const float4 
   return n_test;
 }
 
+// The next batch of a pass that takes its hit decisions from the forward's
+// masks.  Only 5-10 % of a tile's list entries hit any of its rays (the binning
+// rectangles are conservative, and the rays are a sparse grid), so such a pass
+// stages only the entries whose forward mask has a bit on a ray still active:
+// the workgroup scans the list from `pos`, KS entries per thread per step, keeps
+// those entries in list order (their mask words in smw, Gaussian ids in sval) up
+// to B of them, and leaves `pos` at the first entry not taken.  The hits of every
+// ray are the same, in the same order, as over the whole list.  Returns the
+// batch's entry count (0: the list holds no further hit on an active ray).
+template <int R, int B, int MWR, int SPLIT>
+__device__ __forceinline__ int fill_masked(const RenderArgs &a, uint32_t &pos, uint32_t s1, int half,
+                                           const int *sdone, uint32_t *smw, uint32_t *sval, uint32_t *sfill) {
+  constexpr int NT = 256, KS = 4, W = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t *swc = sfill + 2, *sact = sfill + 2 + W;
+  {
+    const bool act = tid < R && !sdone[tid < R ? tid : 0];
+    const uint64_t bm = __ballot(act);
+    if (lane == 0 && 2 * wave < MWR) {
+      sact[2 * wave] = (uint32_t)bm;
+      if (2 * wave + 1 < MWR) sact[2 * wave + 1] = (uint32_t)(bm >> 32);
+    }
+  }
+  __syncthreads();
+  uint32_t act[MWR];
+#pragma unroll
+  for (int rb = 0; rb < MWR; ++rb) act[rb] = sact[rb];
+  int nb = 0;
+  while (nb < B && pos < s1) {   // (nb and pos stay uniform)
+    const uint32_t p0 = pos + (uint32_t)tid * KS;
+    uint32_t mw[KS][MWR], gv[KS], take = 0;
+#pragma unroll
+    for (int e = 0; e < KS; ++e) {
+      const uint32_t p = p0 + e;
+      gv[e] = 0u;
+      uint32_t any = 0u;
+#pragma unroll
+      for (int rb = 0; rb < MWR; ++rb) {
+        mw[e][rb] = p < s1 ? a.hitmask[(size_t)p * (MWR * SPLIT) + half * MWR + rb] : 0u;
+        any |= mw[e][rb] & act[rb];
+      }
+      if (p < s1) gv[e] = a.val[p];
+      if (any) take |= 1u << e;
+    }
+    const int c = __builtin_popcount(take);
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    if (lane == 63) swc[wave] = (uint32_t)incl;
+    __syncthreads();
+    int woff = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int x = (int)swc[w];
+      woff += w < wave ? x : 0;
+      tot += x;
+    }
+    int slot = nb + woff + incl - c;
+#pragma unroll
+    for (int e = 0; e < KS; ++e)
+      if ((take >> e) & 1u) {
+        if (slot < B) {
+#pragma unroll
+          for (int rb = 0; rb < MWR; ++rb) smw[slot * MWR + rb] = mw[e][rb];
+          sval[slot] = gv[e];
+        } else if (slot == B) {
+          sfill[1] = p0 + e;   // the first entry left for the next batch
+        }
+        ++slot;
+      }
+    __syncthreads();
+    if (nb + tot > B) {
+      pos = sfill[1];
+      nb = B;
+    } else {
+      pos += (uint32_t)(KS * NT);
+      nb += tot;
+    }
+  }
+  return nb;
+}
+
 // SPLIT = 2: the bin tile (2R rays) is rendered by two workgroups, each taking
 // R rays (the upper or lower half of the tile's rows) over the whole list;
 // forward launches with few tiles use it to double the waves in flight.  The
@@ -203,7 +295,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   constexpr bool BWD = SH::BWD, STATS = MODE == kTpFwdStats, MULTI = FC > 1;
   constexpr bool COUNT = MODE == kTpCount, COLLECT = MODE == kTpCollect;
   constexpr bool GC = SH::GC, MTOT = MODE == kTpMultiTotal, BMULTI = MODE == kTpBwdMulti;
-  constexpr bool MASKED = BWD || COLLECT || MTOT;   // hit decisions from the forward's masks
+  constexpr bool MASKED = SH::MASKED;   // hit decisions from the forward's masks
   if constexpr (COLLECT)
     if (io.counters[3] != 0) return;           // records over capacity: the whole launch writes nothing
   constexpr int NT = TP::NT, G = TP::G, EP = TP::EP, RPW = TP::RPW;
@@ -219,6 +311,9 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   uint32_t *suni = smask + R * MWS;                         // [4][MW]
   int *sdone = (int *)(suni + 4 * MW);                      // [R]
   float2 *sgc = (float2 *)(sdone + R);                      // [R][kGcChunk] (several-carrier adjoint)
+  uint32_t *smw = (uint32_t *)(sgc + (GC ? R * kGcChunk : 0));   // [B][MWR] batch's mask words (masked passes)
+  uint32_t *sval = smw + B * SH::MWR;                             // [B] batch's Gaussian ids (masked passes)
+  uint32_t *sfill = sval + B;                                     // [kFillWords] batch fill state (masked passes)
   constexpr int MWR = SH::MWR;
   const int gt = blockIdx.x;                 // (pair, tile, half)
   const int gtile = gt / SPLIT, half = gt - gtile * SPLIT;
@@ -316,15 +411,24 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   }
   // each staging thread's list entry for the next batch is loaded one batch
   // ahead, so staging waits for one global round trip (the entry's records), not two
-  uint32_t g_next = (tid < B && s0 + tid < s1) ? a.val[s0 + tid] : 0u;
-  for (uint32_t base = s0; base < s1; base += B) {
-    const int nb = (int)min((uint32_t)B, s1 - base);
+  uint32_t g_next = (!MASKED && tid < B && s0 + tid < s1) ? a.val[s0 + tid] : 0u;
+  uint32_t base = s0;   // the batch's first list entry (masked passes: the next entry to scan)
+  while (true) {
+    int nb;
+    if constexpr (MASKED) {
+      __syncthreads();
+      nb = fill_masked<R, B, MWR, SPLIT>(a, base, s1, half, sdone, smw, sval, sfill);
+      if (nb == 0) break;
+    } else {
+      if (base >= s1) break;
+      nb = (int)min((uint32_t)B, s1 - base);
+    }
     __syncthreads();
-    const uint32_t g_cur = g_next;
+    const uint32_t g_cur = MASKED ? (tid < nb ? sval[tid] : 0u) : g_next;
     if (tid < nb)
       stage_entry<K, MULTI || GC, VAR>(a, g_cur, pr.rx[0], pr.rx[1], pr.rx[2], pr.tx[0], pr.tx[1], pr.tx[2], inv_lam,
                                  sgeo + kGeo * tid, scf + 2 * K * tid, BWD ? stx + tid : nullptr, step_rev);
-    if (tid < B && base + B + tid < s1) g_next = a.val[base + B + tid];
+    if (!MASKED && tid < B && base + B + tid < s1) g_next = a.val[base + B + tid];
     if constexpr (BWD)
       for (int i = tid; i < nb; i += NT) {   // what the previous batch's flush left
         sflag[i] = 0u;
@@ -371,7 +475,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       for (int blk = (tid >> 5); blk < NBLK; blk += NT / 32) {
         const int rb = blk / MW, w = blk - rb * MW;
         const int j = w * 32 + hl;
-        const uint32_t m = j < nb ? a.hitmask[(size_t)(base + j) * (MWR * SPLIT) + half * MWR + rb] : 0u;
+        const uint32_t m = j < nb ? smw[j * MWR + rb] : 0u;
         const uint32_t row = transpose32(m, hl);
         const int rr = rb * 32 + hl;
         smask[rr * MWS + w] = sdone[rr] ? 0u : row;
@@ -548,6 +652,7 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       flush_batch<K, NT>(nb, sacc, sflag, stx, io.acc, io.acc_stride);
     }
     if (__syncthreads_and(done ? 1 : 0)) break;
+    if constexpr (!MASKED) base += B;
   }
   if constexpr (COUNT) {
     if (e == 0 && valid1) io.ray_cnt[((size_t)k * a.n_el + v1) * a.n_az + u1] = n_ray_hits;
