@@ -133,6 +133,7 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.tile_sum = take((size_t)PT * 2 * 8);   // per render workgroup: up to two per tile
   L.grad_acc = take((size_t)G * L.acc_stride * 4);
   L.hitmask = take(g.lanes_per_ray == 0 ? (size_t)L.cap * (size_t)(g.tile_w * g.tile_h / 32) * 4 : 0);
+  L.mask_end = take(g.lanes_per_ray == 0 ? (size_t)PT * (size_t)(g.tile_w * g.tile_h / 32) * 4 : 0);
   L.sig64 = take((size_t)p->n_pairs * g.n_az * g.n_el * 16);
   L.wtot = take(g.lanes_per_ray == 0 ? (size_t)p->n_pairs * g.n_az * g.n_el * 8 : 0);
   L.rays = take((size_t)g.n_az * g.n_el * ray_stride(L.K) * 4);

@@ -144,6 +144,7 @@ struct Layout {
   size_t tkv;             // sort scratch for buckets longer than the LDS chunk: (key, id) pairs
   size_t tile_sum, grad_acc;
   size_t hitmask;         // two-phase traversal: per splat, tile-area / 32 words of forward hit bits
+  size_t mask_end;        // two-phase traversal: per (pair, tile, 32-ray block), the end of the masks written
   size_t sig64;           // [P][n_el * n_az] double2: the forward's S in FP64, read by the adjoint
   size_t wtot;            // [P][n_el * n_az] double: the several-carrier adjoint's per-ray totals
   size_t rays;            // [n_el * n_az][ray_stride(K)] ray directions and FLE basis (FP32)

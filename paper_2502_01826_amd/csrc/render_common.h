@@ -33,6 +33,8 @@ struct RenderArgs {
   const uint32_t *tend;     // [P*T]
   uint32_t *hitmask;        // [splats][R / 32]: per list entry, its hits over the tile's rays (two-phase
                             // traversal: written by the forward, read by the adjoint)
+  uint32_t *mask_end;       // [P*T][area / 32]: per 32-ray block of a tile, the end of the list prefix whose
+                            // masks the forward wrote (it stops once all its rays have terminated)
   const float *rays;        // [n_el * n_az][ray_stride(K)] ray table made by gsrf_project
   const float *logits;      // [G] opacity logits (the chord transmittance's attenuation coefficient)
   int32_t T, nta, n_az, n_el, tw;

@@ -216,6 +216,7 @@ RenderArgs make_render_args(const gsrf_problem *p, const Layout &lay, char *ws) 
   a.tstart = (const uint32_t *)(ws + lay.tile_start);
   a.tend = (const uint32_t *)(ws + lay.tile_end);
   a.hitmask = (uint32_t *)(ws + lay.hitmask);
+  a.mask_end = (uint32_t *)(ws + lay.mask_end);
   a.rays = (const float *)(ws + lay.rays);
   a.logits = p->opacity_logits;
   a.fle_g = p->grid.fle_eval;

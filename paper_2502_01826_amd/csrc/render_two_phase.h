@@ -204,11 +204,14 @@ __device__ __forceinline__ unsigned phase1_tests(const RayMono &v, const float4 
 // the workgroup scans the list from `pos`, KS entries per thread per step, keeps
 // those entries in list order (their mask words in smw, Gaussian ids in sval) up
 // to B of them, and leaves `pos` at the first entry not taken.  The hits of every
-// ray are the same, in the same order, as over the whole list.  Returns the
-// batch's entry count (0: the list holds no further hit on an active ray).
+// ray are the same, in the same order, as over the whole list.  Masks past the
+// forward's end for a ray block (mend, at most s1) count as empty: the forward
+// stops once all its rays have terminated and writes no masks beyond.  Returns
+// the batch's entry count (0: the list holds no further hit on an active ray).
 template <int R, int B, int MWR, int SPLIT>
-__device__ __forceinline__ int fill_masked(const RenderArgs &a, uint32_t &pos, uint32_t s1, int half,
-                                           const int *sdone, uint32_t *smw, uint32_t *sval, uint32_t *sfill) {
+__device__ __forceinline__ int fill_masked(const RenderArgs &a, uint32_t &pos, uint32_t s1, const uint32_t *mend,
+                                           int half, const int *sdone, uint32_t *smw, uint32_t *sval,
+                                           uint32_t *sfill) {
   constexpr int NT = 256, KS = 4, W = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t *swc = sfill + 2, *sact = sfill + 2 + W;
@@ -235,7 +238,7 @@ __device__ __forceinline__ int fill_masked(const RenderArgs &a, uint32_t &pos, u
       uint32_t any = 0u;
 #pragma unroll
       for (int rb = 0; rb < MWR; ++rb) {
-        mw[e][rb] = p < s1 ? a.hitmask[(size_t)p * (MWR * SPLIT) + half * MWR + rb] : 0u;
+        mw[e][rb] = p < mend[rb] ? a.hitmask[(size_t)p * (MWR * SPLIT) + half * MWR + rb] : 0u;
         any |= mw[e][rb] & act[rb];
       }
       if (p < s1) gv[e] = a.val[p];
@@ -413,11 +416,20 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   // ahead, so staging waits for one global round trip (the entry's records), not two
   uint32_t g_next = (!MASKED && tid < B && s0 + tid < s1) ? a.val[s0 + tid] : 0u;
   uint32_t base = s0;   // the batch's first list entry (masked passes: the next entry to scan)
+  uint32_t mend[MASKED ? MWR : 1];   // masked passes: the forward's end per ray block, at most s1
+  uint32_t s1m = s0;
+  if constexpr (MASKED) {
+#pragma unroll
+    for (int rb = 0; rb < MWR; ++rb) {
+      mend[rb] = min(s1, a.mask_end[(size_t)gtile * (MWR * SPLIT) + half * MWR + rb]);
+      s1m = max(s1m, mend[rb]);
+    }
+  }
   while (true) {
     int nb;
     if constexpr (MASKED) {
       __syncthreads();
-      nb = fill_masked<R, B, MWR, SPLIT>(a, base, s1, half, sdone, smw, sval, sfill);
+      nb = fill_masked<R, B, MWR, SPLIT>(a, base, s1m, mend, half, sdone, smw, sval, sfill);
       if (nb == 0) break;
     } else {
       if (base >= s1) break;
@@ -651,8 +663,14 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
       __syncthreads();
       flush_batch<K, NT>(nb, sacc, sflag, stx, io.acc, io.acc_stride);
     }
-    if (__syncthreads_and(done ? 1 : 0)) break;
+    if (__syncthreads_and(done ? 1 : 0)) {
+      if constexpr (!MASKED) base += (uint32_t)nb;
+      break;
+    }
     if constexpr (!MASKED) base += B;
+  }
+  if constexpr (MODE == kTpFwd || COUNT) {   // the end of the masks written, per ray block
+    if (tid < MWR) a.mask_end[(size_t)gtile * (MWR * SPLIT) + half * MWR + tid] = min(base, s1);
   }
   if constexpr (COUNT) {
     if (e == 0 && valid1) io.ray_cnt[((size_t)k * a.n_el + v1) * a.n_az + u1] = n_ray_hits;

@@ -395,3 +395,32 @@ def test_multi_carrier_gradients_in_a_multi_scene_batch():
         ref, scale = _multi_reference(sc, [(k, pr) for k, pr in enumerate(pairs) if pr.scene == s], g, n_freq, step,
                                       Gm, None)
         _compare({n: gg[n][lo:hi] for n in NAMES}, ref, scale=scale)
+
+
+@pytest.mark.parametrize("tw,th", [(8, 8), (16, 8)])
+def test_workspace_contents_do_not_matter(tw, th):
+    """The workspace filled with 0xFF bytes before the step gives the same
+    signal (bit for bit) and gradients (to the rounding of the accumulators'
+    atomic adds, whose order varies from run to run) as a zeroed one.  At paper
+    scale the forward stops most tiles once all their rays have terminated,
+    leaving the rest of the list's hit masks unwritten; the adjoints (one
+    carrier and several) must not read them."""
+    g = Grid(n_az=360, n_el=90, fle_L=2, tile_w=tw, tile_h=th, lanes_per_ray=0)
+    b = synth.paper_scale(grid=g)
+    prob = gpu_problem(b)
+    P = 1
+    G = torch.from_numpy(synth.cotangent((P, g.n_el, g.n_az), seed=51)).cuda()
+    Gm = torch.from_numpy(synth.cotangent((P, 3, g.n_el, g.n_az), seed=52)).cuda()
+    runs = []
+    for fill in (0, 255):
+        prob.ws.fill_(fill)
+        sig, ssum, _ = prob.forward()
+        one = prob.render_bwd(sig, G, None)
+        multi = prob.render_bwd_multi(3, 312.5e3, Gm)
+        torch.cuda.synchronize()
+        runs.append([t.clone() for t in (sig, ssum, *one, *multi)])
+    say("workspace fill: 0 and 0xFF, tile", tw, th)
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    for a, c in zip(runs[0][2:], runs[1][2:]):
+        a, c = a.cpu().numpy().astype(np.float64), c.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(a - c) <= 1e-5 * np.abs(a).max() + 1e-5 * np.abs(a))
