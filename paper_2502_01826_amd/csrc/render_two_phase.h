@@ -742,10 +742,20 @@ __global__ __launch_bounds__(256) void k_render_tp(RenderArgs a, TpIO io) {
   }
 }
 
+// Launches of at most this many (pair, tile) units hold their adjoint
+// workgroups to two per CU (by their LDS request).  Otherwise all of them fit
+// at once (three waves per SIMD), three to some CUs and two to the rest, and
+// the CUs with three finish last; with two per CU the remaining workgroups
+// start wherever a CU frees first (the benchmark's 540 tiles: 104 -> 98 us).
+constexpr int64_t kAdjPairedBlocks = 2048;
+constexpr size_t kLdsPerCu = 160 * 1024;
+
 template <int L, int R, int MODE, int BCAP, int SPLIT, bool VAR = false>
 hipError_t tp_launch(const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
-  constexpr size_t lds = TpShape<L, R, MODE, BCAP>::lds();
-  if constexpr (lds > 65536) {   // high FLE degrees: opt in to more than 64 KB of LDS
+  constexpr size_t lds0 = TpShape<L, R, MODE, BCAP>::lds();
+  const size_t lds = (TpShape<L, R, MODE, BCAP>::BWD && nblocks <= kAdjPairedBlocks && lds0 <= kLdsPerCu / 3)
+                         ? kLdsPerCu / 3 + 256 : lds0;
+  if (lds > 65536) {   // high FLE degrees: opt in to more than 64 KB of LDS
     const hipError_t e = hipFuncSetAttribute((const void *)k_render_tp<L, R, MODE, BCAP, SPLIT, VAR>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
