@@ -195,6 +195,9 @@ __device__ __forceinline__ ushort4 tile_rect(int v_lo, int v_hi, int u_lo, int u
 // 20 times below the tolerance), so an accepted result equals the FP64 one;
 // otherwise the caller evaluates the FP64 definition (about 1 % of records).
 constexpr float kFastAngTol = 2e-5f;
+constexpr double kCosSlack = 0.99999999995;           // cos(kCapSlack)
+constexpr double kSinSlack = 9.9999999998333333e-06;  // sin(kCapSlack)
+static_assert(kCapSlack == 1e-5, "kCosSlack and kSinSlack are cos and sin of kCapSlack");
 constexpr float kFastRelTol = 2e-6f;
 
 __device__ __forceinline__ bool near_int(float x, float tol) { return fabsf(x - rintf(x)) <= tol; }
@@ -251,8 +254,12 @@ __device__ __forceinline__ bool cap_rect_fp32(float ex, float ey, float ez, floa
   return true;
 }
 
-// FP64 evaluation of the rectangle, in the operation order documented above
-// (scalar arguments: not inlined, and nothing of the caller's needs memory).
+// FP64 evaluation of the rectangle, in the operation order documented above,
+// except that sin(theta) and cos(beta_c) come from identities instead of two
+// more transcendental calls: sin(asin(x) + s) = x cos s + sqrt(1 - x^2) sin s and
+// cos(atan2(e_z, rho)) = rho / D (FP64 differences ~1e-16, far inside the 1e-9
+// band within which a decision counts as marginal).  Scalar arguments: not
+// inlined, and nothing of the caller's needs memory.
 __device__ __noinline__ ushort4 cap_rect_fp64(float mx, float my, float mz, float rx, float ry, float rz, float lmaxf,
                                               int n_az, int n_el, float el_lo_f, float el_hi_f, float r_rx, int tw,
                                               int th, int32_t nta) {
@@ -271,8 +278,10 @@ __device__ __noinline__ ushort4 cap_rect_fp64(float mx, float my, float mz, floa
   if (inside) {
     v_lo = 0; v_hi = n_el - 1; full = true;
   } else {
-    const double theta = asin(fmin(Rb / D, 1.0)) + kCapSlack;
-    const double bc = atan2(ez, sqrt(ex * ex + ey * ey));
+    const double sr = fmin(Rb / D, 1.0);
+    const double theta = asin(sr) + kCapSlack;
+    const double rho = sqrt(ex * ex + ey * ey);
+    const double bc = atan2(ez, rho);
     const double lo = bc - theta, hi = bc + theta;
     const double dbeta = (el_hi - el_lo) / n_el;
     v_lo = (long)ceil((lo - el_lo) / dbeta - 0.5);
@@ -283,7 +292,8 @@ __device__ __noinline__ ushort4 cap_rect_fp64(float mx, float my, float mz, floa
     if (!full) {
       const double dalpha = 2.0 * pi / n_az;
       const double ac = atan2(ey, ex);
-      const double da = asin(fmin(sin(theta) / cos(bc), 1.0));
+      const double sin_theta = sr * kCosSlack + sqrt(1.0 - sr * sr) * kSinSlack;
+      const double da = asin(fmin(sin_theta / (rho / D), 1.0));
       u_lo = (long)ceil((ac - da) / dalpha - 0.5);
       u_hi = (long)floor((ac + da) / dalpha - 0.5);
       if (u_hi - u_lo + 1 >= n_az) full = true;
