@@ -120,32 +120,48 @@ __global__ __launch_bounds__(NT) void k_render_fwd(RenderArgs a, float2 *__restr
 }
 
 
-// a6: S_hat per pair (tiles summed in fixed order, FP64) and RSSI in dBm.
-__global__ void k_rssi(const float2 *__restrict__ tile_sum, int32_t T, float *__restrict__ signal_sum,
-                       float *__restrict__ rssi) {
-  __shared__ double sr[256], si[256];
-  const int k = blockIdx.x;
+// a6: S_hat per pair (tiles summed in fixed order, FP64) and RSSI in dBm: thread t
+// takes partials t, t + 256, ... (four loads in flight), then wave butterflies and
+// the four wave totals in wave order.
+__global__ __launch_bounds__(256) void k_rssi(const float2 *__restrict__ tile_sum, int32_t T,
+                                              float *__restrict__ signal_sum, float *__restrict__ rssi) {
+  __shared__ double wr[4], wi[4];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const float2 *src = tile_sum + (size_t)k * T;
   double a = 0.0, b = 0.0;
-  for (int t = threadIdx.x; t < T; t += 256) {
-    const float2 v = tile_sum[(size_t)k * T + t];
-    a += v.x;
-    b += v.y;
+  int t = tid;
+  for (; t + 3 * 256 < T; t += 4 * 256) {
+    const float2 x0 = src[t], x1 = src[t + 256], x2 = src[t + 512], x3 = src[t + 768];
+    a += (double)x0.x;
+    b += (double)x0.y;
+    a += (double)x1.x;
+    b += (double)x1.y;
+    a += (double)x2.x;
+    b += (double)x2.y;
+    a += (double)x3.x;
+    b += (double)x3.y;
   }
-  sr[threadIdx.x] = a;
-  si[threadIdx.x] = b;
+  for (; t < T; t += 256) {
+    const float2 v = src[t];
+    a += (double)v.x;
+    b += (double)v.y;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    a += __shfl_xor(a, d, 64);
+    b += __shfl_xor(b, d, 64);
+  }
+  if ((tid & 63) == 0) {
+    wr[tid >> 6] = a;
+    wi[tid >> 6] = b;
+  }
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      sr[threadIdx.x] += sr[threadIdx.x + off];
-      si[threadIdx.x] += si[threadIdx.x + off];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    signal_sum[2 * k] = (float)sr[0];
-    signal_sum[2 * k + 1] = (float)si[0];
+  if (tid == 0) {
+    const double sr = (wr[0] + wr[1]) + (wr[2] + wr[3]), si = (wi[0] + wi[1]) + (wi[2] + wi[3]);
+    signal_sum[2 * k] = (float)sr;
+    signal_sum[2 * k + 1] = (float)si;
     if (rssi) {
-      const double pw = sr[0] * sr[0] + si[0] * si[0];
+      const double pw = sr * sr + si * si;
       rssi[k] = pw > 0.0 ? (float)(10.0 * log10(pw)) : -INFINITY;
     }
   }
