@@ -384,15 +384,20 @@ __device__ __forceinline__ bool project_record_fast(const gsrf_pair &pr, float4 
   return cap_rect_fp32((float)ex, (float)ey, (float)ez, sqrtf((float)D2), Rb, grid, nta, rect);
 }
 
-// Workgroup = RB consecutive records of one pair; per-tile counts gathered
-// in LDS by a balanced expansion of the rectangles, then one atomic per
-// touched tile on the workgroup's sub-bucket counter.
-// The sub-bucket of a record is (record index / emit's workgroup size) % kSub,
-// so this kernel's workgroups (RB records) count into the sub-bucket from
-// which emit's workgroup of the same records later reserves: sub_shift =
-// log2(emit workgroup / RB).
+// Workgroup = C chunks of RB consecutive records of one pair (C = 1, or 4 for
+// large batches, where emit's workgroup takes 4 x 256 records and so shares
+// one sub-bucket with all four): each chunk's keys and rectangles in FP32, then
+// one FP64 pass, packed onto the first lanes, for every record of the C chunks
+// that the FP32 evaluation could not decide (about 1 %: nearly every 256-record
+// chunk has one, so evaluating them chunk by chunk cost a whole wave pass per
+// chunk); then per chunk a balanced expansion of the rectangles into the
+// per-tile counts in LDS, and one atomic per touched tile on the workgroup's
+// sub-bucket counter.  The sub-bucket of a record is (record index / emit's
+// workgroup size) % kSub, so this kernel counts into the sub-bucket from which
+// emit's workgroup of the same records later reserves: sub_shift =
+// log2(emit workgroup / (C RB)).
 // FOOT: bin by the paper's footprint (grid.footprint = 1) instead of the cap.
-template <int RB, bool FOOT>
+template <int RB, bool FOOT, int C = 1>
 __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pairs,
                                                  const int64_t *__restrict__ scene_off,
                                                  const int64_t *__restrict__ rec_base, const float *__restrict__ prep,
@@ -402,27 +407,31 @@ __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pa
                                                  ushort4 *__restrict__ rec_rect, uint32_t *__restrict__ tile_cnt) {
   extern __shared__ uint32_t hist[];   // [T]
   __shared__ RectScan<RB> rs;
-  __shared__ ushort4 rects[RB];
-  __shared__ int fallback[RB];
+  __shared__ ushort4 rects[C * RB];
+  __shared__ int fallback[C * RB];
   __shared__ int n_fallback;
   const int k = blockIdx.y;
-  for (int t = threadIdx.x; t < T; t += blockDim.x) hist[t] = 0;
-  if (threadIdx.x == 0) n_fallback = 0;
   const gsrf_pair pr = pairs[k];
   const int64_t g0 = scene_off[pr.scene];
   const int64_t n = scene_off[pr.scene + 1] - g0;
-  const int64_t j0 = (int64_t)blockIdx.x * RB;
-  const int64_t j = j0 + threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * (C * RB);   // the workgroup's first record
+  if (C > 1 && j0 >= n) return;                        // (uniform)
+  for (int t = threadIdx.x; t < T; t += blockDim.x) hist[t] = 0;
+  if (threadIdx.x == 0) n_fallback = 0;
   __syncthreads();
-  ushort4 rc = make_ushort4(0, 0, 0, 0);
-  if (j < n) {
-    uint32_t key;
-    const float4 *pg = (const float4 *)(prep + (size_t)kPrep * (g0 + j));   // (mu, N) ... (3 max s, max log s)
-    if (!project_record_fast(pr, pg[0], pg[3].x, grid, nta, &key, &rc) || FOOT)
-      fallback[atomicAdd(&n_fallback, 1)] = threadIdx.x;
-    rec_key[rec_base[k] + j] = key;
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    const int64_t j = j0 + c * RB + threadIdx.x;
+    ushort4 rc = make_ushort4(0, 0, 0, 0);
+    if (j < n) {
+      uint32_t key;
+      const float4 *pg = (const float4 *)(prep + (size_t)kPrep * (g0 + j));   // (mu, N) ... (3 max s, max log s)
+      if (!project_record_fast(pr, pg[0], pg[3].x, grid, nta, &key, &rc) || FOOT)
+        fallback[atomicAdd(&n_fallback, 1)] = c * RB + threadIdx.x;
+      rec_key[rec_base[k] + j] = key;
+    }
+    rects[c * RB + threadIdx.x] = rc;
   }
-  rects[threadIdx.x] = rc;
   __syncthreads();
   // records the FP32 evaluation could not decide, packed onto the first lanes
   for (int i = threadIdx.x; i < n_fallback; i += RB) {
@@ -439,13 +448,17 @@ __global__ __launch_bounds__(RB) void k_project(const gsrf_pair *__restrict__ pa
                                 grid.el_lo, grid.el_hi, grid.r_rx, grid.tile_w, grid.tile_h, nta);
   }
   __syncthreads();
-  rc = rects[threadIdx.x];
-  if (j < n) rec_rect[rec_base[k] + j] = rc;
-  rect_scan(rs, rc);
-  const uint32_t total = rs.off[RB];
-  rect_for_each(rs, total, nta, [&](uint32_t, int, int t) { atomicAdd(&hist[t], 1u); });
-  __syncthreads();
-  uint32_t *dst = tile_cnt + (size_t)((blockIdx.x >> sub_shift) % kSub) * PT + (size_t)k * T;
+#pragma unroll 1
+  for (int c = 0; c < C; ++c) {
+    const int64_t j = j0 + c * RB + threadIdx.x;
+    const ushort4 rc = rects[c * RB + threadIdx.x];
+    if (j < n) rec_rect[rec_base[k] + j] = rc;
+    rect_scan(rs, rc);
+    const uint32_t total = rs.off[RB];
+    rect_for_each(rs, total, nta, [&](uint32_t, int, int t) { atomicAdd(&hist[t], 1u); });
+    __syncthreads();   // (the next chunk's scan rewrites rs)
+  }
+  uint32_t *dst = tile_cnt + (size_t)((((int64_t)blockIdx.x * C) >> sub_shift) % kSub) * PT + (size_t)k * T;
   for (int t = threadIdx.x; t < T; t += blockDim.x)
     if (hist[t]) atomicAdd(dst + t, hist[t]);
 }
@@ -598,6 +611,11 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
     if (p->grid.footprint)
       hipLaunchKernelGGL((k_project<256, true>), grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev,
                          rec_base, (const float *)prep, p->quats, p->log_scales, p->grid, lay.nta, lay.T, PT, sub_shift,
+                         (uint32_t *)(ws + lay.rec_key), (ushort4 *)(ws + lay.rec_rect), tile_cnt);
+    else if (lay.rec_block == 1024)   // four 256-record chunks per workgroup: emit's 1024 records
+      hipLaunchKernelGGL((k_project<256, false, 4>), dim3((unsigned)((lay.max_scene + 1023) / 1024), (unsigned)p->n_pairs),
+                         dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev, rec_base, (const float *)prep,
+                         p->quats, p->log_scales, p->grid, lay.nta, lay.T, PT, sub_shift,
                          (uint32_t *)(ws + lay.rec_key), (ushort4 *)(ws + lay.rec_rect), tile_cnt);
     else
       hipLaunchKernelGGL((k_project<256, false>), grid, dim3(256), (size_t)lay.T * 4, s, p->pairs, p->scene_offsets_dev,
