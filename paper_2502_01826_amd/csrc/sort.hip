@@ -404,14 +404,15 @@ __global__ __launch_bounds__(kTileSortThreads, 8) void k_tile_sort(const uint32_
   sort_bucket(ekv, s0, n, chunk, klo, val, tkv, hist, start, red, skv);
 }
 
-// a4 for launches with many tiles, in three kernels by bucket length: one
+// a4 for launches with many tiles, in four kernels by bucket length: one
 // 256-thread workgroup per tile sorts the buckets of at most 2048 entries
-// (four times as many workgroups per CU as the 1024-thread kernel, for the same
-// waves); a fixed grid of 512-thread workgroups, four per CU, sorts those of
-// 2049-4096 entries, and a fixed grid of 1024-thread workgroups, two per CU,
-// the longer ones.  A bucket's sort is a chain of dependent steps (load,
-// extremes, histogram, scan, scatter, rank, store) that one workgroup cannot
-// overlap, so the shortest buckets get the most workgroups in flight.
+// (seven per CU), one 512-thread workgroup per tile those of 2049-3840 (four
+// per CU), a fixed grid of 1024-thread workgroups with 8 entries per thread
+// (two per CU) those up to its LDS chunk, and a fixed grid of 1024-thread
+// workgroups with 16 entries per thread (one per CU) the longer ones.  A
+// bucket's sort is a chain of dependent steps (load, extremes, histogram,
+// scan, scatter, rank, store) that one workgroup cannot overlap, so the
+// shortest buckets get the most workgroups in flight.
 __global__ __launch_bounds__(kSmallSortThreads) void k_tile_sort_small(const uint32_t *__restrict__ tstart,
                                                                       const uint32_t *__restrict__ tend,
                                                                       const uint2 *__restrict__ ekv,
