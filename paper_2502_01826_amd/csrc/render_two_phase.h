@@ -198,9 +198,10 @@ __device__ __forceinline__ unsigned phase1_tests(const RayMono &v, const float4 
 }
 
 // The next batch of a pass that takes its hit decisions from the forward's
-// masks.  Only 5-10 % of a tile's list entries hit any of its rays (the binning
-// rectangles are conservative, and the rays are a sparse grid), so such a pass
-// stages only the entries whose forward mask has a bit on a ray still active:
+// masks.  About a third of the list entries the forward stages hit any of the
+// tile's rays (the binning rectangles are conservative boxes around caps, and
+// the rays are a sparse grid), so such a pass stages only the entries whose
+// forward mask has a bit on a ray still active:
 // the workgroup scans the list from `pos`, KS entries per thread per step, keeps
 // those entries in list order (their mask words in smw, Gaussian ids in sval) up
 // to B of them, and leaves `pos` at the first entry not taken.  The hits of every
@@ -781,10 +782,14 @@ template <int L, int MODE>
 hipError_t tp_dispatch(int area, const RenderArgs &a, const TpIO &io, int64_t nblocks, hipStream_t s) {
   if constexpr (MODE == kTpFwd || multi_chunk(MODE) > 1) {   // (the counters follow whole tiles, as the adjoint does)
     if (tp_split(area, nblocks, area / a.tw) == 2) {
+      // the split forward stages 256 entries per batch: fewer barriers at three
+      // workgroups per CU (LDS) beat more waves here (200k step: 59.7 -> 58.0 us),
+      // whereas launches with many tiles keep 128 (the 500k batch: 9.6 against 11.1 ms)
+      constexpr int BC = MODE == kTpFwd ? 256 : 128;
       switch (area) {
-        case 64: return tp_launch<L, 32, MODE, 128, 2>(a, io, nblocks, s);
-        case 128: return tp_launch<L, 64, MODE, 128, 2>(a, io, nblocks, s);
-        default: return tp_launch<L, 128, MODE, 128, 2>(a, io, nblocks, s);
+        case 64: return tp_launch<L, 32, MODE, BC, 2>(a, io, nblocks, s);
+        case 128: return tp_launch<L, 64, MODE, BC, 2>(a, io, nblocks, s);
+        default: return tp_launch<L, 128, MODE, BC, 2>(a, io, nblocks, s);
       }
     }
   }
