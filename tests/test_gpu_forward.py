@@ -517,3 +517,37 @@ def test_every_record_on_the_fp64_rectangle_matches_oracle():
     say("splats", int(lens.sum()))
     uv = np.stack([rng.integers(0, g.n_az, 40), rng.integers(80, g.n_el, 40)], 1)
     compare_rays(S[0][uv[:, 1], uv[:, 0]], oracle.trace(sc, p, g, uv), sc, p, g)
+
+
+def test_large_uneven_batch_binning_is_complete():
+    """Three scenes (1,000,000, 333,333 and 40,001 Gaussians, sizes not multiples
+    of the workgroups' 1024 records) and 7 pairs: 4.7 M records, so project takes
+    four 256-record chunks per workgroup (one FP64 rectangle pass for the four)
+    and emit 1024 records per workgroup, across scene boundaries.  Every record's
+    key and rectangle against the oracle and every tile list of every pair
+    against the host expansion of the rectangles."""
+    g = Grid(n_az=360, n_el=90, fle_L=2, tile_w=8, tile_h=8, lanes_per_ray=0)
+    rng = np.random.default_rng(31)
+    room = (10.0, 8.0, 3.0)
+    scenes = [synth.draw_scene(rng, n, room, g.K) for n in (1_000_000, 333_333, 40_001)]
+    pairs = [synth.draw_pair(rng, room, 5e9, scene=s) for s in (0, 0, 0, 0, 1, 1, 2)]
+    b = Batch(scenes, pairs, g)
+    say("large uneven batch: 3 scenes, 7 pairs")
+    prob = gpu_problem(b)
+    n_rec = sum(scenes[p.scene].n for p in pairs)
+    assert prob.layout().n_records == n_rec and n_rec >= (1 << 22)
+    S, _, _ = gpu_forward(prob)
+    L = gpu_lists(prob)
+    assert L["overflow"] == 0
+    offs = np.cumsum([0] + [s.n for s in scenes])
+    for k, p in enumerate(pairs):
+        sc = scenes[p.scene]
+        a, e = int(L["base"][k]), int(L["base"][k + 1])
+        np.testing.assert_array_equal(L["rec_key"][a:e], oracle.depth_key32(sc.means, p.rx).astype(np.uint32))
+        tu0, ntu, tv0, ntv, cm = oracle.cap_rects(sc.means, sc.log_scales, p.rx, g)
+        np.testing.assert_array_equal(L["rec_rect"][a:e][~cm], np.stack([tu0, ntu, tv0, ntv], 1)[~cm])
+    lens = assert_lists_complete(L, g.n_tiles_az, [int(offs[p.scene]) for p in pairs])
+    say("splats", int(lens.sum()), "longest list", int(lens.max()))
+    p = pairs[4]
+    uv = np.stack([rng.integers(0, g.n_az, 24), rng.integers(0, g.n_el, 24)], 1)
+    compare_rays(S[4][uv[:, 1], uv[:, 0]], oracle.trace(scenes[p.scene], p, g, uv), scenes[p.scene], p, g)
