@@ -215,7 +215,10 @@ gsrf_status gsrf_ray_hit_count(const gsrf_problem *p, int64_t *n_hits, void *str
  * ties broken by Gaussian index -- the order a sort of all splats by
  * (tile << 32 | depth key) would give.  If the splat count exceeds
  * splat_capacity the device-side overflow counter is set, every tile list is
- * left empty and renders give zeros; gsrf_splat_count reports it.
+ * left empty and renders give zeros; gsrf_splat_count reports it.  Each call
+ * consumes the emission cursors (and, for more than 2048 (pair, tile) units,
+ * the queue of long buckets) that the preceding gsrf_project left in the
+ * workspace, so every gsrf_bin_sort follows its own gsrf_project.
  */
 gsrf_status gsrf_bin_sort(const gsrf_problem *p, void *stream);
 

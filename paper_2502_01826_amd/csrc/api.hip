@@ -130,6 +130,7 @@ static gsrf_status plan(const gsrf_problem *p, Layout *lay, bool need_device) {
   L.klo = take((size_t)L.cap * 4);
   L.val = take((size_t)L.cap * 4);
   L.tkv = take((size_t)L.cap * 8);
+  L.long_q = take(PT > kSortFewTiles ? (size_t)kLongQueueHeader * 4 + (size_t)kLongClasses * PT * 8 : 0);
   L.tile_sum = take((size_t)PT * 2 * 8);   // per render workgroup: up to two per tile
   L.grad_acc = take((size_t)G * L.acc_stride * 4);
   L.hitmask = take(g.lanes_per_ray == 0 ? (size_t)L.cap * (size_t)(g.tile_w * g.tile_h / 32) * 4 : 0);

@@ -37,6 +37,26 @@ constexpr int64_t kBigBatchRecords = (int64_t)1 << 22;
 constexpr int kSub = 8;
 // Tiles per block of the three-pass tile-count scan (256 threads x 4).
 constexpr int kScanTiles = 1024;
+// Launches with more (pair, tile) units than this sort the buckets in tiers by
+// length (one workgroup per tile below that).
+constexpr int64_t kSortFewTiles = 2048;
+// Queue of the long buckets of a tiered sort.  The tile-range scan appends
+// each tile whose bucket holds more than thr[n] entries to the list of its
+// length class c (thr[c + 1] < entries <= thr[c], thr descending); the two
+// long-bucket sort kernels take classes [0, split) and [split, n), longest
+// class first, one bucket per atomic pop, so that no workgroup is left with
+// the heaviest buckets at the end.  Queue memory: kLongQueueHeader words
+// (class counts, then the pop counters of the two kernels), then
+// kLongClasses lists of P * T (bucket start, entries) pairs.
+constexpr int kLongClasses = 7;
+constexpr int kLongQueueHeader = 16;
+struct LongClasses {
+  int32_t n, split;
+  int32_t thr[kLongClasses + 1];
+  int32_t lo;   // thr[n]: the longest bucket left to the shorter tiers
+};
+// The classes for the device's sort chunks (sort.hip).
+LongClasses long_classes();
 // Ray table row (floats, 16-byte aligned): direction (3), pad, then the FLE
 // basis interleaved Yr_0, Yi_0, Yr_1, Yi_1, ... (2K).
 constexpr int ray_stride(int K) { return (4 + 2 * K + 3) / 4 * 4; }
@@ -142,6 +162,7 @@ struct Layout {
   size_t ekv;             // emitted buckets (unsorted): (depth key, Gaussian id) pairs
   size_t klo, val;        // sorted tile lists: depth key, Gaussian id
   size_t tkv;             // sort scratch for buckets longer than the LDS chunk: (key, id) pairs
+  size_t long_q;          // long-bucket queue of the tiered sort (P * T > kSortFewTiles only)
   size_t tile_sum, grad_acc;
   size_t hitmask;         // two-phase traversal: per splat, tile-area / 32 words of forward hit bits
   size_t mask_end;        // two-phase traversal: per (pair, tile, 32-ray block), the end of the masks written

@@ -114,9 +114,10 @@ __global__ __launch_bounds__(256) void k_activate(const float *__restrict__ mean
                                                   int64_t n_cnt, const gsrf_pair *__restrict__ pairs,
                                                   const int64_t *__restrict__ scene_off, int32_t P,
                                                   int64_t *__restrict__ rec_base, int n_az, int n_el, float el_lo,
-                                                  float el_hi, float *__restrict__ rays) {
+                                                  float el_hi, float *__restrict__ rays, uint32_t *__restrict__ long_q) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_cnt; i += stride) tile_cnt[i] = 0u;
+  if (long_q && blockIdx.x == 0 && threadIdx.x < kLongQueueHeader) long_q[threadIdx.x] = 0u;
   if (blockIdx.x == 0 && P > 0) rec_base_scan(pairs, scene_off, P, rec_base);
   const int64_t nb_g = (G + 255) / 256;
   if ((int64_t)blockIdx.x >= nb_g) {
@@ -528,10 +529,13 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
                                                     const int64_t *__restrict__ blk, int64_t cap,
                                                     int64_t *__restrict__ counters,
                                                     uint32_t *__restrict__ tstart, uint32_t *__restrict__ tend,
-                                                    uint32_t *__restrict__ tcur) {
+                                                    uint32_t *__restrict__ tcur, uint32_t *__restrict__ long_q,
+                                                    LongClasses lc) {
   __shared__ int64_t sh[256];
+  __shared__ uint32_t s_cls[kLongClasses], s_base[kLongClasses];
   constexpr int PER = kScanTiles / 256;
   const int tid = threadIdx.x;
+  if (tid < kLongClasses) s_cls[tid] = 0u;
   const int64_t t0 = (int64_t)blockIdx.x * kScanTiles + (int64_t)tid * PER;
   uint32_t cnt[PER][kSub];
   int64_t local = 0;
@@ -564,17 +568,45 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
       counters[1] = over ? total : 0;
     }
   }
+  const int64_t run0 = run;
+  int cls[PER];
+  uint32_t lpos[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) cls[i] = -1;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int64_t t = t0 + i;
     if (t >= PT) break;
     tstart[t] = over ? 0u : (uint32_t)run;
+    const int64_t r0 = run;
 #pragma unroll
     for (int b = 0; b < kSub; ++b) {
       tcur[(size_t)b * PT + t] = over ? 0u : (uint32_t)run;   // emission cursor of the sub-bucket
       run += cnt[i][b];
     }
     tend[t] = over ? 0u : (uint32_t)run;
+    const int64_t n = over ? 0 : run - r0;
+    if (long_q && n > lc.lo) {   // a long bucket: its length class, and its place in this block's share
+      int c = 0;
+#pragma unroll
+      for (int k = 1; k < kLongClasses; ++k) c += (k < lc.n && n <= lc.thr[k]) ? 1 : 0;
+      cls[i] = c;
+      lpos[i] = atomicAdd(&s_cls[c], 1u);
+    }
+  }
+  if (!long_q) return;
+  __syncthreads();
+  if (tid < lc.n && s_cls[tid] != 0u) s_base[tid] = atomicAdd(&long_q[tid], s_cls[tid]);
+  __syncthreads();
+  uint2 *lists = (uint2 *)(long_q + kLongQueueHeader);
+  int64_t r = run0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    uint32_t n = 0;
+#pragma unroll
+    for (int b = 0; b < kSub; ++b) n += cnt[i][b];
+    if (cls[i] >= 0) lists[(size_t)cls[i] * PT + s_base[cls[i]] + lpos[i]] = make_uint2((uint32_t)r, n);
+    r += n;
   }
 }
 
@@ -583,6 +615,10 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
   int64_t *rec_base = (int64_t *)(ws + lay.rec_base);
   const int64_t PT = (int64_t)p->n_pairs * lay.T;
   uint32_t *tile_cnt = (uint32_t *)(ws + lay.tile_cnt);
+  // the long-bucket queue of a tiered sort: header cleared by k_activate,
+  // lists filled by k_scan_apply
+  uint32_t *long_q = PT > kSortFewTiles ? (uint32_t *)(ws + lay.long_q) : nullptr;
+  const LongClasses lc = long_q ? long_classes() : LongClasses{};
   {
     const gsrf_grid &g = p->grid;
     int64_t nb = (p->n_gauss + 255) / 256 + ((int64_t)g.n_az * g.n_el + 255) / 256;
@@ -593,7 +629,7 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
 #define GSRF_ACTIVATE(LL)                                                                                           \
   hipLaunchKernelGGL(k_activate<LL>, dim3((unsigned)nb), dim3(256), 0, s, p->means, p->log_scales, p->quats,         \
                      p->opacity_logits, p->n_gauss, prep, tile_cnt, PT * kSub, p->pairs, p->scene_offsets_dev,       \
-                     p->n_pairs, rec_base, g.n_az, g.n_el, g.el_lo, g.el_hi, rays)
+                     p->n_pairs, rec_base, g.n_az, g.n_el, g.el_lo, g.el_hi, rays, long_q)
     switch (g.fle_L) {
       case 0: GSRF_ACTIVATE(0); break;
       case 1: GSRF_ACTIVATE(1); break;
@@ -629,13 +665,13 @@ hipError_t launch_project(const gsrf_problem *p, const Layout &lay, char *ws, hi
     // one block: counts, total and ranges in a single launch (also P * T = 0)
     hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(256), 0, s, tile_cnt, PT, (const int64_t *)nullptr, lay.cap,
                        counters, (uint32_t *)(ws + lay.tile_start), (uint32_t *)(ws + lay.tile_end),
-                       (uint32_t *)(ws + lay.tile_cur));
+                       (uint32_t *)(ws + lay.tile_cur), long_q, lc);
   } else {
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(256), 0, s, tile_cnt, PT, blk);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, blk, nblk, lay.cap, counters);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(256), 0, s, tile_cnt, PT, (const int64_t *)blk,
                        lay.cap, counters, (uint32_t *)(ws + lay.tile_start), (uint32_t *)(ws + lay.tile_end),
-                       (uint32_t *)(ws + lay.tile_cur));
+                       (uint32_t *)(ws + lay.tile_cur), long_q, lc);
   }
   return hipGetLastError();
 }

@@ -429,51 +429,6 @@ __global__ __launch_bounds__(kSmallSortThreads) void k_tile_sort_small(const uin
   msd_rank_sort<NT, true>(ekv + s0, n, skv, klo + s0, val + s0, hist, start, red, skv, kSmallSortMax);
 }
 
-// The tiles whose buckets hold lo < n <= hi entries, for a fixed grid:
-// workgroup b takes tiles b, b + grid, ..., finding them NT tiles at a time
-// (kept in tile order), and calls sort(start, n) for each.  `list` (NT words)
-// may share the sort's LDS: each thread keeps one list entry in a register
-// and hands it over through `bcast` when its turn comes.
-template <int NT, typename F>
-__device__ __forceinline__ void for_each_band_tile(const uint32_t *__restrict__ tstart,
-                                                   const uint32_t *__restrict__ tend, int64_t PT, int lo, int hi,
-                                                   uint32_t *list, uint32_t *n_list, uint32_t *bcast, F sort) {
-  constexpr int W = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t stride = gridDim.x;
-  for (int64_t k0 = 0; blockIdx.x + k0 * stride < PT; k0 += NT) {
-    const int64_t t = blockIdx.x + (k0 + tid) * stride;
-    const int n = t < PT ? (int)(tend[t] - tstart[t]) : 0;
-    const bool in = n > lo && n <= hi;
-    const uint64_t m = __ballot(in);
-    if (lane == 0) n_list[wave] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t run = 0;
-      for (int w = 0; w < W; ++w) {
-        const uint32_t c = n_list[w];
-        n_list[w] = run;
-        run += c;
-      }
-      n_list[W] = run;
-    }
-    __syncthreads();
-    if (in) list[n_list[wave] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)t;
-    __syncthreads();
-    const int cnt = (int)n_list[W];
-    const uint32_t mine = tid < cnt ? list[tid] : 0u;
-    __syncthreads();
-    for (int i = 0; i < cnt; ++i) {
-      if (tid == i) *bcast = mine;
-      __syncthreads();
-      const uint32_t tt = *bcast;
-      const uint32_t s0 = tstart[tt];
-      sort(s0, (int)(tend[tt] - s0));
-      __syncthreads();
-    }
-  }
-}
-
 __global__ __launch_bounds__(kMidSortThreads) void k_tile_sort_mid(const uint32_t *__restrict__ tstart,
                                                                   const uint32_t *__restrict__ tend,
                                                                   const uint2 *__restrict__ ekv,
@@ -493,22 +448,61 @@ __global__ __launch_bounds__(kMidSortThreads) void k_tile_sort_mid(const uint32_
 // The long buckets by 1024-thread workgroups: REGS = 8 (two workgroups per CU,
 // 64 VGPRs) for buckets up to that kernel's LDS chunk, REGS = 16 (one per CU,
 // a chunk of 16384 entries in 128 KB of LDS) for the longer ones, which beyond
-// the chunk go through global memory.
+// the chunk go through global memory.  A fixed grid takes the buckets of length
+// classes [c_lo, c_hi) of the queue, longest class first, one bucket per
+// atomic pop of its kernel's counter (`pop`), until the classes are exhausted.
+// Thread 0 runs two buckets ahead: while the workgroup sorts bucket k, the
+// (start, entries) of bucket k + 1 and the queue position of bucket k + 2 are
+// in flight, so no dependent global access separates two sorts.
 template <int REGS>
 __global__ __launch_bounds__(kTileSortThreads, REGS == kSortRegs ? 8 : 4) void k_tile_sort_long(
-    const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend, int64_t PT, int lo, int hi, int chunk,
-    const uint2 *__restrict__ ekv, uint32_t *__restrict__ klo, uint32_t *__restrict__ val, uint2 *__restrict__ tkv) {
+    uint32_t *__restrict__ long_q, int64_t PT, int c_lo, int c_hi, int pop, int chunk,
+    const uint2 *__restrict__ ekv, uint32_t *__restrict__ klo, uint32_t *__restrict__ val,
+    uint2 *__restrict__ tkv) {
   extern __shared__ uint64_t sm64[];
   uint64_t *red = sm64;
   uint32_t *hist = (uint32_t *)(sm64 + 4 * kSortWaves);
   uint32_t *start = hist + kSortBins;
   uint2 *skv = (uint2 *)(start + kSortBins);
-  __shared__ uint32_t n_list[kSortWaves + 1], bcast;
-  // (the tile list shares the scatter buffer: chunk >= 1024 entries)
-  for_each_band_tile<kTileSortThreads>(tstart, tend, PT, lo, hi, (uint32_t *)skv, n_list, &bcast,
-                                       [&](uint32_t s0, int n) {
-    sort_bucket<REGS>(ekv, s0, n, chunk, klo, val, tkv, hist, start, red, skv);
-  });
+  __shared__ uint2 s_job;
+  constexpr uint32_t kDone = 0xffffffffu;   // entries of the job past the queue's end
+  const uint2 *lists = (const uint2 *)(long_q + kLongQueueHeader);
+  uint32_t *ctr = long_q + kLongClasses + pop;
+  uint32_t cnt[kLongClasses];
+  uint32_t next = 0;
+  uint2 job1 = make_uint2(0u, kDone);
+  // queue position -> (start, entries), or kDone past the classes' end
+  auto fetch = [&](uint32_t i) -> uint2 {
+    int64_t slot = -1;
+#pragma unroll
+    for (int k = 0; k < kLongClasses; ++k)
+      if (slot < 0 && k >= c_lo && k < c_hi) {
+        if (i < cnt[k]) slot = (int64_t)k * PT + i;
+        else i -= cnt[k];
+      }
+    return slot < 0 ? make_uint2(0u, kDone) : lists[slot];
+  };
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kLongClasses; ++k) cnt[k] = long_q[k];
+    const uint32_t p0 = atomicAdd(ctr, 1u);
+    const uint32_t p1 = atomicAdd(ctr, 1u);
+    s_job = fetch(p0);
+    job1 = fetch(p1);
+    next = atomicAdd(ctr, 1u);
+  }
+  for (;;) {
+    __syncthreads();
+    const uint2 job = s_job;
+    if (job.y == kDone) return;   // the same for every thread of the workgroup
+    sort_bucket<REGS>(ekv, job.x, (int)job.y, chunk, klo, val, tkv, hist, start, red, skv);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_job = job1;
+      job1 = fetch(next);
+      next = atomicAdd(ctr, 1u);
+    }
+  }
 }
 
 static int g_sort_chunk = 0, g_long_chunk = 0, g_xl_chunk = 0, g_n_cu = 0;
@@ -543,12 +537,12 @@ static void set_lds(const void *f, size_t bytes) {
 
 static void choose_sort_chunk() {
   if (g_sort_chunk) return;
-  const size_t list_bytes = (size_t)4 * (kSortWaves + 2);   // n_list, bcast
+  const size_t item_bytes = 16;   // s_item, rounded up
   g_sort_chunk = sort_chunk_for(0, 2, kSortRegs, &g_sort_lds);
   set_lds((const void *)k_tile_sort, g_sort_lds);
-  g_long_chunk = sort_chunk_for(list_bytes, 2, kSortRegs, &g_long_lds);
+  g_long_chunk = sort_chunk_for(item_bytes, 2, kSortRegs, &g_long_lds);
   set_lds((const void *)k_tile_sort_long<kSortRegs>, g_long_lds);
-  g_xl_chunk = sort_chunk_for(list_bytes, 1, kXlRegs, &g_xl_lds);
+  g_xl_chunk = sort_chunk_for(item_bytes, 1, kXlRegs, &g_xl_lds);
   set_lds((const void *)k_tile_sort_long<kXlRegs>, g_xl_lds);
   int dev = 0, n = 0;
   if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
@@ -558,8 +552,29 @@ static void choose_sort_chunk() {
     g_n_cu = 256;
 }
 
-// Launches with more (pair, tile) units than this sort in two kernels.
-constexpr int64_t kSortFewTiles = 2048;
+// Classes of the long-bucket queue: above the 8-entry kernel's chunk, five
+// classes bounded by 2, 1.5 and 1 times the 16-entry kernel's chunk and the
+// midpoint of the two chunks; from kMidSortMax to the 8-entry chunk, two
+// classes split at their midpoint.  Within a class the buckets' costs differ
+// by at most a factor of about 1.5, so taking the classes in order gives each
+// workgroup a nearly equal share.
+LongClasses long_classes() {
+  choose_sort_chunk();
+  LongClasses lc{};
+  int n = 0;
+  lc.thr[n++] = INT_MAX;
+  const int xl = g_xl_chunk, lg = g_long_chunk;
+  for (const int t : {2 * xl, xl + xl / 2, xl, (xl + lg) / 2})
+    if (t > lg && t < lc.thr[n - 1]) lc.thr[n++] = t;
+  lc.thr[n++] = lg;
+  lc.split = n - 1;
+  const int mid = (lg + kMidSortMax) / 2;
+  if (mid > kMidSortMax && mid < lg) lc.thr[n++] = mid;
+  lc.thr[n++] = kMidSortMax;
+  lc.n = n - 1;
+  lc.lo = kMidSortMax;
+  return lc;
+}
 
 hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, hipStream_t s) {
   const int64_t PT = (int64_t)p->n_pairs * lay.T;
@@ -592,12 +607,14 @@ hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, h
     hipLaunchKernelGGL(k_tile_sort_small, dim3((unsigned)PT), dim3(kSmallSortThreads), 0, s, tstart, tend, ekv, klo,
                        val);
     hipLaunchKernelGGL(k_tile_sort_mid, dim3((unsigned)PT), dim3(kMidSortThreads), 0, s, tstart, tend, ekv, klo, val);
+    const LongClasses lc = long_classes();
+    uint32_t *long_q = (uint32_t *)(ws + lay.long_q);   // filled by k_scan_apply
     const int64_t grid = 2 * (int64_t)g_n_cu < PT ? 2 * (int64_t)g_n_cu : PT;   // two workgroups per CU
     hipLaunchKernelGGL(k_tile_sort_long<kSortRegs>, dim3((unsigned)grid), dim3(kTileSortThreads), g_long_lds, s,
-                       tstart, tend, PT, kMidSortMax, g_long_chunk, g_long_chunk, ekv, klo, val, tkv);
+                       long_q, PT, lc.split, lc.n, 1, g_long_chunk, ekv, klo, val, tkv);
     const int64_t xgrid = (int64_t)g_n_cu < PT ? (int64_t)g_n_cu : PT;         // one workgroup per CU
     hipLaunchKernelGGL(k_tile_sort_long<kXlRegs>, dim3((unsigned)xgrid), dim3(kTileSortThreads), g_xl_lds, s,
-                       tstart, tend, PT, g_long_chunk, INT_MAX, g_xl_chunk, ekv, klo, val, tkv);
+                       long_q, PT, 0, lc.split, 0, g_xl_chunk, ekv, klo, val, tkv);
   }
   return hipGetLastError();
 }
