@@ -197,8 +197,10 @@ __device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint3
 
 // Sort the n entries ekv = (key, value) by composite into (ok, ov) through the scatter
 // buffer bkv; SH: the buffer is in LDS, else in global memory and ranked
-// through the LDS window skv.
-template <int NT, bool SH, int REGS = kSortRegs>
+// through the LDS window skv.  HREGS (global buffer only): the first HREGS * NT
+// entries stay in registers across the extremes, histogram and scatter passes,
+// and only the rest is read from global memory in each of them.
+template <int NT, bool SH, int REGS = kSortRegs, int HREGS = 0>
 __device__ __forceinline__ void msd_rank_sort(const uint2 *__restrict__ ekv, int n, uint2 *bkv, uint32_t *__restrict__ ok,
                               uint32_t *__restrict__ ov, uint32_t *hist, uint32_t *start, uint64_t *red, uint2 *skv,
                               int chunk) {
@@ -206,27 +208,28 @@ __device__ __forceinline__ void msd_rank_sort(const uint2 *__restrict__ ekv, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // LDS path (n <= REGS * NT): each thread keeps its entries in registers
   // across the passes, so the bucket is read from global memory once
-  uint32_t rk[SH ? REGS : 1], rv[SH ? REGS : 1];
-  if constexpr (SH) {
+  constexpr int RR = SH ? REGS : HREGS;
+  uint32_t rk[RR > 0 ? RR : 1], rv[RR > 0 ? RR : 1];
+  const int nr = min(n, RR * NT);   // entries held in registers
 #pragma unroll
-    for (int e = 0; e < REGS; ++e) {
-      const int i = tid + e * NT;
-      const uint2 x = i < n ? ekv[i] : make_uint2(0u, 0u);
-      rk[e] = x.x;
-      rv[e] = x.y;
-    }
+  for (int e = 0; e < RR; ++e) {
+    const int i = tid + e * NT;
+    const uint2 x = i < nr ? ekv[i] : make_uint2(0u, 0u);
+    rk[e] = x.x;
+    rv[e] = x.y;
   }
+  const uint2 *gkv = ekv + nr;      // the rest, read in every pass
+  const int ng = n - nr;
   uint64_t cmin = ~0ull, cmax = 0;
-  if constexpr (SH) {
 #pragma unroll
-    for (int e = 0; e < REGS; ++e)
-      if (tid + e * NT < n) {
-        const uint64_t c = composite(rk[e], rv[e]);
-        cmin = c < cmin ? c : cmin;
-        cmax = c > cmax ? c : cmax;
-      }
-  } else {
-    for_each_global<NT>(ekv, n, [&](uint2 x) {
+  for (int e = 0; e < RR; ++e)
+    if (tid + e * NT < nr) {
+      const uint64_t c = composite(rk[e], rv[e]);
+      cmin = c < cmin ? c : cmin;
+      cmax = c > cmax ? c : cmax;
+    }
+  if constexpr (!SH) {
+    for_each_global<NT>(gkv, ng, [&](uint2 x) {
       const uint64_t c = composite(x.x, x.y);
       cmin = c < cmin ? c : cmin;
       cmax = c > cmax ? c : cmax;
@@ -274,27 +277,23 @@ __device__ __forceinline__ void msd_rank_sort(const uint2 *__restrict__ ekv, int
   };
   for (int i = tid; i < nbins; i += NT) hist[i] = 0;
   __syncthreads();
-  if constexpr (SH) {
 #pragma unroll
-    for (int e = 0; e < REGS; ++e)
-      if (tid + e * NT < n) atomicAdd(&hist[digit(rk[e])], 1u);
-  } else {
-    for_each_global<NT>(ekv, n, [&](uint2 x) { atomicAdd(&hist[digit(x.x)], 1u); });
-  }
+  for (int e = 0; e < RR; ++e)
+    if (tid + e * NT < nr) atomicAdd(&hist[digit(rk[e])], 1u);
+  if constexpr (!SH) for_each_global<NT>(gkv, ng, [&](uint2 x) { atomicAdd(&hist[digit(x.x)], 1u); });
   __syncthreads();
   bins_scan<NT>(hist, start, nbins, (uint32_t *)(red + 2 * kSortWaves + 2));
   __syncthreads();
   for (int i = tid; i < nbins; i += NT) hist[i] = start[i];     // scatter cursors
   __syncthreads();
-  if constexpr (SH) {
 #pragma unroll
-    for (int e = 0; e < REGS; ++e)
-      if (tid + e * NT < n) {
-        const uint32_t p = atomicAdd(&hist[digit(rk[e])], 1u);
-        bkv[p] = make_uint2(rk[e], rv[e]);
-      }
-  } else {
-    for_each_global<NT>(ekv, n, [&](uint2 x) {
+  for (int e = 0; e < RR; ++e)
+    if (tid + e * NT < nr) {
+      const uint32_t p = atomicAdd(&hist[digit(rk[e])], 1u);
+      bkv[p] = make_uint2(rk[e], rv[e]);
+    }
+  if constexpr (!SH) {
+    for_each_global<NT>(gkv, ng, [&](uint2 x) {
       const uint32_t p = atomicAdd(&hist[digit(x.x)], 1u);
       bkv[p] = x;
     });
@@ -374,7 +373,8 @@ __device__ __forceinline__ void msd_rank_sort(const uint2 *__restrict__ ekv, int
 }
 
 // One bucket by the 1024-thread workgroup: in LDS up to `chunk` entries
-// (REGS * 1024 at most), else through the global scratch tkv.
+// (REGS * 1024 at most), else through the global scratch tkv, with the first
+// REGS * 1024 entries kept in registers when REGS exceeds kSortRegs.
 template <int REGS = kSortRegs>
 __device__ __forceinline__ void sort_bucket(const uint2 *__restrict__ ekv, uint32_t s0, int n, int chunk,
                                             uint32_t *__restrict__ klo, uint32_t *__restrict__ val,
@@ -384,7 +384,8 @@ __device__ __forceinline__ void sort_bucket(const uint2 *__restrict__ ekv, uint3
   if (n <= chunk)
     msd_rank_sort<kTileSortThreads, true, REGS>(ekv + s0, n, skv, klo + s0, val + s0, hist, start, red, skv, chunk);
   else
-    msd_rank_sort<kTileSortThreads, false>(ekv + s0, n, tkv + s0, klo + s0, val + s0, hist, start, red, skv, chunk);
+    msd_rank_sort<kTileSortThreads, false, REGS, (REGS > kSortRegs ? REGS : 0)>(ekv + s0, n, tkv + s0, klo + s0,
+                                                                               val + s0, hist, start, red, skv, chunk);
 }
 
 // a4: sort every tile's bucket; writes the sorted depth keys and Gaussian ids.
