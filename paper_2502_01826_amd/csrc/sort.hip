@@ -195,6 +195,91 @@ __device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint3
   }
 }
 
+// a3 for workgroups of RB = 1024 records with at most kEmitStagedTiles tiles:
+// the splats are taken kEmitChunk at a time; each chunk is counted per tile
+// (one search per splat), its tiles' shares are reserved with one global
+// atomic each, and the chunk is placed in LDS in tile order, so that the
+// stores to the buckets run over consecutive addresses of each tile's share
+// instead of one cache line per lane.
+constexpr int kEmitChunk = 4096;
+constexpr int kEmitStagedTiles = 1536;
+
+template <int RB>
+__global__ __launch_bounds__(RB) void k_emit_staged(const gsrf_pair *__restrict__ pairs,
+                                                     const int64_t *__restrict__ scene_off,
+                                                     const int64_t *__restrict__ rec_base,
+                                                     const uint32_t *__restrict__ rec_key,
+                                                     const ushort4 *__restrict__ rec_rect, int32_t T, int32_t nta,
+                                                     int64_t PT, const int64_t *__restrict__ counters,
+                                                     uint32_t *__restrict__ tcur, uint2 *__restrict__ ekv) {
+  if (counters[1] != 0) return;  // over capacity: every range is empty, nothing is emitted
+  constexpr int E = kEmitChunk / RB;
+  extern __shared__ uint32_t sm[];
+  uint32_t *ccnt = sm;            // [T] splats of the chunk per tile
+  uint32_t *cstart = sm + T;      // [T] their start in the staged chunk
+  uint32_t *cbase = sm + 2 * T;   // [T] their reserved start in the bucket
+  __shared__ RectScan<RB> rs;
+  __shared__ uint32_t keys[RB];
+  __shared__ uint2 stage[kEmitChunk];
+  __shared__ uint16_t stile[kEmitChunk];
+  __shared__ uint32_t wsum[RB / 64];
+  const int tid = threadIdx.x;
+  const int k = blockIdx.y;
+  for (int t = tid; t < T; t += RB) ccnt[t] = 0;
+  const int s = pairs[k].scene;
+  const int64_t g0 = scene_off[s];
+  const int64_t n = scene_off[s + 1] - g0;
+  const int64_t j = (int64_t)blockIdx.x * RB + tid;
+  ushort4 rc = make_ushort4(0, 0, 0, 0);
+  uint32_t key = 0;
+  if (j < n) {
+    const int64_t r = rec_base[k] + j;
+    rc = rec_rect[r];
+    key = rec_key[r];
+  }
+  keys[tid] = key;
+  rect_scan(rs, rc);   // (ends with a barrier: ccnt and keys are visible)
+  const uint32_t total = rs.off[RB];
+  const uint32_t gbase = (uint32_t)(g0 + (int64_t)blockIdx.x * RB);
+  uint32_t *cur = tcur + (size_t)(blockIdx.x % kSub) * PT + (size_t)k * T;
+  for (uint32_t c0 = 0; c0 < total; c0 += kEmitChunk) {
+    int tt[E], slot[E];
+    uint32_t rank[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t sp = c0 + (uint32_t)(tid + e * RB);
+      tt[e] = -1;
+      if (sp < total) {
+        slot[e] = rect_splat(rs, sp, nta, &tt[e]);
+        rank[e] = atomicAdd(&ccnt[tt[e]], 1u);
+      }
+    }
+    __syncthreads();
+    bins_scan<RB>(ccnt, cstart, T, wsum);
+    for (int t = tid; t < T; t += RB) {
+      const uint32_t c = ccnt[t];
+      if (c) cbase[t] = atomicAdd(cur + t, c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (tt[e] >= 0) {
+        const uint32_t p = cstart[tt[e]] + rank[e];
+        stage[p] = make_uint2(keys[slot[e]], gbase + (uint32_t)slot[e]);
+        stile[p] = (uint16_t)tt[e];
+      }
+    __syncthreads();
+    const uint32_t m = min((uint32_t)kEmitChunk, total - c0);
+    for (uint32_t i = tid; i < m; i += RB) {
+      const int t = stile[i];
+      ekv[cbase[t] + (i - cstart[t])] = stage[i];
+    }
+    __syncthreads();
+    for (int t = tid; t < T; t += RB) ccnt[t] = 0;
+    __syncthreads();
+  }
+}
+
 // Sort the n entries ekv = (key, value) by composite into (ok, ov) through the scatter
 // buffer bkv; SH: the buffer is in LDS, else in global memory and ranked
 // through the LDS window skv.  HREGS (global buffer only): the first HREGS * NT
@@ -586,7 +671,12 @@ hipError_t launch_bin_sort(const gsrf_problem *p, const Layout &lay, char *ws, h
   {
     const int RB = lay.rec_block;
     dim3 grid((unsigned)((lay.max_scene + RB - 1) / RB), (unsigned)p->n_pairs);
-    if (RB == 1024)
+    if (RB == 1024 && lay.T <= kEmitStagedTiles)
+      hipLaunchKernelGGL(k_emit_staged<1024>, grid, dim3(1024), (size_t)lay.T * 12, s, p->pairs, p->scene_offsets_dev,
+                         (const int64_t *)(ws + lay.rec_base), (const uint32_t *)(ws + lay.rec_key),
+                         (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, PT, counters,
+                         (uint32_t *)(ws + lay.tile_cur), (uint2 *)(ws + lay.ekv));
+    else if (RB == 1024)
       hipLaunchKernelGGL(k_emit<1024>, grid, dim3(1024), (size_t)lay.T * 8, s, p->pairs, p->scene_offsets_dev,
                          (const int64_t *)(ws + lay.rec_base), (const uint32_t *)(ws + lay.rec_key),
                          (const ushort4 *)(ws + lay.rec_rect), lay.T, lay.nta, PT, counters,
