@@ -170,9 +170,10 @@ __device__ __forceinline__ void copy_window(const uint2 *__restrict__ src, uint2
   }
 }
 
-// Exclusive scan of cnt[0, nbins) into start[0, nbins) by the NT threads.
-template <int NT>
-__device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint32_t *wsum) {
+// Exclusive scan of cnt[0, nbins) into start[0, nbins) by the NT threads;
+// CURSOR: cnt is overwritten with the same starts (scatter cursors).
+template <int NT, bool CURSOR = false>
+__device__ void bins_scan(uint32_t *cnt, uint32_t *start, int nbins, uint32_t *wsum) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (nbins + NT - 1) / NT;
   const int lo = min(nbins, tid * per), hi = min(nbins, lo + per);
@@ -190,8 +191,10 @@ __device__ void bins_scan(const uint32_t *cnt, uint32_t *start, int nbins, uint3
   for (int w = 0; w < wave; ++w) off += wsum[w];
   uint32_t run = off + inc - local;
   for (int i = lo; i < hi; ++i) {
+    const uint32_t c = cnt[i];
     start[i] = run;
-    run += cnt[i];
+    if (CURSOR) cnt[i] = run;
+    run += c;
   }
 }
 
@@ -320,6 +323,11 @@ __device__ __forceinline__ void msd_rank_sort(const uint2 *__restrict__ ekv, int
       cmax = c > cmax ? c : cmax;
     });
   }
+  int bits = 1;
+  while (bits < kSortBitsMax && (4 << bits) < n) ++bits;
+  const int nbins = 1 << bits;
+  // the histogram is cleared before the one barrier of the extremes
+  for (int i = tid; i < nbins; i += NT) hist[i] = 0;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     const uint64_t a = shfl_xor_u64(cmin, d), b = shfl_xor_u64(cmax, d);
@@ -347,29 +355,22 @@ __device__ __forceinline__ void msd_rank_sort(const uint2 *__restrict__ ekv, int
   __syncthreads();
   cmin = red[2 * kSortWaves];
   cmax = red[2 * kSortWaves + 1];
-  int bits = 1;
-  while (bits < kSortBitsMax && (4 << bits) < n) ++bits;
   // sub-bucket of an entry: its depth key's value (D^2) scaled linearly onto
   // [0, nbins) -- monotone in the key, so in the composite; the density of
   // splats grows slowly with D^2 (not like the key bits, which are
   // logarithmic in D^2), so the sub-buckets stay balanced
-  const int nbins = 1 << bits;
   const float dlo = __uint_as_float((uint32_t)(cmin >> 32)), dhi = __uint_as_float((uint32_t)(cmax >> 32));
   const float scale = dhi > dlo ? (float)nbins / (dhi - dlo) : 0.f;
   auto digit = [&](uint32_t k) -> uint32_t {   // (a NaN product, from an infinite scale, lands in the last bin)
     const float x = (__uint_as_float(k) - dlo) * scale;
     return x < (float)nbins ? (uint32_t)x : (uint32_t)(nbins - 1);
   };
-  for (int i = tid; i < nbins; i += NT) hist[i] = 0;
-  __syncthreads();
 #pragma unroll
   for (int e = 0; e < RR; ++e)
     if (tid + e * NT < nr) atomicAdd(&hist[digit(rk[e])], 1u);
   if constexpr (!SH) for_each_global<NT>(gkv, ng, [&](uint2 x) { atomicAdd(&hist[digit(x.x)], 1u); });
   __syncthreads();
-  bins_scan<NT>(hist, start, nbins, (uint32_t *)(red + 2 * kSortWaves + 2));
-  __syncthreads();
-  for (int i = tid; i < nbins; i += NT) hist[i] = start[i];     // scatter cursors
+  bins_scan<NT, true>(hist, start, nbins, (uint32_t *)(red + 2 * kSortWaves + 2));   // hist: scatter cursors
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < RR; ++e)
