@@ -66,11 +66,24 @@ __global__ __launch_bounds__(RB) void k_emit(const gsrf_pair *__restrict__ pairs
   }
   __syncthreads();
   // reserve this workgroup's share of each touched tile in sub-bucket b % kSub
+  // (four tiles per thread at a time, so that their atomics are in flight together)
   uint32_t *cur = tcur + (size_t)(blockIdx.x % kSub) * PT + (size_t)k * T;
-  for (int t = threadIdx.x; t < T; t += blockDim.x) {
-    const uint32_t c = cnt[t];
-    if (c) base[t] = atomicAdd(cur + t, c);
-    cnt[t] = 0;
+  for (int t0 = threadIdx.x; t0 < T; t0 += 4 * RB) {
+    uint32_t r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * RB;
+      const uint32_t c = t < T ? cnt[t] : 0u;
+      r[u] = c ? atomicAdd(cur + t, c) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * RB;
+      if (t < T) {
+        base[t] = r[u];
+        cnt[t] = 0;
+      }
+    }
   }
   __syncthreads();
   const uint32_t gbase = (uint32_t)(g0 + (int64_t)blockIdx.x * RB);
