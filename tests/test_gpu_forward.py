@@ -551,3 +551,38 @@ def test_large_uneven_batch_binning_is_complete():
     p = pairs[4]
     uv = np.stack([rng.integers(0, g.n_az, 24), rng.integers(0, g.n_el, 24)], 1)
     compare_rays(S[4][uv[:, 1], uv[:, 0]], oracle.trace(scenes[p.scene], p, g, uv), scenes[p.scene], p, g)
+
+
+@pytest.mark.parametrize("n_gauss,n_pairs", [(200_000, 8), (500_000, 9)])
+def test_tiered_sort_ignores_workspace_contents(n_gauss, n_pairs):
+    """More than 2048 (pair, tile) units: the sort runs in tiers by bucket length,
+    the long buckets taken from a queue whose counts and pop counters live in the
+    workspace.  A workspace filled with 0xFF bytes before the forward gives the
+    same tile ranges, sorted lists and signal, bit for bit, as a zeroed one.
+    200k x 8: 256-record projection and emit workgroups, buckets up to about
+    7,500 entries (the 16-entry tier's classes stay empty); 500k x 9: 4.5 M
+    records, so four-chunk projection and staged 1024-record emit, and buckets
+    past the 16384 entries that the longest tier keeps in LDS."""
+    g = Grid(n_az=360, n_el=90, fle_L=2, tile_w=8, tile_h=8, lanes_per_ray=0)
+    rng = np.random.default_rng([41, n_pairs])
+    room = (10.0, 8.0, 3.0)
+    sc = synth.draw_scene(rng, n_gauss, room, g.K)
+    b = Batch([sc], [synth.draw_pair(rng, room, 5e9) for _ in range(n_pairs)], g)
+    say("tiered sort, workspace fill 0 and 0xFF:", n_gauss, "gaussians,", n_pairs, "pairs")
+    prob = gpu_problem(b)
+    assert n_pairs * g.n_tiles > 2048
+    runs = []
+    for fill in (0, 255):
+        prob.ws.fill_(fill)
+        sig, ssum, _ = prob.forward()
+        L = gpu_lists(prob)
+        runs.append((sig.clone(), ssum.clone(), L))
+    (s0, m0, L0), (s1, m1, L1) = runs
+    assert L0["overflow"] == 0 and L0["n"] == L1["n"]
+    lengths = L0["te"] - L0["ts"]
+    assert lengths.max() > 3840   # the long-bucket tiers are exercised
+    if n_gauss >= 500_000:
+        assert lengths.max() > 16384
+    for key in ("ts", "te", "klo", "val", "rec_key", "rec_rect"):
+        np.testing.assert_array_equal(L0[key], L1[key], err_msg=key)
+    assert torch.equal(s0, s1) and torch.equal(m0, m1)
