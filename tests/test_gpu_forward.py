@@ -586,3 +586,34 @@ def test_tiered_sort_ignores_workspace_contents(n_gauss, n_pairs):
     for key in ("ts", "te", "klo", "val", "rec_key", "rec_rect"):
         np.testing.assert_array_equal(L0[key], L1[key], err_msg=key)
     assert torch.equal(s0, s1) and torch.equal(m0, m1)
+
+
+def test_large_batch_on_a_fine_grid_is_complete():
+    """720 x 180 rays in 8x8 tiles (2070 tiles per pair, past the 1536 that the
+    staged 1024-record emit holds in LDS, so emit takes its direct path) and
+    4.2 M records (one 600,000-Gaussian scene, 7 pairs).  Every record's key and
+    rectangle against the oracle, every tile list of every pair against the
+    host expansion of the rectangles, and sampled rays against the oracle."""
+    g = Grid(n_az=720, n_el=180, fle_L=2, tile_w=8, tile_h=8, lanes_per_ray=0)
+    assert g.n_tiles > 1536
+    rng = np.random.default_rng(43)
+    room = (10.0, 8.0, 3.0)
+    sc = synth.draw_scene(rng, 600_000, room, g.K)
+    pairs = [synth.draw_pair(rng, room, 5e9) for _ in range(7)]
+    b = Batch([sc], pairs, g)
+    say("fine grid batch: 720x180 rays, 600k gaussians, 7 pairs")
+    prob = gpu_problem(b)
+    assert prob.layout().n_records == 7 * sc.n >= (1 << 22)
+    S, _, _ = gpu_forward(prob)
+    L = gpu_lists(prob)
+    assert L["overflow"] == 0
+    for k, p in enumerate(pairs):
+        a, e = int(L["base"][k]), int(L["base"][k + 1])
+        np.testing.assert_array_equal(L["rec_key"][a:e], oracle.depth_key32(sc.means, p.rx).astype(np.uint32))
+        tu0, ntu, tv0, ntv, cm = oracle.cap_rects(sc.means, sc.log_scales, p.rx, g)
+        np.testing.assert_array_equal(L["rec_rect"][a:e][~cm], np.stack([tu0, ntu, tv0, ntv], 1)[~cm])
+    lens = assert_lists_complete(L, g.n_tiles_az, [0] * len(pairs))
+    say("splats", int(lens.sum()), "longest list", int(lens.max()))
+    p = pairs[3]
+    uv = np.stack([rng.integers(0, g.n_az, 16), rng.integers(0, g.n_el, 16)], 1)
+    compare_rays(S[3][uv[:, 1], uv[:, 0]], oracle.trace(sc, p, g, uv), sc, p, g)
