@@ -324,6 +324,12 @@ def main() -> int:
         t = st["median"]
         bufs = dict(sig=step.signal, ssum=step.signal_sum, rssi=step.rssi, G=gs, gsum=gsum, grads=step.grads)
         roof = roofline(prob, bufs, grad)
+        # HBM bytes per launch from the committed PMC record, keyed by tile, lanes and Gaussians x pairs
+        cfg = f"{tw}x{th}/{lanes}/{int(cat.means.shape[0])}x{P}"
+        roof["traffic"] = measured_traffic(roof["kernel"], cfg) if grid.footprint == 0 else None
+        if roof["other_kernel"] is not None:
+            roof["other_kernel"]["traffic"] = (measured_traffic(roof["other_kernel"]["kernel"], cfg)
+                                               if grid.footprint == 0 else None)
         n_splats, ok = prob.splat_count()
         if not ok:
             raise RuntimeError(f"{label}: {n_splats} splats exceed the capacity fixed before capture")
