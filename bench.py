@@ -482,7 +482,9 @@ def main() -> int:
                 "speedup_vs_per_carrier_kernels": nf * t_1k / t_mk,
                 "adjoint": adjoint,
                 "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                             "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None,
+                             "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU,
+                             "traffic": (measured_traffic("render_fwd_multi", f"{args.tile}/{args.lanes}/{args.gaussians}")
+                                         if args.footprint == "cap" else None),
                              "kernel": "render_fwd_multi traversals", "flop_per_launch": fl,
                              "timing": "HIP events recorded by the library around the carrier-chunk traversals",
                              "counts": st}}
